@@ -1,0 +1,331 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each oracle function is checked against something other than itself:
+closed forms on tiny graphs (tests/golden/closed_forms.json), truncated
+Neumann / Taylor / Chebyshev series in the eps -> 0 limit, dense solves with the
+error bound of Theorem 3.2, the exact identities in the proof of Corollary 3.5,
+and the work bounds of Theorem 3.2 / Corollary 3.5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact as X
+from oracle import solvers as O
+from paper_2410_21634_amd import workloads as W
+
+PPR, KATZ = O.PPR, O.KATZ
+TINY = 1e-300  # every nonzero residual is active
+
+
+def two_node():
+    return W.from_edges(2, [(0, 1)])
+
+
+def k5():
+    return W.from_edges(5, [(i, j) for i in range(5) for j in range(i + 1, 5)])
+
+
+def star():
+    return W.from_edges(5, [(0, j) for j in range(1, 5)])
+
+
+@pytest.fixture(scope="module")
+def g300():
+    return W.chung_lu(300, 1200, 2.5, seed=7)
+
+
+@pytest.fixture(scope="module")
+def g2000():
+    return W.chung_lu(2000, 10000, 2.5, seed=11)
+
+
+# --------------------------------------------------------------------------- closed forms
+def test_localgd_two_node_trace(golden):
+    gd = golden["localgd_two_node"]
+    G = two_node()
+    res = O.localgd(G.row_ptr, G.col_idx, PPR, gd["alpha"], gd["eps"], [0], trace_cap=500)
+    assert res["iters"] == gd["T"] == 132
+    assert res["ops"] == gd["ops"]
+    np.testing.assert_allclose(res["x"], gd["x"], rtol=1e-13)
+    rt = res["r"] / gd["alpha"]
+    assert rt[1 - gd["residual_node"]] == 0.0
+    assert rt[gd["residual_node"]] == pytest.approx(gd["residual"], rel=1e-12)
+    assert res["x"].sum() + res["residual_l1"] == pytest.approx(1.0, abs=1e-15)
+    # every iteration pushes exactly one node of degree 1
+    assert list(res["trace_size"]) == [1] * 132 and list(res["trace_vol"]) == [1] * 132
+
+
+@pytest.mark.parametrize("name,maker,seed", [("ppr_two_node", two_node, 0), ("ppr_k5", k5, 0),
+                                             ("ppr_star_centre", star, 0), ("ppr_star_leaf", star, 1)])
+def test_ppr_closed_forms(golden, name, maker, seed):
+    G = maker()
+    f = np.array(golden[name]["f"])
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    np.testing.assert_allclose(X.ppr_exact(A, 0.1, X.seed_vector(G.n, [seed])), f, rtol=1e-12)
+    for eps in (1e-3, 1e-6, 1e-9):
+        for solver in ("gd", "appr"):
+            if solver == "gd":
+                res = O.localgd(G.row_ptr, G.col_idx, PPR, 0.1, eps, [seed])
+            else:
+                res = O.push_fifo(G.row_ptr, G.col_idx, PPR, 0.1, eps, [seed])
+            err = f - res["x"]
+            d = np.diff(G.row_ptr)
+            # Theorem 3.2 / Corollary 3.5: 0 <= f - x <= eps * d componentwise
+            assert (err >= -1e-15).all() and (err <= eps * d + 1e-15).all()
+
+
+def test_katz_two_node(golden):
+    kz = golden["katz_two_node"]
+    G = two_node()
+    res = O.localgd(G.row_ptr, G.col_idx, KATZ, kz["beta"], 1e-12, [0])
+    np.testing.assert_allclose(res["x"], kz["x"], atol=1e-11)
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    np.testing.assert_allclose(X.katz_exact(A, kz["beta"], [1.0, 0.0]), kz["x"], rtol=1e-14)
+
+
+def test_hk_two_node_and_psi(golden):
+    hk = golden["hk_two_node"]
+    ps = golden["hk_psi"]
+    G = two_node()
+    res = O.hk(G.row_ptr, G.col_idx, hk["tau"], ps["K"], 1e-14, [0])
+    np.testing.assert_allclose(res["psi"], ps["psi"], rtol=1e-13)
+    assert res["psi"][0] == pytest.approx(math.exp(5.0), rel=1e-10)  # Poisson tail beyond 30 is ~1e-11
+    # f_K differs from f by ||s||_1 * P(Poisson(tau) > K) in l1
+    tail = 1.0 - sum(math.exp(-5.0) * 5.0**k / math.factorial(k) for k in range(31))
+    assert abs(res["x"] - np.array(hk["f"])).sum() <= tail + 1e-13
+
+
+def test_omega_star(golden):
+    om = golden["omega_star"]["values"]
+    assert om["0.1"] == pytest.approx(1.39286, abs=1e-5)
+    assert om["0.25"] == pytest.approx(1.20378, abs=1e-5)  # the paper's toy example uses 1.19
+
+
+# --------------------------------------------------------------------------- series limits
+@pytest.mark.parametrize("T", [1, 2, 5, 17])
+def test_localgd_eps0_is_truncated_neumann(g300, T):
+    G = g300
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    s = W.uniform_seeds(G, 2, seed=3)
+    sv = np.array([0.25, 0.75])
+    svec = X.seed_vector(G.n, s, sv)
+    res = O.localgd(G.row_ptr, G.col_idx, PPR, 0.15, TINY, s, sv, max_iters=T)
+    assert res["iters"] == T
+    np.testing.assert_allclose(res["x"], X.neumann_ppr(A, 0.15, svec, T), rtol=1e-12, atol=1e-16)
+    beta = 0.02
+    res = O.localgd(G.row_ptr, G.col_idx, KATZ, beta, TINY, s, sv, max_iters=T)
+    np.testing.assert_allclose(res["x"], X.neumann_katz(A, beta, svec, T), rtol=1e-12, atol=1e-16)
+
+
+def test_hk_eps0_is_taylor(g300):
+    G = g300
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    s = W.uniform_seeds(G, 1, seed=5)
+    svec = X.seed_vector(G.n, s)
+    for tau, K in ((5.0, 30), (2.0, 7), (0.0, 3)):
+        res = O.hk(G.row_ptr, G.col_idx, tau, K, TINY, s)
+        np.testing.assert_allclose(res["x"], X.hk_taylor(A, tau, K, svec), rtol=1e-11, atol=1e-17)
+        assert res["residual_l1"] == 0.0
+    fk = X.hk_taylor(A, 5.0, 30, svec)
+    ex = X.hk_expm(A, 5.0, svec)
+    tail = 1.0 - sum(math.exp(-5.0) * 5.0**k / math.factorial(k) for k in range(31))
+    assert abs(abs(fk - ex).sum() - tail) < 1e-12
+
+
+def ring_with_chords(n=200, chords=600, seed=3):
+    rng = np.random.default_rng(seed)
+    edges = [(i, (i + 1) % n) for i in range(n)]
+    edges += [tuple(int(v) for v in rng.choice(n, 2, replace=False)) for _ in range(chords)]
+    return W.from_edges(n, edges)
+
+
+@pytest.mark.parametrize("kind", [PPR, KATZ])
+@pytest.mark.parametrize("T", [1, 2, 3, 8, 20])
+def test_localch_eps0_is_chebyshev_polynomial(kind, T):
+    # With a seed of full support on a connected graph every residual stays
+    # nonzero, so S_t = V and LocalCH is the textbook Chebyshev iteration, whose
+    # residual is T_t((L+mu-2Q)/(L-mu)) r_0 / T_t((L+mu)/(L-mu)).
+    G = ring_with_chords()
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    rng = np.random.default_rng(T)
+    sv = rng.uniform(0.5, 1.5, G.n)
+    sv /= sv.sum()
+    s = np.arange(G.n)
+    svec = X.seed_vector(G.n, s, sv)
+    if kind == PPR:
+        a = 0.1
+        Q = np.eye(G.n) - (1 - a) * X.walk_matrix(A)
+        b, mu, L, lam, param = a * svec, a, 2 - a, 0.0, a
+    else:
+        lo, hi = X.adjacency_eig_bounds(A)
+        lam = max(hi, -lo) * 1.0000001
+        param = 0.5 / lam
+        Q = np.eye(G.n) - param * A
+        b, mu, L = svec, 1 - param * lam, 1 + param * lam
+    res = O.localch(G.row_ptr, G.col_idx, kind, param, TINY, s, sv, lam=lam, max_iters=T, trace_cap=100)
+    assert list(res["trace_size"]) == [G.n] * T
+    rT = X.chebyshev_residual(Q, b, mu, L, T)
+    np.testing.assert_allclose(res["r"], rT, atol=1e-12 * np.abs(b).sum())
+    np.testing.assert_allclose(b - Q @ res["x"], res["r"], atol=1e-14)
+
+
+# --------------------------------------------------------------------------- invariants & bounds
+@pytest.mark.parametrize("eps", [1e-3, 1e-4, 1e-5])
+def test_localgd_ppr_invariants(g2000, eps):
+    G = g2000
+    a = 0.1
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    for s in W.uniform_seeds(G, 4, seed=13):
+        res = O.localgd(G.row_ptr, G.col_idx, PPR, a, eps, [s], trace_cap=10**5)
+        f = X.ppr_exact(A, a, X.seed_vector(G.n, [s]))
+        rt = res["r"] / a
+        assert (rt >= 0).all()                                               # Theorem 3.4 (1)
+        assert res["x"].sum() + rt.sum() == pytest.approx(1.0, abs=1e-13)    # mass conservation
+        assert abs(f - res["x"]).sum() == pytest.approx(rt.sum(), rel=1e-9)  # f - x = Pi r~, Pi col-stochastic
+        err = f - res["x"]
+        assert (err >= -1e-14).all() and (err <= eps * d + 1e-14).all()      # Theorem 3.2 error bound
+        assert ((rt < eps * d) | (rt == 0)).all()                            # stop rule
+        assert res["residual_dinf"] < eps
+        assert res["ops"] <= d[s] + 1.0 / (a * eps)                          # Corollary 3.5 work bound
+        r1, rs = res["trace_r_l1"], res["trace_rs_l1"]
+        # exact step identity (proof of Corollary 3.5): ||r~_{t+1}|| = ||r~_t|| - alpha ||r~_S||
+        np.testing.assert_allclose(r1[1:], r1[:-1] - a * rs[:-1], rtol=1e-9, atol=1e-15)
+        assert (np.diff(r1) <= 1e-15).all()                                  # Theorem 3.4 (2) monotone
+        # Theorem 3.4 bound on T with beta P_max = 1 - alpha
+        gam = np.mean(rs / r1)
+        assert res["iters"] <= math.log(r1[0] / res["residual_l1"]) / (gam * a) + 1e-9
+
+
+def test_localgd_katz_bounds(g2000):
+    G = g2000
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    lo, hi = X.adjacency_eig_bounds(A)
+    beta = 0.5 / hi
+    for s in W.uniform_seeds(G, 3, seed=17):
+        xs = X.katz_exact(A, beta, X.seed_vector(G.n, [s]))
+        for eps in (1e-4, 1e-6):
+            res = O.localgd(G.row_ptr, G.col_idx, KATZ, beta, eps, [s])
+            assert (res["r"] >= 0).all() and (res["x"] >= 0).all()
+            assert (res["x"] <= xs + 1e-12).all()                       # 0 <= x <= x*
+            assert ((res["r"] < eps * d) | (res["r"] == 0)).all()
+            assert res["ops"] <= d[s] + xs.sum() / eps                    # x monotone, each push adds >= eps d
+            # r = b - Q x exactly, and x* - x = Q^-1 r
+            svec = X.seed_vector(G.n, [s])
+            np.testing.assert_allclose(svec - (np.eye(G.n) - beta * A) @ res["x"], res["r"], atol=1e-14)
+
+
+def test_hk_identities(g2000):
+    G = g2000
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    for s in W.uniform_seeds(G, 3, seed=19):
+        svec = X.seed_vector(G.n, [s])
+        fK = X.hk_taylor(A, 5.0, 30, svec)
+        for eps in (1e-3, 1e-5):
+            res = O.hk(G.row_ptr, G.col_idx, 5.0, 30, eps, [s])
+            assert res["iters"] <= 31
+            err = fK - res["x"]
+            assert (err >= -1e-15).all()
+            assert err.sum() == pytest.approx(res["residual_l1"], rel=1e-9)   # sum_k psi_k ||r_k||_1
+            assert (err[d > 0] / d[d > 0] <= eps).all() and (err[d == 0] == 0).all()  # ||D^-1 (f_K - x)||_inf <= eps
+            assert res["residual_dinf"] < eps
+
+
+def test_localch_stops_consistently(g2000):
+    G = g2000
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    s = W.uniform_seeds(G, 2, seed=23)
+    a = 0.1
+    Q = np.eye(G.n) - (1 - a) * X.walk_matrix(A)
+    for eps in (1e-4, 1e-6):
+        res = O.localch(G.row_ptr, G.col_idx, PPR, a, eps, s, [0.5, 0.5])
+        b = a * X.seed_vector(G.n, s, [0.5, 0.5])
+        np.testing.assert_allclose(b - Q @ res["x"], res["r"], atol=1e-14)
+        assert ((np.abs(res["r"]) < a * eps * d) | (res["r"] == 0)).all()
+        f = X.ppr_exact(A, a, X.seed_vector(G.n, s, [0.5, 0.5]))
+        # with |r~| < eps d: |f - x| = |Pi r~| and |(Pi r~)_u| <= eps d_u (Prop. B.1 argument)
+        assert (abs(f - res["x"]) <= eps * d + 1e-14).all()
+
+
+def test_appr_and_localsor(g2000):
+    G = g2000
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    a = 0.1
+    Q = np.eye(G.n) - (1 - a) * X.walk_matrix(A)
+    omega = 2 / (1 + math.sqrt(1 - (1 - a) ** 2))
+    for s in W.uniform_seeds(G, 3, seed=29):
+        svec = X.seed_vector(G.n, [s])
+        f = X.ppr_exact(A, a, svec)
+        eps = 1e-5
+        ap = O.push_fifo(G.row_ptr, G.col_idx, PPR, a, eps, [s])
+        assert (ap["r"] >= 0).all() and ((ap["r"] / a < eps * d) | (ap["r"] == 0)).all()
+        assert ap["ops"] <= d[s] + 1.0 / (a * eps)                            # Algorithm 1 bound
+        np.testing.assert_allclose(a * svec - Q @ ap["x"], ap["r"], atol=1e-14)
+        err = f - ap["x"]
+        assert (err >= -1e-14).all() and (err <= eps * d + 1e-14).all()
+        so = O.push_fifo(G.row_ptr, G.col_idx, PPR, a, eps, [s], omega=omega, max_pops=10**7)
+        assert so["status"] == O.OK
+        np.testing.assert_allclose(a * svec - Q @ so["x"], so["r"], atol=1e-14)
+        assert ((np.abs(so["r"]) / a < eps * d) | (so["r"] == 0)).all()
+
+
+def test_appr_equals_localgd_on_a_path():
+    # on a path seeded at one end every epoch holds a single active node, so the
+    # FIFO push and the synchronous LocalGD make the same moves
+    G = W.from_edges(2, [(0, 1)])
+    gd = O.localgd(G.row_ptr, G.col_idx, PPR, 0.1, 1e-6, [0])
+    ap = O.push_fifo(G.row_ptr, G.col_idx, PPR, 0.1, 1e-6, [0])
+    np.testing.assert_array_equal(gd["x"], ap["x"])
+    assert ap["pops"] == gd["pushes"] == 132
+
+
+def test_prop_b1_symmetry(g300):
+    G = g300
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    d = np.diff(G.row_ptr).astype(float)
+    nz = np.flatnonzero(d > 0)[:20]
+    F = np.stack([X.ppr_exact(A, 0.1, X.seed_vector(G.n, [u])) for u in nz])  # F[i, v] = f_{u_i}[v]
+    for i, u in enumerate(nz):
+        for j, v in enumerate(nz):
+            assert d[u] * F[i, v] == pytest.approx(d[v] * F[j, u], rel=1e-10, abs=1e-16)
+
+
+# --------------------------------------------------------------------------- replay checker
+def test_replay_accepts_own_trace_and_flags_planted_error(g2000):
+    G = g2000
+    s = W.uniform_seeds(G, 1, seed=31)
+    for method in (0, 1):
+        fn = O.localgd if method == 0 else O.localch
+        res = fn(G.row_ptr, G.col_idx, PPR, 0.1, 1e-5, s, trace_cap=10**5, nodes_cap=10**7)
+        off, nodes = res["trace_nodes"]
+        rp = O.replay_gd_ch(G.row_ptr, G.col_idx, method, PPR, 0.1, 1e-5, s, None, off, nodes, 1e-12)
+        assert rp["flips"] == 0 and rp["violations"] == 0
+        np.testing.assert_array_equal(rp["x"], res["x"])
+        # plant a mistake: drop the first node of S_2
+        nodes2 = np.delete(nodes, off[2])
+        off2 = off.copy()
+        off2[3:] -= 1
+        bad = O.replay_gd_ch(G.row_ptr, G.col_idx, method, PPR, 0.1, 1e-5, s, None, off2, nodes2, 1e-12)
+        assert bad["violations"] > 0
+    h = O.hk(G.row_ptr, G.col_idx, 5.0, 30, 1e-5, s, nodes_cap=10**7)
+    off, nodes = h["trace_nodes"]
+    hr = O.hk(G.row_ptr, G.col_idx, 5.0, 30, 1e-5, s, replay=(off, nodes), kappa=1e-12)
+    assert hr["flips"] == 0 and hr["violations"] == 0
+    np.testing.assert_array_equal(hr["x"], h["x"])
+
+
+def test_oracle_rejects_bad_input():
+    G = two_node()
+    with pytest.raises(ValueError):
+        O.localgd(G.row_ptr, G.col_idx, PPR, 0.1, 0.0, [0])
+    with pytest.raises(ValueError):
+        O.localgd(G.row_ptr, G.col_idx, PPR, 1.5, 1e-4, [0])
+    G3 = W.from_edges(3, [(0, 1)])
+    with pytest.raises(ValueError):
+        O.localgd(G3.row_ptr, G3.col_idx, PPR, 0.1, 1e-4, [2])  # isolated seed

@@ -1,0 +1,45 @@
+"""The seeded synthetic inputs: determinism and graph well-formedness."""
+import numpy as np
+
+from paper_2410_21634_amd import workloads as W
+
+
+def test_chung_lu_deterministic_and_simple():
+    a = W.chung_lu(5000, 25000, 2.5, seed=42)
+    b = W.chung_lu(5000, 25000, 2.5, seed=42)
+    c = W.chung_lu(5000, 25000, 2.5, seed=43)
+    assert a.sha256() == b.sha256() != c.sha256()
+    assert a.nnz == 50000
+    rp, ci = a.row_ptr, a.col_idx
+    rows = np.repeat(np.arange(a.n), np.diff(rp))
+    assert (ci != rows).all()                                   # no self-loops
+    for u in range(0, a.n, 97):                                 # ascending, no duplicates
+        row = ci[rp[u]:rp[u + 1]]
+        assert (np.diff(row) > 0).all()
+    key = rows.astype(np.int64) * a.n + ci
+    rkey = ci.astype(np.int64) * a.n + rows
+    assert np.array_equal(np.sort(key), np.sort(rkey))          # symmetric
+
+
+def test_power_law_shape():
+    g = W.chung_lu(20000, 100000, 2.5, seed=1)
+    d = g.degrees
+    assert d.max() > 10 * d.mean()
+    assert abs(d.mean() - 10.0) < 1e-9
+
+
+def test_seed_samplers():
+    g = W.chung_lu(5000, 25000, 2.5, seed=42)
+    s = W.uniform_seeds(g, 64)
+    assert len(np.unique(s)) == 64 and (g.degrees[s] > 0).all()
+    st = W.stratified_seeds(g, 64, bins=8)
+    assert len(np.unique(st)) == 64
+    eps = W.log_uniform_eps(1000)
+    assert eps.min() >= 1e-7 and eps.max() <= 1e-4
+    idx, val = W.seed_set(g, int(s[0]), 8)
+    assert len(idx) == 8 and (np.diff(idx) > 0).all() and abs(val.sum() - 1) < 1e-15
+    t = W.poisson_arrivals(1000.0, 1.0)
+    assert 850 < len(t) < 1150 and (np.diff(t) > 0).all()
+    rng = np.random.default_rng(0)
+    u, v = W.insert_batch(g, 100, rng)
+    assert (u < v).all() and len(set(zip(u.tolist(), v.tolist()))) == 100
