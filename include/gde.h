@@ -1,0 +1,250 @@
+/*
+ * gde.h -- C ABI of the MI355X (gfx950) local graph-diffusion solver library.
+ *
+ * The library computes approximate graph diffusion vectors
+ *     f = sum_k c_k M^k s                       (Eq. (1), Table 1)
+ * for Personalized PageRank, Katz and the heat kernel with the local diffusion
+ * process of Definition 3.1: starting from x = 0, r = b, S_0 = supp(s), each
+ * iteration updates the estimate x and the residual r = b - Q x on the active
+ * set S_t = {u : |r_u| >= theta_u} only, until S_t is empty.
+ *
+ *   PPR  : Q = I - (1-alpha) A D^-1, b = alpha s   (Eq. (2)); theta_u = alpha*eps*d_u
+ *   Katz : Q = I - beta A,           b = s         (Eq. (3)); theta_u = eps*d_u
+ *   HK   : Taylor truncation f_K = sum_{k<=K} e^-tau tau^k/k! (A D^-1)^k s, solved
+ *          level by level on the Kronecker system of the AHK push (Sec. 2);
+ *          level-k threshold eps*d_u/((K+1) psi_k), psi_k = sum_{j=k..K} tau^(j-k) k!/j!.
+ *
+ * Methods: LocalGD (Eq. (9): x += r_S, r -= Q r_S) and LocalCH (Sec. 3.3,
+ * Chebyshev update restricted to S_t).  The heat kernel always uses the
+ * level push.
+ *
+ * Conventions shared by every entry point
+ *   - All sizes and indices are int32 node ids / int64 counts; the graph is a
+ *     simple undirected graph stored as a symmetric CSR (row_ptr[n+1],
+ *     col_idx[nnz], nnz = 2|E| < 2^31, no self-loops).
+ *   - Every call returns a gde_status.  No exception crosses the ABI.  All
+ *     argument validation runs on the host before any device work, so a
+ *     rejected call leaves the device untouched.  gde_last_error() gives a
+ *     thread-local text for the last non-OK status.
+ *   - Device work is enqueued on the hipStream_t passed in (NULL = the
+ *     default stream).  gde_solve and gde_solve_batch return with their
+ *     outputs final (they synchronise that stream).
+ *   - A gde_ctx is used by one host thread at a time.  A gde_graph is
+ *     immutable and may be shared by contexts on the same device.
+ *   - Inputs are borrowed for the duration of the call; results are written
+ *     only into caller-owned buffers.  Every *_create has a matching *_destroy.
+ */
+#ifndef GDE_H
+#define GDE_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GDE_ABI_VERSION 1
+
+typedef enum gde_status {
+    GDE_OK = 0,
+    GDE_ERR_INVALID_ARG = 1,   /* null pointer, malformed CSR, parameter out of range (see gde_params) */
+    GDE_ERR_ISOLATED_SEED = 2, /* some u in supp(s) has d_u = 0: D^-1 is undefined there */
+    GDE_ERR_CAPACITY = 3,      /* result buffer too small: result.nnz holds the size needed, nothing written */
+    GDE_ERR_NOT_CONVERGED = 4, /* max_iters reached; the result is valid and its residual is reported */
+    GDE_ERR_OOM = 5,           /* device or host allocation failed */
+    GDE_ERR_BUSY = 6,          /* server admission refused and its queue is full */
+    GDE_ERR_DEVICE = 7,        /* a HIP call failed; gde_last_error() has the HIP message */
+    GDE_ERR_UNSUPPORTED = 8    /* valid but not provided (LocalCH for the heat kernel) */
+} gde_status;
+
+typedef enum gde_kind { GDE_PPR = 0, GDE_KATZ = 1, GDE_HK = 2 } gde_kind;
+typedef enum gde_method { GDE_LOCAL_GD = 0, GDE_LOCAL_CH = 1 } gde_method;
+typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
+
+/* gde_graph_create flags */
+#define GDE_HOST_PTRS 0x1u   /* row_ptr / col_idx are host pointers (always copied) */
+#define GDE_DEVICE_PTRS 0x2u /* row_ptr / col_idx are device pointers on the context's device */
+#define GDE_COPY 0x4u        /* the library keeps its own device copy */
+#define GDE_BORROW 0x8u      /* device pointers are used in place; they must outlive the graph */
+
+/* gde_params.flags */
+#define GDE_KATZ_SUBTRACT_SEED 0x1u /* Katz: return x - s, the centrality ((I - beta A)^-1 - I) s */
+#define GDE_TRACE 0x2u              /* record |S_t|, vol(S_t) and the S_t lists into the result */
+#define GDE_RESULT_DEVICE 0x4u      /* result idx / val are device pointers (else host) */
+
+typedef struct gde_ctx gde_ctx;
+typedef struct gde_graph gde_graph;
+typedef struct gde_server gde_server;
+
+/*
+ * One diffusion query.
+ *   kind, method     : gde_kind, gde_method (LocalCH with HK -> GDE_ERR_UNSUPPORTED)
+ *   value_type       : GDE_F32 or GDE_F64 -- the type of x and r on the device
+ *   alpha            : PPR damping, 0 < alpha < 1
+ *   beta             : Katz weight, beta > 0 and beta * lambda_bound < 1
+ *   tau, K           : heat-kernel temperature (tau >= 0) and truncation (0 <= K <= 256)
+ *   eps              : tolerance, finite and > 0 (stop iff max_u |r~_u|/d_u < eps)
+ *   lambda_bound     : an upper bound of the spectral radius of A (Katz).  It is
+ *                      required for Katz (validation of beta) and is the
+ *                      Chebyshev bound of Katz-LocalCH: mu = 1 - beta*lambda,
+ *                      L = 1 + beta*lambda.  gde_graph_lambda_max provides one.
+ *   c                : reserved, must be NULL (coefficients follow from kind)
+ *   max_iters        : iteration cap (>= 1); reaching it gives GDE_ERR_NOT_CONVERGED
+ *   flags            : GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE
+ */
+typedef struct gde_params {
+    int32_t kind;
+    int32_t method;
+    int32_t value_type;
+    int32_t K;
+    double alpha;
+    double beta;
+    double tau;
+    double eps;
+    double lambda_bound;
+    const double *c;
+    int32_t max_iters;
+    uint32_t flags;
+} gde_params;
+
+/* Sparse source vector s in host memory: idx strictly increasing node ids,
+ * val finite and > 0 (Theorem 3.4 assumes s >= 0). */
+typedef struct gde_seed {
+    int32_t nnz;
+    const int32_t *idx;
+    const double *val;
+} gde_seed;
+
+/*
+ * Caller-allocated result.
+ * In : capacity          -- entries available in idx / val
+ *      idx               -- int32[capacity], node ids of supp(x), written ascending
+ *      val               -- float[] or double[] (per value_type) x values
+ *                           (host pointers unless GDE_RESULT_DEVICE)
+ *      trace_capacity    -- entries of trace_size / trace_vol (host int64), may be 0
+ *      trace_nodes_capacity, trace_nodes -- host int32 buffer for the concatenated
+ *                           S_t lists (GDE_TRACE), may be 0 / NULL
+ * Out: nnz               -- |supp(x)| (on GDE_ERR_CAPACITY: the capacity needed)
+ *      residual_l1       -- ||r~||_1 in the reported scale (PPR: r/alpha; HK:
+ *                           sum_k psi_k ||leftover_k||_1, which equals ||f_K - x||_1)
+ *      residual_dinf     -- ||D^-1 r~||_inf (HK: max_k (K+1) psi_k ||D^-1 leftover_k||_inf);
+ *                           below eps when the process has converged
+ *      iters             -- T, the number of iterations with a nonempty S_t
+ *      ops               -- sum_t vol(S_t), the paper's operation count (Definition 3.1)
+ *      pushes            -- sum_t |S_t|
+ *      status            -- the gde_status of the call
+ *      trace_len         -- T (entries written: min(T, trace_capacity))
+ *      trace_nodes_len   -- sum_t |S_t| (entries written: min(that, capacity))
+ */
+typedef struct gde_result {
+    int64_t capacity;
+    int32_t *idx;
+    void *val;
+    int64_t trace_capacity;
+    int64_t *trace_size;
+    int64_t *trace_vol;
+    int64_t trace_nodes_capacity;
+    int32_t *trace_nodes;
+    int64_t nnz;
+    double residual_l1;
+    double residual_dinf;
+    int32_t iters;
+    int32_t status;
+    int64_t ops;
+    int64_t pushes;
+    int64_t trace_len;
+    int64_t trace_nodes_len;
+} gde_result;
+
+/* ABI version (GDE_ABI_VERSION). */
+int gde_abi_version(void);
+
+/* Thread-local text describing the last non-OK status returned on this thread. */
+const char *gde_last_error(void);
+
+/* Context bound to HIP device `hip_device`; owns the solver workspaces. */
+int gde_ctx_create(int hip_device, gde_ctx **out);
+int gde_ctx_destroy(gde_ctx *ctx);
+
+/*
+ * Upload (or borrow) a CSR graph.  Host pointers are validated on the host
+ * (monotone row_ptr starting at 0 and ending at nnz, col_idx in range, no
+ * self-loops); device pointers are validated by a device check before use.
+ * With GDE_DEVICE_PTRS | GDE_BORROW the arrays are used in place.
+ */
+int gde_graph_create(gde_ctx *ctx, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     uint32_t flags, hipStream_t stream, gde_graph **out);
+int gde_graph_destroy(gde_graph *g);
+
+/*
+ * Bounds of lambda_max(A) by power iteration on A + I from the all-ones vector
+ * (a global O(nnz) pass per iteration; graph preparation, not part of a solve):
+ * lower = Rayleigh quotient v'Av / v'v, upper = max_u (Av)_u / v_u
+ * (Collatz-Wielandt; a certified bound for nonnegative A and v > 0).  Stops
+ * when (upper - lower) <= rtol * upper or after max_iters iterations.
+ */
+int gde_graph_lambda_max(gde_ctx *ctx, gde_graph *g, int max_iters, double rtol, double *lower, double *upper,
+                         hipStream_t stream);
+
+/* Host-only validation of one query against a host CSR (no device work; usable without a GPU). */
+int gde_validate(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const gde_params *p,
+                 const gde_seed *s);
+
+/* One query (Definition 3.1 with the method of p).  See gde_result. */
+int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
+              hipStream_t stream);
+
+/*
+ * B independent queries on one graph solved together in one persistent
+ * launch: seeds are packed into lanes of node-major residual tiles, so a
+ * CSR row that several queries push in the same round is read once.
+ * Queries may differ in eps; they must share kind, method (LocalGD), value
+ * type and kind parameters.  schedule_json: NULL = the tuned schedule for
+ * this device/graph shape, else a JSON object {"lanes":L,"blocks":G,...}.
+ * res[i].status holds each query's own status; the call returns the first
+ * non-OK status, or GDE_OK.
+ */
+int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
+                    gde_result *res, const char *schedule_json, hipStream_t stream);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct gde_server_cfg {
+    int32_t lanes_per_group;   /* queries per node-major residual tile (8, 16, 32 or 64) */
+    int32_t max_groups;        /* tiles per kind resident at once (memory admission) */
+    int32_t iters_per_step;    /* local iterations per engine step */
+    int32_t queue_capacity;    /* pending queries beyond which submit returns GDE_ERR_BUSY */
+    int32_t value_type;        /* GDE_F32 */
+    int32_t result_capacity;   /* max |supp(x)| kept per completed query */
+    int64_t max_insert_edges;  /* capacity of the dynamic edge store */
+} gde_server_cfg;
+
+typedef struct gde_completion {
+    uint64_t ticket;
+    int32_t status;
+    int32_t iters;
+    int64_t nnz;         /* entries in idx / val (host memory owned by the server until the next poll) */
+    const int32_t *idx;
+    const float *val;
+    double residual_l1;
+    double residual_dinf;
+    double submit_time_s; /* server clock at submit */
+    double done_time_s;   /* server clock when the completion was harvested */
+} gde_completion;
+
+/* A continuous-batching server on a private dynamic copy of the graph. */
+int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cfg, gde_server **out);
+/* Enqueue a query (non-blocking); *ticket identifies its completion. */
+int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, uint64_t *ticket);
+/* Run engine steps while work is in flight and return up to cap completions (non-blocking when idle). */
+int gde_server_poll(gde_server *sv, gde_completion *out, int32_t cap, int32_t *n_out);
+/* Insert k undirected edges (u[i], v[i]); applied between engine steps, with the
+ * warm-start corrections of the dynamic GDE (Sec. 4) to every in-flight query. */
+int gde_server_insert_edges(gde_server *sv, int32_t k, const int32_t *u, const int32_t *v);
+int gde_server_destroy(gde_server *sv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDE_H */

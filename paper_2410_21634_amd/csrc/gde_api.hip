@@ -1,0 +1,680 @@
+// gde_api.hip -- host runtime behind the C ABI of include/gde.h: argument
+// validation, contexts, graphs, workspaces and the plain (one query) solver loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gde_batch.h"
+#include "gde_internal.h"
+#include "gde_kernels.h"
+
+namespace gde {
+
+static thread_local std::string g_err;
+static std::atomic<uint64_t> g_uid{1};
+static std::mutex g_ctx_mu;
+static std::vector<gde_ctx *> g_ctxs;  // live contexts, so a destroyed graph's workspaces are released
+
+int fail(int status, const std::string &msg) {
+    g_err = msg;
+    return status;
+}
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what;
+    return GDE_ERR_DEVICE;
+}
+
+// ------------------------------------------------------------------ validation
+static int validate_csr_host(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci) {
+    if (n <= 0) return fail(GDE_ERR_INVALID_ARG, "n must be > 0");
+    if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GDE_ERR_INVALID_ARG, "nnz must be in [0, 2^31-1)");
+    if (!rp || (nnz > 0 && !ci)) return fail(GDE_ERR_INVALID_ARG, "null CSR pointer");
+    if (rp[0] != 0) return fail(GDE_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+    if ((int64_t)rp[n] != nnz) return fail(GDE_ERR_INVALID_ARG, "row_ptr[n] must equal nnz");
+    for (int32_t u = 0; u < n; u++) {
+        if (rp[u + 1] < rp[u]) return fail(GDE_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++) {
+            if (ci[k] < 0 || ci[k] >= n) return fail(GDE_ERR_INVALID_ARG, "col_idx out of range");
+            if (ci[k] == u) return fail(GDE_ERR_INVALID_ARG, "self-loops are not allowed");
+        }
+    }
+    return GDE_OK;
+}
+
+static int validate_params(const gde_params *p) {
+    if (!p) return fail(GDE_ERR_INVALID_ARG, "null params");
+    if (p->kind < GDE_PPR || p->kind > GDE_HK) return fail(GDE_ERR_INVALID_ARG, "unknown kind");
+    if (p->method != GDE_LOCAL_GD && p->method != GDE_LOCAL_CH) return fail(GDE_ERR_INVALID_ARG, "unknown method");
+    if (p->value_type != GDE_F32 && p->value_type != GDE_F64) return fail(GDE_ERR_INVALID_ARG, "unknown value_type");
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(GDE_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (p->max_iters < 1) return fail(GDE_ERR_INVALID_ARG, "max_iters must be >= 1");
+    if (p->c != nullptr) return fail(GDE_ERR_INVALID_ARG, "params.c is reserved and must be NULL");
+    if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE))
+        return fail(GDE_ERR_INVALID_ARG, "unknown flag bits");
+    switch (p->kind) {
+    case GDE_PPR:
+        if (!(p->alpha > 0.0 && p->alpha < 1.0)) return fail(GDE_ERR_INVALID_ARG, "PPR needs 0 < alpha < 1");
+        break;
+    case GDE_KATZ:
+        if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(GDE_ERR_INVALID_ARG, "Katz needs beta > 0");
+        if (!(p->lambda_bound > 0.0) || !std::isfinite(p->lambda_bound))
+            return fail(GDE_ERR_INVALID_ARG, "Katz needs lambda_bound > 0 (an upper bound of lambda_max(A))");
+        if (!(p->beta * p->lambda_bound < 1.0))
+            return fail(GDE_ERR_INVALID_ARG, "Katz needs beta * lambda_bound < 1");
+        break;
+    case GDE_HK:
+        if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(GDE_ERR_INVALID_ARG, "HK needs tau >= 0");
+        if (p->K < 0 || p->K > 256) return fail(GDE_ERR_INVALID_ARG, "HK needs 0 <= K <= 256");
+        if (p->method == GDE_LOCAL_CH) return fail(GDE_ERR_UNSUPPORTED, "LocalCH is not defined for the heat kernel");
+        break;
+    }
+    return GDE_OK;
+}
+
+// seed check against host row pointers (degrees)
+static int validate_seed(const gde_seed *s, int32_t n, const int32_t *rp_host) {
+    if (!s || s->nnz <= 0 || !s->idx || !s->val) return fail(GDE_ERR_INVALID_ARG, "seed must have nnz > 0 entries");
+    if (s->nnz > n) return fail(GDE_ERR_INVALID_ARG, "seed has more entries than nodes");
+    for (int32_t i = 0; i < s->nnz; i++) {
+        int32_t u = s->idx[i];
+        if (u < 0 || u >= n) return fail(GDE_ERR_INVALID_ARG, "seed index out of range");
+        if (i > 0 && u <= s->idx[i - 1]) return fail(GDE_ERR_INVALID_ARG, "seed indices must be strictly increasing");
+        if (!(s->val[i] > 0.0) || !std::isfinite(s->val[i]))
+            return fail(GDE_ERR_INVALID_ARG, "seed values must be finite and > 0");
+    }
+    for (int32_t i = 0; i < s->nnz; i++) {
+        int32_t u = s->idx[i];
+        if (rp_host[u + 1] == rp_host[u]) return fail(GDE_ERR_ISOLATED_SEED, "seed node has degree 0");
+    }
+    return GDE_OK;
+}
+
+// ------------------------------------------------------------------ workspaces
+struct GraphHost {
+    std::vector<int32_t> row_ptr;  // host copy of the row pointers (seed validation)
+};
+static std::mutex g_graph_mu;
+static std::vector<std::pair<const gde_graph *, GraphHost *>> g_graph_host;
+
+static GraphHost *graph_host(const gde_graph *g) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &e : g_graph_host)
+        if (e.first == g) return e.second;
+    return nullptr;
+}
+
+static void ws_free(Workspace *w) {
+    void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->front[0], w->front[1], w->pushed, w->touched[0], w->touched[1],
+                   w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
+                   w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
+                   w->tr_vol, w->tr_nodes, w->lam_buf};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (w->hst) (void)hipHostFree(w->hst);
+    if (w->h_seed_idx) (void)hipHostFree(w->h_seed_idx);
+    if (w->h_seed_val) (void)hipHostFree(w->h_seed_val);
+    delete w;
+}
+
+#define WS_ALLOC(ptr, bytes)                                            \
+    do {                                                                \
+        hipError_t _e = hipMalloc((void **)&(ptr), (bytes));            \
+        if (_e != hipSuccess) { ws_free(w); return hip_fail(_e, "hipMalloc(workspace)"); } \
+        _e = hipMemsetAsync((ptr), 0, (bytes), s);                      \
+        if (_e != hipSuccess) { ws_free(w); return hip_fail(_e, "hipMemsetAsync"); } \
+    } while (0)
+
+static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out) {
+    Workspace *w = new Workspace();
+    w->g = g;
+    w->guid = g->uid;
+    w->vtype = vtype;
+    w->n = g->n;
+    w->vsize = vtype == GDE_F64 ? 8 : 4;
+    const int64_t n = g->n;
+    const size_t vs = w->vsize;
+    WS_ALLOC(w->rd, 2 * vs * n);
+    WS_ALLOC(w->x, vs * n);
+    int64_t nwords = (n + 31) / 32;
+    w->nblk = (nwords + kBlock - 1) / kBlock;
+    WS_ALLOC(w->bitmap, 4 * nwords);
+    WS_ALLOC(w->blk, 4 * (w->nblk + 1));
+    for (int i = 0; i < 2; i++) WS_ALLOC(w->front[i], 4 * n);
+    WS_ALLOC(w->pushed, 4 * n);
+    WS_ALLOC(w->wl_node, 4 * n);
+    WS_ALLOC(w->wl_beg, 4 * n);
+    WS_ALLOC(w->wl_off, 4 * n);
+    WS_ALLOC(w->wl_sv, vs * n);
+    WS_ALLOC(w->tile_start, 4 * (g->nnz / kTile + 2));
+    WS_ALLOC(w->st, sizeof(DevState));
+    hipError_t e = hipHostMalloc((void **)&w->hst, sizeof(DevState), hipHostMallocDefault);
+    if (e != hipSuccess) { ws_free(w); return hip_fail(e, "hipHostMalloc"); }
+    if (vtype == GDE_F64) launch_init_rd<double>(g->row_ptr, w->rd, g->n, s);
+    else launch_init_rd<float>(g->row_ptr, w->rd, g->n, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) { ws_free(w); return hip_fail(e, "init_rd"); }
+    (void)ctx;
+    *out = w;
+    return GDE_OK;
+}
+
+static int ws_ensure_hk(Workspace *w, const gde_graph *g, hipStream_t s) {
+    const int64_t n = w->n;
+    if (!w->rd2) {
+        GDE_HIP(hipMalloc(&w->rd2, 2 * w->vsize * n));
+        GDE_HIP(hipMemsetAsync(w->rd2, 0, 2 * w->vsize * n, s));
+        if (w->vtype == GDE_F64) launch_init_rd<double>(g->row_ptr, w->rd2, g->n, s);
+        else launch_init_rd<float>(g->row_ptr, w->rd2, g->n, s);
+        GDE_HIP(hipGetLastError());
+    }
+    for (int i = 0; i < 3; i++)
+        if (!w->touched[i]) {
+            GDE_HIP(hipMalloc((void **)&w->touched[i], 4 * n));
+        }
+    return GDE_OK;
+}
+
+static int ws_ensure_ch(Workspace *w, hipStream_t s) {
+    const int64_t n = w->n;
+    if (!w->delta) {
+        GDE_HIP(hipMalloc(&w->delta, w->vsize * n));
+        GDE_HIP(hipMemsetAsync(w->delta, 0, w->vsize * n, s));
+        GDE_HIP(hipMalloc((void **)&w->dstamp, 4 * n));
+        GDE_HIP(hipMemsetAsync(w->dstamp, 0, 4 * n, s));
+        GDE_HIP(hipMalloc((void **)&w->cstamp, 4 * n));
+        GDE_HIP(hipMemsetAsync(w->cstamp, 0, 4 * n, s));
+        w->stamp_base = 1;
+    }
+    return GDE_OK;
+}
+
+static int ws_ensure_seed(Workspace *w, int32_t nnz) {
+    if (nnz <= w->seed_cap) return GDE_OK;
+    int32_t cap = std::max<int32_t>(nnz, 64);
+    if (w->seed_idx) { (void)hipFree(w->seed_idx); (void)hipFree(w->seed_val); }
+    if (w->h_seed_idx) { (void)hipHostFree(w->h_seed_idx); (void)hipHostFree(w->h_seed_val); }
+    w->seed_idx = nullptr; w->seed_val = nullptr; w->h_seed_idx = nullptr; w->h_seed_val = nullptr; w->seed_cap = 0;
+    GDE_HIP(hipMalloc((void **)&w->seed_idx, 4 * (size_t)cap));
+    GDE_HIP(hipMalloc((void **)&w->seed_val, 8 * (size_t)cap));
+    GDE_HIP(hipHostMalloc((void **)&w->h_seed_idx, 4 * (size_t)cap, hipHostMallocDefault));
+    GDE_HIP(hipHostMalloc((void **)&w->h_seed_val, 8 * (size_t)cap, hipHostMallocDefault));
+    w->seed_cap = cap;
+    return GDE_OK;
+}
+
+static int ws_ensure_out(Workspace *w, int64_t cap) {
+    if (cap <= w->out_cap) return GDE_OK;
+    if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
+    w->out_idx = nullptr; w->out_val = nullptr; w->out_cap = 0;
+    GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)cap));
+    GDE_HIP(hipMalloc(&w->out_val, w->vsize * (size_t)cap));
+    w->out_cap = cap;
+    return GDE_OK;
+}
+
+static int ws_ensure_trace(Workspace *w, int64_t cap, int64_t ncap) {
+    if (cap > w->tr_cap) {
+        if (w->tr_size) { (void)hipFree(w->tr_size); (void)hipFree(w->tr_vol); }
+        w->tr_size = w->tr_vol = nullptr; w->tr_cap = 0;
+        GDE_HIP(hipMalloc((void **)&w->tr_size, 8 * (size_t)cap));
+        GDE_HIP(hipMalloc((void **)&w->tr_vol, 8 * (size_t)cap));
+        w->tr_cap = cap;
+    }
+    if (ncap > w->tr_nodes_cap) {
+        if (w->tr_nodes) (void)hipFree(w->tr_nodes);
+        w->tr_nodes = nullptr; w->tr_nodes_cap = 0;
+        GDE_HIP(hipMalloc((void **)&w->tr_nodes, 4 * (size_t)ncap));
+        w->tr_nodes_cap = ncap;
+    }
+    return GDE_OK;
+}
+
+int get_workspace(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out) {
+    for (Workspace *w : ctx->ws)
+        if (w->guid == g->uid && w->vtype == vtype) { w->g = g; *out = w; return GDE_OK; }
+    // keep a small number of workspaces per context
+    while (ctx->ws.size() >= 4) {
+        ws_free(ctx->ws.front());
+        ctx->ws.erase(ctx->ws.begin());
+    }
+    Workspace *w = nullptr;
+    int rc = ws_create(ctx, g, vtype, s, &w);
+    if (rc) return rc;
+    ctx->ws.push_back(w);
+    *out = w;
+    return GDE_OK;
+}
+
+void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
+    for (size_t i = 0; i < ctx->ws.size();) {
+        if (ctx->ws[i]->guid == g->uid) { ws_free(ctx->ws[i]); ctx->ws.erase(ctx->ws.begin() + i); }
+        else i++;
+    }
+}
+
+// ------------------------------------------------------------------ the plain solver
+static int push_grid(const gde_graph *g) {
+    int64_t tiles = g->nnz / kTile + 1;
+    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 2048);
+}
+static int snap_grid(const gde_graph *g) { return (int)std::min<int64_t>((g->n + kBlock - 1) / kBlock, 1024); }
+
+template <typename V>
+static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
+                       hipStream_t s) {
+    Workspace *w = nullptr;
+    int rc = get_workspace(ctx, g, p->value_type, s, &w);
+    if (rc) return rc;
+    const bool hk = p->kind == GDE_HK;
+    const bool ch = p->method == GDE_LOCAL_CH;
+    if (hk && (rc = ws_ensure_hk(w, g, s))) return rc;
+    if (ch && (rc = ws_ensure_ch(w, s))) return rc;
+    if ((rc = ws_ensure_seed(w, sd->nnz))) return rc;
+    const bool trace = (p->flags & GDE_TRACE) != 0;
+    long long tr_cap = 0, tr_ncap = 0;
+    if (trace) {
+        tr_cap = std::max<int64_t>(res->trace_capacity, 0);
+        tr_ncap = res->trace_nodes ? std::max<int64_t>(res->trace_nodes_capacity, 0) : 0;
+        if ((rc = ws_ensure_trace(w, std::max<long long>(tr_cap, 1), std::max<long long>(tr_ncap, 1)))) return rc;
+    }
+    long long *d_trs = trace && tr_cap > 0 ? (long long *)w->tr_size : nullptr;
+    long long *d_trv = trace && tr_cap > 0 ? (long long *)w->tr_vol : nullptr;
+    int32_t *d_trn = trace && tr_ncap > 0 ? w->tr_nodes : nullptr;
+
+    std::memcpy(w->h_seed_idx, sd->idx, 4 * (size_t)sd->nnz);
+    std::memcpy(w->h_seed_val, sd->val, 8 * (size_t)sd->nnz);
+    GDE_HIP(hipMemcpyAsync(w->seed_idx, w->h_seed_idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+    GDE_HIP(hipMemcpyAsync(w->seed_val, w->h_seed_val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+
+    const int pgrid = push_grid(g), sgrid = snap_grid(g);
+    SnapArgs a{};
+    a.grid = sgrid;
+    a.row_ptr = g->row_ptr;
+    a.x = w->x;
+    a.bitmap = w->bitmap;
+    a.st = w->st;
+    a.pushed = w->pushed;
+    a.wl_node = w->wl_node;
+    a.wl_beg = w->wl_beg;
+    a.wl_off = w->wl_off;
+    a.wl_sv = w->wl_sv;
+    a.tile_start = w->tile_start;
+    a.tr_nodes = d_trn;
+    a.tr_cap = tr_ncap;
+    a.cap = g->n;
+
+    bool converged = false;
+    int status = GDE_OK;
+    if (hk) {
+        // ------------------------------------------------ heat kernel, level by level
+        const int K = p->K;
+        const double tau = p->tau;
+        std::vector<double> psi(K + 1);
+        for (int k = 0; k <= K; k++) {
+            double acc = 0.0, term = 1.0;
+            for (int j = k; j <= K; j++) {
+                if (j > k) term *= tau / (double)j;
+                acc += term;
+            }
+            psi[k] = acc;
+        }
+        void *plane[2] = {w->rd, w->rd2};
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
+                            nullptr, 0, w->st, s);
+        for (int k = 0; k <= K; k++) {
+            a.rd = plane[k & 1];
+            a.F = w->front[k & 1];
+            a.cur = k & 1;
+            const bool last = k == K;
+            launch_snap_hk<V>(a, plane[(k + 1) & 1], (V)(tau / (double)(k + 1)), last ? 1 : 0, 1,
+                              k >= 1 ? w->touched[(k + 2) % 3] : nullptr, (k + 2) % 3, (k + 1) % 3,
+                              k >= 1 ? psi[k - 1] : 0.0, k >= 1 ? (double)(K + 1) * psi[k - 1] : 0.0, s);
+            const double eps_next = last ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]);
+            launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
+                           w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
+                           nullptr, 0, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, s);
+        }
+        // clean-up of the last level
+        a.rd = plane[(K + 1) & 1];
+        a.F = w->front[(K + 1) & 1];
+        a.cur = (K + 1) & 1;
+        launch_snap_hk<V>(a, plane[K & 1], (V)0, 1, 0, w->touched[K % 3], K % 3, -1, psi[K], (double)(K + 1) * psi[K],
+                          s);
+        GDE_HIP(hipGetLastError());
+        converged = true;
+    } else {
+        // ------------------------------------------------ PPR / Katz, LocalGD or LocalCH
+        const bool ppr = p->kind == GDE_PPR;
+        const double bscale = ppr ? p->alpha : 1.0;
+        const V wscale = (V)(ppr ? 1.0 - p->alpha : p->beta);
+        const int w_div_deg = ppr ? 1 : 0;
+        const V eps_eff = (V)(ppr ? p->alpha * p->eps : p->eps);
+        double sigma = 1.0, dlt = 0.0;
+        int32_t base = 0;
+        if (ch) {
+            double mu, L;
+            if (ppr) { mu = p->alpha; L = 2.0 - p->alpha; }
+            else { mu = 1.0 - p->beta * p->lambda_bound; L = 1.0 + p->beta * p->lambda_bound; }
+            sigma = (L + mu) / (L - mu);
+            dlt = 1.0 / sigma;
+            if (w->stamp_base > (1 << 30) - p->max_iters - 4) {
+                GDE_HIP(hipMemsetAsync(w->dstamp, 0, 4 * (size_t)w->n, s));
+                GDE_HIP(hipMemsetAsync(w->cstamp, 0, 4 * (size_t)w->n, s));
+                w->stamp_base = 1;
+            }
+            base = w->stamp_base;
+        }
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, bscale, w->front[0], nullptr,
+                            ch ? w->cstamp : nullptr, base, w->st, s);
+        a.rd = w->rd;
+        int t = 0, chunk = 8;
+        while (t < p->max_iters) {
+            int end = std::min(p->max_iters, t + chunk);
+            for (; t < end; t++) {
+                a.F = w->front[t & 1];
+                a.cur = t & 1;
+                if (ch) {
+                    V c_t = (V)1, m_t = (V)0;
+                    if (t > 0) {
+                        double dnext = 1.0 / (2.0 * sigma - dlt);
+                        c_t = (V)(2.0 * sigma * dnext);
+                        m_t = (V)(dlt * dnext);
+                        dlt = dnext;
+                    }
+                    launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
+                                      w->cstamp, base + t, w->front[(t + 1) & 1], s);
+                    launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
+                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
+                                   d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                } else {
+                    launch_snap_gd<V>(a, wscale, w_div_deg, s);
+                    launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
+                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, d_trs, d_trv,
+                                   tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                }
+            }
+            GDE_HIP(hipGetLastError());
+            GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            GDE_HIP(hipStreamSynchronize(s));
+            if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) { converged = true; break; }
+            chunk = std::min(chunk * 2, 32);
+        }
+        if (!converged) {
+            if (ch) {
+                launch_ch_probe<V>(w->rd, w->front[t & 1], w->st, t & 1, eps_eff, g->n, s);
+                GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+                GDE_HIP(hipStreamSynchronize(s));
+                converged = w->hst->probe == 0;
+            } else {
+                converged = w->hst->fcount[t & 1] == 0;
+            }
+        }
+        if (ch) w->stamp_base += t + 2;
+        launch_final_residual<V>(g->row_ptr, g->col_idx, w->rd, w->pushed, w->st, ppr ? 1.0 / p->alpha : 1.0,
+                                 std::min(2048, pgrid), g->n, s);
+        if (p->kind == GDE_KATZ && (p->flags & GDE_KATZ_SUBTRACT_SEED))
+            launch_subtract_seed<V>(w->x, w->seed_idx, w->seed_val, sd->nnz, s);
+        GDE_HIP(hipGetLastError());
+    }
+    if (!converged) status = GDE_ERR_NOT_CONVERGED;
+
+    // ------------------------------------------------ output (sorted by node id) and reset
+    GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipStreamSynchronize(s));
+    const int64_t nnz = w->hst->pushed_count;
+    const int64_t nwords = (w->n + 31) / 32;
+    const bool fits = nnz <= res->capacity && res->idx && res->val;
+    const bool dev_out = (p->flags & GDE_RESULT_DEVICE) != 0;
+    int32_t *o_idx = nullptr;
+    void *o_val = nullptr;
+    if (fits) {
+        if (dev_out) { o_idx = res->idx; o_val = res->val; }
+        else {
+            if ((rc = ws_ensure_out(w, std::max<int64_t>(nnz, 1)))) return rc;
+            o_idx = w->out_idx; o_val = w->out_val;
+        }
+    }
+    launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
+    launch_ex_scan(w->blk, w->nblk, w->st, s);
+    launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, s);
+    GDE_HIP(hipGetLastError());
+    if (fits && !dev_out && nnz > 0) {
+        GDE_HIP(hipMemcpyAsync(res->idx, w->out_idx, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipMemcpyAsync(res->val, w->out_val, w->vsize * (size_t)nnz, hipMemcpyDeviceToHost, s));
+    }
+    const DevState &h = *w->hst;
+    GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipStreamSynchronize(s));
+    if (h.overflow) return fail(GDE_ERR_DEVICE, "internal list overflow (a frontier invariant was broken)");
+    res->nnz = nnz;
+    res->iters = h.iters;
+    res->ops = h.ops;
+    res->pushes = h.pushes;
+    res->residual_l1 = h.res_l1;
+    unsigned long long bits = h.res_dinf;
+    double dinf;
+    std::memcpy(&dinf, &bits, 8);
+    res->residual_dinf = dinf;
+    res->trace_len = h.iters;
+    res->trace_nodes_len = h.pushes;
+    if (trace) {
+        int64_t m = std::min<int64_t>(h.iters, tr_cap);
+        if (m > 0 && res->trace_size) GDE_HIP(hipMemcpy(res->trace_size, w->tr_size, 8 * m, hipMemcpyDeviceToHost));
+        if (m > 0 && res->trace_vol) GDE_HIP(hipMemcpy(res->trace_vol, w->tr_vol, 8 * m, hipMemcpyDeviceToHost));
+        int64_t mn = std::min<int64_t>(h.pushes, tr_ncap);
+        if (mn > 0) GDE_HIP(hipMemcpy(res->trace_nodes, w->tr_nodes, 4 * mn, hipMemcpyDeviceToHost));
+    }
+    if (!fits) {
+        res->status = GDE_ERR_CAPACITY;
+        return fail(GDE_ERR_CAPACITY, "result capacity too small; result.nnz holds the size needed");
+    }
+    res->status = status;
+    if (status == GDE_ERR_NOT_CONVERGED) return fail(status, "max_iters reached before S_t became empty");
+    return GDE_OK;
+}
+
+}  // namespace gde
+
+using namespace gde;
+
+extern "C" {
+
+int gde_abi_version(void) { return GDE_ABI_VERSION; }
+
+const char *gde_last_error(void) { return g_err.c_str(); }
+
+int gde_ctx_create(int hip_device, gde_ctx **out) {
+    if (!out) return fail(GDE_ERR_INVALID_ARG, "null out");
+    int count = 0;
+    GDE_HIP(hipGetDeviceCount(&count));
+    if (hip_device < 0 || hip_device >= count) return fail(GDE_ERR_INVALID_ARG, "no such HIP device");
+    GDE_HIP(hipSetDevice(hip_device));
+    gde_ctx *c = new gde_ctx();
+    c->device = hip_device;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        g_ctxs.push_back(c);
+    }
+    *out = c;
+    return GDE_OK;
+}
+
+int gde_ctx_destroy(gde_ctx *ctx) {
+    if (!ctx) return fail(GDE_ERR_INVALID_ARG, "null ctx");
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        g_ctxs.erase(std::remove(g_ctxs.begin(), g_ctxs.end(), ctx), g_ctxs.end());
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (Workspace *w : ctx->ws) ws_free(w);
+    delete ctx;
+    return GDE_OK;
+}
+
+int gde_validate(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const gde_params *p,
+                 const gde_seed *s) {
+    int rc = validate_csr_host(n, nnz, row_ptr, col_idx);
+    if (rc) return rc;
+    if ((rc = validate_params(p))) return rc;
+    return validate_seed(s, n, row_ptr);
+}
+
+int gde_graph_create(gde_ctx *ctx, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     uint32_t flags, hipStream_t stream, gde_graph **out) {
+    if (!ctx || !out) return fail(GDE_ERR_INVALID_ARG, "null ctx or out");
+    const bool host = (flags & GDE_HOST_PTRS) != 0, dev = (flags & GDE_DEVICE_PTRS) != 0;
+    if (host == dev) return fail(GDE_ERR_INVALID_ARG, "exactly one of GDE_HOST_PTRS / GDE_DEVICE_PTRS");
+    if ((flags & GDE_COPY) && (flags & GDE_BORROW)) return fail(GDE_ERR_INVALID_ARG, "GDE_COPY and GDE_BORROW");
+    if (host && (flags & GDE_BORROW)) return fail(GDE_ERR_INVALID_ARG, "host pointers cannot be borrowed");
+    if (n <= 0) return fail(GDE_ERR_INVALID_ARG, "n must be > 0");
+    if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GDE_ERR_INVALID_ARG, "nnz must be in [0, 2^31-1)");
+    if (!row_ptr || (nnz > 0 && !col_idx)) return fail(GDE_ERR_INVALID_ARG, "null CSR pointer");
+    GDE_HIP(hipSetDevice(ctx->device));
+    GraphHost *gh = new GraphHost();
+    gh->row_ptr.resize((size_t)n + 1);
+    if (host) {
+        int rc = validate_csr_host(n, nnz, row_ptr, col_idx);
+        if (rc) { delete gh; return rc; }
+        std::memcpy(gh->row_ptr.data(), row_ptr, 4 * ((size_t)n + 1));
+    } else {
+        hipError_t e = hipMemcpy(gh->row_ptr.data(), row_ptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { delete gh; return hip_fail(e, "hipMemcpy(row_ptr)"); }
+        if (gh->row_ptr[0] != 0 || (int64_t)gh->row_ptr[n] != nnz) {
+            delete gh;
+            return fail(GDE_ERR_INVALID_ARG, "row_ptr must start at 0 and end at nnz");
+        }
+    }
+    gde_graph *g = new gde_graph();
+    g->device = ctx->device;
+    g->n = n;
+    g->nnz = nnz;
+    g->uid = g_uid++;
+    auto cleanup = [&](hipError_t e, const char *what) {
+        if (g->owned) { (void)hipFree(g->row_ptr); (void)hipFree(g->col_idx); }
+        delete g;
+        delete gh;
+        return hip_fail(e, what);
+    };
+    if (host || (flags & GDE_COPY) || !(flags & GDE_BORROW)) {
+        hipError_t e = hipMalloc((void **)&g->row_ptr, 4 * ((size_t)n + 1));
+        if (e != hipSuccess) return cleanup(e, "hipMalloc(row_ptr)");
+        g->owned = true;
+        e = hipMalloc((void **)&g->col_idx, 4 * (size_t)std::max<int64_t>(nnz, 1));
+        if (e != hipSuccess) return cleanup(e, "hipMalloc(col_idx)");
+        hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        e = hipMemcpyAsync(g->row_ptr, row_ptr, 4 * ((size_t)n + 1), kind, stream);
+        if (e == hipSuccess && nnz > 0) e = hipMemcpyAsync(g->col_idx, col_idx, 4 * (size_t)nnz, kind, stream);
+        if (e != hipSuccess) return cleanup(e, "hipMemcpyAsync(csr)");
+    } else {
+        g->row_ptr = const_cast<int32_t *>(row_ptr);
+        g->col_idx = const_cast<int32_t *>(col_idx);
+    }
+    // device-side structural check (covers device pointers; cheap for host ones)
+    int32_t *chk = nullptr;
+    hipError_t e = hipMalloc((void **)&chk, 8);
+    if (e != hipSuccess) return cleanup(e, "hipMalloc(check)");
+    e = hipMemsetAsync(chk, 0, 8, stream);
+    if (e == hipSuccess) {
+        launch_check_csr(g->row_ptr, g->col_idx, n, nnz, chk, chk + 1, stream);
+        e = hipGetLastError();
+    }
+    int32_t hc[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, chk, 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(chk);
+    if (e != hipSuccess) return cleanup(e, "graph check");
+    if (hc[0] != 0) {
+        if (g->owned) { (void)hipFree(g->row_ptr); (void)hipFree(g->col_idx); }
+        delete g;
+        delete gh;
+        return fail(GDE_ERR_INVALID_ARG, "malformed CSR (row_ptr order, col_idx range or self-loop)");
+    }
+    g->d_max = hc[1];
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_graph_host.emplace_back(g, gh);
+    }
+    *out = g;
+    return GDE_OK;
+}
+
+int gde_graph_destroy(gde_graph *g) {
+    if (!g) return fail(GDE_ERR_INVALID_ARG, "null graph");
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (size_t i = 0; i < g_graph_host.size(); i++)
+            if (g_graph_host[i].first == g) {
+                delete g_graph_host[i].second;
+                g_graph_host.erase(g_graph_host.begin() + i);
+                break;
+            }
+    }
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        for (gde_ctx *c : g_ctxs) drop_workspaces_of(g, c);
+    }
+    if (g->owned) { (void)hipFree(g->row_ptr); (void)hipFree(g->col_idx); }
+    delete g;
+    return GDE_OK;
+}
+
+int gde_graph_lambda_max(gde_ctx *ctx, gde_graph *g, int max_iters, double rtol, double *lower, double *upper,
+                         hipStream_t s) {
+    if (!ctx || !g || !lower || !upper) return fail(GDE_ERR_INVALID_ARG, "null argument");
+    if (max_iters < 1 || !(rtol >= 0.0)) return fail(GDE_ERR_INVALID_ARG, "max_iters >= 1 and rtol >= 0");
+    GDE_HIP(hipSetDevice(ctx->device));
+    const int64_t n = g->n;
+    double *buf = nullptr;
+    GDE_HIP(hipMalloc((void **)&buf, 8 * (2 * (size_t)n + 4)));
+    double *v = buf, *y = buf + n, *red = buf + 2 * n;
+    double hred[4];
+    double lo = 0.0, hi = 0.0;
+    launch_fill_f64(v, n, 1.0, s);
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < max_iters; it++) {
+        e = hipMemsetAsync(red, 0, 32, s);
+        if (e != hipSuccess) break;
+        launch_lam_step(g->row_ptr, g->col_idx, v, y, g->n, red, s);
+        launch_lam_scale(y, v, g->n, red, s);
+        e = hipMemcpyAsync(hred, red, 32, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        double cw;
+        std::memcpy(&cw, &hred[3], 8);
+        lo = hred[0] / hred[1];
+        hi = cw;
+        if (hi - lo <= rtol * hi) break;
+    }
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "lambda_max");
+    *lower = lo;
+    *upper = hi;
+    return GDE_OK;
+}
+
+int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
+              hipStream_t stream) {
+    if (!ctx || !g || !res) return fail(GDE_ERR_INVALID_ARG, "null ctx, graph or result");
+    int rc = validate_params(p);
+    if (rc) { res->status = rc; return rc; }
+    GraphHost *gh = graph_host(g);
+    if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");
+    if ((rc = validate_seed(s, g->n, gh->row_ptr.data()))) { res->status = rc; return rc; }
+    if (res->capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
+    if (g->device != ctx->device) return fail(GDE_ERR_INVALID_ARG, "graph and context on different devices");
+    GDE_HIP(hipSetDevice(ctx->device));
+    if (p->value_type == GDE_F64) return solve_plain<double>(ctx, g, p, s, res, stream);
+    return solve_plain<float>(ctx, g, p, s, res, stream);
+}
+
+}  // extern "C"

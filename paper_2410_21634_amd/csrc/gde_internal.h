@@ -1,0 +1,113 @@
+// gde_internal.h -- data layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gde.h"
+
+namespace gde {
+
+constexpr int kWave = 64;      // CDNA wavefront width
+constexpr int kBlock = 256;    // threads per workgroup of the frontier kernels
+constexpr int kTile = 1024;    // edges per push tile (4 per thread)
+
+// Residual and degree of one node side by side, so that the atomic update of
+// r_w and the read of d_w for the activation test hit the same cache line.
+template <typename V>
+struct alignas(2 * sizeof(V)) RD {
+    V r;
+    V d;
+};
+
+// Per-solve device counters.  Ping-pong slots are indexed by iteration parity.
+struct DevState {
+    unsigned long long packed[2];  // work-list reservation: (entries << 32) | edges
+    int32_t fcount[2];             // frontier / candidate list lengths
+    int32_t tcount[3];             // heat-kernel touched-list lengths (level mod 3)
+    int32_t pushed_count;          // |union of S_t|, length of the pushed list
+    int32_t iters;                 // iterations with a nonempty active set
+    int32_t pad0;
+    long long ops;                 // sum vol(S_t)
+    long long pushes;              // sum |S_t|
+    double res_l1;                 // reported residual l1 norm
+    unsigned long long res_dinf;   // bit pattern of the reported ||D^-1 r||_inf (>= 0)
+    int32_t out_count;             // entries emitted by the extraction
+    int32_t empty_seen;            // an iteration found S_t empty (converged)
+    int32_t probe;                 // LocalCH: active candidates at the iteration cap
+    int32_t overflow;              // a list append found its capacity exhausted (invariant broken)
+};
+
+// Solver workspace for one (graph, value type).  All node-indexed arrays are
+// dense over n; between solves every entry is back at its rest value (zero),
+// restored by the finalisation kernels, so a solve costs O(work), not O(n).
+struct Workspace {
+    const gde_graph *g = nullptr;
+    uint64_t guid = 0;             // uid of the graph it was built for
+    int vtype = 0;
+    int64_t n = 0;
+    size_t vsize = 0;
+    void *rd = nullptr;            // RD<V>[n]  (residual plane 0 + degree)
+    void *rd2 = nullptr;           // RD<V>[n]  heat-kernel plane 1 (lazily)
+    void *x = nullptr;             // V[n]
+    uint32_t *bitmap = nullptr;    // pushed set, ceil(n/32) words
+    int32_t *front[2] = {nullptr, nullptr};
+    int32_t *pushed = nullptr;
+    int32_t *touched[3] = {nullptr, nullptr, nullptr};
+    int32_t *wl_node = nullptr, *wl_beg = nullptr, *wl_off = nullptr;
+    void *wl_sv = nullptr;
+    int32_t *tile_start = nullptr;
+    void *delta = nullptr;         // LocalCH previous update
+    int32_t *dstamp = nullptr, *cstamp = nullptr;
+    int32_t stamp_base = 1;
+    int32_t *blk = nullptr;        // extraction block sums
+    int64_t nblk = 0;
+    DevState *st = nullptr;        // device
+    DevState *hst = nullptr;       // pinned host mirror
+    int32_t *seed_idx = nullptr;   // device staging for seeds
+    double *seed_val = nullptr;
+    int32_t seed_cap = 0;
+    int32_t *h_seed_idx = nullptr; // pinned staging
+    double *h_seed_val = nullptr;
+    int32_t *out_idx = nullptr;    // device staging of the sparse output
+    void *out_val = nullptr;
+    int64_t out_cap = 0;
+    int64_t *tr_size = nullptr, *tr_vol = nullptr;
+    int64_t tr_cap = 0;
+    int32_t *tr_nodes = nullptr;
+    int64_t tr_nodes_cap = 0;
+    double *lam_buf = nullptr;     // power-iteration vectors and reductions
+};
+
+}  // namespace gde
+
+struct gde_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *row_ptr = nullptr;
+    int32_t *col_idx = nullptr;
+    bool owned = false;
+    uint64_t uid = 0;
+    int32_t d_max = 0;
+};
+
+struct gde_ctx {
+    int device = 0;
+    std::vector<gde::Workspace *> ws;
+};
+
+namespace gde {
+// error reporting (thread-local message)
+int fail(int status, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+}  // namespace gde
+
+#define GDE_HIP(call)                                               \
+    do {                                                            \
+        hipError_t _e = (call);                                     \
+        if (_e != hipSuccess) return ::gde::hip_fail(_e, #call);    \
+    } while (0)

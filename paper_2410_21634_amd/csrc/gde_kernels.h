@@ -1,0 +1,61 @@
+// gde_kernels.h -- host-side launch interface of the gfx950 kernels.
+#pragma once
+
+#include "gde_internal.h"
+
+namespace gde {
+
+// Arguments common to the snapshot kernels (one iteration, one work list).
+struct SnapArgs {
+    int grid;
+    const int32_t *row_ptr;
+    void *rd;             // residual plane read and zeroed by the snapshot
+    void *x;
+    uint32_t *bitmap;
+    const int32_t *F;     // S_t (GD, HK) or the candidates C_t (CH)
+    DevState *st;
+    int cur;
+    int32_t *pushed;
+    int32_t *wl_node, *wl_beg, *wl_off;
+    void *wl_sv;
+    int32_t *tile_start;
+    int32_t *tr_nodes;
+    long long tr_cap;
+    int32_t cap;          // capacity of every node list (n)
+};
+
+template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
+template <typename V>
+void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
+                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, DevState *st, hipStream_t s);
+template <typename V> void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s);
+template <typename V>
+void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
+                    int prev_tslot, int next_tslot, double psi_prev, double wdinf_prev, hipStream_t s);
+template <typename V>
+void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t, V m_t, int force, void *delta,
+                    int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur, int32_t *next_list, hipStream_t s);
+template <typename V>
+void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
+                 const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
+                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, long long *tr_size,
+                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s);
+template <typename V>
+void launch_final_residual(const int32_t *row_ptr, const int32_t *col_idx, void *rd, const int32_t *pushed,
+                           DevState *st, double rscale, int grid, int32_t cap, hipStream_t s);
+template <typename V> void launch_subtract_seed(void *x, const int32_t *sidx, const double *sval, int nnz, hipStream_t s);
+template <typename V>
+void launch_ch_probe(const void *rd, const int32_t *C, DevState *st, int cur, V eps_eff, int32_t cap, hipStream_t s);
+void launch_ex_count(const uint32_t *bm, int64_t nwords, int32_t *blk, int64_t nblk, hipStream_t s);
+void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s);
+template <typename V>
+void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
+                    void *out_val, int64_t cap, hipStream_t s);
+void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
+                      int32_t *dmax, hipStream_t s);
+void launch_lam_step(const int32_t *row_ptr, const int32_t *col_idx, const double *v, double *y, int32_t n,
+                     double *red, hipStream_t s);
+void launch_lam_scale(const double *y, double *v, int32_t n, const double *red, hipStream_t s);
+void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s);
+
+}  // namespace gde

@@ -1,0 +1,709 @@
+// gde_kernels.hip -- gfx950 kernels of the local diffusion process (Definition 3.1).
+//
+// One iteration t of LocalGD (Eq. (9)) is two launches:
+//   snap : for every u in S_t take v_u = r_u (the synchronous snapshot), set
+//          r_u = 0, x_u += v_u, and reserve a contiguous slice of the work list
+//          and of the edge space with one 64-bit atomic per wavefront;
+//   push : edge-balanced scatter r_w += W_u v_u over the CSR rows of S_t, tiles
+//          of kTile edges staged through LDS; every returned old value is
+//          tested against theta_w, and the unique add that lifts r_w over
+//          theta_w appends w to S_{t+1} (wave-ballot compaction).
+// Because snap has already zeroed the residual of every u in S_t, the push only
+// adds nonnegative mass, r_w is monotone during the launch and the crossing
+// test fires exactly once for every node whose residual ends at or above its
+// threshold: S_{t+1} is produced without scanning candidates.
+//
+// LocalCH (Sec. 3.3) has signed updates, so its push marks touched nodes as
+// candidates (stamp de-duplication) and its snap applies the threshold.
+// The heat kernel runs the same pair per Taylor level with the residual
+// planes of level k and k+1 (the Kronecker block structure of the AHK push).
+#include <hip/hip_runtime.h>
+
+#include "gde_internal.h"
+#include "gde_kernels.h"
+
+namespace gde {
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+__device__ __forceinline__ unsigned long long lanemask_lt() { return (1ull << lane()) - 1ull; }
+
+// Wave-aggregated append: one atomic per wavefront, slots in lane order.
+__device__ __forceinline__ int wave_append(bool pred, int32_t *counter) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return -1;
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane() == leader) base = atomicAdd(counter, (int)__popcll(mask));
+    base = __shfl(base, leader);
+    return pred ? base + (int)__popcll(mask & lanemask_lt()) : -1;
+}
+
+// Guarded list append: entries beyond cap are dropped and flagged.
+__device__ __forceinline__ void list_append(bool pred, int32_t v, int32_t *counter, int32_t *list, int32_t cap,
+                                            DevState *st) {
+    int s = wave_append(pred, counter);
+    if (pred) {
+        if (s < cap) list[s] = v;
+        else st->overflow = 1;
+    }
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(v, off);
+        if (lane() >= off) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// block-wide sum and max of two doubles, folded into the device state
+__device__ void block_fold_norms(double l1, double mx, DevState *st) {
+    __shared__ double s_l1[kBlock / kWave], s_mx[kBlock / kWave];
+    l1 = wave_sum(l1);
+    mx = wave_max(mx);
+    int w = threadIdx.x / kWave;
+    if (lane() == 0) { s_l1[w] = l1; s_mx[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, m = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); i++) { a += s_l1[i]; m = fmax(m, s_mx[i]); }
+        if (a != 0.0) atomicAdd(&st->res_l1, a);
+        if (m > 0.0) atomicMax(&st->res_dinf, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ V atomic_take(V *p);
+template <>
+__device__ __forceinline__ float atomic_take<float>(float *p) { return atomicExch(p, 0.0f); }
+template <>
+__device__ __forceinline__ double atomic_take<double>(double *p) {
+    return __longlong_as_double((long long)atomicExch((unsigned long long *)p, 0ull));
+}
+
+// ------------------------------------------------------------------ setup
+template <typename V>
+__global__ void k_init_rd(const int32_t *__restrict__ row_ptr, RD<V> *rd, int32_t n) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        RD<V> e;
+        e.r = (V)0;
+        e.d = (V)(row_ptr[u + 1] - row_ptr[u]);
+        rd[u] = e;
+    }
+}
+
+// r <- b on supp(s); S_0 = supp(s) (forced, Definition 3.1); counters reset.
+template <typename V>
+__global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const double *__restrict__ sval, int32_t nnz,
+                            double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp, int32_t stamp0,
+                            DevState *st) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) {
+        int32_t u = sidx[i];
+        rd[u].r = (V)(bscale * sval[i]);
+        f0[i] = u;
+        if (touched0) touched0[i] = u;
+        if (cstamp) cstamp[u] = stamp0;
+    }
+    if (i == 0) {
+        st->packed[0] = st->packed[1] = 0ull;
+        st->fcount[0] = nnz;
+        st->fcount[1] = 0;
+        st->tcount[0] = touched0 ? nnz : 0;
+        st->tcount[1] = st->tcount[2] = 0;
+        st->pushed_count = 0;
+        st->iters = 0;
+        st->ops = st->pushes = 0;
+        st->res_l1 = 0.0;
+        st->res_dinf = 0ull;
+        st->out_count = 0;
+        st->empty_seen = 0;
+        st->probe = 0;
+        st->overflow = 0;
+    }
+}
+
+// ------------------------------------------------------------------ snapshot (A2 + A5)
+// List discipline per iteration t (cur = t & 1, nxt = cur ^ 1): snap(t) reads
+// list[cur] and may append to list[nxt]; push(t) appends to list[nxt] and then
+// empties list[cur].  list[nxt] was emptied by push(t-1) (or by seed_init).
+// Shared tail of every snap kernel: record u in the pushed set, reserve work-list
+// slots and edge offsets for the active lanes of the wave, write the entries.
+template <typename V>
+__device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, int32_t deg, V sv, uint32_t *bitmap,
+                                             int32_t *pushed, DevState *st, int cur, int32_t *wl_node,
+                                             int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start,
+                                             int32_t *tr_nodes, long long push_base, long long tr_cap, int32_t cap) {
+    bool first = false;
+    if (act) {
+        uint32_t bit = 1u << (u & 31);
+        uint32_t old = atomicOr(&bitmap[u >> 5], bit);
+        first = (old & bit) == 0u;
+    }
+    list_append(first, u, &st->pushed_count, pushed, cap, st);
+    int d = act ? deg : 0;
+    int incl = wave_incl_scan(d);
+    unsigned long long amask = __ballot(act);
+    int cnt = (int)__popcll(amask);
+    int tot = __shfl(incl, kWave - 1);
+    unsigned long long res = 0ull;
+    if (cnt > 0 && lane() == 0)
+        res = atomicAdd(&st->packed[cur], ((unsigned long long)cnt << 32) | (unsigned long long)(unsigned)tot);
+    res = __shfl(res, 0);
+    if (act) {
+        int slot = (int)(res >> 32) + (int)__popcll(amask & lanemask_lt());
+        if (slot >= cap) { st->overflow = 1; return; }
+        int off = (int)(res & 0xffffffffull) + incl - d;
+        wl_node[slot] = u;
+        wl_beg[slot] = beg;
+        wl_off[slot] = off;
+        wl_sv[slot] = sv;
+        for (int k = (off + kTile - 1) / kTile; (long long)k * kTile < (long long)off + d; k++) tile_start[k] = slot;
+        if (tr_nodes && push_base + slot < tr_cap) tr_nodes[push_base + slot] = u;
+    }
+}
+
+// LocalGD: v = r_u, r_u = 0, x_u += v, scatter value W_u v with
+// W_u = wscale / d_u (PPR, wscale = 1 - alpha) or wscale (Katz, beta).
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+                                                     uint32_t *bitmap, const int32_t *__restrict__ F, DevState *st,
+                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
+                                                     int w_div_deg, int32_t *tr_nodes, long long tr_cap, int32_t cap) {
+    const int nxt = cur ^ 1;
+    const int n_f = min(st->fcount[cur], cap);
+    const long long push_base = st->pushes;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < n_f; base += stride) {
+        int i = base + threadIdx.x;
+        bool act = i < n_f;
+        int32_t u = 0, beg = 0, deg = 0;
+        V sv = (V)0;
+        if (act) {
+            u = F[i];
+            V v = rd[u].r;
+            rd[u].r = (V)0;
+            x[u] += v;
+            beg = row_ptr[u];
+            deg = row_ptr[u + 1] - beg;
+            V w = w_div_deg ? wscale / (V)deg : wscale;
+            sv = w * v;
+        }
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+                        tr_nodes, push_base, tr_cap, cap);
+    }
+}
+
+// Heat kernel, level k: snapshot of S_k from plane k (scatter value
+// (tau/(k+1)) v / d_u, no edges at the last level), plus the clean-up of plane
+// k-1: its leftover residuals are folded into the reported norms
+// (psi_{k-1}-weighted) and the plane is zeroed for reuse by level k+1.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_snap_hk(const int32_t *__restrict__ row_ptr, RD<V> *plane, RD<V> *prev,
+                                                     V *x, uint32_t *bitmap, const int32_t *__restrict__ F,
+                                                     DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                                                     int32_t *wl_beg, int32_t *wl_off, V *wl_sv,
+                                                     int32_t *tile_start, V wmul, int last_level, int frontier_on,
+                                                     const int32_t *__restrict__ prev_touched, int prev_tslot,
+                                                     int next_tslot, double psi_prev, double wdinf_prev,
+                                                     int32_t *tr_nodes, long long tr_cap, int32_t cap) {
+    const int nxt = cur ^ 1;
+    const int n_f = frontier_on ? min(st->fcount[cur], cap) : 0;
+    const int n_c = prev_touched ? min(st->tcount[prev_tslot], cap) : 0;
+    const long long push_base = st->pushes;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->packed[nxt] = 0ull;
+        if (next_tslot >= 0) st->tcount[next_tslot] = 0;
+    }
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < n_f; base += stride) {
+        int i = base + threadIdx.x;
+        bool act = i < n_f;
+        int32_t u = 0, beg = 0, deg = 0;
+        V sv = (V)0;
+        if (act) {
+            u = F[i];
+            V v = plane[u].r;
+            plane[u].r = (V)0;
+            x[u] += v;
+            beg = row_ptr[u];
+            deg = row_ptr[u + 1] - beg;
+            sv = last_level ? (V)0 : wmul * v / plane[u].d;
+        }
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+                        tr_nodes, push_base, tr_cap, cap);
+    }
+    double l1 = 0.0, mx = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_c; j += stride) {
+        int32_t w = prev_touched[j];
+        V val = prev[w].r;
+        prev[w].r = (V)0;
+        double a = fabs((double)val);
+        l1 += psi_prev * a;
+        if (a > 0.0) mx = fmax(mx, wdinf_prev * a / (double)prev[w].d);
+    }
+    if (prev_touched) block_fold_norms(l1, mx, st);
+}
+
+// LocalCH: over the candidates C_t, S_t = {u : r_u != 0, |r_u| >= theta_u}
+// (all of C_0 = supp(s) at t = 0); h_u = c_t r_u + m_t Delta_u with Delta_u
+// the previous update if u was in S_{t-1}; x_u += h_u, r_u -= h_u, Delta_u = h_u.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+                                                     uint32_t *bitmap, const int32_t *__restrict__ C, DevState *st,
+                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
+                                                     int w_div_deg, V eps_eff, V c_t, V m_t, int force, V *delta,
+                                                     int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur,
+                                                     int32_t *next_list, int32_t *tr_nodes, long long tr_cap,
+                                                     int32_t cap) {
+    const int nxt = cur ^ 1;
+    const int n_c = min(st->fcount[cur], cap);
+    const long long push_base = st->pushes;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < n_c; base += stride) {
+        int i = base + threadIdx.x;
+        bool valid = i < n_c;
+        bool act = false;
+        int32_t u = 0, beg = 0, deg = 0;
+        V sv = (V)0;
+        if (valid) {
+            u = C[i];
+            RD<V> e = rd[u];
+            act = force || (e.r != (V)0 && fabs(e.r) >= eps_eff * e.d);
+            if (act) {
+                V h = force ? e.r : c_t * e.r + m_t * (dstamp[u] == stamp_cur - 1 ? delta[u] : (V)0);
+                x[u] += h;
+                rd[u].r = e.r - h;
+                delta[u] = h;
+                dstamp[u] = stamp_cur;
+                beg = row_ptr[u];
+                deg = row_ptr[u + 1] - beg;
+                V w = w_div_deg ? wscale / (V)deg : wscale;
+                sv = w * h;
+            }
+        }
+        // u's own residual changed: it is a candidate of the next iteration
+        bool mark = act && atomicExch(&cstamp[u], stamp_cur + 1) != stamp_cur + 1;
+        list_append(mark, u, &st->fcount[nxt], next_list, cap, st);
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+                        tr_nodes, push_base, tr_cap, cap);
+    }
+}
+
+// ------------------------------------------------------------------ push (A3 + A4)
+// MODE 0: LocalGD / monotone residual -- returned old value, crossing test.
+// MODE 1: heat kernel -- crossing test on plane k+1 and first-touch list.
+// MODE 2: LocalCH -- signed add, candidate marking by stamp.
+template <typename V, int MODE>
+__global__ void __launch_bounds__(kBlock) k_push(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st,
+                                                  int cur, const int32_t *__restrict__ wl_beg,
+                                                  const int32_t *__restrict__ wl_off, const V *__restrict__ wl_sv,
+                                                  const int32_t *__restrict__ tile_start, V eps_eff,
+                                                  int32_t *next_list, int32_t *touched, int tslot, int32_t *cstamp,
+                                                  int32_t stamp_next, long long *tr_size, long long *tr_vol,
+                                                  long long tr_cap, int scatter, int32_t cap, int32_t nnz) {
+    __shared__ int32_t s_off[kTile + 1];
+    __shared__ int32_t s_beg[kTile + 1];
+    __shared__ V s_sv[kTile + 1];
+    const int nxt = cur ^ 1;
+    const unsigned long long pk = st->packed[cur];
+    const int count = min((int)(pk >> 32), cap);
+    const int total = (int)(pk & 0xffffffffull);
+    // S_t (or C_t) has been consumed by the snapshot: its list becomes the
+    // next-but-one append target, which the snapshot of t+1 may append to.
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->fcount[cur] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && count == 0) st->empty_seen = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) {
+        int it = st->iters;
+        if (tr_size && it < tr_cap) {
+            tr_size[it] = count;
+            tr_vol[it] = total;
+        }
+        st->ops += total;
+        st->pushes += count;
+        st->iters = it + 1;
+    }
+    const int ntiles = scatter ? (total + kTile - 1) / kTile : 0;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int e0 = tile * kTile;
+        const int e1 = min(e0 + kTile, total);
+        const int i0 = tile_start[tile];
+        const int i1 = (tile + 1 < ntiles) ? tile_start[tile + 1] : count - 1;
+        const int m = min(i1 - i0 + 1, kTile + 1);
+        if (m <= 0 || i0 < 0 || i1 >= cap) {  // a broken work list: never index with it
+            if (threadIdx.x == 0) st->overflow = 1;
+            continue;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            s_off[j] = wl_off[i0 + j];
+            s_beg[j] = wl_beg[i0 + j];
+            s_sv[j] = wl_sv[i0 + j];
+        }
+        __syncthreads();
+        for (int eb = e0; eb < e1; eb += blockDim.x) {
+            const int e = eb + threadIdx.x;
+            const bool valid = e < e1;
+            bool hit = false, first = false;
+            int32_t w = 0;
+            if (valid) {
+                int lo = 0, hi = m - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const int k = s_beg[lo] + (e - s_off[lo]);
+                const bool in_range = k >= 0 && k < nnz;
+                if (!in_range) st->overflow = 1;
+                w = in_range ? col_idx[k] : 0;
+                const V dv = in_range ? s_sv[lo] : (V)0;
+                if (MODE == 2) {
+                    if (in_range) unsafeAtomicAdd(&dst[w].r, dv);
+                    if (in_range && cstamp[w] != stamp_next) hit = atomicExch(&cstamp[w], stamp_next) != stamp_next;
+                } else {
+                    if (dv != (V)0) {
+                        const V old = unsafeAtomicAdd(&dst[w].r, dv);
+                        const V nw = old + dv;
+                        const V th = eps_eff * dst[w].d;
+                        hit = (old < th) && (nw >= th);
+                        if (MODE == 1) first = (old == (V)0);
+                    }
+                }
+            }
+            list_append(hit, w, &st->fcount[nxt], next_list, cap, st);
+            if (MODE == 1) list_append(first, w, &st->tcount[tslot], touched, cap, st);
+        }
+    }
+}
+
+// LocalCH at the iteration cap: is S_t empty?  (counts without updating)
+template <typename V>
+__global__ void k_ch_probe(const RD<V> *rd, const int32_t *__restrict__ C, DevState *st, int cur, V eps_eff,
+                           int32_t cap) {
+    const int n_c = min(st->fcount[cur], cap);
+    int c = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_c; i += gridDim.x * blockDim.x) {
+        RD<V> e = rd[C[i]];
+        c += (e.r != (V)0 && fabs(e.r) >= eps_eff * e.d) ? 1 : 0;
+    }
+    if (c) atomicAdd(&st->probe, c);
+}
+
+// ------------------------------------------------------------------ finalisation (A6 + A7)
+// Residual norms of LocalGD / LocalCH: r is nonzero only on the closed
+// neighbourhood of the pushed set; each entry is read and zeroed exactly once
+// (atomic exchange), accumulating ||r~||_1 and ||D^-1 r~||_inf in FP64.
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_final_residual(const int32_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col_idx, RD<V> *rd,
+                                                            const int32_t *__restrict__ pushed, DevState *st,
+                                                            double rscale, int32_t cap) {
+    const int np = min(st->pushed_count, cap);
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    double l1 = 0.0, mx = 0.0;
+    for (int i = wave; i < np; i += nwaves) {
+        const int32_t u = pushed[i];
+        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+        for (int e = beg - 1 + lane(); e < end; e += kWave) {
+            const int32_t w = e < beg ? u : col_idx[e];
+            const V val = atomic_take<V>(&rd[w].r);
+            const double a = fabs((double)val) * rscale;
+            l1 += a;
+            if (a > 0.0) mx = fmax(mx, a / (double)rd[w].d);
+        }
+    }
+    block_fold_norms(l1, mx, st);
+}
+
+// Katz centrality option: x <- x - s on supp(s).
+template <typename V>
+__global__ void k_subtract_seed(V *x, const int32_t *__restrict__ sidx, const double *__restrict__ sval, int nnz) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) x[sidx[i]] -= (V)sval[i];
+}
+
+// Sparse output in ascending node order from the pushed-set bitmap:
+// count -> scan -> emit; emit also restores x and the bitmap to zero.
+__global__ void __launch_bounds__(kBlock) k_ex_count(const uint32_t *__restrict__ bm, int64_t nwords, int32_t *blk) {
+    __shared__ int s[kBlock / kWave];
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int c = i < nwords ? __popc(bm[i]) : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane() == 0) s[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int k = 0; k < (int)(blockDim.x / kWave); k++) a += s[k];
+        blk[blockIdx.x] = a;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_ex_scan(int32_t *blk, int64_t nblk, DevState *st) {
+    __shared__ int s[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        int v = i < nblk ? blk[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int y = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nblk) blk[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st->out_count = carry;
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kBlock) k_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *__restrict__ blk,
+                                                     V *x, int32_t *out_idx, V *out_val, int64_t cap) {
+    __shared__ int s[kBlock];
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t word = i < nwords ? bm[i] : 0u;
+    int c = __popc(word);
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int y = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (word) {
+        int64_t pos = blk[blockIdx.x] + s[threadIdx.x] - c;
+        while (word) {
+            int b = __ffs(word) - 1;
+            word &= word - 1u;
+            int32_t u = (int32_t)(i * 32 + b);
+            if (out_idx && pos < cap) {
+                out_idx[pos] = u;
+                out_val[pos] = x[u];
+            }
+            x[u] = (V)0;
+            pos++;
+        }
+        bm[i] = 0u;
+    }
+}
+
+// ------------------------------------------------------------------ graph preparation (A0)
+__global__ void k_check_csr(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, int32_t n,
+                            int64_t nnz, int32_t *bad, int32_t *dmax) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        int32_t b = row_ptr[u], e = row_ptr[u + 1];
+        if (u == 0 && b != 0) atomicAdd(bad, 1);
+        if (u == n - 1 && (int64_t)e != nnz) atomicAdd(bad, 1);
+        if (e < b) { atomicAdd(bad, 1); continue; }
+        atomicMax(dmax, e - b);
+        for (int32_t k = b; k < e; k++) {
+            int32_t w = col_idx[k];
+            if (w < 0 || w >= n || w == (int32_t)u) { atomicAdd(bad, 1); break; }
+        }
+    }
+}
+
+// One power-iteration step on A + I: y = A v + v, with the Rayleigh terms
+// v'Av, v'v, ||y||^2 and the Collatz-Wielandt ratio max (Av)_u / v_u.
+__global__ void __launch_bounds__(kBlock) k_lam_step(const int32_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col_idx,
+                                                      const double *__restrict__ v, double *y, int32_t n,
+                                                      double *red) {
+    __shared__ double s[3][kBlock / kWave];
+    __shared__ double sm[kBlock / kWave];
+    double a = 0.0, b = 0.0, c = 0.0, m = 0.0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int32_t k = row_ptr[u]; k < row_ptr[u + 1]; k++) acc += v[col_idx[k]];
+        double vu = v[u];
+        double yu = acc + vu;
+        y[u] = yu;
+        a += vu * acc;
+        b += vu * vu;
+        c += yu * yu;
+        m = fmax(m, acc / vu);
+    }
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); m = wave_max(m);
+    int w = threadIdx.x / kWave;
+    if (lane() == 0) { s[0][w] = a; s[1][w] = b; s[2][w] = c; sm[w] = m; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0, t1 = 0, t2 = 0, tm = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); i++) { t0 += s[0][i]; t1 += s[1][i]; t2 += s[2][i]; tm = fmax(tm, sm[i]); }
+        atomicAdd(&red[0], t0);
+        atomicAdd(&red[1], t1);
+        atomicAdd(&red[2], t2);
+        atomicMax((unsigned long long *)&red[3], (unsigned long long)__double_as_longlong(tm));
+    }
+}
+
+__global__ void k_lam_scale(const double *__restrict__ y, double *v, int32_t n, const double *red) {
+    double inv = rsqrt(red[2]);
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        v[u] = y[u] * inv;
+}
+
+__global__ void k_fill_f64(double *v, int64_t n, double val) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        v[u] = val;
+}
+
+// ------------------------------------------------------------------ launchers
+static inline int grid_for(int64_t items, int block, int cap) {
+    int64_t g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+template <typename V>
+void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_rd<V>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, (RD<V> *)rd, n);
+}
+
+template <typename V>
+void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
+                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_seed_init<V>, dim3(grid_for(nnz, 256, 65535)), dim3(256), 0, s, (RD<V> *)rd, sidx, sval, nnz,
+                       bscale, f0, touched0, cstamp, stamp0, st);
+}
+
+template <typename V>
+void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s) {
+    hipLaunchKernelGGL(k_snap_gd<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
+                       a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
+                       w_div_deg, a.tr_nodes, a.tr_cap, a.cap);
+}
+
+template <typename V>
+void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
+                    int prev_tslot, int next_tslot, double psi_prev, double wdinf_prev, hipStream_t s) {
+    hipLaunchKernelGGL(k_snap_hk<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (RD<V> *)prev,
+                       (V *)a.x, a.bitmap, a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv,
+                       a.tile_start, wmul, last_level, frontier_on, prev_touched, prev_tslot, next_tslot, psi_prev,
+                       wdinf_prev, a.tr_nodes, a.tr_cap, a.cap);
+}
+
+template <typename V>
+void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t, V m_t, int force, void *delta,
+                    int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur, int32_t *next_list, hipStream_t s) {
+    hipLaunchKernelGGL(k_snap_ch<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
+                       a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
+                       w_div_deg, eps_eff, c_t, m_t, force, (V *)delta, dstamp, cstamp, stamp_cur, next_list,
+                       a.tr_nodes, a.tr_cap, a.cap);
+}
+
+template <typename V>
+void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
+                 const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
+                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, long long *tr_size,
+                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s) {
+    if (mode == 0)
+        hipLaunchKernelGGL((k_push<V, 0>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
+                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
+                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_push<V, 1>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
+                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
+                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
+    else
+        hipLaunchKernelGGL((k_push<V, 2>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
+                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
+                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
+}
+
+template <typename V>
+void launch_final_residual(const int32_t *row_ptr, const int32_t *col_idx, void *rd, const int32_t *pushed,
+                           DevState *st, double rscale, int grid, int32_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_residual<V>, dim3(grid), dim3(kBlock), 0, s, row_ptr, col_idx, (RD<V> *)rd, pushed,
+                       st, rscale, cap);
+}
+
+template <typename V>
+void launch_subtract_seed(void *x, const int32_t *sidx, const double *sval, int nnz, hipStream_t s) {
+    hipLaunchKernelGGL(k_subtract_seed<V>, dim3(grid_for(nnz, 256, 65535)), dim3(256), 0, s, (V *)x, sidx, sval, nnz);
+}
+
+template <typename V>
+void launch_ch_probe(const void *rd, const int32_t *C, DevState *st, int cur, V eps_eff, int32_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_ch_probe<V>, dim3(256), dim3(256), 0, s, (const RD<V> *)rd, C, st, cur, eps_eff, cap);
+}
+
+void launch_ex_count(const uint32_t *bm, int64_t nwords, int32_t *blk, int64_t nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_ex_count, dim3((unsigned)nblk), dim3(kBlock), 0, s, bm, nwords, blk);
+}
+void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_ex_scan, dim3(1), dim3(1024), 0, s, blk, nblk, st);
+}
+template <typename V>
+void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
+                    void *out_val, int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_ex_emit<V>, dim3((unsigned)nblk), dim3(kBlock), 0, s, bm, nwords, blk, (V *)x, out_idx,
+                       (V *)out_val, cap);
+}
+
+void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
+                      int32_t *dmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, col_idx, n, nnz, bad,
+                       dmax);
+}
+void launch_lam_step(const int32_t *row_ptr, const int32_t *col_idx, const double *v, double *y, int32_t n,
+                     double *red, hipStream_t s) {
+    hipLaunchKernelGGL(k_lam_step, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, row_ptr, col_idx, v, y, n,
+                       red);
+}
+void launch_lam_scale(const double *y, double *v, int32_t n, const double *red, hipStream_t s) {
+    hipLaunchKernelGGL(k_lam_scale, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, y, v, n, red);
+}
+void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, v, n, val);
+}
+
+#define GDE_INST(V)                                                                                               \
+    template void launch_init_rd<V>(const int32_t *, void *, int32_t, hipStream_t);                               \
+    template void launch_seed_init<V>(void *, const int32_t *, const double *, int32_t, double, int32_t *,        \
+                                      int32_t *, int32_t *, int32_t, DevState *, hipStream_t);                    \
+    template void launch_snap_gd<V>(const SnapArgs &, V, int, hipStream_t);                                       \
+    template void launch_snap_hk<V>(const SnapArgs &, void *, V, int, int, const int32_t *, int, int, double,    \
+                                    double, hipStream_t);                                                         \
+    template void launch_snap_ch<V>(const SnapArgs &, V, int, V, V, V, int, void *, int32_t *, int32_t *,        \
+                                    int32_t, int32_t *, hipStream_t);                                             \
+    template void launch_push<V>(int, int, const int32_t *, void *, DevState *, int, const int32_t *,            \
+                                 const int32_t *, const void *, const int32_t *, V, int32_t *, int32_t *, int,    \
+                                 int32_t *, int32_t, long long *, long long *, long long, int, int32_t, int32_t,  \
+                                 hipStream_t);                                                                    \
+    template void launch_final_residual<V>(const int32_t *, const int32_t *, void *, const int32_t *, DevState *, \
+                                           double, int, int32_t, hipStream_t);                                    \
+    template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
+    template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \
+    template void launch_ex_emit<V>(uint32_t *, int64_t, const int32_t *, int64_t, void *, int32_t *, void *,     \
+                                    int64_t, hipStream_t);
+
+GDE_INST(float)
+GDE_INST(double)
+
+}  // namespace gde

@@ -1,0 +1,328 @@
+"""Python binding of ``libgde.so`` (the C ABI declared in ``include/gde.h``).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch is used, when given, for device memory (``tensor.data_ptr()``)
+and streams (``torch.cuda.current_stream().cuda_stream``).  If the library has
+not been built this module raises at import time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgde.so")
+
+OK, INVALID_ARG, ISOLATED_SEED, CAPACITY, NOT_CONVERGED, OOM, BUSY, DEVICE, UNSUPPORTED = range(9)
+PPR, KATZ, HK = 0, 1, 2
+LOCAL_GD, LOCAL_CH = 0, 1
+F32, F64 = 0, 1
+HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
+KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
+STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
+                "UNSUPPORTED"]
+KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK}
+METHODS = {"gd": LOCAL_GD, "localgd": LOCAL_GD, "ch": LOCAL_CH, "localch": LOCAL_CH}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2410_21634_amd.build` (hipcc, gfx950)")
+
+# PyTorch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+# first makes libgde.so bind to that same runtime, so that torch streams and
+# device pointers are valid in the library and only one runtime owns the GPU.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library also works without torch (host buffers)
+    torch = None
+
+
+class Params(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("method", C.c_int32), ("value_type", C.c_int32), ("K", C.c_int32),
+                ("alpha", C.c_double), ("beta", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
+                ("lambda_bound", C.c_double), ("c", C.POINTER(C.c_double)), ("max_iters", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class Seed(C.Structure):
+    _fields_ = [("nnz", C.c_int32), ("idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("idx", C.c_void_p), ("val", C.c_void_p), ("trace_capacity", C.c_int64),
+                ("trace_size", C.c_void_p), ("trace_vol", C.c_void_p), ("trace_nodes_capacity", C.c_int64),
+                ("trace_nodes", C.c_void_p), ("nnz", C.c_int64), ("residual_l1", C.c_double),
+                ("residual_dinf", C.c_double), ("iters", C.c_int32), ("status", C.c_int32), ("ops", C.c_int64),
+                ("pushes", C.c_int64), ("trace_len", C.c_int64), ("trace_nodes_len", C.c_int64)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("lanes_per_group", C.c_int32), ("max_groups", C.c_int32), ("iters_per_step", C.c_int32),
+                ("queue_capacity", C.c_int32), ("value_type", C.c_int32), ("result_capacity", C.c_int32),
+                ("max_insert_edges", C.c_int64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("iters", C.c_int32), ("nnz", C.c_int64),
+                ("idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_float)), ("residual_l1", C.c_double),
+                ("residual_dinf", C.c_double), ("submit_time_s", C.c_double), ("done_time_s", C.c_double)]
+
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
+_SIGS = {
+    "gde_abi_version": ([], C.c_int),
+    "gde_last_error": ([], C.c_char_p),
+    "gde_ctx_create": ([C.c_int, C.POINTER(_vp)], C.c_int),
+    "gde_ctx_destroy": ([_vp], C.c_int),
+    "gde_graph_create": ([_vp, _i32, _i64, _vp, _vp, C.c_uint32, _vp, C.POINTER(_vp)], C.c_int),
+    "gde_graph_destroy": ([_vp], C.c_int),
+    "gde_graph_lambda_max": ([_vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), _vp],
+                             C.c_int),
+    "gde_validate": ([_i32, _i64, _vp, _vp, C.POINTER(Params), C.POINTER(Seed)], C.c_int),
+    "gde_solve": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
+    "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
+                        C.c_int),
+    "gde_server_create": ([_vp, _vp, C.POINTER(ServerCfg), C.POINTER(_vp)], C.c_int),
+    "gde_server_submit": ([_vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(C.c_uint64)], C.c_int),
+    "gde_server_poll": ([_vp, C.POINTER(Completion), _i32, C.POINTER(_i32)], C.c_int),
+    "gde_server_insert_edges": ([_vp, _i32, _vp, _vp], C.c_int),
+    "gde_server_destroy": ([_vp], C.c_int),
+}
+for _name, (_args, _ret) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _ret
+EXPORTED = tuple(_SIGS)
+
+
+class GDEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+def last_error() -> str:
+    return (_lib.gde_last_error() or b"").decode()
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise GDEError(rc, last_error())
+    return rc
+
+
+def abi_version() -> int:
+    return _lib.gde_abi_version()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_params(kind="ppr", method="gd", *, alpha=0.1, beta=0.0, tau=5.0, K=30, eps=1e-6, lambda_bound=0.0,
+                value_type=F32, max_iters=10000, flags=0) -> Params:
+    k = KINDS[kind] if isinstance(kind, str) else int(kind)
+    m = METHODS[method] if isinstance(method, str) else int(method)
+    vt = {"f32": F32, "f64": F64}.get(value_type, value_type) if isinstance(value_type, str) else int(value_type)
+    return Params(k, m, vt, int(K), float(alpha), float(beta), float(tau), float(eps), float(lambda_bound), None,
+                  int(max_iters), int(flags))
+
+
+class _SeedHolder:
+    """Keeps the numpy arrays behind a Seed struct alive."""
+
+    def __init__(self, idx, val=None):
+        self.idx = np.ascontiguousarray(np.atleast_1d(idx), dtype=np.int32)
+        if val is None:
+            val = np.ones(len(self.idx))
+        self.val = np.ascontiguousarray(np.atleast_1d(val), dtype=np.float64)
+        self.seed = Seed(len(self.idx), self.idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                         self.val.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def validate(row_ptr, col_idx, params: Params, seed_idx, seed_val=None) -> int:
+    """Host-only validation (no device work)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    sh = _SeedHolder(seed_idx, seed_val)
+    return _lib.gde_validate(len(rp) - 1, int(rp[-1]) if len(rp) else 0, rp.ctypes.data_as(_vp),
+                             ci.ctypes.data_as(_vp), C.byref(params), C.byref(sh.seed))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(_lib.gde_ctx_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.gde_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A CSR graph on the context's device.  numpy arrays are copied; torch
+    device tensors are borrowed (they must stay alive with the graph)."""
+
+    def __init__(self, ctx: Context, row_ptr, col_idx, stream=None):
+        self.ctx = ctx
+        h = _vp()
+        if hasattr(row_ptr, "data_ptr") and getattr(row_ptr, "is_cuda", False):
+            self._keep = (row_ptr, col_idx)
+            n = row_ptr.numel() - 1
+            nnz = col_idx.numel()
+            rc = _lib.gde_graph_create(ctx.handle, n, nnz, _vp(row_ptr.data_ptr()), _vp(col_idx.data_ptr()),
+                                       DEVICE_PTRS | BORROW, _stream_ptr(stream), C.byref(h))
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+            n, nnz = len(rp) - 1, len(ci)
+            rc = _lib.gde_graph_create(ctx.handle, n, nnz, rp.ctypes.data_as(_vp), ci.ctypes.data_as(_vp),
+                                       HOST_PTRS | COPY, _stream_ptr(stream), C.byref(h))
+        _check(rc)
+        self.handle = h
+        self.n = int(n)
+        self.nnz = int(nnz)
+
+    def lambda_max(self, max_iters=500, rtol=1e-3, stream=None):
+        lo, hi = C.c_double(), C.c_double()
+        _check(_lib.gde_graph_lambda_max(self.ctx.handle, self.handle, int(max_iters), float(rtol), C.byref(lo),
+                                         C.byref(hi), _stream_ptr(stream)))
+        return lo.value, hi.value
+
+    def close(self):
+        if self.handle:
+            _lib.gde_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class SolveResult:
+    idx: object
+    val: object
+    status: int
+    residual_l1: float
+    residual_dinf: float
+    iters: int
+    ops: int
+    pushes: int
+    trace_size: np.ndarray | None = None
+    trace_vol: np.ndarray | None = None
+    trace_nodes: np.ndarray | None = None
+    extra: dict = field(default_factory=dict)
+
+    def dense(self, n):
+        x = np.zeros(n)
+        idx = self.idx.cpu().numpy() if hasattr(self.idx, "cpu") else self.idx
+        val = self.val.cpu().numpy() if hasattr(self.val, "cpu") else self.val
+        x[idx] = val
+        return x
+
+
+def _result_struct(params, capacity, out_idx, out_val, trace_cap, nodes_cap):
+    r = Result()
+    r.capacity = capacity
+    r.idx = out_idx
+    r.val = out_val
+    keep = []
+    if params.flags & TRACE:
+        ts = np.zeros(max(trace_cap, 1), np.int64)
+        tv = np.zeros(max(trace_cap, 1), np.int64)
+        tn = np.zeros(max(nodes_cap, 1), np.int32)
+        r.trace_capacity = trace_cap
+        r.trace_size = ts.ctypes.data
+        r.trace_vol = tv.ctypes.data
+        r.trace_nodes_capacity = nodes_cap
+        r.trace_nodes = tn.ctypes.data if nodes_cap else None
+        keep = [ts, tv, tn]
+    return r, keep
+
+
+def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *, capacity=None, out=None,
+          trace_cap=4096, nodes_cap=0, stream=None, raise_on_error=True) -> SolveResult:
+    """One query.  ``out``: optional (idx, val) torch device tensors (the result
+    stays in HBM, GDE_RESULT_DEVICE); otherwise numpy host arrays are returned."""
+    sh = _SeedHolder(seed_idx, seed_val)
+    vdt = np.float64 if params.value_type == F64 else np.float32
+    p = Params.from_buffer_copy(params)
+    if out is not None:
+        p.flags |= RESULT_DEVICE
+        oi, ov = out
+        cap = oi.numel() if capacity is None else capacity
+        r, keep = _result_struct(p, cap, oi.data_ptr(), ov.data_ptr(), trace_cap, nodes_cap)
+    else:
+        cap = graph.n if capacity is None else capacity
+        oi = np.zeros(max(cap, 1), np.int32)
+        ov = np.zeros(max(cap, 1), vdt)
+        r, keep = _result_struct(p, cap, oi.ctypes.data, ov.ctypes.data, trace_cap, nodes_cap)
+    rc = _lib.gde_solve(ctx.handle, graph.handle, C.byref(p), C.byref(sh.seed), C.byref(r), _stream_ptr(stream))
+    if raise_on_error:
+        _check(rc, (OK, NOT_CONVERGED))
+    nnz = int(r.nnz) if rc in (OK, NOT_CONVERGED) else 0
+    res = SolveResult(oi[:nnz], ov[:nnz], rc, r.residual_l1, r.residual_dinf, r.iters, r.ops, r.pushes)
+    res.extra["nnz_needed"] = int(r.nnz)
+    if p.flags & TRACE:
+        m = min(int(r.trace_len), trace_cap)
+        res.trace_size = keep[0][:m].copy()
+        res.trace_vol = keep[1][:m].copy()
+        if nodes_cap:
+            res.trace_nodes = keep[2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
+    return res
+
+
+def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None, schedule=None, stream=None,
+                raise_on_error=True):
+    """B queries in one call.  ``seeds``: list of (idx, val) pairs.  Returns a list of SolveResult."""
+    B = len(params_list)
+    P = (Params * B)(*[Params.from_buffer_copy(p) for p in params_list])
+    holders = [_SeedHolder(i, v) for i, v in seeds]
+    S = (Seed * B)(*[h.seed for h in holders])
+    R = (Result * B)()
+    bufs = []
+    for i, p in enumerate(params_list):
+        vdt = np.float64 if p.value_type == F64 else np.float32
+        cap = graph.n if capacity is None else capacity
+        oi = np.zeros(max(cap, 1), np.int32)
+        ov = np.zeros(max(cap, 1), vdt)
+        R[i].capacity = cap
+        R[i].idx = oi.ctypes.data
+        R[i].val = ov.ctypes.data
+        bufs.append((oi, ov))
+    sched = schedule.encode() if isinstance(schedule, str) else schedule
+    rc = _lib.gde_solve_batch(ctx.handle, graph.handle, B, P, S, R, sched, _stream_ptr(stream))
+    if raise_on_error:
+        _check(rc, (OK, NOT_CONVERGED))
+    out = []
+    for i in range(B):
+        r = R[i]
+        nnz = int(r.nnz) if r.status in (OK, NOT_CONVERGED) else 0
+        out.append(SolveResult(bufs[i][0][:nnz], bufs[i][1][:nnz], r.status, r.residual_l1, r.residual_dinf,
+                               r.iters, r.ops, r.pushes))
+    return out

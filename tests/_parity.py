@@ -1,0 +1,80 @@
+"""Parity protocol between the HIP path (through the C ABI) and the FP64 oracle.
+
+P1 free run: when the integer traces (T, |S_t|, vol(S_t)) agree, the GPU x must
+   match the oracle x within tol * ||s||_1 in l1 (tol 1e-12 for FP64 values,
+   1e-6 for FP32 values) and the residual norms within rtol.
+P2 replay: when the traces differ (an FP32 value within rounding of its
+   threshold), the oracle re-runs on the GPU's recorded S_t lists in FP64 and
+   grades every decision against the band theta*(1 +- kappa); no decision may
+   fall outside the band and x must match the replay within the P1 bound.
+P3 certificate: the recorded l1 error against the FP64 oracle is returned for
+   every result.
+"""
+import numpy as np
+
+from oracle import solvers as O
+from paper_2410_21634_amd import gde
+
+TOL = {gde.F64: 1e-12, gde.F32: 1e-6}
+RTOL = {gde.F64: 1e-10, gde.F32: 1e-5}
+KAPPA = {gde.F64: 1e-12, gde.F32: 1e-5}
+
+
+def oracle_run(G, kind, method, prm, seed_idx, seed_val, nodes_cap=0):
+    rp, ci = G.row_ptr, G.col_idx
+    if kind == gde.HK:
+        return O.hk(rp, ci, prm["tau"], prm["K"], prm["eps"], seed_idx, seed_val, trace_cap=prm["K"] + 2,
+                    nodes_cap=nodes_cap)
+    param = prm["alpha"] if kind == gde.PPR else prm["beta"]
+    if method == gde.LOCAL_GD:
+        return O.localgd(rp, ci, kind, param, prm["eps"], seed_idx, seed_val, max_iters=prm.get("max_iters", 100000),
+                         trace_cap=100000, nodes_cap=nodes_cap)
+    return O.localch(rp, ci, kind, param, prm["eps"], seed_idx, seed_val, lam=prm.get("lambda_bound", 0.0),
+                     max_iters=prm.get("max_iters", 100000), trace_cap=100000, nodes_cap=nodes_cap)
+
+
+def oracle_replay(G, kind, method, prm, seed_idx, seed_val, sizes, nodes, kappa):
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    rp, ci = G.row_ptr, G.col_idx
+    if kind == gde.HK:
+        return O.hk(rp, ci, prm["tau"], prm["K"], prm["eps"], seed_idx, seed_val, replay=(off, nodes), kappa=kappa)
+    param = prm["alpha"] if kind == gde.PPR else prm["beta"]
+    return O.replay_gd_ch(rp, ci, method, kind, param, prm["eps"], seed_idx, seed_val, off, nodes, kappa,
+                          lam=prm.get("lambda_bound", 0.0))
+
+
+def check(ctx, g, G, kind, method, vt, prm, seed_idx, seed_val=None, force_replay=False):
+    """Run the GPU solve and the oracle, enforce P1 (or P2), return a report dict."""
+    seed_idx = np.atleast_1d(np.asarray(seed_idx, dtype=np.int32))
+    seed_val = np.ones(len(seed_idx)) if seed_val is None else np.asarray(seed_val, dtype=np.float64)
+    s1 = float(np.abs(seed_val).sum())
+    p = gde.make_params(kind, method, value_type=vt, flags=gde.TRACE, **prm)
+    nodes_cap = int(min(30_000_000, max(1_000_000, 16 * G.n)))
+    res = gde.solve(ctx, g, p, seed_idx, seed_val, trace_cap=100000, nodes_cap=nodes_cap)
+    x_gpu = res.dense(G.n)
+    ref = oracle_run(G, kind, method, prm, seed_idx, seed_val)
+    same = (res.iters == ref["iters"] and res.ops == ref["ops"] and res.pushes == ref["pushes"]
+            and np.array_equal(res.trace_size, ref["trace_size"]) and np.array_equal(res.trace_vol, ref["trace_vol"]))
+    err_oracle = float(np.abs(x_gpu - ref["x"]).sum())
+    rep = dict(iters=res.iters, ops=res.ops, trace_equal=same, l1_err_vs_oracle=err_oracle / s1, status=res.status,
+               nnz=len(res.idx))
+    assert res.status == ref["status"] or not same
+    # support: exactly the pushed nodes, ascending
+    assert np.all(np.diff(res.idx) > 0)
+    if same and not force_replay:
+        assert err_oracle <= TOL[vt] * s1, rep
+        np.testing.assert_allclose(res.residual_l1, ref["residual_l1"], rtol=RTOL[vt], atol=1e-300)
+        np.testing.assert_allclose(res.residual_dinf, ref["residual_dinf"], rtol=RTOL[vt], atol=1e-300)
+        if method == gde.LOCAL_GD and kind != gde.HK:
+            assert set(res.idx.tolist()) == set(np.flatnonzero(ref["x"] != 0).tolist())
+        rep["mode"] = "free-run"
+    else:
+        assert res.trace_nodes is not None and len(res.trace_nodes) == res.pushes
+        rp = oracle_replay(G, kind, method, prm, seed_idx, seed_val, res.trace_size, res.trace_nodes, KAPPA[vt])
+        assert rp["violations"] == 0, rp
+        err_rp = float(np.abs(x_gpu - rp["x"]).sum())
+        assert err_rp <= TOL[vt] * s1, (err_rp, rep)
+        np.testing.assert_allclose(res.residual_l1, rp["residual_l1"], rtol=RTOL[vt] * 10, atol=1e-300)
+        rep.update(mode="replay", flips=rp["flips"], l1_err_vs_replay=err_rp / s1)
+    return rep

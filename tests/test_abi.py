@@ -1,0 +1,77 @@
+"""The C ABI library loads, exports every symbol of include/gde.h and validates
+arguments on the host (no GPU needed: validation runs before any device work)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "gde.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(gde_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported():
+    from paper_2410_21634_amd import gde
+    lib = C.CDLL(gde.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(gde.EXPORTED)
+    assert gde.abi_version() == 1
+
+
+@pytest.fixture(scope="module")
+def small():
+    from paper_2410_21634_amd import workloads as W
+    return W.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4)])  # node 5 isolated
+
+
+def test_validation_errors(small):
+    from paper_2410_21634_amd import gde
+    rp, ci = small.row_ptr, small.col_idx
+
+    def v(seed=(0,), val=None, **kw):
+        base = dict(kind="ppr", method="gd", alpha=0.1, eps=1e-4)
+        base.update(kw)
+        return gde.validate(rp, ci, gde.make_params(**base), list(seed), val)
+
+    assert v() == gde.OK
+    assert v(eps=0.0) == gde.INVALID_ARG
+    assert v(eps=float("nan")) == gde.INVALID_ARG
+    assert v(alpha=1.0) == gde.INVALID_ARG
+    assert v(alpha=0.0) == gde.INVALID_ARG
+    assert v(kind="katz", beta=0.1, lambda_bound=2.0) == gde.OK
+    assert v(kind="katz", beta=0.6, lambda_bound=2.0) == gde.INVALID_ARG   # beta * lambda >= 1
+    assert v(kind="katz", beta=0.1, lambda_bound=0.0) == gde.INVALID_ARG
+    assert v(kind="hk", tau=5.0, K=30) == gde.OK
+    assert v(kind="hk", tau=-1.0) == gde.INVALID_ARG
+    assert v(kind="hk", K=300) == gde.INVALID_ARG
+    assert v(kind="hk", method="ch") == gde.UNSUPPORTED
+    assert v(max_iters=0) == gde.INVALID_ARG
+    assert v(seed=(1, 0)) == gde.INVALID_ARG            # unsorted
+    assert v(seed=(1, 1)) == gde.INVALID_ARG            # duplicate
+    assert v(seed=(9,)) == gde.INVALID_ARG              # out of range
+    assert v(seed=(0,), val=[-1.0]) == gde.INVALID_ARG  # nonpositive value
+    assert v(seed=(5,)) == gde.ISOLATED_SEED
+    p = gde.make_params(value_type=7)
+    assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
+    p = gde.make_params(flags=0x100)
+    assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
+    # malformed CSR
+    bad = rp.copy()
+    bad[-1] += 1
+    assert gde.validate(bad, ci, gde.make_params(), [0]) == gde.INVALID_ARG
+    ci2 = ci.copy()
+    ci2[0] = 0  # self-loop at node 0
+    assert gde.validate(rp, ci2, gde.make_params(), [0]) == gde.INVALID_ARG
+    ci3 = ci.copy()
+    ci3[0] = 17
+    assert gde.validate(rp, ci3, gde.make_params(), [0]) == gde.INVALID_ARG
+    assert "self-loop" in gde.last_error() or "range" in gde.last_error()
