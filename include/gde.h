@@ -188,6 +188,22 @@ int gde_graph_destroy(gde_graph *g);
 int gde_graph_lambda_max(gde_ctx *ctx, gde_graph *g, int max_iters, double rtol, double *lower, double *upper,
                          hipStream_t stream);
 
+/*
+ * Kernel timing for measurement.  While enabled, every launch of the push
+ * (residual scatter) kernel in this context is bracketed by HIP events on the
+ * solve's stream; the totals accumulate until read.  `out` may be NULL.
+ *   launches -- push launches,   total_ms -- summed event time of those launches,
+ *   edges    -- CSR entries they traversed (sum vol(S_t)), entries -- sum |S_t|.
+ * reset != 0 clears the totals after reading.
+ */
+typedef struct gde_kernel_profile {
+    int64_t launches;
+    double total_ms;
+    int64_t edges;
+    int64_t entries;
+} gde_kernel_profile;
+int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset);
+
 /* Host-only validation of one query against a host CSR (no device work; usable without a GPU). */
 int gde_validate(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const gde_params *p,
                  const gde_seed *s);

@@ -259,6 +259,33 @@ void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
     }
 }
 
+// ------------------------------------------------------------------ kernel timing
+int prof_mark(gde_ctx *ctx, hipStream_t s) {
+    if (!ctx->prof_on) return GDE_OK;
+    if (ctx->ev_used == ctx->ev.size()) {
+        hipEvent_t e;
+        GDE_HIP(hipEventCreate(&e));
+        ctx->ev.push_back(e);
+    }
+    GDE_HIP(hipEventRecord(ctx->ev[ctx->ev_used++], s));
+    return GDE_OK;
+}
+
+// after the stream has been synchronised: fold the recorded pairs into the totals
+int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries) {
+    if (!ctx->prof_on) return GDE_OK;
+    for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+        float ms = 0.f;
+        GDE_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+        ctx->prof_ms += ms;
+        ctx->prof_launches++;
+    }
+    ctx->ev_used = 0;
+    ctx->prof_edges += edges;
+    ctx->prof_entries += entries;
+    return GDE_OK;
+}
+
 // ------------------------------------------------------------------ the plain solver
 static int push_grid(const gde_graph *g) {
     int64_t tiles = g->nnz / kTile + 1;
@@ -337,9 +364,11 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                               k >= 1 ? w->touched[(k + 2) % 3] : nullptr, (k + 2) % 3, (k + 1) % 3,
                               k >= 1 ? psi[k - 1] : 0.0, k >= 1 ? (double)(K + 1) * psi[k - 1] : 0.0, s);
             const double eps_next = last ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]);
+            if ((rc = prof_mark(ctx, s))) return rc;
             launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
                            w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
                            nullptr, 0, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, s);
+            if ((rc = prof_mark(ctx, s))) return rc;
         }
         // clean-up of the last level
         a.rd = plane[(K + 1) & 1];
@@ -390,14 +419,18 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     }
                     launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
                                       w->cstamp, base + t, w->front[(t + 1) & 1], s);
+                    if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
                                    d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                    if ((rc = prof_mark(ctx, s))) return rc;
                 } else {
                     launch_snap_gd<V>(a, wscale, w_div_deg, s);
+                    if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, d_trs, d_trv,
                                    tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                    if ((rc = prof_mark(ctx, s))) return rc;
                 }
             }
             GDE_HIP(hipGetLastError());
@@ -453,6 +486,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipStreamSynchronize(s));
     if (h.overflow) return fail(GDE_ERR_DEVICE, "internal list overflow (a frontier invariant was broken)");
+    if ((rc = prof_collect(ctx, h.ops, h.pushes))) return rc;
     res->nnz = nnz;
     res->iters = h.iters;
     res->ops = h.ops;
@@ -515,7 +549,25 @@ int gde_ctx_destroy(gde_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (Workspace *w : ctx->ws) ws_free(w);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
     delete ctx;
+    return GDE_OK;
+}
+
+int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset) {
+    if (!ctx) return fail(GDE_ERR_INVALID_ARG, "null ctx");
+    if (out) {
+        out->launches = ctx->prof_launches;
+        out->total_ms = ctx->prof_ms;
+        out->edges = ctx->prof_edges;
+        out->entries = ctx->prof_entries;
+    }
+    if (reset) {
+        ctx->prof_launches = ctx->prof_edges = ctx->prof_entries = 0;
+        ctx->prof_ms = 0.0;
+    }
+    ctx->prof_on = enable != 0;
+    ctx->ev_used = 0;
     return GDE_OK;
 }
 

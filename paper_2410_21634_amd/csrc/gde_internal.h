@@ -98,6 +98,12 @@ struct gde_graph {
 struct gde_ctx {
     int device = 0;
     std::vector<gde::Workspace *> ws;
+    // push-kernel timing (gde_ctx_profile)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev;   // pairs: [2i] before, [2i+1] after launch i of the current solve
+    size_t ev_used = 0;
+    int64_t prof_launches = 0, prof_edges = 0, prof_entries = 0;
+    double prof_ms = 0.0;
 };
 
 namespace gde {

@@ -64,6 +64,10 @@ class ServerCfg(C.Structure):
                 ("max_insert_edges", C.c_int64)]
 
 
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("edges", C.c_int64), ("entries", C.c_int64)]
+
+
 class Completion(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("iters", C.c_int32), ("nnz", C.c_int64),
                 ("idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_float)), ("residual_l1", C.c_double),
@@ -82,6 +86,7 @@ _SIGS = {
     "gde_graph_lambda_max": ([_vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), _vp],
                              C.c_int),
     "gde_validate": ([_i32, _i64, _vp, _vp, C.POINTER(Params), C.POINTER(Seed)], C.c_int),
+    "gde_ctx_profile": ([_vp, C.c_int, C.POINTER(KernelProfile), C.c_int], C.c_int),
     "gde_solve": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
     "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
                         C.c_int),
@@ -168,6 +173,12 @@ class Context:
         _check(_lib.gde_ctx_create(int(device), C.byref(h)))
         self.handle = h
         self.device = device
+
+    def profile(self, enable: bool = True, reset: bool = True) -> dict:
+        """Push-kernel event timing: returns the totals so far, then sets the mode."""
+        kp = KernelProfile()
+        _check(_lib.gde_ctx_profile(self.handle, int(enable), C.byref(kp), int(reset)))
+        return dict(launches=kp.launches, total_ms=kp.total_ms, edges=kp.edges, entries=kp.entries)
 
     def close(self):
         if self.handle:
