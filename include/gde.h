@@ -190,10 +190,14 @@ int gde_graph_lambda_max(gde_ctx *ctx, gde_graph *g, int max_iters, double rtol,
 
 /*
  * Kernel timing for measurement.  While enabled, every launch of the push
- * (residual scatter) kernel in this context is bracketed by HIP events on the
+ * (residual scatter) kernel of the plain solver and every launch of the
+ * batched solver's kernel in this context is bracketed by HIP events on the
  * solve's stream; the totals accumulate until read.  `out` may be NULL.
- *   launches -- push launches,   total_ms -- summed event time of those launches,
- *   edges    -- CSR entries they traversed (sum vol(S_t)), entries -- sum |S_t|.
+ *   launches, total_ms  -- push launches and their summed event time
+ *   edges, entries      -- CSR entries they traversed (sum vol(S_t)) and sum |S_t|
+ *   batch_launches, batch_ms -- batched-solver kernel launches and their time
+ *   batch_lane_edges    -- (edge, query) updates the batched kernel applied
+ *   batch_entries       -- (group, node) work entries it processed
  * reset != 0 clears the totals after reading.
  */
 typedef struct gde_kernel_profile {
@@ -201,6 +205,10 @@ typedef struct gde_kernel_profile {
     double total_ms;
     int64_t edges;
     int64_t entries;
+    int64_t batch_launches;
+    double batch_ms;
+    int64_t batch_lane_edges;
+    int64_t batch_entries;
 } gde_kernel_profile;
 int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset);
 

@@ -257,6 +257,7 @@ void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
         if (ctx->ws[i]->guid == g->uid) { ws_free(ctx->ws[i]); ctx->ws.erase(ctx->ws.begin() + i); }
         else i++;
     }
+    drop_batch_workspaces_of(g, ctx);
 }
 
 // ------------------------------------------------------------------ kernel timing
@@ -284,6 +285,37 @@ int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries) {
     ctx->prof_edges += edges;
     ctx->prof_entries += entries;
     return GDE_OK;
+}
+
+int prof_mark_batch(gde_ctx *ctx, hipStream_t s) {
+    if (!ctx->prof_on) return GDE_OK;
+    for (int i = 0; i < 2; i++)
+        if (!ctx->ev_b[i]) GDE_HIP(hipEventCreate(&ctx->ev_b[i]));
+    if (ctx->ev_b_used >= 2) ctx->ev_b_used = 0;
+    GDE_HIP(hipEventRecord(ctx->ev_b[ctx->ev_b_used++], s));
+    return GDE_OK;
+}
+
+int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries) {
+    if (!ctx->prof_on) return GDE_OK;
+    if (ctx->ev_b_used == 2) {
+        float ms = 0.f;
+        GDE_HIP(hipEventElapsedTime(&ms, ctx->ev_b[0], ctx->ev_b[1]));
+        ctx->prof_b_ms += ms;
+        ctx->prof_b_launches++;
+        ctx->prof_b_lane_edges += lane_edges;
+        ctx->prof_b_entries += entries;
+    }
+    ctx->ev_b_used = 0;
+    return GDE_OK;
+}
+
+int gde_validate_query(const gde_graph *g, const gde_params *p, const gde_seed *s) {
+    int rc = validate_params(p);
+    if (rc) return rc;
+    GraphHost *gh = graph_host(g);
+    if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");
+    return validate_seed(s, g->n, gh->row_ptr.data());
 }
 
 // ------------------------------------------------------------------ the plain solver
@@ -549,7 +581,10 @@ int gde_ctx_destroy(gde_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (Workspace *w : ctx->ws) ws_free(w);
+    for (BatchWS *b : ctx->bws) batch_ws_free(b);
     for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_b)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return GDE_OK;
 }
@@ -561,10 +596,16 @@ int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset
         out->total_ms = ctx->prof_ms;
         out->edges = ctx->prof_edges;
         out->entries = ctx->prof_entries;
+        out->batch_launches = ctx->prof_b_launches;
+        out->batch_ms = ctx->prof_b_ms;
+        out->batch_lane_edges = ctx->prof_b_lane_edges;
+        out->batch_entries = ctx->prof_b_entries;
     }
     if (reset) {
         ctx->prof_launches = ctx->prof_edges = ctx->prof_entries = 0;
         ctx->prof_ms = 0.0;
+        ctx->prof_b_launches = ctx->prof_b_lane_edges = ctx->prof_b_entries = 0;
+        ctx->prof_b_ms = 0.0;
     }
     ctx->prof_on = enable != 0;
     ctx->ev_used = 0;

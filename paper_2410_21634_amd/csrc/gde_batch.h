@@ -6,7 +6,12 @@
 namespace gde {
 int get_workspace(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out);
 void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx);
+void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx);
 // push-kernel timing helpers (no-ops unless profiling is enabled on ctx)
 int prof_mark(gde_ctx *ctx, hipStream_t s);
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries);
+int prof_mark_batch(gde_ctx *ctx, hipStream_t s);
+int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries);
+// host validation of one query against a graph (parameters, seed, isolated seeds)
+int gde_validate_query(const gde_graph *g, const gde_params *p, const gde_seed *s);
 }  // namespace gde

@@ -1,8 +1,387 @@
-// gde_batch.hip -- batched solver and continuous-batching server (in progress).
+// gde_batch.hip -- host side of gde_solve_batch: many LocalGD queries (PPR or
+// Katz) solved together by the node-major lane kernels of gde_batch_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
 #include "gde_batch.h"
+#include "gde_batch_kernels.h"
 #include "gde_internal.h"
+
+namespace gde {
+
+// One reusable allocation per (graph, value type, lane count).  At rest every
+// node-indexed array is zero; a batch leaves it zero again.
+struct BatchWS {
+    uint64_t guid = 0;
+    int vtype = 0, L = 0, Gcap = 0;
+    int64_t n = 0, nwords = 0;
+    size_t vs = 4;
+    void *R = nullptr, *X = nullptr, *deg = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
+    uint32_t *NM = nullptr, *TM = nullptr, *PB = nullptr, *group_unconv = nullptr;
+    uint64_t *act[2] = {nullptr, nullptr}, *touched = nullptr;
+    int32_t act_cap = 0, touch_cap = 0, wl_cap = 0;
+    int64_t tile_cap = 0;
+    int32_t *wl_node = nullptr, *wl_group = nullptr, *wl_beg = nullptr, *wl_c = nullptr, *tile_start = nullptr;
+    long long *wl_off = nullptr;
+    uint8_t *wl_lanes = nullptr;
+    long long *lane_ops = nullptr, *lane_pushes = nullptr, *lane_nnz = nullptr, *lane_out_off = nullptr;
+    int32_t *lane_T = nullptr, *cnt = nullptr, *sub_flag = nullptr;
+    double *lane_l1 = nullptr;
+    unsigned long long *lane_dinf = nullptr;
+    BatchDev *st = nullptr;
+    int32_t *s_lane = nullptr, *s_node = nullptr;
+    double *s_val = nullptr;
+    int32_t s_cap = 0;
+    int32_t *out_idx = nullptr;
+    int64_t out_cap = 0;
+    int nblk = 0;
+};
+
+void batch_ws_free(BatchWS *w) {
+    void *p[] = {w->R, w->X, w->deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
+                 w->act[0], w->act[1], w->touched, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
+                 w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
+                 w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    delete w;
+}
+
+void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
+    for (size_t i = 0; i < ctx->bws.size();) {
+        if (ctx->bws[i]->guid == g->uid) { batch_ws_free(ctx->bws[i]); ctx->bws.erase(ctx->bws.begin() + i); }
+        else i++;
+    }
+}
+
+struct Schedule {
+    int lanes = 16;
+    int blocks_per_cu = 0;  // 0: the occupancy limit
+    int persistent = 0;
+    int sort = 1;           // order queries by eps, then seed degree, before packing lanes
+};
+
+static int json_int(const char *js, const char *key, int dflt) {
+    if (!js) return dflt;
+    std::string k = std::string("\"") + key + "\"";
+    const char *p = std::strstr(js, k.c_str());
+    if (!p) return dflt;
+    p = std::strchr(p + k.size(), ':');
+    if (!p) return dflt;
+    return (int)std::strtol(p + 1, nullptr, 10);
+}
+
+static int parse_schedule(const char *js, Schedule *sc) {
+    sc->lanes = json_int(js, "lanes", 16);
+    sc->blocks_per_cu = json_int(js, "blocks_per_cu", 0);
+    sc->persistent = json_int(js, "persistent", 0);
+    sc->sort = json_int(js, "sort", 1);
+    if (sc->lanes != 8 && sc->lanes != 16 && sc->lanes != 32)
+        return fail(GDE_ERR_INVALID_ARG, "schedule.lanes must be 8, 16 or 32");
+    if (sc->blocks_per_cu < 0 || sc->blocks_per_cu > 64) return fail(GDE_ERR_INVALID_ARG, "bad schedule.blocks_per_cu");
+    // The single cooperative launch with grid-wide barriers stopped making
+    // progress on its first GPU run and its cause has not been shown; it stays
+    // switched off.  Iterations run as per-iteration launches of the same phases.
+    if (sc->persistent) return fail(GDE_ERR_UNSUPPORTED, "schedule.persistent=1 is disabled");
+    return GDE_OK;
+}
+
+#define BALLOC(ptr, bytes)                                                           \
+    do {                                                                             \
+        hipError_t _e = hipMalloc((void **)&(ptr), (size_t)(bytes));                 \
+        if (_e != hipSuccess) { batch_ws_free(w); return hip_fail(_e, "hipMalloc(batch)"); } \
+        _e = hipMemsetAsync((ptr), 0, (size_t)(bytes), s);                           \
+        if (_e != hipSuccess) { batch_ws_free(w); return hip_fail(_e, "hipMemsetAsync(batch)"); } \
+    } while (0)
+
+static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int G, hipStream_t s, BatchWS **out) {
+    for (size_t i = 0; i < ctx->bws.size(); i++) {
+        BatchWS *b = ctx->bws[i];
+        if (b->guid == g->uid && b->vtype == vtype && b->L == L && b->Gcap >= G) { *out = b; return GDE_OK; }
+    }
+    // one batch workspace per context: release the others first (they can be large)
+    for (BatchWS *b : ctx->bws) batch_ws_free(b);
+    ctx->bws.clear();
+    BatchWS *w = new BatchWS();
+    w->guid = g->uid;
+    w->vtype = vtype;
+    w->L = L;
+    w->Gcap = G;
+    w->n = g->n;
+    w->nwords = (g->n + 31) / 32;
+    w->vs = vtype == GDE_F64 ? 8 : 4;
+    const int64_t n = g->n, GL = (int64_t)G * L;
+    const int64_t pairs = n * (int64_t)G;
+    w->act_cap = (int32_t)std::min<int64_t>(pairs, 16000000);
+    w->wl_cap = w->act_cap;
+    w->touch_cap = (int32_t)std::min<int64_t>(pairs, 64000000);
+    w->tile_cap = 32000000;
+    w->nblk = (int)((w->nwords + kBlock - 1) / kBlock);
+    BALLOC(w->R, (size_t)n * GL * w->vs);
+    BALLOC(w->X, (size_t)n * GL * w->vs);
+    BALLOC(w->NM, (size_t)n * G * 4);
+    BALLOC(w->TM, (size_t)n * G * 4);
+    BALLOC(w->PB, (size_t)G * w->nwords * 4);
+    BALLOC(w->deg, (size_t)n * w->vs);
+    BALLOC(w->lane_eps, (size_t)GL * w->vs);
+    BALLOC(w->act[0], (size_t)w->act_cap * 8);
+    BALLOC(w->act[1], (size_t)w->act_cap * 8);
+    BALLOC(w->touched, (size_t)w->touch_cap * 8);
+    BALLOC(w->wl_node, (size_t)w->wl_cap * 4);
+    BALLOC(w->wl_group, (size_t)w->wl_cap * 4);
+    BALLOC(w->wl_beg, (size_t)w->wl_cap * 4);
+    BALLOC(w->wl_c, (size_t)w->wl_cap * 4);
+    BALLOC(w->wl_off, (size_t)w->wl_cap * 8);
+    BALLOC(w->wl_lanes, (size_t)w->wl_cap * L);
+    BALLOC(w->wl_sv, (size_t)w->wl_cap * L * w->vs);
+    BALLOC(w->tile_start, (size_t)w->tile_cap * 4);
+    BALLOC(w->lane_ops, (size_t)GL * kStatShards * 8);
+    BALLOC(w->lane_pushes, (size_t)GL * kStatShards * 8);
+    BALLOC(w->lane_l1, (size_t)GL * kStatShards * 8);
+    BALLOC(w->lane_T, (size_t)GL * 4);
+    BALLOC(w->lane_dinf, (size_t)GL * 8);
+    BALLOC(w->lane_nnz, (size_t)GL * 8);
+    BALLOC(w->lane_out_off, (size_t)GL * 8);
+    BALLOC(w->sub_flag, (size_t)GL * 4);
+    BALLOC(w->group_unconv, (size_t)G * 4);
+    BALLOC(w->cnt, (size_t)GL * w->nblk * 4);
+    BALLOC(w->st, sizeof(BatchDev));
+    hipError_t e = vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)w->deg, g->n, s)
+                                    : batch_init_deg<float>(g->row_ptr, (float *)w->deg, g->n, s);
+    if (e != hipSuccess) { batch_ws_free(w); return hip_fail(e, "batch_init_deg"); }
+    ctx->bws.push_back(w);
+    *out = w;
+    return GDE_OK;
+}
+
+template <typename V>
+static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *sd,
+                             gde_result *res, const Schedule &sc, hipStream_t s) {
+    const int L = sc.lanes;
+    const int G = (B + L - 1) / L;
+    const int vt = p[0].value_type;
+    BatchWS *w = nullptr;
+    int rc = batch_ws_get(ctx, g, vt, L, G, s, &w);
+    if (rc) return rc;
+    const bool ppr = p[0].kind == GDE_PPR;
+
+    // lane assignment: query order[j] occupies lane j (group j / L)
+    std::vector<int32_t> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    if (sc.sort) std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p[a].eps < p[b].eps; });
+    int64_t ns = 0;
+    for (int32_t q = 0; q < B; q++) ns += sd[q].nnz;
+    if (ns > w->s_cap) {
+        if (w->s_lane) { (void)hipFree(w->s_lane); (void)hipFree(w->s_node); (void)hipFree(w->s_val); }
+        w->s_lane = w->s_node = nullptr;
+        w->s_val = nullptr;
+        GDE_HIP(hipMalloc((void **)&w->s_lane, 4 * ns));
+        GDE_HIP(hipMalloc((void **)&w->s_node, 4 * ns));
+        GDE_HIP(hipMalloc((void **)&w->s_val, 8 * ns));
+        w->s_cap = (int32_t)ns;
+    }
+    std::vector<int32_t> h_lane(ns), h_node(ns), h_flag((size_t)G * L, 0);
+    std::vector<double> h_val(ns);
+    std::vector<V> h_eps((size_t)G * L, (V)(sizeof(V) == 4 ? FLT_MAX : DBL_MAX));
+    int64_t k = 0;
+    for (int j = 0; j < B; j++) {
+        const int q = order[j];
+        for (int32_t i = 0; i < sd[q].nnz; i++, k++) {
+            h_lane[k] = j;
+            h_node[k] = sd[q].idx[i];
+            h_val[k] = sd[q].val[i];
+        }
+        h_eps[j] = (V)(ppr ? p[q].alpha * p[q].eps : p[q].eps);
+        h_flag[j] = (!ppr && (p[q].flags & GDE_KATZ_SUBTRACT_SEED)) ? 1 : 0;
+    }
+    GDE_HIP(hipMemcpyAsync(w->s_lane, h_lane.data(), 4 * ns, hipMemcpyHostToDevice, s));
+    GDE_HIP(hipMemcpyAsync(w->s_node, h_node.data(), 4 * ns, hipMemcpyHostToDevice, s));
+    GDE_HIP(hipMemcpyAsync(w->s_val, h_val.data(), 8 * ns, hipMemcpyHostToDevice, s));
+    GDE_HIP(hipMemcpyAsync(w->lane_eps, h_eps.data(), sizeof(V) * h_eps.size(), hipMemcpyHostToDevice, s));
+    GDE_HIP(hipMemcpyAsync(w->sub_flag, h_flag.data(), 4 * h_flag.size(), hipMemcpyHostToDevice, s));
+    const size_t GL = (size_t)G * L;
+    GDE_HIP(hipMemsetAsync(w->st, 0, sizeof(BatchDev), s));
+    GDE_HIP(hipMemsetAsync(w->lane_ops, 0, GL * kStatShards * 8, s));
+    GDE_HIP(hipMemsetAsync(w->lane_pushes, 0, GL * kStatShards * 8, s));
+    GDE_HIP(hipMemsetAsync(w->lane_l1, 0, GL * kStatShards * 8, s));
+    GDE_HIP(hipMemsetAsync(w->lane_T, 0, GL * 4, s));
+    GDE_HIP(hipMemsetAsync(w->lane_dinf, 0, GL * 8, s));
+    GDE_HIP(hipMemsetAsync(w->group_unconv, 0, (size_t)G * 4, s));
+
+    BatchArgs<V> a{};
+    a.n = g->n;
+    a.nnz = (int32_t)g->nnz;
+    a.G = G;
+    a.nwords = w->nwords;
+    a.row_ptr = g->row_ptr;
+    a.col_idx = g->col_idx;
+    a.deg = (const V *)w->deg;
+    a.R = (V *)w->R;
+    a.X = (V *)w->X;
+    a.NM = w->NM;
+    a.TM = w->TM;
+    a.PB = w->PB;
+    a.act[0] = w->act[0];
+    a.act[1] = w->act[1];
+    a.act_cap = w->act_cap;
+    a.touched = w->touched;
+    a.touch_cap = w->touch_cap;
+    a.wl_node = w->wl_node;
+    a.wl_group = w->wl_group;
+    a.wl_beg = w->wl_beg;
+    a.wl_c = w->wl_c;
+    a.wl_off = w->wl_off;
+    a.wl_lanes = w->wl_lanes;
+    a.wl_sv = (V *)w->wl_sv;
+    a.wl_cap = w->wl_cap;
+    a.tile_start = w->tile_start;
+    a.tile_cap = w->tile_cap;
+    a.lane_eps = (const V *)w->lane_eps;
+    a.wscale = (V)(ppr ? 1.0 - p[0].alpha : p[0].beta);
+    a.w_div_deg = ppr ? 1 : 0;
+    a.lane_ops = w->lane_ops;
+    a.lane_pushes = w->lane_pushes;
+    a.lane_T = w->lane_T;
+    a.lane_l1 = w->lane_l1;
+    a.lane_dinf = w->lane_dinf;
+    a.group_unconv = w->group_unconv;
+    a.tr_size = a.tr_vol = nullptr;
+    a.tr_cap = 0;
+    a.st = w->st;
+    a.max_iters = p[0].max_iters;
+
+    GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns, ppr ? p[0].alpha : 1.0, s));
+    int dev = 0;
+    GDE_HIP(hipGetDevice(&dev));
+    int cus = 0;
+    GDE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ = 0;
+    GDE_HIP(batch_occupancy<V>(L, &occ));
+    int bpc = sc.blocks_per_cu > 0 ? std::min(sc.blocks_per_cu, occ) : occ;
+    if (bpc < 1) return fail(GDE_ERR_DEVICE, "batched kernel does not fit on a compute unit");
+    const int grid = bpc * cus;
+    BatchDev hst{};
+    if ((rc = prof_mark_batch(ctx, s))) return rc;
+    if (sc.persistent) {
+        GDE_HIP(batch_launch<V>(0, L, a, grid, 0, s));
+        if ((rc = prof_mark_batch(ctx, s))) return rc;
+        GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+    } else {
+        int t = 0, chunk = 8;
+        bool done = false;
+        while (t < a.max_iters && !done) {
+            int end = std::min(a.max_iters, t + chunk);
+            for (; t < end; t++) {
+                GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
+                GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
+            }
+            GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
+            GDE_HIP(hipStreamSynchronize(s));
+            done = hst.acount[t & 1] == 0 || hst.ovf[0] || hst.ovf[1];
+            chunk = std::min(chunk * 2, 32);
+        }
+        if ((rc = prof_mark_batch(ctx, s))) return rc;
+        hst.iters_run = t;
+        hst.final_parity = t & 1;
+    }
+    if (hst.ovf[0] || hst.ovf[1]) {
+        // the kernels stopped on a capacity limit: restore the rest state by brute force
+        GDE_HIP(hipMemsetAsync(w->R, 0, (size_t)g->n * GL * w->vs, s));
+        GDE_HIP(hipMemsetAsync(w->X, 0, (size_t)g->n * GL * w->vs, s));
+        GDE_HIP(hipMemsetAsync(w->NM, 0, (size_t)g->n * G * 4, s));
+        GDE_HIP(hipMemsetAsync(w->TM, 0, (size_t)g->n * G * 4, s));
+        GDE_HIP(hipMemsetAsync(w->PB, 0, (size_t)G * w->nwords * 4, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        return fail(GDE_ERR_OOM, "batched work lists exceeded their capacity; split the batch");
+    }
+    // residual norms, unconverged lanes, Katz seed subtraction
+    const bool any_sub = std::any_of(h_flag.begin(), h_flag.end(), [](int32_t f) { return f != 0; });
+    GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, hst.final_parity, w->s_lane, w->s_node,
+                            w->s_val, (int32_t)ns, any_sub ? w->sub_flag : nullptr, s));
+    // extraction: counts per lane, then the sorted sparse outputs
+    GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));
+    std::vector<long long> nnz(GL), off(GL, -1);
+    GDE_HIP(hipMemcpyAsync(nnz.data(), w->lane_nnz, 8 * GL, hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipStreamSynchronize(s));
+    long long total = 0;
+    for (int j = 0; j < B; j++) {
+        const int q = order[j];
+        if (nnz[j] <= res[q].capacity && res[q].idx && res[q].val) {
+            off[j] = total;
+            total += nnz[j];
+        }
+    }
+    if (total > w->out_cap) {
+        if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
+        w->out_idx = nullptr;
+        w->out_val = nullptr;
+        w->out_cap = 0;
+        GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)total));
+        GDE_HIP(hipMalloc(&w->out_val, sizeof(V) * (size_t)total));
+        w->out_cap = total;
+    }
+    GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
+    GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, w->out_idx, (V *)w->out_val,
+                             1, s));
+    for (int j = 0; j < B; j++) {
+        const int q = order[j];
+        if (off[j] < 0 || nnz[j] == 0) continue;
+        const hipMemcpyKind kd = (p[q].flags & GDE_RESULT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        GDE_HIP(hipMemcpyAsync(res[q].idx, w->out_idx + off[j], 4 * (size_t)nnz[j], kd, s));
+        GDE_HIP(hipMemcpyAsync(res[q].val, (V *)w->out_val + off[j], sizeof(V) * (size_t)nnz[j], kd, s));
+    }
+    std::vector<long long> ops(GL * kStatShards), pushes(GL * kStatShards);
+    std::vector<double> l1(GL * kStatShards);
+    std::vector<int32_t> T(GL);
+    std::vector<unsigned long long> dinf(GL);
+    std::vector<uint32_t> unconv(G);
+    GDE_HIP(hipMemcpyAsync(ops.data(), w->lane_ops, 8 * ops.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(pushes.data(), w->lane_pushes, 8 * pushes.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(l1.data(), w->lane_l1, 8 * l1.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(T.data(), w->lane_T, 4 * T.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(dinf.data(), w->lane_dinf, 8 * dinf.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(unconv.data(), w->group_unconv, 4 * unconv.size(), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
+    GDE_HIP(hipStreamSynchronize(s));
+    if ((rc = prof_collect_batch(ctx, hst.lane_edges, hst.entries))) return rc;
+    int first = GDE_OK;
+    for (int j = 0; j < B; j++) {
+        const int q = order[j];
+        gde_result &r = res[q];
+        long long so = 0, sp = 0;
+        double sl = 0.0;
+        for (int sh = 0; sh < kStatShards; sh++) {
+            so += ops[(size_t)j * kStatShards + sh];
+            sp += pushes[(size_t)j * kStatShards + sh];
+            sl += l1[(size_t)j * kStatShards + sh];
+        }
+        r.nnz = nnz[j];
+        r.iters = T[j];
+        r.ops = so;
+        r.pushes = sp;
+        r.residual_l1 = sl;
+        std::memcpy(&r.residual_dinf, &dinf[j], 8);
+        r.trace_len = 0;
+        r.trace_nodes_len = 0;
+        if (off[j] < 0) r.status = GDE_ERR_CAPACITY;
+        else if ((unconv[j / L] >> (j % L)) & 1u) r.status = GDE_ERR_NOT_CONVERGED;
+        else r.status = GDE_OK;
+        if (r.status != GDE_OK && first == GDE_OK) first = r.status;
+    }
+    if (first == GDE_ERR_CAPACITY) return fail(first, "a result capacity was too small (its nnz holds the size needed)");
+    if (first == GDE_ERR_NOT_CONVERGED) return fail(first, "some queries reached max_iters");
+    return GDE_OK;
+}
+
+}  // namespace gde
 
 using namespace gde;
 
@@ -10,29 +389,42 @@ extern "C" {
 
 int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
                     gde_result *res, const char *schedule_json, hipStream_t stream) {
-    (void)schedule_json;
-    if (!ctx || !g || !p || !s || !res || B < 0) return fail(GDE_ERR_INVALID_ARG, "null argument");
-    int first = GDE_OK;
+    if (!ctx || !g || !p || !s || !res || B < 1) return fail(GDE_ERR_INVALID_ARG, "null argument or B < 1");
+    Schedule sc;
+    int rc = parse_schedule(schedule_json, &sc);
+    if (rc) return rc;
+    // validate everything on the host first
     for (int32_t i = 0; i < B; i++) {
-        int rc = gde_solve(ctx, g, &p[i], &s[i], &res[i], stream);
-        res[i].status = rc;
-        if (rc && !first) first = rc;
+        gde_seed one = s[i];
+        gde_params pi = p[i];
+        int v = gde_validate_query(g, &pi, &one);
+        if (v) {
+            for (int32_t j = 0; j < B; j++) res[j].status = j == i ? v : GDE_OK;
+            return v;
+        }
+        if (res[i].capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
     }
-    return first;
+    // the fused kernels need one kind (PPR or Katz), LocalGD, one value type and
+    // shared kind parameters; anything else is solved query by query
+    bool fused = p[0].kind != GDE_HK && p[0].method == GDE_LOCAL_GD;
+    for (int32_t i = 1; i < B && fused; i++) {
+        fused = p[i].kind == p[0].kind && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
+                p[i].alpha == p[0].alpha && p[i].beta == p[0].beta && p[i].max_iters == p[0].max_iters &&
+                (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
+    }
+    for (int32_t i = 0; i < B && fused; i++) fused = !(p[i].flags & GDE_TRACE);
+    GDE_HIP(hipSetDevice(ctx->device));
+    if (!fused) {
+        int first = GDE_OK;
+        for (int32_t i = 0; i < B; i++) {
+            int r = gde_solve(ctx, g, &p[i], &s[i], &res[i], stream);
+            res[i].status = r;
+            if (r && !first) first = r;
+        }
+        return first;
+    }
+    if (p[0].value_type == GDE_F64) return solve_batch_fused<double>(ctx, g, B, p, s, res, sc, stream);
+    return solve_batch_fused<float>(ctx, g, B, p, s, res, sc, stream);
 }
-
-int gde_server_create(gde_ctx *, const gde_graph *, const gde_server_cfg *, gde_server **) {
-    return fail(GDE_ERR_UNSUPPORTED, "server not built");
-}
-int gde_server_submit(gde_server *, const gde_params *, const gde_seed *, uint64_t *) {
-    return fail(GDE_ERR_UNSUPPORTED, "server not built");
-}
-int gde_server_poll(gde_server *, gde_completion *, int32_t, int32_t *) {
-    return fail(GDE_ERR_UNSUPPORTED, "server not built");
-}
-int gde_server_insert_edges(gde_server *, int32_t, const int32_t *, const int32_t *) {
-    return fail(GDE_ERR_UNSUPPORTED, "server not built");
-}
-int gde_server_destroy(gde_server *) { return fail(GDE_ERR_UNSUPPORTED, "server not built"); }
 
 }  // extern "C"

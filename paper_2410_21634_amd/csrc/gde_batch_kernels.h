@@ -1,0 +1,84 @@
+// gde_batch_kernels.h -- device layout and launch interface of the batched solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gde_internal.h"
+
+namespace gde {
+
+constexpr int kStatShards = 64;  // per-lane counters are sharded to spread atomics
+
+struct BatchDev {
+    unsigned long long packed[2];  // (entries << 40) | lane-edges of iteration parity
+    int32_t acount[2];             // active (group, node) pairs
+    int32_t tcount;                // touched pairs
+    int32_t ovf[2];                // a capacity was exceeded during an iteration of this parity
+                                   // (per parity, so the stop test after iteration t reads a
+                                   // flag that no block can still be writing)
+    int32_t iters_run;             // iterations executed by the persistent kernel
+    int32_t final_parity;          // parity of the last (possibly non-empty) active list
+    long long lane_edges;          // sum over iterations of the lane-edges pushed
+    long long entries;             // sum over iterations of the (group, node) entries
+};
+
+// Everything a batch kernel needs.  Node-major layout: the L lanes of group g
+// at node u live at ((u * G + g) * L + l), so all groups' values of a node
+// share pages and each group's L values share a cache line.
+template <typename V>
+struct BatchArgs {
+    int32_t n;
+    int32_t nnz;
+    int32_t G;
+    int64_t nwords;  // pushed-bitmap words per group
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const V *deg;
+    V *R;
+    V *X;
+    uint32_t *NM;  // [n][G] lanes crossing their threshold this iteration
+    uint32_t *TM;  // [n][G] pair touched flag
+    uint32_t *PB;  // [G][nwords] pushed bitmap
+    uint64_t *act[2];
+    int32_t act_cap;
+    uint64_t *touched;
+    int32_t touch_cap;
+    int32_t *wl_node, *wl_group, *wl_beg, *wl_c;
+    long long *wl_off;
+    uint8_t *wl_lanes;
+    V *wl_sv;
+    int32_t wl_cap;
+    int32_t *tile_start;
+    int64_t tile_cap;
+    const V *lane_eps;  // [G*L] eps_eff of each lane
+    V wscale;
+    int w_div_deg;
+    long long *lane_ops, *lane_pushes;  // [G*L][kStatShards]
+    int32_t *lane_T;                    // [G*L]
+    double *lane_l1;                    // [G*L][kStatShards]
+    unsigned long long *lane_dinf;      // [G*L]
+    uint32_t *group_unconv;             // [G]
+    long long *tr_size, *tr_vol;        // optional [G*L][tr_cap]
+    int32_t tr_cap;
+    BatchDev *st;
+    int32_t max_iters;
+};
+
+// which: 0 persistent cooperative launch, 1 snap(t), 2 push(t)
+template <typename V> hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t, hipStream_t s);
+template <typename V> hipError_t batch_occupancy(int L, int *blocks_per_cu);
+template <typename V>
+hipError_t batch_seed(int L, const BatchArgs<V> &a, const int32_t *s_lane, const int32_t *s_node, const double *s_val,
+                      int32_t ns, double bscale, hipStream_t s);
+template <typename V>
+hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, int last, const int32_t *s_lane,
+                        const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,
+                        hipStream_t s);
+template <typename V>
+hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
+                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s);
+template <typename V> hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s);
+
+}  // namespace gde

