@@ -155,6 +155,39 @@ def run_c2(args):
     elapsed = time.perf_counter() - t_start
     prof = ctx.profile(False, reset=True)
 
+    # batched comparison: the same LocalGD queries of one step as one gde_solve_batch call
+    batched = None
+    if not args.no_batch:
+        gd_q = [(eps, s) for m, eps, s in queries if m == "gd"]
+        bparams = [params[("gd", eps)] for eps, _ in gd_q]
+        bseeds = [([s], None) for _, s in gd_q]
+        sched = args.schedule
+        bcap = G.n // 4
+        bout = (torch.empty(len(gd_q) * bcap, dtype=torch.int32, device=dev),
+                torch.empty(len(gd_q) * bcap, dtype=torch.float32, device=dev))
+        for _ in range(max(1, args.warmup)):
+            gde.solve_batch(ctx, g, bparams, bseeds, schedule=sched, out=bout)
+        torch.cuda.synchronize()
+        ctx.profile(True, reset=True)
+        tb = time.perf_counter()
+        for _ in range(args.steps):
+            bres = gde.solve_batch(ctx, g, bparams, bseeds, schedule=sched, out=bout)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb
+        bprof = ctx.profile(False, reset=True)
+        plain_gd = [r for r in recs if r[0] == "gd"]
+        plain_gd_rate = len(plain_gd) / sum(r[3] for r in plain_gd)
+        bops = sum(r.ops for r in bres)
+        bpush = sum(r.pushes for r in bres)
+        batched = dict(queries=len(gd_q), solves_per_s=round(len(gd_q) * args.steps / tb, 2),
+                       ms_per_batch=round(1e3 * tb / args.steps, 3),
+                       plain_solves_per_s_same_queries=round(plain_gd_rate, 2),
+                       speedup_vs_plain=round(len(gd_q) * args.steps / tb / plain_gd_rate, 2),
+                       hbm_gbs_alg=round(alg_bytes(bops, bpush) * args.steps / tb / 1e9, 2),
+                       kernel_ms=round(bprof["batch_ms"] / max(bprof["batch_launches"], 1), 3),
+                       schedule=sched or "default", not_converged=int(sum(r.status != 0 for r in bres)))
+        log(f"batched: {batched}")
+
     nq = len(queries)
     ms_per_step = 1e3 * elapsed / args.steps
     value = nq * args.steps / elapsed
@@ -189,7 +222,7 @@ def run_c2(args):
                     n=G.n, edges=G.nnz // 2, d_max=int(G.degrees.max()), solves_per_step=nq, path="plain"),
         hbm_gbs_alg=round(gbs, 2), hbm_frac_alg=round(gbs / PEAK_HBM_GBS, 5),
         latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 4), p99=round(float(np.percentile(lat, 99)), 4)),
-        per_query=per, roofline=roof)
+        per_query=per, roofline=roof, batched=batched)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline_c2(G, seeds, budget_s=args.cpu_budget)
@@ -206,6 +239,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps(dict(error="this build measures one GPU only; multi-GPU sharding is by query "

@@ -61,6 +61,13 @@ void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
     }
 }
 
+struct DevBuf {  // device scratch released on every return path
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 struct Schedule {
     int lanes = 16;
     int blocks_per_cu = 0;  // 0: the occupancy limit
@@ -254,6 +261,44 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.group_unconv = w->group_unconv;
     a.tr_size = a.tr_vol = nullptr;
     a.tr_cap = 0;
+    a.tr_nodes = nullptr;
+    a.tr_noff = a.tr_ncap = nullptr;
+    a.tr_ncount = nullptr;
+    // optional trace (GDE_TRACE): per-lane |S_t|, vol(S_t) and the S_t lists
+    bool trace = false;
+    int32_t tr_cap = 0;
+    std::vector<long long> h_noff(GL, 0), h_ncap(GL, 0);
+    long long ntot = 0;
+    for (int j = 0; j < B; j++) {
+        const int q = order[j];
+        if (!(p[q].flags & GDE_TRACE)) continue;
+        trace = true;
+        tr_cap = std::max<int32_t>(tr_cap, (int32_t)std::min<int64_t>(res[q].trace_capacity, 1 << 20));
+        if (res[q].trace_nodes && res[q].trace_nodes_capacity > 0) {
+            h_noff[j] = ntot;
+            h_ncap[j] = res[q].trace_nodes_capacity;
+            ntot += res[q].trace_nodes_capacity;
+        }
+    }
+    DevBuf trbuf;
+    if (trace) {
+        tr_cap = std::max(tr_cap, 1);
+        const size_t need = GL * (size_t)tr_cap * 16 + GL * 24 + (size_t)std::max<long long>(ntot, 1) * 4;
+        GDE_HIP(hipMalloc(&trbuf.p, need));
+        GDE_HIP(hipMemsetAsync(trbuf.p, 0, need, s));
+        char *b = (char *)trbuf.p;
+        a.tr_size = (long long *)b;
+        a.tr_vol = a.tr_size + GL * tr_cap;
+        a.tr_cap = tr_cap;
+        long long *noff = a.tr_vol + GL * tr_cap;
+        long long *ncap = noff + GL;
+        a.tr_ncount = (unsigned long long *)(ncap + GL);
+        a.tr_nodes = (int32_t *)(a.tr_ncount + GL);
+        a.tr_noff = noff;
+        a.tr_ncap = ncap;
+        GDE_HIP(hipMemcpyAsync(noff, h_noff.data(), 8 * GL, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(ncap, h_ncap.data(), 8 * GL, hipMemcpyHostToDevice, s));
+    }
     a.st = w->st;
     a.max_iters = p[0].max_iters;
 
@@ -352,6 +397,22 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipStreamSynchronize(s));
     if ((rc = prof_collect_batch(ctx, hst.lane_edges, hst.entries))) return rc;
+    std::vector<unsigned long long> ncount(trace ? GL : 0);
+    if (trace) {
+        GDE_HIP(hipMemcpy(ncount.data(), a.tr_ncount, 8 * GL, hipMemcpyDeviceToHost));
+        for (int j = 0; j < B; j++) {
+            const int q = order[j];
+            if (!(p[q].flags & GDE_TRACE)) continue;
+            const int64_t m = std::min<int64_t>(res[q].trace_capacity, tr_cap);
+            if (m > 0 && res[q].trace_size)
+                GDE_HIP(hipMemcpy(res[q].trace_size, a.tr_size + (size_t)j * tr_cap, 8 * m, hipMemcpyDeviceToHost));
+            if (m > 0 && res[q].trace_vol)
+                GDE_HIP(hipMemcpy(res[q].trace_vol, a.tr_vol + (size_t)j * tr_cap, 8 * m, hipMemcpyDeviceToHost));
+            const int64_t mn = std::min<int64_t>((int64_t)ncount[j], h_ncap[j]);
+            if (mn > 0)
+                GDE_HIP(hipMemcpy(res[q].trace_nodes, a.tr_nodes + h_noff[j], 4 * mn, hipMemcpyDeviceToHost));
+        }
+    }
     int first = GDE_OK;
     for (int j = 0; j < B; j++) {
         const int q = order[j];
@@ -369,8 +430,8 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         r.pushes = sp;
         r.residual_l1 = sl;
         std::memcpy(&r.residual_dinf, &dinf[j], 8);
-        r.trace_len = 0;
-        r.trace_nodes_len = 0;
+        r.trace_len = trace && (p[q].flags & GDE_TRACE) ? T[j] : 0;
+        r.trace_nodes_len = trace && (p[q].flags & GDE_TRACE) ? (int64_t)ncount[j] : 0;
         if (off[j] < 0) r.status = GDE_ERR_CAPACITY;
         else if ((unconv[j / L] >> (j % L)) & 1u) r.status = GDE_ERR_NOT_CONVERGED;
         else r.status = GDE_OK;
@@ -412,7 +473,6 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
                 p[i].alpha == p[0].alpha && p[i].beta == p[0].beta && p[i].max_iters == p[0].max_iters &&
                 (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
     }
-    for (int32_t i = 0; i < B && fused; i++) fused = !(p[i].flags & GDE_TRACE);
     GDE_HIP(hipSetDevice(ctx->device));
     if (!fused) {
         int first = GDE_OK;

@@ -62,6 +62,9 @@ struct BatchArgs {
     uint32_t *group_unconv;             // [G]
     long long *tr_size, *tr_vol;        // optional [G*L][tr_cap]
     int32_t tr_cap;
+    int32_t *tr_nodes;                  // optional S_t lists: lane l writes at tr_noff[l] + k, k < tr_ncap[l]
+    const long long *tr_noff, *tr_ncap;
+    unsigned long long *tr_ncount;      // [G*L] entries recorded (may exceed the capacity)
     BatchDev *st;
     int32_t max_iters;
 };

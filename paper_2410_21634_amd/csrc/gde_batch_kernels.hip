@@ -153,6 +153,11 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                         atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);
                         atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)deg);
                     }
+                    if (a.tr_nodes) {
+                        // positions grow across iterations, so each S_t is one contiguous run
+                        const unsigned long long k2 = atomicAdd(&a.tr_ncount[lane_id], 1ull);
+                        if ((long long)k2 < a.tr_ncap[lane_id]) a.tr_nodes[a.tr_noff[lane_id] + (long long)k2] = u;
+                    }
                 }
             }
         }

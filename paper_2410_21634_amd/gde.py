@@ -311,23 +311,34 @@ def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *
 
 
 def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None, schedule=None, stream=None,
-                raise_on_error=True):
-    """B queries in one call.  ``seeds``: list of (idx, val) pairs.  Returns a list of SolveResult."""
+                raise_on_error=True, trace_cap=4096, nodes_cap=0, out=None):
+    """B queries in one call.  ``seeds``: list of (idx, val) pairs.  ``out``: optional
+    flat (idx, val) torch device tensors split evenly between the queries (the
+    results stay in HBM).  Returns a list of SolveResult."""
     B = len(params_list)
     P = (Params * B)(*[Params.from_buffer_copy(p) for p in params_list])
+    if out is not None:
+        for p in P:
+            p.flags |= RESULT_DEVICE
     holders = [_SeedHolder(i, v) for i, v in seeds]
     S = (Seed * B)(*[h.seed for h in holders])
     R = (Result * B)()
     bufs = []
-    for i, p in enumerate(params_list):
-        vdt = np.float64 if p.value_type == F64 else np.float32
-        cap = graph.n if capacity is None else capacity
-        oi = np.zeros(max(cap, 1), np.int32)
-        ov = np.zeros(max(cap, 1), vdt)
-        R[i].capacity = cap
-        R[i].idx = oi.ctypes.data
-        R[i].val = ov.ctypes.data
+    keeps = []
+    for i, p in enumerate(P):
+        if out is not None:
+            cap = out[0].numel() // B if capacity is None else capacity
+            oi, ov = out[0][i * cap:(i + 1) * cap], out[1][i * cap:(i + 1) * cap]
+            r, keep = _result_struct(p, cap, oi.data_ptr(), ov.data_ptr(), trace_cap, nodes_cap)
+        else:
+            vdt = np.float64 if p.value_type == F64 else np.float32
+            cap = graph.n if capacity is None else capacity
+            oi = np.zeros(max(cap, 1), np.int32)
+            ov = np.zeros(max(cap, 1), vdt)
+            r, keep = _result_struct(p, cap, oi.ctypes.data, ov.ctypes.data, trace_cap, nodes_cap)
+        R[i] = r
         bufs.append((oi, ov))
+        keeps.append(keep)
     sched = schedule.encode() if isinstance(schedule, str) else schedule
     rc = _lib.gde_solve_batch(ctx.handle, graph.handle, B, P, S, R, sched, _stream_ptr(stream))
     if raise_on_error:
@@ -336,6 +347,14 @@ def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None
     for i in range(B):
         r = R[i]
         nnz = int(r.nnz) if r.status in (OK, NOT_CONVERGED) else 0
-        out.append(SolveResult(bufs[i][0][:nnz], bufs[i][1][:nnz], r.status, r.residual_l1, r.residual_dinf,
-                               r.iters, r.ops, r.pushes))
+        sr = SolveResult(bufs[i][0][:nnz], bufs[i][1][:nnz], r.status, r.residual_l1, r.residual_dinf, r.iters,
+                         r.ops, r.pushes)
+        sr.extra["nnz_needed"] = int(r.nnz)
+        if params_list[i].flags & TRACE:
+            m = min(int(r.trace_len), trace_cap)
+            sr.trace_size = keeps[i][0][:m].copy()
+            sr.trace_vol = keeps[i][1][:m].copy()
+            if nodes_cap:
+                sr.trace_nodes = keeps[i][2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
+        out.append(sr)
     return out

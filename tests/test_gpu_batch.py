@@ -13,6 +13,8 @@ from oracle import exact as X  # noqa: E402
 from oracle import solvers as O  # noqa: E402
 from paper_2410_21634_amd import workloads as W  # noqa: E402
 
+from _parity import KAPPA, oracle_replay  # noqa: E402
+
 TOL = {1: 1e-12, 0: 1e-6}
 
 
@@ -52,24 +54,41 @@ def make_queries(G, B, seed=0):
 
 
 def run_and_check(gde, ctx, g, G, queries, kind, vt, schedule, param, lam=0.0):
+    """P1 when the lane's integer trace equals the oracle's; otherwise (an FP32
+    value within rounding of its threshold) P2: replay of the lane's recorded S_t."""
     params = []
     for idx, val, eps in queries:
         if kind == gde.PPR:
-            params.append(gde.make_params("ppr", alpha=param, eps=eps, value_type=vt))
+            params.append(gde.make_params("ppr", alpha=param, eps=eps, value_type=vt, flags=gde.TRACE))
         else:
-            params.append(gde.make_params("katz", beta=param, eps=eps, lambda_bound=lam, value_type=vt))
-    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], schedule=schedule)
-    worst = 0.0
+            params.append(gde.make_params("katz", beta=param, eps=eps, lambda_bound=lam, value_type=vt,
+                                          flags=gde.TRACE))
+    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], schedule=schedule, trace_cap=100000,
+                          nodes_cap=60 * G.n)
+    worst, replays = 0.0, 0
+    prm = dict(alpha=param) if kind == gde.PPR else dict(beta=param, lambda_bound=lam)
     for (idx, val, eps), r in zip(queries, out):
-        ref = O.localgd(G.row_ptr, G.col_idx, kind, param, eps, idx, val)
+        ref = O.localgd(G.row_ptr, G.col_idx, kind, param, eps, idx, val, trace_cap=100000)
         assert r.status == gde.OK
-        assert (r.iters, r.ops, r.pushes) == (ref["iters"], ref["ops"], ref["pushes"]), (eps, r.iters, ref["iters"])
         assert np.all(np.diff(r.idx) > 0)
-        err = np.abs(r.dense(G.n) - ref["x"]).sum() / val.sum()
-        assert err <= TOL[vt], (eps, err)
-        np.testing.assert_allclose(r.residual_l1, ref["residual_l1"], rtol=1e-5 if vt == 0 else 1e-10)
-        np.testing.assert_allclose(r.residual_dinf, ref["residual_dinf"], rtol=1e-5 if vt == 0 else 1e-10)
+        assert len(r.trace_nodes) == r.pushes
+        same = ((r.iters, r.ops, r.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+                and np.array_equal(r.trace_size, ref["trace_size"]) and np.array_equal(r.trace_vol, ref["trace_vol"]))
+        if vt == 1:
+            assert same, (eps, r.iters, ref["iters"])
+        if same:
+            err = np.abs(r.dense(G.n) - ref["x"]).sum() / val.sum()
+            np.testing.assert_allclose(r.residual_l1, ref["residual_l1"], rtol=1e-5 if vt == 0 else 1e-10)
+            np.testing.assert_allclose(r.residual_dinf, ref["residual_dinf"], rtol=1e-5 if vt == 0 else 1e-10)
+        else:
+            rp = oracle_replay(G, kind, gde.LOCAL_GD, dict(prm, eps=eps), idx, val, r.trace_size, r.trace_nodes,
+                               KAPPA[vt])
+            assert rp["violations"] == 0, rp
+            err = np.abs(r.dense(G.n) - rp["x"]).sum() / val.sum()
+            replays += 1
+        assert err <= TOL[vt], (eps, err, same)
         worst = max(worst, err)
+    print("replays", replays, flush=True)
     return worst
 
 
@@ -120,10 +139,17 @@ def test_batch_status_paths(gde, ctx, c1):
     G, g = c1
     queries = make_queries(G, 20, seed=4)
     params = [gde.make_params("ppr", alpha=0.1, eps=q[2], value_type=gde.F64) for q in queries]
-    # tiny capacity: CAPACITY for the queries that do not fit, the rest still valid
-    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], capacity=50, raise_on_error=False)
+    # a capacity between the sizes: CAPACITY (with the size needed) for the queries
+    # that do not fit, the others still valid
+    full = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries])
+    sizes = np.array([len(r.idx) for r in full])
+    cap = int(np.median(sizes))
+    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], capacity=cap, raise_on_error=False)
     caps = [r.status for r in out]
     assert gde.CAPACITY in caps and gde.OK in caps
+    for r, sz in zip(out, sizes):
+        assert r.status == (gde.OK if sz <= cap else gde.CAPACITY)
+        assert r.extra["nnz_needed"] == sz
     for (idx, val, eps), r in zip(queries, out):
         if r.status == gde.OK:
             ref = O.localgd(G.row_ptr, G.col_idx, O.PPR, 0.1, eps, idx, val)
