@@ -141,23 +141,33 @@ def run_c2(args):
             if record is not None:
                 record.append((m, eps, s, time.perf_counter() - t, r.iters, r.ops, r.pushes, r.status))
 
-    for i in range(args.warmup):
+    if args.phase == "batch":  # profiling aid: only the batched call below
+        queries_run = [q for q in queries if q[0] == "gd"][:1]
+    else:
+        queries_run = queries
+    for i in range(args.warmup if args.phase != "batch" else 0):
         step()
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True, reset=True)
     recs = []
     t_start = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(args.steps if args.phase != "batch" else 0):
         step(recs)
         log(f"timed step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = ctx.profile(False, reset=True)
+    if args.phase == "batch":
+        for m, eps, s in queries_run:
+            t = time.perf_counter()
+            r = gde.solve(ctx, g, params[(m, eps)], [s], out=(oi, ov))
+            recs.append((m, eps, s, time.perf_counter() - t, r.iters, r.ops, r.pushes, r.status))
+        elapsed = max(elapsed, 1e-9)
 
     # batched comparison: the same LocalGD queries of one step as one gde_solve_batch call
     batched = None
-    if not args.no_batch:
+    if not args.no_batch and args.phase != "plain":
         gd_q = [(eps, s) for m, eps, s in queries if m == "gd"]
         bparams = [params[("gd", eps)] for eps, _ in gd_q]
         bseeds = [([s], None) for _, s in gd_q]
@@ -240,6 +250,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--phase", default="all", choices=["all", "plain", "batch"],
+                    help="profiling aid: run only one path (the JSON line then covers that path only)")
     ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
     args = ap.parse_args()
     if args.gpus != 1:

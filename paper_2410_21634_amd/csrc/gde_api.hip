@@ -96,9 +96,25 @@ static int validate_seed(const gde_seed *s, int32_t n, const int32_t *rp_host) {
     return GDE_OK;
 }
 
+static int validate_seed_deg(const gde_seed *s, int32_t n, const std::vector<int32_t> &deg) {
+    if (!s || s->nnz <= 0 || !s->idx || !s->val) return fail(GDE_ERR_INVALID_ARG, "seed must have nnz > 0 entries");
+    if (s->nnz > n) return fail(GDE_ERR_INVALID_ARG, "seed has more entries than nodes");
+    for (int32_t i = 0; i < s->nnz; i++) {
+        int32_t u = s->idx[i];
+        if (u < 0 || u >= n) return fail(GDE_ERR_INVALID_ARG, "seed index out of range");
+        if (i > 0 && u <= s->idx[i - 1]) return fail(GDE_ERR_INVALID_ARG, "seed indices must be strictly increasing");
+        if (!(s->val[i] > 0.0) || !std::isfinite(s->val[i]))
+            return fail(GDE_ERR_INVALID_ARG, "seed values must be finite and > 0");
+    }
+    for (int32_t i = 0; i < s->nnz; i++)
+        if (deg[s->idx[i]] == 0) return fail(GDE_ERR_ISOLATED_SEED, "seed node has degree 0");
+    return GDE_OK;
+}
+
 // ------------------------------------------------------------------ workspaces
 struct GraphHost {
-    std::vector<int32_t> row_ptr;  // host copy of the row pointers (seed validation)
+    std::vector<int32_t> row_ptr;  // host copy of the row pointers at creation
+    std::vector<int32_t> deg;      // current degrees (seed validation); updated on edge insertions
 };
 static std::mutex g_graph_mu;
 static std::vector<std::pair<const gde_graph *, GraphHost *>> g_graph_host;
@@ -315,7 +331,54 @@ int gde_validate_query(const gde_graph *g, const gde_params *p, const gde_seed *
     if (rc) return rc;
     GraphHost *gh = graph_host(g);
     if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");
-    return validate_seed(s, g->n, gh->row_ptr.data());
+    return validate_seed_deg(s, g->n, gh->deg);
+}
+
+static void register_graph(gde_graph *g, GraphHost *gh) {
+    gh->deg.resize(g->n);
+    for (int32_t u = 0; u < g->n; u++) gh->deg[u] = gh->row_ptr[u + 1] - gh->row_ptr[u];
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graph_host.emplace_back(g, gh);
+}
+
+// a graph over device CSR arrays that the library takes ownership of (the server's private copy)
+gde_graph *graph_wrap_device(gde_ctx *ctx, int32_t n, int64_t nnz, int32_t *rp, int32_t *ci) {
+    gde_graph *g = new gde_graph();
+    g->device = ctx->device;
+    g->n = n;
+    g->nnz = nnz;
+    g->row_ptr = rp;
+    g->col_idx = ci;
+    g->owned = true;
+    g->uid = g_uid++;
+    GraphHost *gh = new GraphHost();
+    gh->row_ptr.resize((size_t)n + 1);
+    (void)hipMemcpy(gh->row_ptr.data(), rp, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost);
+    register_graph(g, gh);
+    return g;
+}
+
+// swap in a rebuilt CSR (owned); degrees of the host copy grow by `inc` (directed sources)
+int graph_replace_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std::vector<int32_t> &inc) {
+    if (g->owned) {
+        (void)hipFree(g->row_ptr);
+        (void)hipFree(g->col_idx);
+    }
+    g->row_ptr = rp;
+    g->col_idx = ci;
+    g->nnz = nnz;
+    g->owned = true;
+    GraphHost *gh = graph_host(g);
+    if (gh)
+        for (int32_t u : inc) gh->deg[u]++;
+    return GDE_OK;
+}
+
+void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx) {
+    for (size_t i = 0; i < ctx->ws.size();) {
+        if (ctx->ws[i]->guid == g->uid) { ws_free(ctx->ws[i]); ctx->ws.erase(ctx->ws.begin() + i); }
+        else i++;
+    }
 }
 
 // ------------------------------------------------------------------ the plain solver
@@ -691,10 +754,7 @@ int gde_graph_create(gde_ctx *ctx, int32_t n, int64_t nnz, const int32_t *row_pt
         return fail(GDE_ERR_INVALID_ARG, "malformed CSR (row_ptr order, col_idx range or self-loop)");
     }
     g->d_max = hc[1];
-    {
-        std::lock_guard<std::mutex> lk(g_graph_mu);
-        g_graph_host.emplace_back(g, gh);
-    }
+    register_graph(g, gh);
     *out = g;
     return GDE_OK;
 }
@@ -762,7 +822,7 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
     if (rc) { res->status = rc; return rc; }
     GraphHost *gh = graph_host(g);
     if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");
-    if ((rc = validate_seed(s, g->n, gh->row_ptr.data()))) { res->status = rc; return rc; }
+    if ((rc = validate_seed_deg(s, g->n, gh->deg))) { res->status = rc; return rc; }
     if (res->capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
     if (g->device != ctx->device) return fail(GDE_ERR_INVALID_ARG, "graph and context on different devices");
     GDE_HIP(hipSetDevice(ctx->device));

@@ -12,6 +12,9 @@ int prof_mark(gde_ctx *ctx, hipStream_t s);
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries);
 int prof_mark_batch(gde_ctx *ctx, hipStream_t s);
 int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries);
+struct BatchWS;
+void batch_ws_extract_buffers(BatchWS *w, int32_t **cnt, long long **lane_nnz, long long **lane_off);
+void batch_ws_swap_list(BatchWS *w, int which, uint64_t **spare);
 // host validation of one query against a graph (parameters, seed, isolated seeds)
 int gde_validate_query(const gde_graph *g, const gde_params *p, const gde_seed *s);
 }  // namespace gde

@@ -168,6 +168,65 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     return GDE_OK;
 }
 
+// ---- access for the server (gde_server.hip)
+int batch_ws_acquire(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int G, hipStream_t s, BatchWS **out) {
+    return batch_ws_get(ctx, g, vtype, L, G, s, out);
+}
+
+void batch_args_from_ws(BatchWS *w, const gde_graph *g, int G, BatchArgs<float> *a) {
+    *a = BatchArgs<float>{};
+    a->n = g->n;
+    a->nnz = (int32_t)g->nnz;
+    a->G = G;
+    a->nwords = w->nwords;
+    a->row_ptr = g->row_ptr;
+    a->col_idx = g->col_idx;
+    a->deg = (const float *)w->deg;
+    a->R = (float *)w->R;
+    a->X = (float *)w->X;
+    a->NM = w->NM;
+    a->TM = w->TM;
+    a->PB = w->PB;
+    a->act[0] = w->act[0];
+    a->act[1] = w->act[1];
+    a->act_cap = w->act_cap;
+    a->touched = w->touched;
+    a->touch_cap = w->touch_cap;
+    a->wl_node = w->wl_node;
+    a->wl_group = w->wl_group;
+    a->wl_beg = w->wl_beg;
+    a->wl_c = w->wl_c;
+    a->wl_off = w->wl_off;
+    a->wl_lanes = w->wl_lanes;
+    a->wl_sv = (float *)w->wl_sv;
+    a->wl_cap = w->wl_cap;
+    a->tile_start = w->tile_start;
+    a->tile_cap = w->tile_cap;
+    a->lane_eps = (const float *)w->lane_eps;
+    a->lane_ops = w->lane_ops;
+    a->lane_pushes = w->lane_pushes;
+    a->lane_T = w->lane_T;
+    a->lane_l1 = w->lane_l1;
+    a->lane_dinf = w->lane_dinf;
+    a->group_unconv = w->group_unconv;
+    a->st = w->st;
+}
+
+int32_t *batch_ws_touch_count(BatchWS *w) { return &w->st->tcount; }
+
+void batch_ws_extract_buffers(BatchWS *w, int32_t **cnt, long long **lane_nnz, long long **lane_off) {
+    *cnt = w->cnt;
+    *lane_nnz = w->lane_nnz;
+    *lane_off = w->lane_out_off;
+}
+
+// exchange one of the two active lists (or the touched list, which = 2) with a
+// buffer of the same capacity: compaction writes into the spare and swaps it in
+void batch_ws_swap_list(BatchWS *w, int which, uint64_t **spare) {
+    uint64_t **slot = which == 2 ? &w->touched : &w->act[which];
+    std::swap(*slot, *spare);
+}
+
 template <typename V>
 static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *sd,
                              gde_result *res, const Schedule &sc, hipStream_t s) {

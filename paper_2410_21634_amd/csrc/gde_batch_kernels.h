@@ -55,6 +55,11 @@ struct BatchArgs {
     const V *lane_eps;  // [G*L] eps_eff of each lane
     V wscale;
     int w_div_deg;
+    // optional per-group overrides (serving mixes PPR and Katz groups in one launch):
+    // g_wscale[g] replaces wscale; g_mode[g] bit 0 = divide by d_u (PPR), bit 1 =
+    // candidate mode (signed residuals: every touched lane is re-tested in the snapshot)
+    const V *g_wscale;
+    const int32_t *g_mode;
     long long *lane_ops, *lane_pushes;  // [G*L][kStatShards]
     int32_t *lane_T;                    // [G*L]
     double *lane_l1;                    // [G*L][kStatShards]
@@ -79,9 +84,11 @@ template <typename V>
 hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, int last, const int32_t *s_lane,
                         const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,
                         hipStream_t s);
+// gmap (optional): the ngroups groups to extract (all a.G groups when null)
 template <typename V>
 hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
-                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s);
+                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s,
+                         const int32_t *gmap = nullptr, int ngroups = 0);
 template <typename V> hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s);
 
 }  // namespace gde

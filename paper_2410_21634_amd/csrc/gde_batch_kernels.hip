@@ -90,30 +90,41 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         uint32_t m = 0u;
         V v = (V)0;
         bool mine = false;
+        int mode = 0;
+        size_t ri = 0;
         if (valid) {
             const uint64_t p = a.act[cur][i];
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
             m = a.NM[(size_t)u * a.G + g];
-            mine = (m >> l) & 1u;
+            mode = a.g_mode ? a.g_mode[g] : (a.w_div_deg ? 1 : 0);
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
+            ri = ((size_t)u * a.G + g) * L + l;
+            mine = (m >> l) & 1u;
+            if (mine && (mode & 2)) {  // candidate mode: the threshold decides
+                const V r = a.R[ri];
+                mine = r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg;
+            }
             if (mine) {
-                const size_t ri = ((size_t)u * a.G + g) * L + l;
                 v = a.R[ri];
                 a.R[ri] = (V)0;
                 a.X[ri] += v;
             }
         }
+        // the pair's active lanes, from the wave ballot
+        const unsigned long long bal = __ballot(mine);
+        const uint32_t pm = (uint32_t)((bal >> (sub * L)) & ((L == 32) ? 0xffffffffull : ((1ull << L) - 1ull)));
+        const int c = __popc(pm);
         // the whole wave has read its masks: the pair leaders clear them
         if (valid && l == 0) {
             a.NM[(size_t)u * a.G + g] = 0u;
-            atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
+            if (c > 0) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
         }
-        const int c = __popc(m);
-        const long long le = (valid && l == 0) ? (long long)deg * c : 0ll;
+        const bool leader = valid && l == 0 && c > 0;
+        const long long le = leader ? (long long)deg * c : 0ll;
         const long long incl = bwave_incl_scan64(le);
-        const unsigned long long lead = __ballot(valid && l == 0);
+        const unsigned long long lead = __ballot(leader);
         const int cnt = (int)__popcll(lead);
         const long long tot = __shfl(incl, kWave - 1);
         unsigned long long res = 0ull;
@@ -123,7 +134,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         int slot = (int)(res >> 40) + (int)__popcll(lead & ((1ull << blane()) - 1ull));
         const long long off = (long long)(res & kLaneEdgeMask) + incl - le;
         slot = __shfl(slot, sub * L);  // the pair's slot, from its leader
-        if (valid) {
+        if (valid && c > 0) {
             if (slot >= a.wl_cap) {
                 *ovf = 1;
             } else {
@@ -140,8 +151,9 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                     }
                 }
                 if (mine) {
-                    const int k = __popc(m & ((1u << l) - 1u));
-                    const V w = a.w_div_deg ? a.wscale / (V)deg : a.wscale;
+                    const int k = __popc(pm & ((1u << l) - 1u));
+                    const V ws = a.g_wscale ? a.g_wscale[g] : a.wscale;
+                    const V w = (mode & 1) ? ws / (V)deg : ws;
                     a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
                     a.wl_sv[(size_t)slot * L + k] = w * v;
                     const int lane_id = g * L + l;
@@ -227,7 +239,8 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                         const V old = unsafeAtomicAdd(&a.R[ri], dv);
                         const V nw = old + dv;
                         const V th = a.lane_eps[g * L + l] * a.deg[w];
-                        hit = (old < th) && (nw >= th);
+                        const bool cand = a.g_mode && (a.g_mode[g] & 2);
+                        hit = cand || ((old < th) && (nw >= th));
                         first = old == (V)0;
                         bit = 1u << l;
                     } else {
@@ -355,9 +368,10 @@ __global__ void k_batch_subtract_seed(BatchArgs<V> a, const int32_t *__restrict_
 // Extraction, per group: the pushed bitmap gives the nodes in ascending order;
 // lane l's support is {u : X[g][u][l] != 0}.  count -> scan -> emit.
 template <typename V, int L>
-__global__ void __launch_bounds__(kBlock) k_batch_ex_count(BatchArgs<V> a, int32_t *cnt, int nblk) {
+__global__ void __launch_bounds__(kBlock) k_batch_ex_count(BatchArgs<V> a, int32_t *cnt, int nblk,
+                                                            const int32_t *__restrict__ gmap) {
     __shared__ int s[L];
-    const int g = blockIdx.y;
+    const int g = gmap ? gmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (threadIdx.x < L) s[threadIdx.x] = 0;
     __syncthreads();
@@ -383,10 +397,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_ex_count(BatchArgs<V> a, int32
 }
 
 // one block per lane: exclusive scan over its blocks' counts, total into lane_nnz
-__global__ void __launch_bounds__(256) k_batch_ex_scan(int32_t *cnt, int nblk, long long *lane_nnz) {
+__global__ void __launch_bounds__(256) k_batch_ex_scan(int32_t *cnt, int nblk, long long *lane_nnz, int L,
+                                                       const int32_t *__restrict__ gmap) {
     __shared__ int s[256];
     __shared__ long long carry;
-    int32_t *c = cnt + (size_t)blockIdx.x * nblk;
+    const int lane_id = gmap ? gmap[blockIdx.x / L] * L + (int)(blockIdx.x % L) : (int)blockIdx.x;
+    int32_t *c = cnt + (size_t)lane_id * nblk;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base < nblk; base += 256) {
@@ -405,15 +421,16 @@ __global__ void __launch_bounds__(256) k_batch_ex_scan(int32_t *cnt, int nblk, l
         if (threadIdx.x == 255) carry += s[255];
         __syncthreads();
     }
-    if (threadIdx.x == 0) lane_nnz[blockIdx.x] = carry;
+    if (threadIdx.x == 0) lane_nnz[lane_id] = carry;
 }
 
 template <typename V, int L>
 __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const int32_t *__restrict__ cnt, int nblk,
                                                            const long long *__restrict__ lane_out_off,
-                                                           int32_t *out_idx, V *out_val, int write) {
+                                                           int32_t *out_idx, V *out_val, int write,
+                                                           const int32_t *__restrict__ gmap) {
     __shared__ int s[L][kBlock];
-    const int g = blockIdx.y;
+    const int g = gmap ? gmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t word = wi < a.nwords ? a.PB[(size_t)g * a.nwords + wi] : 0u;
     int my[L];
@@ -547,17 +564,21 @@ hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, i
 
 template <typename V>
 hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
-                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s) {
-    dim3 grid((unsigned)nblk, (unsigned)a.G);
+                         const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s,
+                         const int32_t *gmap, int ngroups) {
+    const int ng = gmap ? ngroups : a.G;
+    if (ng <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblk, (unsigned)ng);
     switch (L) {
 #define GDE_BE(LL)                                                                                                  \
     case LL:                                                                                                        \
         if (stage == 0) {                                                                                           \
-            hipLaunchKernelGGL((k_batch_ex_count<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk);                  \
-            hipLaunchKernelGGL(k_batch_ex_scan, dim3((unsigned)(a.G * LL)), dim3(256), 0, s, cnt, nblk, lane_nnz);  \
+            hipLaunchKernelGGL((k_batch_ex_count<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk, gmap);            \
+            hipLaunchKernelGGL(k_batch_ex_scan, dim3((unsigned)(ng * LL)), dim3(256), 0, s, cnt, nblk, lane_nnz, LL,  \
+                               gmap);                                                                               \
         } else {                                                                                                    \
             hipLaunchKernelGGL((k_batch_ex_emit<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk, lane_out_off,      \
-                               out_idx, out_val, write);                                                            \
+                               out_idx, out_val, write, gmap);                                                      \
         }                                                                                                           \
         break;
         GDE_BE(8)
@@ -584,7 +605,8 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
     template hipError_t batch_finish<V>(int, const BatchArgs<V> &, int, double, int, const int32_t *,              \
                                         const int32_t *, const double *, int32_t, const int32_t *, hipStream_t);   \
     template hipError_t batch_extract<V>(int, const BatchArgs<V> &, int, int32_t *, int, long long *,              \
-                                         const long long *, int32_t *, V *, int, hipStream_t);                     \
+                                         const long long *, int32_t *, V *, int, hipStream_t, const int32_t *,     \
+                                         int);                                                                     \
     template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);
 
 GDE_BINST(float)

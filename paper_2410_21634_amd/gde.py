@@ -358,3 +358,54 @@ def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None
                 sr.trace_nodes = keeps[i][2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
         out.append(sr)
     return out
+
+
+class Server:
+    """Continuous-batching server (gde_server_*): submit queries, insert edges,
+    poll completions.  Each completion is returned as a dict with its sparse x."""
+
+    def __init__(self, ctx: Context, graph: Graph, lanes_per_group=16, max_groups=8, iters_per_step=4,
+                 queue_capacity=1 << 20, result_capacity=None, max_insert_edges=0):
+        cfg = ServerCfg(int(lanes_per_group), int(max_groups), int(iters_per_step), int(queue_capacity), F32,
+                        int(result_capacity if result_capacity is not None else graph.n), int(max_insert_edges))
+        h = _vp()
+        _check(_lib.gde_server_create(ctx.handle, graph.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self._buf = (Completion * 4096)()
+
+    def submit(self, params: Params, seed_idx, seed_val=None) -> int:
+        sh = _SeedHolder(seed_idx, seed_val)
+        t = C.c_uint64()
+        _check(_lib.gde_server_submit(self.handle, C.byref(params), C.byref(sh.seed), C.byref(t)))
+        return int(t.value)
+
+    def insert_edges(self, u, v):
+        u = np.ascontiguousarray(u, dtype=np.int32)
+        v = np.ascontiguousarray(v, dtype=np.int32)
+        _check(_lib.gde_server_insert_edges(self.handle, len(u), u.ctypes.data_as(_vp), v.ctypes.data_as(_vp)))
+
+    def poll(self) -> list:
+        n = C.c_int32()
+        _check(_lib.gde_server_poll(self.handle, self._buf, len(self._buf), C.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = self._buf[i]
+            k = int(c.nnz)
+            idx = np.ctypeslib.as_array(c.idx, shape=(k,)).copy() if k else np.zeros(0, np.int32)
+            val = np.ctypeslib.as_array(c.val, shape=(k,)).copy() if k else np.zeros(0, np.float32)
+            out.append(dict(ticket=int(c.ticket), status=int(c.status), iters=int(c.iters), idx=idx, val=val,
+                            residual_l1=c.residual_l1, residual_dinf=c.residual_dinf,
+                            submit_time_s=c.submit_time_s, done_time_s=c.done_time_s))
+        return out
+
+    def close(self):
+        if self.handle:
+            _lib.gde_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

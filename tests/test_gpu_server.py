@@ -1,0 +1,183 @@
+"""The continuous-batching server: mixed PPR / Katz / HK queries arriving while
+others run, and edge insertions applied to in-flight queries.
+
+A static-graph result must be the same alone and inside the mix (within the
+FP32 tolerance 1e-6 ||s||_1, or, if an FP32 threshold decision flipped, both
+must satisfy the stop certificate), and must agree with the FP64 oracle.  A
+result that lived through edge insertions is checked against the *new* graph:
+r = b - Q_new x recomputed in FP64 on the host satisfies the stop rule, and
+|f_new - x| <= eps d_new componentwise (the Theorem 3.2 bound, which holds for
+signed residuals as well).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import exact as X  # noqa: E402
+from oracle import solvers as O  # noqa: E402
+from paper_2410_21634_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def gde():
+    from paper_2410_21634_amd import gde as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(gde):
+    c = gde.Context(0)
+    yield c
+    c.close()
+
+
+def ppr_certificate(row_ptr, col_idx, alpha, eps, seed_idx, seed_val, x, kappa=1e-4):
+    """FP64 residual of x on the given graph and the stop test max |r~_u| / (eps d_u) < 1 + kappa."""
+    n = len(row_ptr) - 1
+    d = np.diff(row_ptr).astype(float)
+    A = X.sparse_adjacency(row_ptr, col_idx)
+    s = np.zeros(n)
+    s[np.asarray(seed_idx)] = seed_val
+    inv = np.where(d > 0, 1.0 / np.maximum(d, 1), 0.0)
+    r = alpha * s - (x - (1 - alpha) * (A @ (inv * x)))
+    rt = r / alpha
+    ratio = np.abs(rt[d > 0]) / (eps * d[d > 0])
+    return float(ratio.max()), r
+
+
+def drain(srv, want, limit=20000):
+    got = {}
+    for _ in range(limit):
+        for c in srv.poll():
+            got[c["ticket"]] = c
+        if len(got) >= want:
+            break
+    return got
+
+
+def test_server_static_mix(gde, ctx):
+    G = W.chung_lu(10000, 50000, 2.5, seed=42)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    lo, hi = g.lambda_max(max_iters=500, rtol=1e-4)
+    beta = 0.5 / lo
+    rng = np.random.default_rng(5)
+    seeds = W.uniform_seeds(G, 48, seed=5)
+    qs = []
+    for i, s in enumerate(seeds):
+        eps = float(10 ** rng.uniform(-6, -4))
+        kind = ("ppr", "katz", "hk")[i % 3]
+        if i % 4 == 1:
+            idx, val = W.seed_set(G, int(s), 8, rng)
+        else:
+            idx, val = np.array([s], np.int32), np.ones(1)
+        if kind == "ppr":
+            p = gde.make_params("ppr", alpha=0.1, eps=eps)
+        elif kind == "katz":
+            p = gde.make_params("katz", beta=beta, eps=eps, lambda_bound=hi)
+        else:
+            p = gde.make_params("hk", tau=5.0, K=30, eps=eps)
+        qs.append((kind, p, idx, val, eps))
+    srv = gde.Server(ctx, g, lanes_per_group=8, max_groups=3, iters_per_step=3)
+    tickets = {}
+    # staggered arrivals: a third now, the rest while the first groups run
+    for j, q in enumerate(qs[:16]):
+        tickets[srv.submit(q[1], q[2], q[3])] = j
+    got = {}
+    for c in srv.poll():
+        got[c["ticket"]] = c
+    for j, q in enumerate(qs[16:], start=16):
+        tickets[srv.submit(q[1], q[2], q[3])] = j
+    got.update(drain(srv, len(qs)))
+    assert len(got) == len(qs)
+    mix = {tickets[t]: c for t, c in got.items()}
+    srv.close()
+    # each query alone on a fresh server, and against the FP64 oracle
+    srv1 = gde.Server(ctx, g, lanes_per_group=8, max_groups=1, iters_per_step=3)
+    for j, (kind, p, idx, val, eps) in enumerate(qs):
+        t = srv1.submit(p, idx, val)
+        alone = drain(srv1, 1)[t]
+        m = mix[j]
+        assert m["status"] == gde.OK and alone["status"] == gde.OK
+        xm = np.zeros(G.n)
+        xm[m["idx"]] = m["val"]
+        xa = np.zeros(G.n)
+        xa[alone["idx"]] = alone["val"]
+        if kind == "ppr":
+            ref = O.localgd(G.row_ptr, G.col_idx, O.PPR, 0.1, eps, idx, val)["x"]
+        elif kind == "katz":
+            ref = O.localgd(G.row_ptr, G.col_idx, O.KATZ, beta, eps, idx, val)["x"]
+        else:
+            ref = O.hk(G.row_ptr, G.col_idx, 5.0, 30, eps, idx, val)["x"]
+        s1 = val.sum()
+        d_mix_alone = np.abs(xm - xa).sum() / s1
+        d_oracle = np.abs(xm - ref).sum() / s1
+        if kind == "ppr" and (d_mix_alone > 1e-6 or d_oracle > 1e-6):
+            # an FP32 threshold flip: both answers must still meet the Theorem 3.2
+            # bound |f - x| <= eps d (x holds FP32 rounding, hence the small slack)
+            svec = np.zeros(G.n)
+            svec[idx] = val
+            f = X.global_ppr(G.row_ptr, G.col_idx, 0.1, svec, tol=1e-13)
+            dd = np.diff(G.row_ptr).astype(float)
+            for x in (xm, xa):
+                assert (np.abs(f - x) <= eps * dd * (1 + 1e-3) + 1e-6 * np.abs(f) + 1e-9).all(), j
+                ratio, _ = ppr_certificate(G.row_ptr, G.col_idx, 0.1, eps, idx, val, x)
+                assert ratio < 1.5, (j, ratio)
+        else:
+            assert d_mix_alone <= 1e-6, (j, kind, d_mix_alone)
+            assert d_oracle <= 1e-6 * max(1.0, np.abs(ref).sum() / s1), (j, kind, d_oracle)
+    srv1.close()
+    g.close()
+
+
+def test_server_dynamic_inserts(gde, ctx):
+    G = W.chung_lu(10000, 50000, 2.5, seed=7)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    rng = np.random.default_rng(11)
+    seeds = W.uniform_seeds(G, 24, seed=11)
+    eps = 1e-6
+    srv = gde.Server(ctx, g, lanes_per_group=8, max_groups=3, iters_per_step=2)
+    tickets = {}
+    for s in seeds:
+        tickets[srv.submit(gde.make_params("ppr", alpha=0.1, eps=eps), [int(s)])] = int(s)
+    got = {}
+    for c in srv.poll():  # the first groups are in flight now
+        got[c["ticket"]] = c
+    existing = set()
+    all_u, all_v = [], []
+    for _ in range(3):
+        u, v = W.insert_batch(G, 500, rng, existing)
+        all_u.append(u)
+        all_v.append(v)
+        srv.insert_edges(u, v)
+        for c in srv.poll():
+            got[c["ticket"]] = c
+    got.update(drain(srv, len(seeds)))
+    assert len(got) == len(seeds)
+    # the final graph
+    u = np.concatenate(all_u)
+    v = np.concatenate(all_v)
+    edges = set()
+    for a in range(G.n):
+        for b in G.col_idx[G.row_ptr[a]:G.row_ptr[a + 1]]:
+            if a < b:
+                edges.add((a, int(b)))
+    edges.update(zip(u.tolist(), v.tolist()))
+    Gn = W.from_edges(G.n, sorted(edges))
+    A = X.sparse_adjacency(Gn.row_ptr, Gn.col_idx)
+    d = np.diff(Gn.row_ptr).astype(float)
+    for t, c in got.items():
+        s = tickets[t]
+        assert c["status"] == gde.OK
+        x = np.zeros(G.n)
+        x[c["idx"]] = c["val"]
+        # the FP64 residual of the FP32 x on the new graph meets the stop rule up to
+        # the FP32 rounding of x (a missing insert correction would exceed it by orders)
+        ratio, _ = ppr_certificate(Gn.row_ptr, Gn.col_idx, 0.1, eps, [s], [1.0], x)
+        assert ratio < 1.5, (s, ratio)
+        svec = np.zeros(G.n)
+        svec[s] = 1.0
+        f = X.global_ppr(Gn.row_ptr, Gn.col_idx, 0.1, svec, tol=1e-13)
+        assert (np.abs(f - x) <= eps * d * (1 + 1e-3) + 1e-6 * np.abs(f) + 1e-9).all()
+    srv.close()
+    g.close()
