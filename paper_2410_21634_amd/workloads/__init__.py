@@ -236,24 +236,28 @@ def poisson_arrivals(qps: float, duration_s: float, seed: int = 42) -> np.ndarra
 def insert_batch(graph: Graph, k: int, rng, existing=None) -> tuple[np.ndarray, np.ndarray]:
     """k new undirected edges, endpoints drawn proportional to degree+1, no
     self-loops and no edge already in ``graph`` or in ``existing`` (a set of
-    canonical (u, v) pairs that is updated in place)."""
+    canonical (u, v) pairs that is updated in place).  Candidates are drawn in
+    vectorised rounds and kept in draw order."""
     d = graph.degrees.astype(np.float64) + 1.0
-    p = d / d.sum()
+    cdf = np.cumsum(d)
+    cdf /= cdf[-1]
     rp, ci = graph.row_ptr, graph.col_idx
     existing = existing if existing is not None else set()
     us, vs = [], []
     while len(us) < k:
-        u, v = (int(a) for a in rng.choice(graph.n, size=2, p=p))
-        if u == v:
-            continue
-        a, b = min(u, v), max(u, v)
-        if (a, b) in existing:
-            continue
-        row = ci[rp[a]:rp[a + 1]]
-        j = np.searchsorted(row, b)
-        if j < len(row) and row[j] == b:
-            continue
-        existing.add((a, b))
-        us.append(a)
-        vs.append(b)
+        m = 2 * (k - len(us)) + 16
+        cand = np.minimum(np.searchsorted(cdf, rng.random(2 * m), side="right"), graph.n - 1).reshape(m, 2)
+        for u, v in cand:
+            if len(us) == k:
+                break
+            a, b = (int(u), int(v)) if u < v else (int(v), int(u))
+            if a == b or (a, b) in existing:
+                continue
+            row = ci[rp[a]:rp[a + 1]]
+            j = np.searchsorted(row, b)
+            if j < len(row) and row[j] == b:
+                continue
+            existing.add((a, b))
+            us.append(a)
+            vs.append(b)
     return np.array(us, dtype=np.int32), np.array(vs, dtype=np.int32)
