@@ -128,6 +128,27 @@ def adjacency_eig_bounds(A):
     return float(w[0]), float(w[-1])
 
 
+def lambda_bounds_power(row_ptr, col_idx, iters=100):
+    """Bounds on the largest adjacency eigenvalue for graphs too large for a dense
+    eigensolver (the Katz settings of Sec. 5 need beta * lambda_max < 1): power
+    iteration on A + I from the all-ones vector.  Lower bound: the Rayleigh
+    quotient v'Av / v'v.  Upper bound: the Collatz-Wielandt value max_u (Av)_u / v_u,
+    which bounds the Perron root of a nonnegative matrix from above for any
+    positive v.  Isolated nodes are excluded from the maximum (their ratio is 0)."""
+    A = sparse_adjacency(row_ptr, col_idx)
+    n = A.shape[0]
+    v = np.ones(n)
+    lo, hi = 0.0, float("inf")
+    for _ in range(iters):
+        Av = A @ v
+        lo = max(lo, float(v @ Av) / float(v @ v))
+        hi = min(hi, float(np.max(Av / v)))
+        y = Av + v
+        v = y / np.linalg.norm(y)
+        v = np.maximum(v, 1e-300)
+    return lo, hi
+
+
 def global_ppr(row_ptr, col_idx, alpha, s, tol=1e-14, max_iter=100000):
     """Global FP64 Richardson on the whole graph until ||r||_1 < tol ||s||_1."""
     A = sparse_adjacency(row_ptr, col_idx)

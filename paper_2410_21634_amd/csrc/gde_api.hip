@@ -127,7 +127,7 @@ static GraphHost *graph_host(const gde_graph *g) {
 }
 
 static void ws_free(Workspace *w) {
-    void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->front[0], w->front[1], w->pushed, w->touched[0], w->touched[1],
+    void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->pushed, w->touched[0], w->touched[1],
                    w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
                    w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
                    w->tr_vol, w->tr_nodes, w->lam_buf};
@@ -161,6 +161,7 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     int64_t nwords = (n + 31) / 32;
     w->nblk = (nwords + kBlock - 1) / kBlock;
     WS_ALLOC(w->bitmap, 4 * nwords);
+    WS_ALLOC(w->tbm, 4 * nwords);
     WS_ALLOC(w->blk, 4 * (w->nblk + 1));
     for (int i = 0; i < 2; i++) WS_ALLOC(w->front[i], 4 * n);
     WS_ALLOC(w->pushed, 4 * n);
@@ -449,7 +450,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         }
         void *plane[2] = {w->rd, w->rd2};
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
-                            nullptr, 0, w->st, s);
+                            nullptr, 0, nullptr, w->st, s);
         for (int k = 0; k <= K; k++) {
             a.rd = plane[k & 1];
             a.F = w->front[k & 1];
@@ -462,7 +463,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             if ((rc = prof_mark(ctx, s))) return rc;
             launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
                            w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
-                           nullptr, 0, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, s);
+                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, s);
             if ((rc = prof_mark(ctx, s))) return rc;
         }
         // clean-up of the last level
@@ -496,7 +497,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             base = w->stamp_base;
         }
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, bscale, w->front[0], nullptr,
-                            ch ? w->cstamp : nullptr, base, w->st, s);
+                            ch ? w->cstamp : nullptr, base, w->tbm, w->st, s);
         a.rd = w->rd;
         int t = 0, chunk = 8;
         while (t < p->max_iters) {
@@ -517,14 +518,14 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
-                                   d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 } else {
                     launch_snap_gd<V>(a, wscale, w_div_deg, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
-                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, d_trs, d_trv,
-                                   tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
+                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 }
             }
@@ -545,8 +546,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             }
         }
         if (ch) w->stamp_base += t + 2;
-        launch_final_residual<V>(g->row_ptr, g->col_idx, w->rd, w->pushed, w->st, ppr ? 1.0 / p->alpha : 1.0,
-                                 std::min(2048, pgrid), g->n, s);
+        launch_final_residual<V>(w->tbm, (w->n + 31) / 32, w->rd, w->st, ppr ? 1.0 / p->alpha : 1.0, s);
         if (p->kind == GDE_KATZ && (p->flags & GDE_KATZ_SUBTRACT_SEED))
             launch_subtract_seed<V>(w->x, w->seed_idx, w->seed_val, sd->nnz, s);
         GDE_HIP(hipGetLastError());

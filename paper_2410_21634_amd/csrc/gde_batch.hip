@@ -126,9 +126,11 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     w->vs = vtype == GDE_F64 ? 8 : 4;
     const int64_t n = g->n, GL = (int64_t)G * L;
     const int64_t pairs = n * (int64_t)G;
-    w->act_cap = (int32_t)std::min<int64_t>(pairs, 16000000);
+    // list capacities in (group, node) pairs; a batch whose lists outgrow them is
+    // split in two by gde_solve_batch
+    w->act_cap = (int32_t)std::min<int64_t>(pairs, 32000000);
     w->wl_cap = w->act_cap;
-    w->touch_cap = (int32_t)std::min<int64_t>(pairs, 64000000);
+    w->touch_cap = (int32_t)std::min<int64_t>(pairs, 128000000);
     w->tile_cap = 32000000;
     w->nblk = (int)((w->nwords + kBlock - 1) / kBlock);
     BALLOC(w->R, (size_t)n * GL * w->vs);
@@ -505,6 +507,19 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
 
 using namespace gde;
 
+// A batch whose work lists outgrow the workspace (GDE_ERR_OOM, state already
+// restored) is solved as two halves, recursively, down to one lane group.
+static int solve_batch_split(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
+                             gde_result *res, const Schedule &sc, hipStream_t stream) {
+    int rc = p[0].value_type == GDE_F64 ? solve_batch_fused<double>(ctx, g, B, p, s, res, sc, stream)
+                                        : solve_batch_fused<float>(ctx, g, B, p, s, res, sc, stream);
+    if (rc != GDE_ERR_OOM || B <= sc.lanes) return rc;
+    const int32_t h = ((B / 2 + sc.lanes - 1) / sc.lanes) * sc.lanes;
+    const int r1 = solve_batch_split(ctx, g, h, p, s, res, sc, stream);
+    const int r2 = solve_batch_split(ctx, g, B - h, p + h, s + h, res + h, sc, stream);
+    return r1 ? r1 : r2;
+}
+
 extern "C" {
 
 int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
@@ -542,8 +557,7 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
         }
         return first;
     }
-    if (p[0].value_type == GDE_F64) return solve_batch_fused<double>(ctx, g, B, p, s, res, sc, stream);
-    return solve_batch_fused<float>(ctx, g, B, p, s, res, sc, stream);
+    return solve_batch_split(ctx, g, B, p, s, res, sc, stream);
 }
 
 }  // extern "C"

@@ -13,7 +13,8 @@ namespace gde {
 
 constexpr int kWave = 64;      // CDNA wavefront width
 constexpr int kBlock = 256;    // threads per workgroup of the frontier kernels
-constexpr int kTile = 1024;    // edges per push tile (4 per thread)
+constexpr int kTile = 1024;    // edges per push tile
+constexpr int kPushBlock = kTile;  // threads of a plain push block: one edge of the tile each
 
 // Residual and degree of one node side by side, so that the atomic update of
 // r_w and the read of d_w for the activation test hit the same cache line.
@@ -54,6 +55,7 @@ struct Workspace {
     void *rd2 = nullptr;           // RD<V>[n]  heat-kernel plane 1 (lazily)
     void *x = nullptr;             // V[n]
     uint32_t *bitmap = nullptr;    // pushed set, ceil(n/32) words
+    uint32_t *tbm = nullptr;       // nodes whose residual may be nonzero (LocalGD / LocalCH), ceil(n/32) words
     int32_t *front[2] = {nullptr, nullptr};
     int32_t *pushed = nullptr;
     int32_t *touched[3] = {nullptr, nullptr, nullptr};

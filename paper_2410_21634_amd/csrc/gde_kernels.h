@@ -27,7 +27,7 @@ struct SnapArgs {
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
 template <typename V>
 void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
-                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, DevState *st, hipStream_t s);
+                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s);
 template <typename V> void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s);
 template <typename V>
 void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
@@ -38,11 +38,10 @@ void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t
 template <typename V>
 void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
-                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, long long *tr_size,
+                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
                  long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s);
 template <typename V>
-void launch_final_residual(const int32_t *row_ptr, const int32_t *col_idx, void *rd, const int32_t *pushed,
-                           DevState *st, double rscale, int grid, int32_t cap, hipStream_t s);
+void launch_final_residual(uint32_t *tbm, int64_t nwords, void *rd, DevState *st, double rscale, hipStream_t s);
 template <typename V> void launch_subtract_seed(void *x, const int32_t *sidx, const double *sval, int nnz, hipStream_t s);
 template <typename V>
 void launch_ch_probe(const void *rd, const int32_t *C, DevState *st, int cur, V eps_eff, int32_t cap, hipStream_t s);

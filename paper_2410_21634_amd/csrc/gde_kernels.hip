@@ -108,7 +108,7 @@ __global__ void k_init_rd(const int32_t *__restrict__ row_ptr, RD<V> *rd, int32_
 template <typename V>
 __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const double *__restrict__ sval, int32_t nnz,
                             double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp, int32_t stamp0,
-                            DevState *st) {
+                            uint32_t *tbm, DevState *st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nnz) {
         int32_t u = sidx[i];
@@ -116,6 +116,7 @@ __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const d
         f0[i] = u;
         if (touched0) touched0[i] = u;
         if (cstamp) cstamp[u] = stamp0;
+        if (tbm) atomicOr(&tbm[u >> 5], 1u << (u & 31));
     }
     if (i == 0) {
         st->packed[0] = st->packed[1] = 0ull;
@@ -310,14 +311,20 @@ __global__ void __launch_bounds__(kBlock) k_snap_ch(const int32_t *__restrict__ 
 // MODE 0: LocalGD / monotone residual -- returned old value, crossing test.
 // MODE 1: heat kernel -- crossing test on plane k+1 and first-touch list.
 // MODE 2: LocalCH -- signed add, candidate marking by stamp.
+// One block of kPushBlock = kTile threads per tile: every edge of a tile is in
+// flight at once, so a tile costs one gather + atomic round trip, not several.
+// tbm (MODE 0 and 2): the set of nodes whose residual may be nonzero; a node is
+// added when an add finds its residual at zero (MODE 0) or when it is first
+// marked as a candidate in an iteration (MODE 2).
 template <typename V, int MODE>
-__global__ void __launch_bounds__(kBlock) k_push(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st,
-                                                  int cur, const int32_t *__restrict__ wl_beg,
-                                                  const int32_t *__restrict__ wl_off, const V *__restrict__ wl_sv,
-                                                  const int32_t *__restrict__ tile_start, V eps_eff,
-                                                  int32_t *next_list, int32_t *touched, int tslot, int32_t *cstamp,
-                                                  int32_t stamp_next, long long *tr_size, long long *tr_vol,
-                                                  long long tr_cap, int scatter, int32_t cap, int32_t nnz) {
+__global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st,
+                                                      int cur, const int32_t *__restrict__ wl_beg,
+                                                      const int32_t *__restrict__ wl_off, const V *__restrict__ wl_sv,
+                                                      const int32_t *__restrict__ tile_start, V eps_eff,
+                                                      int32_t *next_list, int32_t *touched, int tslot,
+                                                      int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
+                                                      long long *tr_size, long long *tr_vol, long long tr_cap,
+                                                      int scatter, int32_t cap, int32_t nnz) {
     __shared__ int32_t s_off[kTile + 1];
     __shared__ int32_t s_beg[kTile + 1];
     __shared__ V s_sv[kTile + 1];
@@ -376,13 +383,15 @@ __global__ void __launch_bounds__(kBlock) k_push(const int32_t *__restrict__ col
                 if (MODE == 2) {
                     if (in_range) unsafeAtomicAdd(&dst[w].r, dv);
                     if (in_range && cstamp[w] != stamp_next) hit = atomicExch(&cstamp[w], stamp_next) != stamp_next;
+                    if (hit && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
                 } else {
                     if (dv != (V)0) {
+                        const V th = eps_eff * dst[w].d;  // d is read-only here: load it beside the atomic
                         const V old = unsafeAtomicAdd(&dst[w].r, dv);
                         const V nw = old + dv;
-                        const V th = eps_eff * dst[w].d;
                         hit = (old < th) && (nw >= th);
-                        if (MODE == 1) first = (old == (V)0);
+                        first = (old == (V)0);
+                        if (MODE == 0 && first && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
                     }
                 }
             }
@@ -406,27 +415,28 @@ __global__ void k_ch_probe(const RD<V> *rd, const int32_t *__restrict__ C, DevSt
 }
 
 // ------------------------------------------------------------------ finalisation (A6 + A7)
-// Residual norms of LocalGD / LocalCH: r is nonzero only on the closed
-// neighbourhood of the pushed set; each entry is read and zeroed exactly once
-// (atomic exchange), accumulating ||r~||_1 and ||D^-1 r~||_inf in FP64.
+// Residual norms of LocalGD / LocalCH: r can be nonzero only on the nodes of the
+// touched bitmap.  One thread per bitmap word reads and zeroes the residual of
+// each set bit and clears the word, accumulating ||r~||_1 and ||D^-1 r~||_inf
+// in FP64.  Cost O(n/32 + |touched|); every entry is handled by one thread.
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_final_residual(const int32_t *__restrict__ row_ptr,
-                                                            const int32_t *__restrict__ col_idx, RD<V> *rd,
-                                                            const int32_t *__restrict__ pushed, DevState *st,
-                                                            double rscale, int32_t cap) {
-    const int np = min(st->pushed_count, cap);
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int nwaves = gridDim.x * blockDim.x / kWave;
+__global__ void __launch_bounds__(kBlock) k_final_residual(uint32_t *tbm, int64_t nwords, RD<V> *rd, DevState *st,
+                                                            double rscale) {
     double l1 = 0.0, mx = 0.0;
-    for (int i = wave; i < np; i += nwaves) {
-        const int32_t u = pushed[i];
-        const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
-        for (int e = beg - 1 + lane(); e < end; e += kWave) {
-            const int32_t w = e < beg ? u : col_idx[e];
-            const V val = atomic_take<V>(&rd[w].r);
-            const double a = fabs((double)val) * rscale;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t m = tbm[i];
+        if (m == 0u) continue;
+        tbm[i] = 0u;
+        while (m) {
+            const int b = __ffs((int)m) - 1;
+            m &= m - 1u;
+            const int64_t w = i * 32 + b;
+            const RD<V> e = rd[w];
+            rd[w].r = (V)0;
+            const double a = fabs((double)e.r) * rscale;
             l1 += a;
-            if (a > 0.0) mx = fmax(mx, a / (double)rd[w].d);
+            if (a > 0.0) mx = fmax(mx, a / (double)e.d);
         }
     }
     block_fold_norms(l1, mx, st);
@@ -587,9 +597,9 @@ void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s) 
 
 template <typename V>
 void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
-                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, DevState *st, hipStream_t s) {
+                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s) {
     hipLaunchKernelGGL(k_seed_init<V>, dim3(grid_for(nnz, 256, 65535)), dim3(256), 0, s, (RD<V> *)rd, sidx, sval, nnz,
-                       bscale, f0, touched0, cstamp, stamp0, st);
+                       bscale, f0, touched0, cstamp, stamp0, tbm, st);
 }
 
 template <typename V>
@@ -620,27 +630,18 @@ void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t
 template <typename V>
 void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
-                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, long long *tr_size,
+                 int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
                  long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s) {
-    if (mode == 0)
-        hipLaunchKernelGGL((k_push<V, 0>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
-                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
-                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
-    else if (mode == 1)
-        hipLaunchKernelGGL((k_push<V, 1>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
-                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
-                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
-    else
-        hipLaunchKernelGGL((k_push<V, 2>), dim3(grid), dim3(kBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg,
-                           wl_off, (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp,
-                           stamp_next, tr_size, tr_vol, tr_cap, scatter, cap, nnz);
+    auto kern = mode == 0 ? k_push<V, 0> : mode == 1 ? k_push<V, 1> : k_push<V, 2>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kPushBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg, wl_off,
+                       (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp, stamp_next, tbm,
+                       tr_size, tr_vol, tr_cap, scatter, cap, nnz);
 }
 
 template <typename V>
-void launch_final_residual(const int32_t *row_ptr, const int32_t *col_idx, void *rd, const int32_t *pushed,
-                           DevState *st, double rscale, int grid, int32_t cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_final_residual<V>, dim3(grid), dim3(kBlock), 0, s, row_ptr, col_idx, (RD<V> *)rd, pushed,
-                       st, rscale, cap);
+void launch_final_residual(uint32_t *tbm, int64_t nwords, void *rd, DevState *st, double rscale, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_residual<V>, dim3(grid_for(nwords, kBlock, 2048)), dim3(kBlock), 0, s, tbm, nwords,
+                       (RD<V> *)rd, st, rscale);
 }
 
 template <typename V>
@@ -686,7 +687,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
 #define GDE_INST(V)                                                                                               \
     template void launch_init_rd<V>(const int32_t *, void *, int32_t, hipStream_t);                               \
     template void launch_seed_init<V>(void *, const int32_t *, const double *, int32_t, double, int32_t *,        \
-                                      int32_t *, int32_t *, int32_t, DevState *, hipStream_t);                    \
+                                      int32_t *, int32_t *, int32_t, uint32_t *, DevState *, hipStream_t);        \
     template void launch_snap_gd<V>(const SnapArgs &, V, int, hipStream_t);                                       \
     template void launch_snap_hk<V>(const SnapArgs &, void *, V, int, int, const int32_t *, int, int, double,    \
                                     double, hipStream_t);                                                         \
@@ -694,10 +695,9 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
                                     int32_t, int32_t *, hipStream_t);                                             \
     template void launch_push<V>(int, int, const int32_t *, void *, DevState *, int, const int32_t *,            \
                                  const int32_t *, const void *, const int32_t *, V, int32_t *, int32_t *, int,    \
-                                 int32_t *, int32_t, long long *, long long *, long long, int, int32_t, int32_t,  \
-                                 hipStream_t);                                                                    \
-    template void launch_final_residual<V>(const int32_t *, const int32_t *, void *, const int32_t *, DevState *, \
-                                           double, int, int32_t, hipStream_t);                                    \
+                                 int32_t *, int32_t, uint32_t *, long long *, long long *, long long, int,        \
+                                 int32_t, int32_t, hipStream_t);                                                  \
+    template void launch_final_residual<V>(uint32_t *, int64_t, void *, DevState *, double, hipStream_t);         \
     template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
     template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \
     template void launch_ex_emit<V>(uint32_t *, int64_t, const int32_t *, int64_t, void *, int32_t *, void *,     \

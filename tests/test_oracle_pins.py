@@ -329,3 +329,21 @@ def test_oracle_rejects_bad_input():
     G3 = W.from_edges(3, [(0, 1)])
     with pytest.raises(ValueError):
         O.localgd(G3.row_ptr, G3.col_idx, PPR, 0.1, 1e-4, [2])  # isolated seed
+
+
+def test_lambda_bounds_power(g2000):
+    # closed forms: star with k leaves sqrt(k), complete K5 4, cycle 2; and the dense eigensolver
+    star = W.from_edges(9, [(0, i) for i in range(1, 9)])
+    lo, hi = X.lambda_bounds_power(star.row_ptr, star.col_idx, iters=200)
+    assert lo <= math.sqrt(8) + 1e-12 and math.sqrt(8) <= hi + 1e-12 and hi - lo < 1e-6
+    k5 = W.from_edges(5, [(i, j) for i in range(5) for j in range(i + 1, 5)])
+    lo, hi = X.lambda_bounds_power(k5.row_ptr, k5.col_idx, iters=5)
+    assert lo == pytest.approx(4.0, abs=1e-12) and hi == pytest.approx(4.0, abs=1e-12)
+    cyc = W.from_edges(7, [(i, (i + 1) % 7) for i in range(7)])
+    lo, hi = X.lambda_bounds_power(cyc.row_ptr, cyc.col_idx, iters=5)
+    assert lo == pytest.approx(2.0, abs=1e-12) and hi == pytest.approx(2.0, abs=1e-12)
+    G = g2000
+    ev = np.linalg.eigvalsh(X.dense_adjacency(G.row_ptr, G.col_idx))
+    lo, hi = X.lambda_bounds_power(G.row_ptr, G.col_idx, iters=300)
+    assert lo <= ev[-1] + 1e-9 and ev[-1] <= hi + 1e-9
+    assert lo >= 0.99 * ev[-1]
