@@ -435,6 +435,8 @@ def main():
     ap.add_argument("--phase", default="all", choices=["all", "plain", "batch"],
                     help="profiling aid: run only one path (the JSON line then covers that path only)")
     ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="end with one 256 MiB device-to-device copy kernel, the calibration for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps(dict(error="this build measures one GPU only; multi-GPU sharding is by query "
@@ -442,6 +444,15 @@ def main():
         sys.exit(2)
     out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
     print(json.dumps(out), flush=True)
+    if args.copy_calib:
+        import torch
+
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
 
 
 if __name__ == "__main__":

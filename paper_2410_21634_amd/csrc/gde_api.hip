@@ -169,7 +169,7 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     WS_ALLOC(w->wl_beg, 4 * n);
     WS_ALLOC(w->wl_off, 4 * n);
     WS_ALLOC(w->wl_sv, vs * n);
-    WS_ALLOC(w->tile_start, 4 * (g->nnz / kTile + 2));
+    WS_ALLOC(w->tile_start, 4 * (g->nnz / kPushTile + 2));
     WS_ALLOC(w->st, sizeof(DevState));
     hipError_t e = hipHostMalloc((void **)&w->hst, sizeof(DevState), hipHostMallocDefault);
     if (e != hipSuccess) { ws_free(w); return hip_fail(e, "hipHostMalloc"); }
@@ -384,10 +384,12 @@ void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx) {
 
 // ------------------------------------------------------------------ the plain solver
 static int push_grid(const gde_graph *g) {
-    int64_t tiles = g->nnz / kTile + 1;
-    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 2048);
+    int64_t tiles = g->nnz / kPushTile + 1;
+    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 1024);
 }
-static int snap_grid(const gde_graph *g) { return (int)std::min<int64_t>((g->n + kBlock - 1) / kBlock, 1024); }
+static int snap_grid(const gde_graph *g) {
+    return (int)std::max<int64_t>(std::min<int64_t>((g->n + kSnapBlock - 1) / kSnapBlock, 512), 1);
+}
 
 template <typename V>
 static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,

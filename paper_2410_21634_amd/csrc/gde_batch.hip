@@ -129,7 +129,8 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     // list capacities in (group, node) pairs; a batch whose lists outgrow them is
     // split in two by gde_solve_batch
     w->act_cap = (int32_t)std::min<int64_t>(pairs, 32000000);
-    w->wl_cap = w->act_cap;
+    // work-list entries are counted in the top 24 bits of the packed reservation
+    w->wl_cap = std::min<int32_t>(w->act_cap, (1 << 24) - 1);
     w->touch_cap = (int32_t)std::min<int64_t>(pairs, 128000000);
     w->tile_cap = 32000000;
     w->nblk = (int)((w->nwords + kBlock - 1) / kBlock);

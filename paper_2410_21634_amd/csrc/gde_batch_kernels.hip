@@ -6,20 +6,22 @@
 //   snap : over the active (group, node) pairs, the lanes whose residual
 //          crossed their own threshold are snapshot (v = r, r = 0, x += v) by
 //          L threads per pair (one coalesced line access); each pair reserves
-//          deg * c "lane-edges" (c = active lanes) with one 64-bit atomic per
-//          wavefront;
+//          deg * c "lane-edges" (c = active lanes); the reservations of a
+//          workgroup are summed and taken with one 64-bit atomic;
 //   push : lane-edges are spread evenly over the grid in LDS-staged tiles; the
 //          c threads of one edge update c residuals of the same line.  A
 //          returned old value that crosses theta_lane * d_w sets the lane's bit
 //          in the pair's next-mask; the first bit appends the pair to the next
 //          active list.  A returned zero marks the pair as touched (the
-//          residual clean-up at the end reads only touched pairs).
+//          residual clean-up at the end reads only touched pairs).  List
+//          appends are aggregated per workgroup and tile (one counter atomic).
 // The persistent kernel runs both phases for all iterations in one
 // cooperative launch, separated by grid barriers.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "gde_batch_kernels.h"
+#include "gde_device.h"
 
 namespace cg = cooperative_groups;
 
@@ -42,15 +44,6 @@ __device__ __forceinline__ int bwave_append64(bool pred, int32_t *counter, uint6
         return s;
     }
     return -1;
-}
-
-__device__ __forceinline__ long long bwave_incl_scan64(long long v) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        long long y = __shfl_up(v, off);
-        if (blane() >= off) v += y;
-    }
-    return v;
 }
 
 template <typename V>
@@ -81,10 +74,10 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     }
     constexpr int PPW = kWave / L;  // pairs per wavefront
     const int sub = blane() / L, l = blane() % L;
-    const int wave_id = bid * (kBlock / kWave) + (int)threadIdx.x / kWave;
-    const int nwaves = nblocks * (kBlock / kWave);
-    for (int base = wave_id * PPW; base < nact; base += nwaves * PPW) {
-        const int i = base + sub;
+    const int wpb = (int)blockDim.x / kWave;
+    // workgroup-uniform trip count: every thread takes part in each reservation
+    for (int bbase = bid * wpb * PPW; bbase < nact; bbase += nblocks * wpb * PPW) {
+        const int i = bbase + ((int)threadIdx.x / kWave) * PPW + sub;
         const bool valid = i < nact;
         int32_t g = 0, u = 0, beg = 0, deg = 0;
         uint32_t m = 0u;
@@ -123,16 +116,10 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         }
         const bool leader = valid && l == 0 && c > 0;
         const long long le = leader ? (long long)deg * c : 0ll;
-        const long long incl = bwave_incl_scan64(le);
-        const unsigned long long lead = __ballot(leader);
-        const int cnt = (int)__popcll(lead);
-        const long long tot = __shfl(incl, kWave - 1);
-        unsigned long long res = 0ull;
-        if (cnt > 0 && blane() == 0)
-            res = atomicAdd(&st->packed[cur], ((unsigned long long)cnt << 40) | (unsigned long long)tot);
-        res = __shfl(res, 0);
-        int slot = (int)(res >> 40) + (int)__popcll(lead & ((1ull << blane()) - 1ull));
-        const long long off = (long long)(res & kLaneEdgeMask) + incl - le;
+        const unsigned long long res =
+            block_reserve64(leader ? ((1ull << 40) | (unsigned long long)le) : 0ull, &st->packed[cur]);
+        int slot = (int)(res >> 40);
+        const long long off = (long long)(res & kLaneEdgeMask);
         slot = __shfl(slot, sub * L);  // the pair's slot, from its leader
         if (valid && c > 0) {
             if (slot >= a.wl_cap) {
@@ -212,51 +199,85 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             s_g[j] = a.wl_group[i0 + j];
         }
         __syncthreads();
-        for (long long eb = e0; eb < e1; eb += blockDim.x) {
-            const long long e = eb + threadIdx.x;
-            bool hit = false, first = false;
-            int32_t g = 0, w = 0;
-            uint32_t bit = 0u;
+        // kPer lane-edges per thread, strided by the workgroup size; their loads
+        // and atomics are issued before any result is waited on
+        constexpr int kPer = kTile / kBlock;
+        int32_t gq[kPer], wq[kPer], lq[kPer];
+        V dv[kPer];
+        bool hit[kPer], first[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const long long e = e0 + (long long)q * kBlock + threadIdx.x;
+            hit[q] = first[q] = false;
+            gq[q] = 0;
+            wq[q] = -1;
+            lq[q] = 0;
+            dv[q] = (V)0;
             if (e < e1) {
                 int lo = 0, hi = m - 1;
                 while (lo < hi) {
                     int mid = (lo + hi + 1) >> 1;
                     if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
                 }
-                const long long q = e - s_off[lo];
+                const long long qq = e - s_off[lo];
                 const int c = s_c[lo];
                 if (c > 0) {
-                    const long long edge = q / c;
-                    const int k = (int)(q - edge * c);
+                    const long long edge = qq / c;
+                    const int k = (int)(qq - edge * c);
                     const size_t slot = (size_t)(i0 + lo);
                     const int l = a.wl_lanes[slot * L + k];
-                    const V dv = a.wl_sv[slot * L + k];
                     const long long ci = (long long)s_beg[lo] + edge;
                     if (ci >= 0 && ci < a.nnz && l < L) {
-                        g = s_g[lo];
-                        w = a.col_idx[ci];
-                        const size_t ri = ((size_t)w * a.G + g) * L + l;
-                        const V old = unsafeAtomicAdd(&a.R[ri], dv);
-                        const V nw = old + dv;
-                        const V th = a.lane_eps[g * L + l] * a.deg[w];
-                        const bool cand = a.g_mode && (a.g_mode[g] & 2);
-                        hit = cand || ((old < th) && (nw >= th));
-                        first = old == (V)0;
-                        bit = 1u << l;
+                        gq[q] = s_g[lo];
+                        wq[q] = a.col_idx[ci];
+                        lq[q] = l;
+                        dv[q] = a.wl_sv[slot * L + k];
                     } else {
                         *ovf = 1;
                     }
                 }
             }
-            bool new_act = false, new_touch = false;
-            if (hit) new_act = atomicOr(&a.NM[(size_t)w * a.G + g], bit) == 0u;
-            if (first) {
-                uint32_t *tm = &a.TM[(size_t)w * a.G + g];
-                if (*tm == 0u) new_touch = atomicOr(tm, 1u) == 0u;
+        }
+        V old[kPer], th[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            th[q] = wq[q] >= 0 ? a.lane_eps[gq[q] * L + lq[q]] * a.deg[wq[q]] : (V)0;
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            old[q] = wq[q] >= 0 ? unsafeAtomicAdd(&a.R[((size_t)wq[q] * a.G + gq[q]) * L + lq[q]], dv[q]) : (V)0;
+        int n_act = 0, n_touch = 0;
+        bool new_act[kPer], new_touch[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            new_act[q] = new_touch[q] = false;
+            if (wq[q] >= 0) {
+                const bool cand = a.g_mode && (a.g_mode[gq[q]] & 2);
+                hit[q] = cand || ((old[q] < th[q]) && (old[q] + dv[q] >= th[q]));
+                first[q] = old[q] == (V)0;
+                if (hit[q]) new_act[q] = atomicOr(&a.NM[(size_t)wq[q] * a.G + gq[q]], 1u << lq[q]) == 0u;
+                if (first[q]) {
+                    uint32_t *tm = &a.TM[(size_t)wq[q] * a.G + gq[q]];
+                    if (*tm == 0u) new_touch[q] = atomicOr(tm, 1u) == 0u;
+                }
             }
-            const uint64_t pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)w;
-            bwave_append64(new_act, &st->acount[nxt], pair, a.act[nxt], a.act_cap, ovf);
-            bwave_append64(new_touch, &st->tcount, pair, a.touched, a.touch_cap, ovf);
+            n_act += new_act[q] ? 1 : 0;
+            n_touch += new_touch[q] ? 1 : 0;
+        }
+        int sa = block_reserve(n_act, &st->acount[nxt]);
+        int stt = block_reserve(n_touch, &st->tcount);
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint64_t pair = ((uint64_t)(uint32_t)gq[q] << 32) | (uint32_t)wq[q];
+            if (new_act[q]) {
+                if (sa < a.act_cap) a.act[nxt][sa] = pair;
+                else *ovf = 1;
+                sa++;
+            }
+            if (new_touch[q]) {
+                if (stt < a.touch_cap) a.touched[stt] = pair;
+                else *ovf = 1;
+                stt++;
+            }
         }
     }
 }
@@ -285,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_persistent(BatchArgs<V> a) {
 }
 
 template <typename V, int L>
-__global__ void __launch_bounds__(kBlock) k_batch_snap(BatchArgs<V> a, int t) {
+__global__ void __launch_bounds__(kBatchSnapBlock) k_batch_snap(BatchArgs<V> a, int t) {
     batch_snap<V, L>(a, t, blockIdx.x, gridDim.x);
 }
 template <typename V, int L>
@@ -504,7 +525,9 @@ hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t
 #define GDE_BL(LL)                                                                                       \
     case LL:                                                                                             \
         if (which == 0) return launch_persistent_t<V, LL>(a, grid, s);                                    \
-        if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, t);  \
+        if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL>),                                         \
+                                           dim3((grid * kBlock + kBatchSnapBlock - 1) / kBatchSnapBlock),   \
+                                           dim3(kBatchSnapBlock), 0, s, a, t);                            \
         else hipLaunchKernelGGL((k_batch_push<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, t);             \
         return hipGetLastError();
     switch (L) {

@@ -12,9 +12,17 @@
 namespace gde {
 
 constexpr int kWave = 64;      // CDNA wavefront width
-constexpr int kBlock = 256;    // threads per workgroup of the frontier kernels
-constexpr int kTile = 1024;    // edges per push tile
-constexpr int kPushBlock = kTile;  // threads of a plain push block: one edge of the tile each
+constexpr int kBlock = 256;    // threads per workgroup of the batched and helper kernels
+constexpr int kTile = 1024;    // lane-edges per batched push tile
+constexpr int kMaxWaves = 16;  // wavefronts of the largest workgroup (1024 threads)
+// Plain path.  Appends to the frontier lists and work-list reservations are
+// aggregated per workgroup: a returning atomic on one shared counter costs
+// about 11 ns on MI355X (measured), so one per 1024 threads instead of one per
+// wavefront keeps the counters off the critical path.
+constexpr int kSnapBlock = 1024;  // threads per snapshot workgroup
+constexpr int kPushBlock = 1024;  // threads per push workgroup
+constexpr int kPushTile = 4096;   // edges per push tile (4 per thread, issued together)
+constexpr int kBatchSnapBlock = 1024;  // threads per batched snapshot workgroup
 
 // Residual and degree of one node side by side, so that the atomic update of
 // r_w and the read of d_w for the activation test hit the same cache line.

@@ -3,11 +3,11 @@
 // One iteration t of LocalGD (Eq. (9)) is two launches:
 //   snap : for every u in S_t take v_u = r_u (the synchronous snapshot), set
 //          r_u = 0, x_u += v_u, and reserve a contiguous slice of the work list
-//          and of the edge space with one 64-bit atomic per wavefront;
+//          and of the edge space with one 64-bit atomic per workgroup;
 //   push : edge-balanced scatter r_w += W_u v_u over the CSR rows of S_t, tiles
-//          of kTile edges staged through LDS; every returned old value is
+//          of kPushTile edges staged through LDS; every returned old value is
 //          tested against theta_w, and the unique add that lifts r_w over
-//          theta_w appends w to S_{t+1} (wave-ballot compaction).
+//          theta_w appends w to S_{t+1} (workgroup-aggregated compaction).
 // Because snap has already zeroed the residual of every u in S_t, the push only
 // adds nonnegative mass, r_w is monotone during the launch and the crossing
 // test fires exactly once for every node whose residual ends at or above its
@@ -19,42 +19,20 @@
 // planes of level k and k+1 (the Kronecker block structure of the AHK push).
 #include <hip/hip_runtime.h>
 
+#include "gde_device.h"
 #include "gde_internal.h"
 #include "gde_kernels.h"
 
 namespace gde {
 
-__device__ __forceinline__ int lane() { return (int)__lane_id(); }
-__device__ __forceinline__ unsigned long long lanemask_lt() { return (1ull << lane()) - 1ull; }
-
-// Wave-aggregated append: one atomic per wavefront, slots in lane order.
-__device__ __forceinline__ int wave_append(bool pred, int32_t *counter) {
-    unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return -1;
-    int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane() == leader) base = atomicAdd(counter, (int)__popcll(mask));
-    base = __shfl(base, leader);
-    return pred ? base + (int)__popcll(mask & lanemask_lt()) : -1;
-}
-
-// Guarded list append: entries beyond cap are dropped and flagged.
-__device__ __forceinline__ void list_append(bool pred, int32_t v, int32_t *counter, int32_t *list, int32_t cap,
-                                            DevState *st) {
-    int s = wave_append(pred, counter);
+// Workgroup-aggregated list append of v where pred; entries beyond cap are dropped and flagged.
+__device__ __forceinline__ void block_list_append(bool pred, int32_t v, int32_t *counter, int32_t *list, int32_t cap,
+                                                  DevState *st) {
+    const int slot = block_reserve(pred ? 1 : 0, counter);
     if (pred) {
-        if (s < cap) list[s] = v;
+        if (slot < cap) list[slot] = v;
         else st->overflow = 1;
     }
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        int y = __shfl_up(v, off);
-        if (lane() >= off) v += y;
-    }
-    return v;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -70,7 +48,7 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // block-wide sum and max of two doubles, folded into the device state
 __device__ void block_fold_norms(double l1, double mx, DevState *st) {
-    __shared__ double s_l1[kBlock / kWave], s_mx[kBlock / kWave];
+    __shared__ double s_l1[kMaxWaves], s_mx[kMaxWaves];
     l1 = wave_sum(l1);
     mx = wave_max(mx);
     int w = threadIdx.x / kWave;
@@ -153,25 +131,19 @@ __device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, i
         uint32_t old = atomicOr(&bitmap[u >> 5], bit);
         first = (old & bit) == 0u;
     }
-    list_append(first, u, &st->pushed_count, pushed, cap, st);
-    int d = act ? deg : 0;
-    int incl = wave_incl_scan(d);
-    unsigned long long amask = __ballot(act);
-    int cnt = (int)__popcll(amask);
-    int tot = __shfl(incl, kWave - 1);
-    unsigned long long res = 0ull;
-    if (cnt > 0 && lane() == 0)
-        res = atomicAdd(&st->packed[cur], ((unsigned long long)cnt << 32) | (unsigned long long)(unsigned)tot);
-    res = __shfl(res, 0);
+    block_list_append(first, u, &st->pushed_count, pushed, cap, st);
+    const unsigned long long mine = act ? ((1ull << 32) | (unsigned long long)(unsigned)deg) : 0ull;
+    const unsigned long long res = block_reserve64(mine, &st->packed[cur]);
     if (act) {
-        int slot = (int)(res >> 32) + (int)__popcll(amask & lanemask_lt());
+        const int slot = (int)(res >> 32);
         if (slot >= cap) { st->overflow = 1; return; }
-        int off = (int)(res & 0xffffffffull) + incl - d;
+        const int off = (int)(res & 0xffffffffull);
         wl_node[slot] = u;
         wl_beg[slot] = beg;
         wl_off[slot] = off;
         wl_sv[slot] = sv;
-        for (int k = (off + kTile - 1) / kTile; (long long)k * kTile < (long long)off + d; k++) tile_start[k] = slot;
+        for (int k = (off + kPushTile - 1) / kPushTile; (long long)k * kPushTile < (long long)off + deg; k++)
+            tile_start[k] = slot;
         if (tr_nodes && push_base + slot < tr_cap) tr_nodes[push_base + slot] = u;
     }
 }
@@ -179,7 +151,7 @@ __device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, i
 // LocalGD: v = r_u, r_u = 0, x_u += v, scatter value W_u v with
 // W_u = wscale / d_u (PPR, wscale = 1 - alpha) or wscale (Katz, beta).
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+__global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
                                                      uint32_t *bitmap, const int32_t *__restrict__ F, DevState *st,
                                                      int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
                                                      int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
@@ -214,7 +186,7 @@ __global__ void __launch_bounds__(kBlock) k_snap_gd(const int32_t *__restrict__ 
 // k-1: its leftover residuals are folded into the reported norms
 // (psi_{k-1}-weighted) and the plane is zeroed for reuse by level k+1.
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_snap_hk(const int32_t *__restrict__ row_ptr, RD<V> *plane, RD<V> *prev,
+__global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restrict__ row_ptr, RD<V> *plane, RD<V> *prev,
                                                      V *x, uint32_t *bitmap, const int32_t *__restrict__ F,
                                                      DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
                                                      int32_t *wl_beg, int32_t *wl_off, V *wl_sv,
@@ -264,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_snap_hk(const int32_t *__restrict__ 
 // (all of C_0 = supp(s) at t = 0); h_u = c_t r_u + m_t Delta_u with Delta_u
 // the previous update if u was in S_{t-1}; x_u += h_u, r_u -= h_u, Delta_u = h_u.
 template <typename V>
-__global__ void __launch_bounds__(kBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+__global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
                                                      uint32_t *bitmap, const int32_t *__restrict__ C, DevState *st,
                                                      int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
                                                      int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
@@ -301,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_snap_ch(const int32_t *__restrict__ 
         }
         // u's own residual changed: it is a candidate of the next iteration
         bool mark = act && atomicExch(&cstamp[u], stamp_cur + 1) != stamp_cur + 1;
-        list_append(mark, u, &st->fcount[nxt], next_list, cap, st);
+        block_list_append(mark, u, &st->fcount[nxt], next_list, cap, st);
         emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
     }
@@ -311,8 +283,9 @@ __global__ void __launch_bounds__(kBlock) k_snap_ch(const int32_t *__restrict__ 
 // MODE 0: LocalGD / monotone residual -- returned old value, crossing test.
 // MODE 1: heat kernel -- crossing test on plane k+1 and first-touch list.
 // MODE 2: LocalCH -- signed add, candidate marking by stamp.
-// One block of kPushBlock = kTile threads per tile: every edge of a tile is in
-// flight at once, so a tile costs one gather + atomic round trip, not several.
+// A workgroup of kPushBlock threads takes one tile of kPushTile edges; each
+// thread owns kPer edges strided by kPushBlock (coalesced col_idx reads) and
+// issues their loads, then their atomics, before waiting on any of them.
 // tbm (MODE 0 and 2): the set of nodes whose residual may be nonzero; a node is
 // added when an add finds its residual at zero (MODE 0) or when it is first
 // marked as a candidate in an iteration (MODE 2).
@@ -325,9 +298,10 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                                                       int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
                                                       long long *tr_size, long long *tr_vol, long long tr_cap,
                                                       int scatter, int32_t cap, int32_t nnz) {
-    __shared__ int32_t s_off[kTile + 1];
-    __shared__ int32_t s_beg[kTile + 1];
-    __shared__ V s_sv[kTile + 1];
+    constexpr int kPer = kPushTile / kPushBlock;
+    __shared__ int32_t s_off[kPushTile + 1];
+    __shared__ int32_t s_beg[kPushTile + 1];
+    __shared__ V s_sv[kPushTile + 1];
     const int nxt = cur ^ 1;
     const unsigned long long pk = st->packed[cur];
     const int count = min((int)(pk >> 32), cap);
@@ -346,13 +320,13 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
         st->pushes += count;
         st->iters = it + 1;
     }
-    const int ntiles = scatter ? (total + kTile - 1) / kTile : 0;
+    const int ntiles = scatter ? (total + kPushTile - 1) / kPushTile : 0;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int e0 = tile * kTile;
-        const int e1 = min(e0 + kTile, total);
+        const int e0 = tile * kPushTile;
+        const int e1 = min(e0 + kPushTile, total);
         const int i0 = tile_start[tile];
         const int i1 = (tile + 1 < ntiles) ? tile_start[tile + 1] : count - 1;
-        const int m = min(i1 - i0 + 1, kTile + 1);
+        const int m = min(i1 - i0 + 1, kPushTile + 1);
         if (m <= 0 || i0 < 0 || i1 >= cap) {  // a broken work list: never index with it
             if (threadIdx.x == 0) st->overflow = 1;
             continue;
@@ -364,39 +338,80 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
             s_sv[j] = wl_sv[i0 + j];
         }
         __syncthreads();
-        for (int eb = e0; eb < e1; eb += blockDim.x) {
-            const int e = eb + threadIdx.x;
-            const bool valid = e < e1;
-            bool hit = false, first = false;
-            int32_t w = 0;
-            if (valid) {
+        int32_t w[kPer];
+        V dv[kPer];
+        bool hit[kPer], first[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {  // gather: work-list entry by binary search, then col_idx
+            const int e = e0 + q * kPushBlock + threadIdx.x;
+            w[q] = -1;
+            dv[q] = (V)0;
+            hit[q] = first[q] = false;
+            if (e < e1) {
                 int lo = 0, hi = m - 1;
                 while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
+                    const int mid = (lo + hi + 1) >> 1;
                     if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
                 }
                 const int k = s_beg[lo] + (e - s_off[lo]);
-                const bool in_range = k >= 0 && k < nnz;
-                if (!in_range) st->overflow = 1;
-                w = in_range ? col_idx[k] : 0;
-                const V dv = in_range ? s_sv[lo] : (V)0;
-                if (MODE == 2) {
-                    if (in_range) unsafeAtomicAdd(&dst[w].r, dv);
-                    if (in_range && cstamp[w] != stamp_next) hit = atomicExch(&cstamp[w], stamp_next) != stamp_next;
-                    if (hit && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
+                if (k >= 0 && k < nnz) {
+                    w[q] = col_idx[k];
+                    dv[q] = s_sv[lo];
                 } else {
-                    if (dv != (V)0) {
-                        const V th = eps_eff * dst[w].d;  // d is read-only here: load it beside the atomic
-                        const V old = unsafeAtomicAdd(&dst[w].r, dv);
-                        const V nw = old + dv;
-                        hit = (old < th) && (nw >= th);
-                        first = (old == (V)0);
-                        if (MODE == 0 && first && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
-                    }
+                    st->overflow = 1;
                 }
             }
-            list_append(hit, w, &st->fcount[nxt], next_list, cap, st);
-            if (MODE == 1) list_append(first, w, &st->tcount[tslot], touched, cap, st);
+        }
+        if (MODE == 2) {
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if (w[q] >= 0) unsafeAtomicAdd(&dst[w[q]].r, dv[q]);
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if (w[q] >= 0 && cstamp[w[q]] != stamp_next) hit[q] = atomicExch(&cstamp[w[q]], stamp_next) != stamp_next;
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if (hit[q] && tbm) atomicOr(&tbm[w[q] >> 5], 1u << (w[q] & 31));
+        } else {
+            V th[kPer], old[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++)  // d is read-only during the push
+                th[q] = (w[q] >= 0 && dv[q] != (V)0) ? eps_eff * dst[w[q]].d : (V)0;
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                old[q] = (w[q] >= 0 && dv[q] != (V)0) ? unsafeAtomicAdd(&dst[w[q]].r, dv[q]) : (V)0;
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                if (w[q] >= 0 && dv[q] != (V)0) {
+                    hit[q] = (old[q] < th[q]) && (old[q] + dv[q] >= th[q]);
+                    first[q] = old[q] == (V)0;
+                    if (MODE == 0 && first[q] && tbm) atomicOr(&tbm[w[q] >> 5], 1u << (w[q] & 31));
+                }
+            }
+        }
+        int nh = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; q++) nh += hit[q] ? 1 : 0;
+        int slot = block_reserve(nh, &st->fcount[nxt]);
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            if (hit[q]) {
+                if (slot < cap) next_list[slot] = w[q];
+                else st->overflow = 1;
+                slot++;
+            }
+        if (MODE == 1) {
+            int nf = 0;
+#pragma unroll
+            for (int q = 0; q < kPer; q++) nf += first[q] ? 1 : 0;
+            int ts = block_reserve(nf, &st->tcount[tslot]);
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if (first[q]) {
+                    if (ts < cap) touched[ts] = w[q];
+                    else st->overflow = 1;
+                    ts++;
+                }
         }
     }
 }
@@ -604,7 +619,7 @@ void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t
 
 template <typename V>
 void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s) {
-    hipLaunchKernelGGL(k_snap_gd<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
+    hipLaunchKernelGGL(k_snap_gd<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
                        a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
                        w_div_deg, a.tr_nodes, a.tr_cap, a.cap);
 }
@@ -612,7 +627,7 @@ void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s) {
 template <typename V>
 void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
                     int prev_tslot, int next_tslot, double psi_prev, double wdinf_prev, hipStream_t s) {
-    hipLaunchKernelGGL(k_snap_hk<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (RD<V> *)prev,
+    hipLaunchKernelGGL(k_snap_hk<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (RD<V> *)prev,
                        (V *)a.x, a.bitmap, a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv,
                        a.tile_start, wmul, last_level, frontier_on, prev_touched, prev_tslot, next_tslot, psi_prev,
                        wdinf_prev, a.tr_nodes, a.tr_cap, a.cap);
@@ -621,7 +636,7 @@ void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int f
 template <typename V>
 void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t, V m_t, int force, void *delta,
                     int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur, int32_t *next_list, hipStream_t s) {
-    hipLaunchKernelGGL(k_snap_ch<V>, dim3(a.grid), dim3(kBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
+    hipLaunchKernelGGL(k_snap_ch<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
                        a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
                        w_div_deg, eps_eff, c_t, m_t, force, (V *)delta, dstamp, cstamp, stamp_cur, next_list,
                        a.tr_nodes, a.tr_cap, a.cap);
