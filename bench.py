@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "diffusion solves/s + HBM GB/s at fixed ε (batched vs plain); p50/p99 latency"
 PEAK_HBM_GBS = 8000.0
+CALIB_BYTES = 2 << 30
 EPS_C2 = (1e-4, 1e-5, 1e-6, 1e-7)
 
 
@@ -72,44 +73,76 @@ def traffic_from_profile(entry_name):
     return d.get(entry_name)
 
 
+def pmc_summary(fetch_dir, write_dir, out_path):
+    """HBM traffic per push launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of `bench.py --phase plain --copy-calib`, each
+    scaled by what the same counter read for the calibration kernel (a 2 GiB
+    elementwise multiply: CALIB_BYTES read and CALIB_BYTES written)."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+        return rows
+
+    res = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = load(d, counter)
+        calib = [v for k, v in rows if "MulFunctor" in k]
+        push = [v for k, v in rows if "k_push<" in k]
+        if not calib or not push:
+            raise SystemExit(f"{d}: no calibration or push dispatches with {counter}")
+        factor = CALIB_BYTES / max(calib)
+        res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor,
+                        launches=len(push), bytes_per_launch=factor * sum(push) / len(push))
+    out = dict(kernel="k_push<float,0|2>", workload="ppr-plain-n1M (bench.py --phase plain)",
+               kernel_source_sha=kernel_source_hash(),
+               bytes_per_launch=round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"], 1),
+               fetch=res["fetch"], write=res["write"])
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline_c2(G, seeds, budget_s=20.0):
-    """The FP64 oracle (LocalGD, as it stands) on a bounded sample of the same
-    queries, seeds spread over a thread pool (ctypes releases the GIL)."""
+    """The FP64 oracle (LocalGD and LocalCH, as it stands) on a bounded sample of
+    the same queries, seeds spread over a thread pool (ctypes releases the GIL)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import solvers as O
 
     O._load()
     cores = max(1, min(16, os.cpu_count() or 1))
-    per_eps = {}
-    for eps in EPS_C2:
-        deadline = time.perf_counter() + budget_s / len(EPS_C2)
-        done = 0
-        t0 = time.perf_counter()
-        with ThreadPoolExecutor(cores) as ex:
-            futs = []
-            it = iter(seeds)
-            # keep `cores` solves in flight until the per-eps budget is spent
-            for _ in range(cores):
-                s = next(it, None)
-                if s is not None:
-                    futs.append(ex.submit(O.localgd, G.row_ptr, G.col_idx, O.PPR, 0.1, eps, [int(s)]))
-            while futs:
-                f = futs.pop(0)
-                f.result()
-                done += 1
-                if time.perf_counter() < deadline:
-                    s = next(it, None)
-                    if s is not None:
-                        futs.append(ex.submit(O.localgd, G.row_ptr, G.col_idx, O.PPR, 0.1, eps, [int(s)]))
-        dt = time.perf_counter() - t0
-        per_eps[eps] = (done, dt)
-    # CPU time of one step's LocalGD queries = sum over eps of len(seeds) / throughput(eps)
-    step_s = sum(len(seeds) * dt / done for done, dt in per_eps.values())
-    return dict(value=len(seeds) * len(EPS_C2) / step_s, unit="solves/s", cores=cores, kind="oracle",
-                sample=("FP64 LocalGD oracle, PPR alpha=0.1, same graph and seeds; per eps "
-                        + ", ".join(f"{e:g}: {d} solves in {t:.1f}s" for e, (d, t) in per_eps.items())
-                        + f"; {cores} threads, one solve per thread; throughput of the 4-eps LocalGD mix"))
+    solvers = {"gd": lambda eps, s: O.localgd(G.row_ptr, G.col_idx, O.PPR, 0.1, eps, [s]),
+               "ch": lambda eps, s: O.localch(G.row_ptr, G.col_idx, O.PPR, 0.1, eps, [s])}
+    per = {}
+    for m, fn in solvers.items():
+        for eps in EPS_C2:
+            deadline = time.perf_counter() + budget_s / (2 * len(EPS_C2))
+            done = 0
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(cores) as ex:
+                it = iter(seeds)
+                # keep `cores` solves in flight until this (method, eps) budget is spent
+                futs = [ex.submit(fn, eps, int(s)) for s in (next(it, None) for _ in range(cores)) if s is not None]
+                while futs:
+                    futs.pop(0).result()
+                    done += 1
+                    if time.perf_counter() < deadline:
+                        s = next(it, None)
+                        if s is not None:
+                            futs.append(ex.submit(fn, eps, int(s)))
+            per[(m, eps)] = (done, time.perf_counter() - t0)
+    # CPU time of one step (every method x eps x seed) = sum of len(seeds) / throughput
+    step_s = sum(len(seeds) * dt / done for done, dt in per.values())
+    return dict(value=len(seeds) * len(per) / step_s, unit="solves/s", cores=cores, kind="oracle",
+                sample=("FP64 LocalGD and LocalCH oracle, PPR alpha=0.1, same graph and seeds; "
+                        + ", ".join(f"{m}@{e:g}: {d} solves in {t:.1f}s" for (m, e), (d, t) in per.items())
+                        + f"; {cores} threads, one solve per thread; rate of the full {len(seeds) * len(per)}-solve step mix"))
 
 
 def run_c2(args):
@@ -195,6 +228,8 @@ def run_c2(args):
                        speedup_vs_plain=round(len(gd_q) * args.steps / tb / plain_gd_rate, 2),
                        hbm_gbs_alg=round(alg_bytes(bops, bpush) * args.steps / tb / 1e9, 2),
                        kernel_ms=round(bprof["batch_ms"] / max(bprof["batch_launches"], 1), 3),
+                       lane_edges_per_batch=int(bprof["batch_lane_edges"] // max(args.steps, 1)),
+                       entries_per_batch=int(bprof["batch_entries"] // max(args.steps, 1)),
                        schedule=sched or "default", not_converged=int(sum(r.status != 0 for r in bres)))
         log(f"batched: {batched}")
 
@@ -435,9 +470,14 @@ def main():
     ap.add_argument("--phase", default="all", choices=["all", "plain", "batch"],
                     help="profiling aid: run only one path (the JSON line then covers that path only)")
     ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="write the per-launch push traffic from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with one 256 MiB device-to-device copy kernel, the calibration for HBM byte counters")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(json.dumps(dict(error="this build measures one GPU only; multi-GPU sharding is by query "
                                     "(replicated graph) and is described, not run")), flush=True)
@@ -447,12 +487,14 @@ def main():
     if args.copy_calib:
         import torch
 
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        # 2 GiB each way, far beyond the caches: one elementwise kernel that reads
+        # CALIB_BYTES and writes CALIB_BYTES, the reference for the byte counters
+        a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
-        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        log(f"copy calibration: {CALIB_BYTES} bytes read, {CALIB_BYTES} bytes written")
 
 
 if __name__ == "__main__":

@@ -56,7 +56,9 @@ static int validate_params(const gde_params *p) {
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(GDE_ERR_INVALID_ARG, "eps must be finite and > 0");
     if (p->max_iters < 1) return fail(GDE_ERR_INVALID_ARG, "max_iters must be >= 1");
     if (p->c != nullptr) return fail(GDE_ERR_INVALID_ARG, "params.c is reserved and must be NULL");
-    if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE))
+    if ((p->flags & GDE_SCATTER_BINNED) && (p->flags & GDE_SCATTER_ATOMIC))
+        return fail(GDE_ERR_INVALID_ARG, "GDE_SCATTER_BINNED and GDE_SCATTER_ATOMIC exclude each other");
+    if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE | GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC))
         return fail(GDE_ERR_INVALID_ARG, "unknown flag bits");
     switch (p->kind) {
     case GDE_PPR:
@@ -130,7 +132,7 @@ static void ws_free(Workspace *w) {
     void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->pushed, w->touched[0], w->touched[1],
                    w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
                    w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
-                   w->tr_vol, w->tr_nodes, w->lam_buf};
+                   w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_w, w->bin_v};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (w->hst) (void)hipHostFree(w->hst);
@@ -177,6 +179,31 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     else launch_init_rd<float>(g->row_ptr, w->rd, g->n, s);
     e = hipGetLastError();
     if (e != hipSuccess) { ws_free(w); return hip_fail(e, "init_rd"); }
+    // bins of the binned scatter: one per range of 2^S nodes, sized by the range's in-volume
+    int shift = 0;
+    while (((int64_t)vs << (shift + 1)) <= kBinLdsBytes) shift++;
+    const int64_t nranges = (n + ((int64_t)1 << shift) - 1) >> shift;
+    if (nranges <= kBinMaxRanges) {
+        w->bin_shift = shift;
+        w->bin_nranges = (int)nranges;
+        unsigned long long *cnt = nullptr;
+        WS_ALLOC(cnt, 8 * nranges);
+        launch_bin_count(g->col_idx, g->nnz, shift, (int)nranges, cnt, s);
+        std::vector<unsigned long long> h(nranges);
+        e = hipMemcpyAsync(h.data(), cnt, 8 * nranges, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(cnt);
+        if (e != hipSuccess) { ws_free(w); return hip_fail(e, "bin counts"); }
+        std::vector<long long> base(nranges + 1, 0);
+        for (int64_t r = 0; r < nranges; r++) base[r + 1] = base[r] + (long long)h[r];
+        WS_ALLOC(w->bin_base, 8 * (nranges + 1));
+        WS_ALLOC(w->bin_cursor, 4 * nranges);
+        WS_ALLOC(w->bin_w, 4 * (size_t)std::max<long long>(base[nranges], 1));
+        WS_ALLOC(w->bin_v, vs * (size_t)std::max<long long>(base[nranges], 1));
+        e = hipMemcpyAsync(w->bin_base, base.data(), 8 * (nranges + 1), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { ws_free(w); return hip_fail(e, "bin bases"); }
+    }
     (void)ctx;
     *out = w;
     return GDE_OK;
@@ -419,6 +446,17 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     GDE_HIP(hipMemcpyAsync(w->seed_val, w->h_seed_val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
 
     const int pgrid = push_grid(g), sgrid = snap_grid(g);
+    BinArgs<V> bins{};
+    if (w->bin_nranges > 0) {
+        bins.shift = w->bin_shift;
+        bins.nranges = w->bin_nranges;
+        bins.min_edges = (p->flags & GDE_SCATTER_BINNED) ? 0 : kBinMinEdges;
+        if (p->flags & GDE_SCATTER_ATOMIC) bins.nranges = 0;
+        bins.base = w->bin_base;
+        bins.cursor = w->bin_cursor;
+        bins.bw = w->bin_w;
+        bins.bv = (V *)w->bin_v;
+    }
     SnapArgs a{};
     a.grid = sgrid;
     a.row_ptr = g->row_ptr;
@@ -465,7 +503,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             if ((rc = prof_mark(ctx, s))) return rc;
             launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
                            w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
-                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, s);
+                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, bins, s);
             if ((rc = prof_mark(ctx, s))) return rc;
         }
         // clean-up of the last level
@@ -520,14 +558,14 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
-                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 } else {
                     launch_snap_gd<V>(a, wscale, w_div_deg, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
-                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, s);
+                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 }
             }

@@ -23,6 +23,25 @@ constexpr int kSnapBlock = 1024;  // threads per snapshot workgroup
 constexpr int kPushBlock = 1024;  // threads per push workgroup
 constexpr int kPushTile = 4096;   // edges per push tile (4 per thread, issued together)
 constexpr int kBatchSnapBlock = 1024;  // threads per batched snapshot workgroup
+// Binned scatter for large frontiers: updates are written, grouped by
+// destination range of 2^S nodes, into per-range bins and then summed in LDS
+// by one workgroup per range (no global atomic per edge).
+constexpr int kBinMaxRanges = 4096;     // ranges a graph may have for the binned scatter
+constexpr int kBinLdsBytes = 32768;     // LDS accumulator bytes of one range (2^S values)
+constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
+constexpr long long kBinMinEdges = 131072;  // frontier volume from which the scatter is binned
+
+// Device description of the bins of one workspace (value type V).
+template <typename V>
+struct BinArgs {
+    int shift;               // S: range r holds nodes [r << S, (r + 1) << S)
+    int nranges;             // 0: binning disabled for this graph
+    long long min_edges;     // frontier volume from which the binned scatter runs
+    const long long *base;   // [nranges + 1]: bin r occupies [base[r], base[r + 1])
+    int32_t *cursor;         // [nranges]: entries written to bin r this iteration
+    int32_t *bw;             // destination node of each binned update
+    V *bv;                   // value of each binned update
+};
 
 // Residual and degree of one node side by side, so that the atomic update of
 // r_w and the read of d_w for the activation test hit the same cache line.
@@ -90,6 +109,13 @@ struct Workspace {
     int32_t *tr_nodes = nullptr;
     int64_t tr_nodes_cap = 0;
     double *lam_buf = nullptr;     // power-iteration vectors and reductions
+    // binned scatter (graphs with at most kBinMaxRanges ranges)
+    int bin_shift = 0;
+    int bin_nranges = 0;
+    long long *bin_base = nullptr; // device [nranges + 1]
+    int32_t *bin_cursor = nullptr; // device [nranges], zero between iterations
+    int32_t *bin_w = nullptr;      // device [nnz]
+    void *bin_v = nullptr;         // device [nnz] values
 };
 
 struct BatchWS;

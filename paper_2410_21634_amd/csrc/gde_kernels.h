@@ -39,7 +39,10 @@ template <typename V>
 void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
                  int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
-                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s);
+                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, const BinArgs<V> &bins,
+                 hipStream_t s);
+void launch_bin_count(const int32_t *col_idx, long long nnz, int shift, int nranges, unsigned long long *counts,
+                      hipStream_t s);
 template <typename V>
 void launch_final_residual(uint32_t *tbm, int64_t nwords, void *rd, DevState *st, double rscale, hipStream_t s);
 template <typename V> void launch_subtract_seed(void *x, const int32_t *sidx, const double *sval, int nnz, hipStream_t s);

@@ -297,11 +297,12 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                                                       int32_t *next_list, int32_t *touched, int tslot,
                                                       int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
                                                       long long *tr_size, long long *tr_vol, long long tr_cap,
-                                                      int scatter, int32_t cap, int32_t nnz) {
+                                                      int scatter, int32_t cap, int32_t nnz, BinArgs<V> bins) {
     constexpr int kPer = kPushTile / kPushBlock;
     __shared__ int32_t s_off[kPushTile + 1];
     __shared__ int32_t s_beg[kPushTile + 1];
     __shared__ V s_sv[kPushTile + 1];
+    extern __shared__ int32_t s_bin[];  // binned scatter: [nranges] counts, then [nranges] bases
     const int nxt = cur ^ 1;
     const unsigned long long pk = st->packed[cur];
     const int count = min((int)(pk >> 32), cap);
@@ -321,6 +322,13 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
         st->iters = it + 1;
     }
     const int ntiles = scatter ? (total + kPushTile - 1) / kPushTile : 0;
+    // large frontier: write the updates into the destination-range bins (summed
+    // by k_reduce); small frontier: atomic scatter with the crossing test here
+    const bool binned = bins.nranges > 0 && (long long)total >= bins.min_edges && scatter;
+    int32_t *s_cnt = s_bin;
+    int32_t *s_rbase = s_bin + bins.nranges;
+    if (binned)
+        for (int r = threadIdx.x; r < bins.nranges; r += blockDim.x) s_cnt[r] = 0;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int e0 = tile * kPushTile;
         const int e1 = min(e0 + kPushTile, total);
@@ -361,6 +369,40 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                     st->overflow = 1;
                 }
             }
+        }
+        if (binned) {
+            // rank of each update inside its range for this tile (LDS), one global
+            // reservation per nonempty range, then the writes
+            int rb[kPer], rk[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                rb[q] = -1;
+                if (w[q] >= 0 && (MODE == 2 || dv[q] != (V)0)) {
+                    rb[q] = w[q] >> bins.shift;
+                    rk[q] = atomicAdd(&s_cnt[rb[q]], 1);
+                }
+            }
+            __syncthreads();
+            for (int r = threadIdx.x; r < bins.nranges; r += blockDim.x) {
+                const int c = s_cnt[r];
+                if (c) {
+                    s_rbase[r] = atomicAdd(&bins.cursor[r], c);
+                    s_cnt[r] = 0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if (rb[q] >= 0) {
+                    const long long pos = bins.base[rb[q]] + s_rbase[rb[q]] + rk[q];
+                    if (pos < bins.base[rb[q] + 1]) {
+                        bins.bw[pos] = w[q];
+                        bins.bv[pos] = dv[q];
+                    } else {
+                        st->overflow = 1;
+                    }
+                }
+            continue;
         }
         if (MODE == 2) {
 #pragma unroll
@@ -414,6 +456,107 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                 }
         }
     }
+}
+
+// Binned scatter, second half: workgroup r sums the updates of bin r into an
+// LDS accumulator over its node range, then applies each touched node's total
+// once: r_w += sum, with the same tests as the atomic scatter (MODE 0/1: the
+// crossing test, and first touch when the old residual was zero; MODE 2: the
+// candidate stamp).  Each node belongs to one range, so the updates of r_w,
+// the stamps and the bitmap words of the range need no global atomics.  Every
+// thread owns kRedPer consecutive nodes of the range; appends are aggregated
+// per workgroup.  The bin cursor is reset for the next iteration.
+template <typename V, int MODE>
+__global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> *dst, DevState *st, int cur,
+                                                          V eps_eff, int32_t *next_list, int32_t *touched, int tslot,
+                                                          int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
+                                                          int scatter, int32_t cap, int32_t n) {
+    // 16-byte aligned: the FP64 accumulator takes 64-bit LDS atomics, which need natural alignment
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_red[];
+    const int span_max = 1 << bins.shift;
+    V *s_acc = (V *)s_red;
+    uint32_t *s_bits = (uint32_t *)(s_acc + span_max);
+    const int total = (int)(st->packed[cur] & 0xffffffffull);
+    if (!(bins.nranges > 0 && (long long)total >= bins.min_edges && scatter)) return;
+    const int r = blockIdx.x;
+    const int lo = r << bins.shift;
+    const int span = min(span_max, n - lo);
+    const int cnt = bins.cursor[r];
+    const long long b0 = bins.base[r];
+    const long long avail = bins.base[r + 1] - b0;
+    for (int j = threadIdx.x; j < span_max; j += blockDim.x) s_acc[j] = (V)0;
+    for (int j = threadIdx.x; j < span_max / 32; j += blockDim.x) s_bits[j] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) bins.cursor[r] = 0;
+    const int m = (int)min((long long)cnt, avail);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int j = bins.bw[b0 + i] - lo;
+        if (j >= 0 && j < span) {
+            atomicAdd(&s_acc[j], bins.bv[b0 + i]);
+            atomicOr(&s_bits[j >> 5], 1u << (j & 31));
+        } else {
+            st->overflow = 1;
+        }
+    }
+    __syncthreads();
+    const int per = span_max / (int)blockDim.x;  // nodes per thread (power of two, <= 32)
+    const int j0 = (int)threadIdx.x * per;
+    uint32_t hits = 0u, firsts = 0u;
+    for (int k = 0; k < per; k++) {
+        const int j = j0 + k;
+        if (j >= span || !((s_bits[j >> 5] >> (j & 31)) & 1u)) continue;
+        const int32_t w = lo + j;
+        const V acc = s_acc[j];
+        if (MODE == 2) {
+            dst[w].r += acc;
+            if (cstamp[w] != stamp_next) {
+                cstamp[w] = stamp_next;
+                hits |= 1u << k;
+                if (tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
+            }
+        } else {
+            const RD<V> e = dst[w];
+            const V nw = e.r + acc;
+            dst[w].r = nw;
+            const V th = eps_eff * e.d;
+            if (e.r < th && nw >= th) hits |= 1u << k;
+            if (e.r == (V)0) {
+                firsts |= 1u << k;
+                if (MODE == 0 && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
+            }
+        }
+    }
+    int slot = block_reserve(__popc(hits), &st->fcount[cur ^ 1]);
+    for (uint32_t h = hits; h; h &= h - 1u) {
+        const int32_t w = lo + j0 + (__ffs((int)h) - 1);
+        if (slot < cap) next_list[slot] = w;
+        else st->overflow = 1;
+        slot++;
+    }
+    if (MODE == 1) {
+        int ts = block_reserve(__popc(firsts), &st->tcount[tslot]);
+        for (uint32_t h = firsts; h; h &= h - 1u) {
+            const int32_t w = lo + j0 + (__ffs((int)h) - 1);
+            if (ts < cap) touched[ts] = w;
+            else st->overflow = 1;
+            ts++;
+        }
+    }
+}
+
+// In-volume of every destination range: the number of CSR entries whose
+// column falls in it, the capacity of the range's bin (a node receives at
+// most one update per entry of its column per iteration).
+__global__ void __launch_bounds__(kBlock) k_bin_count(const int32_t *__restrict__ col_idx, long long nnz, int shift,
+                                                       int nranges, unsigned long long *counts) {
+    __shared__ int s_c[kBinMaxRanges];
+    for (int r = threadIdx.x; r < nranges; r += blockDim.x) s_c[r] = 0;
+    __syncthreads();
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz; e += (long long)gridDim.x * blockDim.x)
+        atomicAdd(&s_c[col_idx[e] >> shift], 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < nranges; r += blockDim.x)
+        if (s_c[r]) atomicAdd(&counts[r], (unsigned long long)s_c[r]);
 }
 
 // LocalCH at the iteration cap: is S_t empty?  (counts without updating)
@@ -646,11 +789,25 @@ template <typename V>
 void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState *st, int cur, const int32_t *wl_beg,
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
                  int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
-                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, hipStream_t s) {
+                 long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, const BinArgs<V> &bins,
+                 hipStream_t s) {
     auto kern = mode == 0 ? k_push<V, 0> : mode == 1 ? k_push<V, 1> : k_push<V, 2>;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kPushBlock), 0, s, col_idx, (RD<V> *)dst, st, cur, wl_beg, wl_off,
+    const size_t dyn = 2 * sizeof(int32_t) * (size_t)bins.nranges;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kPushBlock), dyn, s, col_idx, (RD<V> *)dst, st, cur, wl_beg, wl_off,
                        (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp, stamp_next, tbm,
-                       tr_size, tr_vol, tr_cap, scatter, cap, nnz);
+                       tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins);
+    if (bins.nranges > 0) {
+        auto red = mode == 0 ? k_reduce<V, 0> : mode == 1 ? k_reduce<V, 1> : k_reduce<V, 2>;
+        const size_t rdyn = sizeof(V) * ((size_t)1 << bins.shift) + sizeof(uint32_t) * (((size_t)1 << bins.shift) / 32);
+        hipLaunchKernelGGL(red, dim3(bins.nranges), dim3(kReduceBlock), rdyn, s, bins, (RD<V> *)dst, st, cur, eps_eff,
+                           next_list, touched, tslot, cstamp, stamp_next, tbm, scatter, cap, (int32_t)(cap));
+    }
+}
+
+void launch_bin_count(const int32_t *col_idx, long long nnz, int shift, int nranges, unsigned long long *counts,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(nnz, kBlock, 2048)), dim3(kBlock), 0, s, col_idx, nnz, shift,
+                       nranges, counts);
 }
 
 template <typename V>
@@ -711,7 +868,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
     template void launch_push<V>(int, int, const int32_t *, void *, DevState *, int, const int32_t *,            \
                                  const int32_t *, const void *, const int32_t *, V, int32_t *, int32_t *, int,    \
                                  int32_t *, int32_t, uint32_t *, long long *, long long *, long long, int,        \
-                                 int32_t, int32_t, hipStream_t);                                                  \
+                                 int32_t, int32_t, const BinArgs<V> &, hipStream_t);                              \
     template void launch_final_residual<V>(uint32_t *, int64_t, void *, DevState *, double, hipStream_t);         \
     template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
     template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \

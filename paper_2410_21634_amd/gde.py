@@ -22,6 +22,7 @@ LOCAL_GD, LOCAL_CH = 0, 1
 F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
 KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
+SCATTER_BINNED, SCATTER_ATOMIC = 0x8, 0x10
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
 KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK}

@@ -44,12 +44,12 @@ def oracle_replay(G, kind, method, prm, seed_idx, seed_val, sizes, nodes, kappa)
                           lam=prm.get("lambda_bound", 0.0))
 
 
-def check(ctx, g, G, kind, method, vt, prm, seed_idx, seed_val=None, force_replay=False):
+def check(ctx, g, G, kind, method, vt, prm, seed_idx, seed_val=None, force_replay=False, extra_flags=0):
     """Run the GPU solve and the oracle, enforce P1 (or P2), return a report dict."""
     seed_idx = np.atleast_1d(np.asarray(seed_idx, dtype=np.int32))
     seed_val = np.ones(len(seed_idx)) if seed_val is None else np.asarray(seed_val, dtype=np.float64)
     s1 = float(np.abs(seed_val).sum())
-    p = gde.make_params(kind, method, value_type=vt, flags=gde.TRACE, **prm)
+    p = gde.make_params(kind, method, value_type=vt, flags=gde.TRACE | extra_flags, **prm)
     nodes_cap = int(min(30_000_000, max(1_000_000, 16 * G.n)))
     res = gde.solve(ctx, g, p, seed_idx, seed_val, trace_cap=100000, nodes_cap=nodes_cap)
     x_gpu = res.dense(G.n)

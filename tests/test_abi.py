@@ -64,6 +64,10 @@ def test_validation_errors(small):
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
     p = gde.make_params(flags=0x100)
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
+    p = gde.make_params(flags=gde.SCATTER_BINNED | gde.SCATTER_ATOMIC)  # exclusive strategies
+    assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
+    for f in (gde.SCATTER_BINNED, gde.SCATTER_ATOMIC):
+        assert gde.validate(rp, ci, gde.make_params(flags=f), [0]) == gde.OK
     # malformed CSR
     bad = rp.copy()
     bad[-1] += 1

@@ -168,3 +168,27 @@ def test_lambda_bounds(gde, ctx, g2k):
     lam = max(ev[-1], -ev[0])
     assert lo <= ev[-1] * (1 + 1e-12) and hi >= lam * (1 - 1e-12)
     assert (hi - lo) / hi < 0.05
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+@pytest.mark.parametrize("strategy", ["binned", "atomic"])
+def test_scatter_strategies(gde, ctx, c1, g2k, vt, strategy):
+    """Every iteration binned (destination-range bins summed in LDS) or every
+    iteration atomic: the same iteration either way, for all kinds and methods."""
+    G, g = c1
+    f = gde.SCATTER_BINNED if strategy == "binned" else gde.SCATTER_ATOMIC
+    for s in seeds_of(G, k=2, seed=3):
+        for method in (gde.LOCAL_GD, gde.LOCAL_CH):
+            rep = check(ctx, g, G, gde.PPR, method, vt, dict(alpha=0.1, eps=1e-6), [s], extra_flags=f)
+            print("scatter", strategy, vt, method, s, rep, flush=True)
+        rep = check(ctx, g, G, gde.HK, gde.LOCAL_GD, vt, dict(tau=5.0, K=30, eps=1e-6), [s], extra_flags=f)
+        print("scatter hk", strategy, vt, s, rep, flush=True)
+    G2, g2 = g2k
+    A = X.dense_adjacency(G2.row_ptr, G2.col_idx)
+    ev = np.linalg.eigvalsh(A)
+    lam = max(ev[-1], -ev[0])
+    for s in seeds_of(G2, k=2, seed=4):
+        for method in (gde.LOCAL_GD, gde.LOCAL_CH):
+            rep = check(ctx, g2, G2, gde.KATZ, method, vt, dict(beta=0.5 / lam, eps=1e-6, lambda_bound=lam * 1.001),
+                        [s], extra_flags=f)
+            print("scatter katz", strategy, vt, method, s, rep, flush=True)
