@@ -27,7 +27,7 @@ constexpr int kBatchSnapBlock = 1024;  // threads per batched snapshot workgroup
 // destination range of 2^S nodes, into per-range bins and then summed in LDS
 // by one workgroup per range (no global atomic per edge).
 constexpr int kBinMaxRanges = 4096;     // ranges a graph may have for the binned scatter
-constexpr int kBinLdsBytes = 32768;     // LDS accumulator bytes of one range (2^S values)
+constexpr int kBinLdsBytes = 16384;     // LDS accumulator bytes of one range (2^S values)
 constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
 constexpr long long kBinMinEdges = 131072;  // frontier volume from which the scatter is binned
 

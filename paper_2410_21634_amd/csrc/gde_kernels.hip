@@ -460,9 +460,10 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
 
 // Binned scatter, second half: workgroup r sums the updates of bin r into an
 // LDS accumulator over its node range, then applies each touched node's total
-// once: r_w += sum, with the same tests as the atomic scatter (MODE 0/1: the
-// crossing test, and first touch when the old residual was zero; MODE 2: the
-// candidate stamp).  Each node belongs to one range, so the updates of r_w,
+// once: r_w += sum, with the tests of the atomic scatter (MODE 0/1: the
+// crossing test, and first touch when the old residual was zero; MODE 2: w
+// becomes a candidate of t+1 only if its final residual passes the threshold,
+// since no later add of this iteration can change it).  Each node belongs to one range, so the updates of r_w,
 // the stamps and the bitmap words of the range need no global atomics.  Every
 // thread owns kRedPer consecutive nodes of the range; appends are aggregated
 // per workgroup.  The bin cursor is reset for the next iteration.
@@ -489,13 +490,27 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     __syncthreads();
     if (threadIdx.x == 0) bins.cursor[r] = 0;
     const int m = (int)min((long long)cnt, avail);
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const int j = bins.bw[b0 + i] - lo;
-        if (j >= 0 && j < span) {
-            atomicAdd(&s_acc[j], bins.bv[b0 + i]);
-            atomicOr(&s_bits[j >> 5], 1u << (j & 31));
-        } else {
-            st->overflow = 1;
+    constexpr int kRedUnroll = 4;  // bin entries per thread and step, loaded before any LDS update
+    for (int i0 = 0; i0 < m; i0 += kRedUnroll * (int)blockDim.x) {
+        int jj[kRedUnroll];
+        V vv[kRedUnroll];
+        bool ok[kRedUnroll];
+#pragma unroll
+        for (int q = 0; q < kRedUnroll; q++) {
+            const int i = i0 + q * (int)blockDim.x + (int)threadIdx.x;
+            ok[q] = i < m;
+            jj[q] = ok[q] ? bins.bw[b0 + i] - lo : 0;
+            vv[q] = ok[q] ? bins.bv[b0 + i] : (V)0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRedUnroll; q++) {
+            if (!ok[q]) continue;
+            if (jj[q] >= 0 && jj[q] < span) {
+                atomicAdd(&s_acc[jj[q]], vv[q]);
+                atomicOr(&s_bits[jj[q] >> 5], 1u << (jj[q] & 31));
+            } else {
+                st->overflow = 1;
+            }
         }
     }
     __syncthreads();
@@ -508,11 +523,15 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
         const int32_t w = lo + j;
         const V acc = s_acc[j];
         if (MODE == 2) {
-            dst[w].r += acc;
-            if (cstamp[w] != stamp_next) {
+            // the residual of w is final for this iteration: only an active w joins
+            // the candidates of t+1 (nodes of S_t were added by the snapshot)
+            const RD<V> e = dst[w];
+            const V nr = e.r + acc;
+            dst[w].r = nr;
+            if (tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
+            if (nr != (V)0 && fabs(nr) >= eps_eff * e.d && cstamp[w] != stamp_next) {
                 cstamp[w] = stamp_next;
                 hits |= 1u << k;
-                if (tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
             }
         } else {
             const RD<V> e = dst[w];
