@@ -149,6 +149,55 @@ static void ws_free(Workspace *w) {
         if (_e != hipSuccess) { ws_free(w); return hip_fail(_e, "hipMemsetAsync"); } \
     } while (0)
 
+// Graph-dependent parts of a workspace: degrees in the residual planes, the
+// push tile table and the bins (capacity nnz_cap, with headroom so that a graph
+// growing by edge insertions keeps its buffers).  Called at creation and after
+// the graph's CSR has been replaced.
+static int ws_graph_state(Workspace *w, const gde_graph *g, hipStream_t s) {
+    const int64_t n = w->n;
+    const size_t vs = w->vsize;
+    if (g->nnz > w->nnz_cap) {
+        (void)hipFree(w->tile_start);
+        (void)hipFree(w->bin_w);
+        (void)hipFree(w->bin_v);
+        w->tile_start = nullptr;
+        w->bin_w = nullptr;
+        w->bin_v = nullptr;
+        const int64_t cap = g->nnz + g->nnz / 8 + 65536;
+        GDE_HIP(hipMalloc((void **)&w->tile_start, 4 * (size_t)(cap / kPushTile + 2)));
+        if (w->bin_nranges > 0) {
+            GDE_HIP(hipMalloc((void **)&w->bin_w, 4 * (size_t)cap));
+            GDE_HIP(hipMalloc(&w->bin_v, vs * (size_t)cap));
+        }
+        w->nnz_cap = cap;
+    }
+    if (w->vtype == GDE_F64) launch_init_rd<double>(g->row_ptr, w->rd, g->n, s);
+    else launch_init_rd<float>(g->row_ptr, w->rd, g->n, s);
+    if (w->rd2) {
+        if (w->vtype == GDE_F64) launch_init_rd<double>(g->row_ptr, w->rd2, g->n, s);
+        else launch_init_rd<float>(g->row_ptr, w->rd2, g->n, s);
+    }
+    GDE_HIP(hipGetLastError());
+    if (w->bin_nranges > 0) {
+        const int64_t nr = w->bin_nranges;
+        unsigned long long *cnt = nullptr;
+        GDE_HIP(hipMalloc((void **)&cnt, 8 * nr));
+        GDE_HIP(hipMemsetAsync(cnt, 0, 8 * nr, s));
+        launch_bin_count(g->col_idx, g->nnz, w->bin_shift, (int)nr, cnt, s);
+        std::vector<unsigned long long> h(nr);
+        hipError_t e = hipMemcpyAsync(h.data(), cnt, 8 * nr, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(cnt);
+        if (e != hipSuccess) return hip_fail(e, "bin counts");
+        std::vector<long long> base(nr + 1, 0);
+        for (int64_t r = 0; r < nr; r++) base[r + 1] = base[r] + (long long)h[r];
+        GDE_HIP(hipMemcpyAsync(w->bin_base, base.data(), 8 * (nr + 1), hipMemcpyHostToDevice, s));
+        GDE_HIP(hipStreamSynchronize(s));
+    }
+    (void)n;
+    return GDE_OK;
+}
+
 static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out) {
     Workspace *w = new Workspace();
     w->g = g;
@@ -171,14 +220,9 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     WS_ALLOC(w->wl_beg, 4 * n);
     WS_ALLOC(w->wl_off, 4 * n);
     WS_ALLOC(w->wl_sv, vs * n);
-    WS_ALLOC(w->tile_start, 4 * (g->nnz / kPushTile + 2));
     WS_ALLOC(w->st, sizeof(DevState));
     hipError_t e = hipHostMalloc((void **)&w->hst, sizeof(DevState), hipHostMallocDefault);
     if (e != hipSuccess) { ws_free(w); return hip_fail(e, "hipHostMalloc"); }
-    if (vtype == GDE_F64) launch_init_rd<double>(g->row_ptr, w->rd, g->n, s);
-    else launch_init_rd<float>(g->row_ptr, w->rd, g->n, s);
-    e = hipGetLastError();
-    if (e != hipSuccess) { ws_free(w); return hip_fail(e, "init_rd"); }
     // bins of the binned scatter: one per range of 2^S nodes, sized by the range's in-volume
     int shift = 0;
     while (((int64_t)vs << (shift + 1)) <= kBinLdsBytes) shift++;
@@ -186,24 +230,12 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     if (nranges <= kBinMaxRanges) {
         w->bin_shift = shift;
         w->bin_nranges = (int)nranges;
-        unsigned long long *cnt = nullptr;
-        WS_ALLOC(cnt, 8 * nranges);
-        launch_bin_count(g->col_idx, g->nnz, shift, (int)nranges, cnt, s);
-        std::vector<unsigned long long> h(nranges);
-        e = hipMemcpyAsync(h.data(), cnt, 8 * nranges, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        (void)hipFree(cnt);
-        if (e != hipSuccess) { ws_free(w); return hip_fail(e, "bin counts"); }
-        std::vector<long long> base(nranges + 1, 0);
-        for (int64_t r = 0; r < nranges; r++) base[r + 1] = base[r] + (long long)h[r];
         WS_ALLOC(w->bin_base, 8 * (nranges + 1));
         WS_ALLOC(w->bin_cursor, 4 * nranges);
-        WS_ALLOC(w->bin_w, 4 * (size_t)std::max<long long>(base[nranges], 1));
-        WS_ALLOC(w->bin_v, vs * (size_t)std::max<long long>(base[nranges], 1));
-        e = hipMemcpyAsync(w->bin_base, base.data(), 8 * (nranges + 1), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { ws_free(w); return hip_fail(e, "bin bases"); }
     }
+    w->nnz_cap = -1;  // the graph state allocates tile table and bins
+    int rc = ws_graph_state(w, g, s);
+    if (rc) { ws_free(w); return rc; }
     (void)ctx;
     *out = w;
     return GDE_OK;
@@ -407,6 +439,19 @@ void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx) {
         if (ctx->ws[i]->guid == g->uid) { ws_free(ctx->ws[i]); ctx->ws.erase(ctx->ws.begin() + i); }
         else i++;
     }
+}
+
+// after the CSR of g was replaced (same node count): update every workspace of g in place
+int plain_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s) {
+    for (size_t i = 0; i < ctx->ws.size(); i++)
+        if (ctx->ws[i]->guid == g->uid) {
+            const int rc = ws_graph_state(ctx->ws[i], g, s);
+            if (rc) {
+                plain_workspaces_drop(g, ctx);
+                return rc;
+            }
+        }
+    return GDE_OK;
 }
 
 // ------------------------------------------------------------------ the plain solver

@@ -114,8 +114,9 @@ struct Workspace {
     int bin_nranges = 0;
     long long *bin_base = nullptr; // device [nranges + 1]
     int32_t *bin_cursor = nullptr; // device [nranges], zero between iterations
-    int32_t *bin_w = nullptr;      // device [nnz]
-    void *bin_v = nullptr;         // device [nnz] values
+    int32_t *bin_w = nullptr;      // device [nnz_cap]
+    void *bin_v = nullptr;         // device [nnz_cap] values
+    int64_t nnz_cap = 0;           // CSR entries the tile table and bins can hold
 };
 
 struct BatchWS;

@@ -37,6 +37,7 @@
 
 #include "gde_batch.h"
 #include "gde_batch_kernels.h"
+#include "gde_device.h"
 #include "gde_internal.h"
 #include "gde_kernels.h"
 
@@ -45,60 +46,73 @@ namespace gde {
 // ------------------------------------------------------------------ device helpers
 // per (group) count of active pairs; pairs of dropped groups are removed (and
 // their lanes flagged as unconverged), the rest compacted into `out`
-__global__ void k_srv_active(const uint64_t *__restrict__ in, const int32_t *cnt_in, uint64_t *out, int32_t *cnt_out,
-                             int32_t cap, int32_t G, const int32_t *__restrict__ drop, int32_t *group_active,
-                             uint32_t *NM, uint32_t *unconv) {
+__global__ void __launch_bounds__(kSnapBlock) k_srv_active(const uint64_t *__restrict__ in, const int32_t *cnt_in,
+                                                            uint64_t *out, int32_t *cnt_out, int32_t cap, int32_t G,
+                                                            const int32_t *__restrict__ drop, int32_t *group_active,
+                                                            uint32_t *NM, uint32_t *unconv) {
     const int n_in = min(*cnt_in, cap);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += gridDim.x * blockDim.x) {
-        const uint64_t p = in[i];
-        const int32_t g = (int32_t)(p >> 32), u = (int32_t)(p & 0xffffffffull);
-        if (drop[g]) {
-            uint32_t *nm = &NM[(size_t)u * G + g];
-            const uint32_t m = *nm;
-            *nm = 0u;
-            if (m) atomicOr(&unconv[g], m);
-        } else {
-            atomicAdd(&group_active[g], 1);
-            const int s = atomicAdd(cnt_out, 1);
-            if (s < cap) out[s] = p;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < n_in; base += stride) {  // workgroup-uniform trip count
+        const int i = base + (int)threadIdx.x;
+        bool keep = false;
+        uint64_t p = 0;
+        if (i < n_in) {
+            p = in[i];
+            const int32_t g = (int32_t)(p >> 32), u = (int32_t)(p & 0xffffffffull);
+            if (drop[g]) {
+                uint32_t *nm = &NM[(size_t)u * G + g];
+                const uint32_t m = *nm;
+                *nm = 0u;
+                if (m) atomicOr(&unconv[g], m);
+            } else {
+                keep = true;
+                if (group_active[g] == 0) group_active[g] = 1;  // a flag: any writer stores 1
+            }
         }
+        const int s = block_reserve(keep ? 1 : 0, cnt_out);
+        if (keep && s < cap) out[s] = p;
     }
 }
 
 // residual norms of the harvested groups over their touched pairs (each read and
 // zeroed once); the other groups' pairs are kept (compacted into `out`)
 template <int L>
-__global__ void k_srv_residual(const uint64_t *__restrict__ in, const int32_t *cnt_in, uint64_t *out,
-                               int32_t *cnt_out, int32_t cap, int32_t G, const int32_t *__restrict__ harvest,
-                               float *R, uint32_t *TM, const float *__restrict__ deg, const float *__restrict__ rscale,
-                               double *lane_l1, unsigned long long *lane_dinf) {
+__global__ void __launch_bounds__(kBlock) k_srv_residual(const uint64_t *__restrict__ in, const int32_t *cnt_in,
+                                                          uint64_t *out, int32_t *cnt_out, int32_t cap, int32_t G,
+                                                          const int32_t *__restrict__ harvest, float *R, uint32_t *TM,
+                                                          const float *__restrict__ deg,
+                                                          const float *__restrict__ rscale, double *lane_l1,
+                                                          unsigned long long *lane_dinf) {
     constexpr int PPW = kWave / L;
     const int lane = (int)__lane_id();
     const int sub = lane / L, l = lane % L;
     const int n_in = min(*cnt_in, cap);
-    const int wave_id = blockIdx.x * (blockDim.x / kWave) + (int)threadIdx.x / kWave;
-    const int nwaves = gridDim.x * (blockDim.x / kWave);
-    for (int base = wave_id * PPW; base < n_in; base += nwaves * PPW) {
-        const int i = base + sub;
-        if (i >= n_in) continue;
-        const uint64_t p = in[i];
-        const int32_t g = (int32_t)(p >> 32), w = (int32_t)(p & 0xffffffffull);
-        if (harvest[g]) {
-            const size_t ri = ((size_t)w * G + g) * L + l;
-            const float val = R[ri];
-            R[ri] = 0.0f;
-            if (l == 0) TM[(size_t)w * G + g] = 0u;
-            const double av = fabs((double)val) * (double)rscale[g];
-            if (av > 0.0) {
-                const int lane_id = g * L + l;
-                atomicAdd(&lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)deg[w]);
-                if (lane_dinf[lane_id] < bits) atomicMax(&lane_dinf[lane_id], bits);
+    const int wpb = (int)blockDim.x / kWave;
+    for (int bbase = blockIdx.x * wpb * PPW; bbase < n_in; bbase += gridDim.x * wpb * PPW) {
+        const int i = bbase + ((int)threadIdx.x / kWave) * PPW + sub;
+        bool keep = false;
+        uint64_t p = 0;
+        if (i < n_in) {
+            p = in[i];
+            const int32_t g = (int32_t)(p >> 32), w = (int32_t)(p & 0xffffffffull);
+            if (harvest[g]) {
+                const size_t ri = ((size_t)w * G + g) * L + l;
+                const float val = R[ri];
+                R[ri] = 0.0f;
+                if (l == 0) TM[(size_t)w * G + g] = 0u;
+                const double av = fabs((double)val) * (double)rscale[g];
+                if (av > 0.0) {
+                    const int lane_id = g * L + l;
+                    atomicAdd(&lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)deg[w]);
+                    if (lane_dinf[lane_id] < bits) atomicMax(&lane_dinf[lane_id], bits);
+                }
+            } else {
+                keep = l == 0;
             }
-        } else if (l == 0) {
-            const int s = atomicAdd(cnt_out, 1);
-            if (s < cap) out[s] = p;
         }
+        const int s = block_reserve(keep ? 1 : 0, cnt_out);
+        if (keep && s < cap) out[s] = p;
     }
 }
 
@@ -325,6 +339,16 @@ struct gde_server {
     float *d_out_val = nullptr;
     int64_t out_cap = 0;
     int64_t inserted_edges = 0;
+    // insertion buffers, kept across batches: the CSR being built next (spare)
+    // and the node-sized and batch-sized scratch
+    int32_t *spare_rp = nullptr, *spare_ci = nullptr;
+    int64_t spare_ci_cap = 0, cur_ci_cap = 0;
+    int32_t *t_add = nullptr, *t_olddeg = nullptr, *t_cursor = nullptr, *t_bsum = nullptr;
+    int32_t *t_src = nullptr, *t_dst = nullptr, *t_flag = nullptr;
+    int64_t t_cap = 0;
+    // host staging of heat-kernel results (result_capacity entries)
+    std::vector<int32_t> hk_idx;
+    std::vector<float> hk_val;
 };
 
 namespace gde {
@@ -334,6 +358,7 @@ int batch_ws_acquire(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int G, 
 void batch_args_from_ws(BatchWS *w, const gde_graph *g, int G, BatchArgs<float> *a);
 int32_t *batch_ws_touch_count(BatchWS *w);
 void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx);
+int plain_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s);
 gde_graph *graph_wrap_device(gde_ctx *ctx, int32_t n, int64_t nnz, int32_t *rp, int32_t *ci);
 int graph_replace_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std::vector<int32_t> &inc);
 
@@ -582,7 +607,7 @@ static int srv_step(gde_server *sv) {
     GDE_HIP(hipMemcpyAsync(sv->d_drop, drop.data(), 4 * sv->G, hipMemcpyHostToDevice, sv->s));
     GDE_HIP(hipMemsetAsync(sv->d_gactive, 0, 4 * sv->G, sv->s));
     GDE_HIP(hipMemsetAsync(sv->d_cnt, 0, 4, sv->s));
-    hipLaunchKernelGGL(k_srv_active, dim3(1024), dim3(256), 0, sv->s, a.act[cur], &a.st->acount[cur], sv->d_act_tmp,
+    hipLaunchKernelGGL(k_srv_active, dim3(512), dim3(kSnapBlock), 0, sv->s, a.act[cur], &a.st->acount[cur], sv->d_act_tmp,
                        sv->d_cnt, a.act_cap, sv->G, sv->d_drop, sv->d_gactive, a.NM, a.group_unconv);
     GDE_HIP(hipGetLastError());
     batch_ws_swap_list(sv->w, cur, &sv->d_act_tmp);
@@ -601,20 +626,26 @@ static int srv_step(gde_server *sv) {
 }
 
 static int srv_hk(gde_server *sv) {
-    // heat-kernel queries: the plain level-push solver on the server's stream
-    for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+    // heat-kernel queries: the plain level-push solver on the server's stream,
+    // oldest first, at most kHkPerPoll per call so that the batched groups keep
+    // advancing between them
+    constexpr int kHkPerPoll = 4;
+    int done = 0;
+    const int64_t cap = std::max<int32_t>(sv->cfg.result_capacity, 1);
+    if ((int64_t)sv->hk_idx.size() < cap) {
+        sv->hk_idx.resize(cap);
+        sv->hk_val.resize(cap);
+    }
+    for (auto it = sv->pending.begin(); it != sv->pending.end() && done < kHkPerPoll;) {
         if (it->p.kind != GDE_HK) { ++it; continue; }
         gde_seed sd{(int32_t)it->idx.size(), it->idx.data(), it->val.data()};
         gde_params p = it->p;
         p.value_type = GDE_F32;
         p.flags &= ~(uint32_t)(GDE_RESULT_DEVICE | GDE_TRACE);
-        const int64_t cap = std::max<int32_t>(sv->cfg.result_capacity, 1);
-        std::vector<int32_t> ii(cap);
-        std::vector<float> vv(cap);
         gde_result r{};
         r.capacity = cap;
-        r.idx = ii.data();
-        r.val = vv.data();
+        r.idx = sv->hk_idx.data();
+        r.val = sv->hk_val.data();
         const int rc = gde_solve(sv->ctx, sv->g, &p, &sd, &r, sv->s);
         gde_completion c{};
         c.ticket = it->ticket;
@@ -625,12 +656,11 @@ static int srv_hk(gde_server *sv) {
         c.residual_l1 = r.residual_l1;
         c.residual_dinf = r.residual_dinf;
         c.nnz = (rc == GDE_OK || rc == GDE_ERR_NOT_CONVERGED) ? r.nnz : 0;
-        ii.resize(c.nnz);
-        vv.resize(c.nnz);
         sv->done.push_back(c);
-        sv->done_idx.push_back(std::move(ii));
-        sv->done_val.push_back(std::move(vv));
+        sv->done_idx.emplace_back(sv->hk_idx.begin(), sv->hk_idx.begin() + c.nnz);
+        sv->done_val.emplace_back(sv->hk_val.begin(), sv->hk_val.begin() + c.nnz);
         it = sv->pending.erase(it);
+        done++;
         if (rc == GDE_ERR_DEVICE) return rc;
     }
     return GDE_OK;
@@ -650,10 +680,16 @@ static int srv_apply_inserts(gde_server *sv) {
         std::vector<int32_t> cu, cv;
         for (const auto &e : uniq) { cu.push_back(e.first); cv.push_back(e.second); }
         const int32_t mc = (int32_t)cu.size();
-        int32_t *du = nullptr, *dv = nullptr, *fl = nullptr;
-        GDE_HIP(hipMalloc((void **)&du, 4 * (size_t)mc));
-        GDE_HIP(hipMalloc((void **)&dv, 4 * (size_t)mc));
-        GDE_HIP(hipMalloc((void **)&fl, 4 * (size_t)mc));
+        if (2 * (int64_t)mc > sv->t_cap) {  // batch-sized scratch, grown geometrically
+            (void)hipFree(sv->t_src); (void)hipFree(sv->t_dst); (void)hipFree(sv->t_flag);
+            sv->t_src = sv->t_dst = sv->t_flag = nullptr;
+            const int64_t c = std::max<int64_t>(2 * (int64_t)mc, 2 * sv->t_cap);
+            GDE_HIP(hipMalloc((void **)&sv->t_src, 4 * (size_t)c));
+            GDE_HIP(hipMalloc((void **)&sv->t_dst, 4 * (size_t)c));
+            GDE_HIP(hipMalloc((void **)&sv->t_flag, 4 * (size_t)c));
+            sv->t_cap = c;
+        }
+        int32_t *du = sv->t_src, *dv = sv->t_dst, *fl = sv->t_flag;
         GDE_HIP(hipMemcpyAsync(du, cu.data(), 4 * (size_t)mc, hipMemcpyHostToDevice, sv->s));
         GDE_HIP(hipMemcpyAsync(dv, cv.data(), 4 * (size_t)mc, hipMemcpyHostToDevice, sv->s));
         hipLaunchKernelGGL(k_srv_present, dim3(1024), dim3(256), 0, sv->s, sv->g->row_ptr, sv->g->col_idx, du, dv, mc,
@@ -661,7 +697,6 @@ static int srv_apply_inserts(gde_server *sv) {
         std::vector<int32_t> hf(mc);
         GDE_HIP(hipMemcpyAsync(hf.data(), fl, 4 * (size_t)mc, hipMemcpyDeviceToHost, sv->s));
         GDE_HIP(hipStreamSynchronize(sv->s));
-        (void)hipFree(du); (void)hipFree(dv); (void)hipFree(fl);
         for (int32_t i = 0; i < mc; i++) {
             if (hf[i]) continue;
             src.push_back(cu[i]); dst.push_back(cv[i]);
@@ -673,17 +708,31 @@ static int srv_apply_inserts(gde_server *sv) {
     const int32_t n = sv->g->n;
     const int64_t new_nnz = sv->g->nnz + m;
     if (new_nnz >= (int64_t)INT32_MAX) return fail(GDE_ERR_OOM, "graph would exceed 2^31 entries");
-    int32_t *d_src = nullptr, *d_dst = nullptr, *add = nullptr, *newrp = nullptr, *newci = nullptr, *cursor = nullptr,
-            *bsum = nullptr, *olddeg = nullptr, *nodes = nullptr;
     const int nb = (n + 255) / 256;
-    GDE_HIP(hipMalloc((void **)&d_src, 4 * (size_t)m));
-    GDE_HIP(hipMalloc((void **)&d_dst, 4 * (size_t)m));
-    GDE_HIP(hipMalloc((void **)&add, 4 * (size_t)n));
-    GDE_HIP(hipMalloc((void **)&olddeg, 4 * (size_t)n));
-    GDE_HIP(hipMalloc((void **)&newrp, 4 * ((size_t)n + 1)));
-    GDE_HIP(hipMalloc((void **)&newci, 4 * (size_t)new_nnz));
-    GDE_HIP(hipMalloc((void **)&cursor, 4 * (size_t)n));
-    GDE_HIP(hipMalloc((void **)&bsum, 4 * (size_t)nb));
+    if (!sv->t_add) {  // node-sized scratch, allocated once
+        GDE_HIP(hipMalloc((void **)&sv->t_add, 4 * (size_t)n));
+        GDE_HIP(hipMalloc((void **)&sv->t_olddeg, 4 * (size_t)n));
+        GDE_HIP(hipMalloc((void **)&sv->t_cursor, 4 * (size_t)n));
+        GDE_HIP(hipMalloc((void **)&sv->t_bsum, 4 * (size_t)nb));
+        GDE_HIP(hipMalloc((void **)&sv->spare_rp, 4 * ((size_t)n + 1)));
+    }
+    if (sv->spare_ci_cap < new_nnz) {  // the next CSR, with room for later batches
+        (void)hipFree(sv->spare_ci);
+        sv->spare_ci = nullptr;
+        const int64_t c = std::min<int64_t>(new_nnz + new_nnz / 8 + 65536, (int64_t)INT32_MAX);
+        GDE_HIP(hipMalloc((void **)&sv->spare_ci, 4 * (size_t)c));
+        sv->spare_ci_cap = c;
+    }
+    if (m > sv->t_cap) {
+        (void)hipFree(sv->t_src); (void)hipFree(sv->t_dst); (void)hipFree(sv->t_flag);
+        sv->t_src = sv->t_dst = sv->t_flag = nullptr;
+        GDE_HIP(hipMalloc((void **)&sv->t_src, 4 * (size_t)m));
+        GDE_HIP(hipMalloc((void **)&sv->t_dst, 4 * (size_t)m));
+        GDE_HIP(hipMalloc((void **)&sv->t_flag, 4 * (size_t)m));
+        sv->t_cap = m;
+    }
+    int32_t *d_src = sv->t_src, *d_dst = sv->t_dst, *add = sv->t_add, *newrp = sv->spare_rp, *newci = sv->spare_ci,
+            *cursor = sv->t_cursor, *bsum = sv->t_bsum, *olddeg = sv->t_olddeg, *nodes = sv->t_flag;
     GDE_HIP(hipMemcpyAsync(d_src, src.data(), 4 * (size_t)m, hipMemcpyHostToDevice, sv->s));
     GDE_HIP(hipMemcpyAsync(d_dst, dst.data(), 4 * (size_t)m, hipMemcpyHostToDevice, sv->s));
     GDE_HIP(hipMemsetAsync(add, 0, 4 * (size_t)n, sv->s));
@@ -703,7 +752,6 @@ static int srv_apply_inserts(gde_server *sv) {
     std::vector<int32_t> hnodes(src);
     std::sort(hnodes.begin(), hnodes.end());
     hnodes.erase(std::unique(hnodes.begin(), hnodes.end()), hnodes.end());
-    GDE_HIP(hipMalloc((void **)&nodes, 4 * hnodes.size()));
     GDE_HIP(hipMemcpyAsync(nodes, hnodes.data(), 4 * hnodes.size(), hipMemcpyHostToDevice, sv->s));
     bool any_busy = false;
     for (SGroup &gr : sv->groups)
@@ -723,14 +771,19 @@ static int srv_apply_inserts(gde_server *sv) {
         GDE_HIP(hipGetLastError());
     }
     GDE_HIP(hipStreamSynchronize(sv->s));
-    // swap in the new CSR; degree-dependent state follows
+    // swap in the new CSR (the old one becomes the spare); degree-dependent state follows
+    int32_t *old_rp = sv->g->row_ptr, *old_ci = sv->g->col_idx;
+    const int64_t old_cap = sv->cur_ci_cap > 0 ? sv->cur_ci_cap : sv->g->nnz;
+    sv->g->owned = false;  // keep the old arrays: they are reused for the next batch
     int rc = graph_replace_csr(sv->g, newrp, newci, new_nnz, src);
     if (rc) return rc;
-    plain_workspaces_drop(sv->g, sv->ctx);
+    sv->cur_ci_cap = sv->spare_ci_cap;
+    sv->spare_rp = old_rp;
+    sv->spare_ci = old_ci;
+    sv->spare_ci_cap = old_cap;
+    if ((rc = plain_workspaces_refresh(sv->g, sv->ctx, sv->s))) return rc;
     GDE_HIP(batch_init_deg<float>(sv->g->row_ptr, (float *)a.deg, n, sv->s));
     GDE_HIP(hipStreamSynchronize(sv->s));
-    (void)hipFree(d_src); (void)hipFree(d_dst); (void)hipFree(add); (void)hipFree(olddeg); (void)hipFree(cursor);
-    (void)hipFree(bsum); (void)hipFree(nodes);
     sv->inserted_edges += m / 2;
     return GDE_OK;
 }
@@ -856,7 +909,9 @@ int gde_server_destroy(gde_server *sv) {
     if (!sv) return fail(GDE_ERR_INVALID_ARG, "null server");
     if (sv->s) (void)hipStreamSynchronize(sv->s);
     void *p[] = {sv->d_drop, sv->d_gactive, sv->d_kind, sv->d_mode, sv->d_cnt, sv->d_gws, sv->d_gparam, sv->d_rscale,
-                 sv->d_act_tmp, sv->d_touch_tmp, sv->d_seed_b, sv->d_seed_lane, sv->d_seed_node, sv->d_out_idx, sv->d_out_val};
+                 sv->d_act_tmp, sv->d_touch_tmp, sv->d_seed_b, sv->d_seed_lane, sv->d_seed_node, sv->d_out_idx, sv->d_out_val,
+                 sv->spare_rp, sv->spare_ci, sv->t_add, sv->t_olddeg, sv->t_cursor, sv->t_bsum, sv->t_src, sv->t_dst,
+                 sv->t_flag};
     for (void *q : p)
         if (q) (void)hipFree(q);
     if (sv->ctx) gde_ctx_destroy(sv->ctx);
