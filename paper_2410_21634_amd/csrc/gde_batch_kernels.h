@@ -10,6 +10,7 @@
 namespace gde {
 
 constexpr int kStatShards = 64;  // per-lane counters are sharded to spread atomics
+constexpr int kResLdsLanes = 4096;  // lanes whose residual norms a workgroup can sum in LDS (64 KB)
 
 struct BatchDev {
     unsigned long long packed[2];  // (entries << 40) | lane-edges of iteration parity

@@ -335,14 +335,25 @@ __global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane,
 
 // Residual norms per lane over the touched pairs (each pair read and zeroed
 // once, L threads per pair), plus the lanes still active at the iteration cap.
+// With lds_lanes (G*L lanes fit in the dynamic LDS) a workgroup first sums its
+// share per lane in LDS and adds each lane's total once at the end, instead of
+// one global atomic per nonzero (pair, lane).
 template <typename V, int L>
-__global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, double rscale, int last) {
+__global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, double rscale, int last, int lds_lanes) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_res[];
+    double *s_l1 = (double *)s_res;
+    unsigned long long *s_dm = (unsigned long long *)(s_l1 + lds_lanes);
     BatchDev *st = a.st;
     constexpr int PPW = kWave / L;
     const int sub = blane() / L, l = blane() % L;
     const int wave_id = blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave;
     const int nwaves = gridDim.x * (kBlock / kWave);
     const int nt = min(st->tcount, a.touch_cap);
+    for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
+        s_l1[j] = 0.0;
+        s_dm[j] = 0ull;
+    }
+    __syncthreads();
     for (int base = wave_id * PPW; base < nt; base += nwaves * PPW) {
         const int i = base + sub;
         if (i < nt) {
@@ -355,13 +366,22 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
             const double av = fabs((double)val) * rscale;
             if (av > 0.0) {
                 const int lane_id = g * L + l;
-                atomicAdd(&a.lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
-                const double dv = av / (double)a.deg[w];
-                unsigned long long *dm = &a.lane_dinf[lane_id];
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(dv);
-                if (*dm < bits) atomicMax(dm, bits);
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)a.deg[w]);
+                if (lds_lanes) {
+                    atomicAdd(&s_l1[lane_id], av);
+                    if (s_dm[lane_id] < bits) atomicMax(&s_dm[lane_id], bits);
+                } else {
+                    atomicAdd(&a.lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
+                    unsigned long long *dm = &a.lane_dinf[lane_id];
+                    if (*dm < bits) atomicMax(dm, bits);
+                }
             }
         }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
+        if (s_l1[j] != 0.0) atomicAdd(&a.lane_l1[(size_t)j * kStatShards + (blockIdx.x & (kStatShards - 1))], s_l1[j]);
+        if (s_dm[j] != 0ull && a.lane_dinf[j] < s_dm[j]) atomicMax(&a.lane_dinf[j], s_dm[j]);
     }
     // pairs left in the active list at the iteration cap: their lanes did not converge
     const int na = min(st->acount[last], a.act_cap);
@@ -568,10 +588,12 @@ hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, i
                         const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,
                         hipStream_t s) {
     const int sg = (ns + 255) / 256;
+    const int lds_lanes = (int64_t)a.G * L <= kResLdsLanes ? a.G * L : 0;
     switch (L) {
 #define GDE_BF(LL)                                                                                             \
     case LL:                                                                                                   \
-        hipLaunchKernelGGL((k_batch_residual<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, rscale, last);        \
+        hipLaunchKernelGGL((k_batch_residual<V, LL>), dim3(grid), dim3(kBlock), 16 * (size_t)lds_lanes, s, a,   \
+                           rscale, last, lds_lanes);                                                           \
         if (sub_flag) hipLaunchKernelGGL((k_batch_subtract_seed<V, LL>), dim3(sg), dim3(256), 0, s, a, s_lane, \
                                          s_node, s_val, ns, sub_flag);                                         \
         break;
