@@ -639,32 +639,47 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     if (!converged) status = GDE_ERR_NOT_CONVERGED;
 
     // ------------------------------------------------ output (sorted by node id) and reset
-    GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    GDE_HIP(hipStreamSynchronize(s));
-    const int64_t nnz = w->hst->pushed_count;
     const int64_t nwords = (w->n + 31) / 32;
-    const bool fits = nnz <= res->capacity && res->idx && res->val;
     const bool dev_out = (p->flags & GDE_RESULT_DEVICE) != 0;
-    int32_t *o_idx = nullptr;
-    void *o_val = nullptr;
-    if (fits) {
-        if (dev_out) { o_idx = res->idx; o_val = res->val; }
-        else {
+    int64_t nnz = 0;
+    bool fits = false;
+    if (dev_out) {
+        // device buffers: the output kernel itself checks |support| <= capacity
+        // and writes nothing otherwise, so one synchronisation suffices
+        const bool bufs = res->idx && res->val;
+        launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
+        launch_ex_scan(w->blk, w->nblk, w->st, s);
+        launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, bufs ? res->idx : nullptr,
+                          bufs ? res->val : nullptr, bufs ? res->capacity : 0, w->st, s);
+        GDE_HIP(hipGetLastError());
+        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        nnz = w->hst->pushed_count;
+        fits = bufs && nnz <= res->capacity;
+    } else {
+        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        nnz = w->hst->pushed_count;
+        fits = nnz <= res->capacity && res->idx && res->val;
+        int32_t *o_idx = nullptr;
+        void *o_val = nullptr;
+        if (fits) {
             if ((rc = ws_ensure_out(w, std::max<int64_t>(nnz, 1)))) return rc;
-            o_idx = w->out_idx; o_val = w->out_val;
+            o_idx = w->out_idx;
+            o_val = w->out_val;
         }
-    }
-    launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
-    launch_ex_scan(w->blk, w->nblk, w->st, s);
-    launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, s);
-    GDE_HIP(hipGetLastError());
-    if (fits && !dev_out && nnz > 0) {
-        GDE_HIP(hipMemcpyAsync(res->idx, w->out_idx, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
-        GDE_HIP(hipMemcpyAsync(res->val, w->out_val, w->vsize * (size_t)nnz, hipMemcpyDeviceToHost, s));
+        launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
+        launch_ex_scan(w->blk, w->nblk, w->st, s);
+        launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, nullptr, s);
+        GDE_HIP(hipGetLastError());
+        if (fits && nnz > 0) {
+            GDE_HIP(hipMemcpyAsync(res->idx, w->out_idx, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+            GDE_HIP(hipMemcpyAsync(res->val, w->out_val, w->vsize * (size_t)nnz, hipMemcpyDeviceToHost, s));
+        }
+        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
     }
     const DevState &h = *w->hst;
-    GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    GDE_HIP(hipStreamSynchronize(s));
     if (h.overflow) return fail(GDE_ERR_DEVICE, "internal list overflow (a frontier invariant was broken)");
     if ((rc = prof_collect(ctx, h.ops, h.pushes))) return rc;
     res->nnz = nnz;

@@ -42,13 +42,15 @@ struct BatchWS {
     int32_t *out_idx = nullptr;
     int64_t out_cap = 0;
     int nblk = 0;
+    void **lane_dst = nullptr;  // [2 * Gcap * L]: per-lane output pointers (idx, then val) for device results
 };
 
 void batch_ws_free(BatchWS *w) {
     void *p[] = {w->R, w->X, w->deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
                  w->act[0], w->act[1], w->touched, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
-                 w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx};
+                 w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
+                 w->lane_dst};
     for (void *q : p)
         if (q) (void)hipFree(q);
     delete w;
@@ -163,6 +165,7 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     BALLOC(w->group_unconv, (size_t)G * 4);
     BALLOC(w->cnt, (size_t)GL * w->nblk * 4);
     BALLOC(w->st, sizeof(BatchDev));
+    BALLOC(w->lane_dst, 2 * (size_t)GL * sizeof(void *));
     hipError_t e = vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)w->deg, g->n, s)
                                     : batch_init_deg<float>(g->row_ptr, (float *)w->deg, g->n, s);
     if (e != hipSuccess) { batch_ws_free(w); return hip_fail(e, "batch_init_deg"); }
@@ -426,24 +429,39 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
             total += nnz[j];
         }
     }
-    if (total > w->out_cap) {
-        if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
-        w->out_idx = nullptr;
-        w->out_val = nullptr;
-        w->out_cap = 0;
-        GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)total));
-        GDE_HIP(hipMalloc(&w->out_val, sizeof(V) * (size_t)total));
-        w->out_cap = total;
-    }
-    GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
-    GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, w->out_idx, (V *)w->out_val,
-                             1, s));
-    for (int j = 0; j < B; j++) {
-        const int q = order[j];
-        if (off[j] < 0 || nnz[j] == 0) continue;
-        const hipMemcpyKind kd = (p[q].flags & GDE_RESULT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        GDE_HIP(hipMemcpyAsync(res[q].idx, w->out_idx + off[j], 4 * (size_t)nnz[j], kd, s));
-        GDE_HIP(hipMemcpyAsync(res[q].val, (V *)w->out_val + off[j], sizeof(V) * (size_t)nnz[j], kd, s));
+    const bool dev_out = (p[0].flags & GDE_RESULT_DEVICE) != 0;
+    if (dev_out) {
+        // every lane's entries go straight to its query's device buffers
+        std::vector<void *> dst(2 * (size_t)GL, nullptr);
+        for (int j = 0; j < B; j++) {
+            if (off[j] < 0) continue;
+            dst[j] = res[order[j]].idx;
+            dst[GL + j] = res[order[j]].val;
+        }
+        GDE_HIP(hipMemcpyAsync(w->lane_dst, dst.data(), sizeof(void *) * dst.size(), hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
+        GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, nullptr, nullptr, 1, s,
+                                 nullptr, 0, (int32_t *const *)w->lane_dst, (V *const *)(w->lane_dst + GL)));
+    } else {
+        if (total > w->out_cap) {
+            if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
+            w->out_idx = nullptr;
+            w->out_val = nullptr;
+            w->out_cap = 0;
+            GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)total));
+            GDE_HIP(hipMalloc(&w->out_val, sizeof(V) * (size_t)total));
+            w->out_cap = total;
+        }
+        GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
+        GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, w->out_idx,
+                                 (V *)w->out_val, 1, s));
+        for (int j = 0; j < B; j++) {
+            const int q = order[j];
+            if (off[j] < 0 || nnz[j] == 0) continue;
+            GDE_HIP(hipMemcpyAsync(res[q].idx, w->out_idx + off[j], 4 * (size_t)nnz[j], hipMemcpyDeviceToHost, s));
+            GDE_HIP(hipMemcpyAsync(res[q].val, (V *)w->out_val + off[j], sizeof(V) * (size_t)nnz[j],
+                                   hipMemcpyDeviceToHost, s));
+        }
     }
     std::vector<long long> ops(GL * kStatShards), pushes(GL * kStatShards);
     std::vector<double> l1(GL * kStatShards);

@@ -89,7 +89,8 @@ hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, i
 template <typename V>
 hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
                          const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s,
-                         const int32_t *gmap = nullptr, int ngroups = 0);
+                         const int32_t *gmap = nullptr, int ngroups = 0, int32_t *const *lane_idx = nullptr,
+                         V *const *lane_val = nullptr);
 template <typename V> hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s);
 
 }  // namespace gde

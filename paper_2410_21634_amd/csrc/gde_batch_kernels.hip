@@ -469,7 +469,9 @@ template <typename V, int L>
 __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const int32_t *__restrict__ cnt, int nblk,
                                                            const long long *__restrict__ lane_out_off,
                                                            int32_t *out_idx, V *out_val, int write,
-                                                           const int32_t *__restrict__ gmap) {
+                                                           const int32_t *__restrict__ gmap,
+                                                           int32_t *const *__restrict__ lane_idx,
+                                                           V *const *__restrict__ lane_val) {
     __shared__ int s[L][kBlock];
     const int g = gmap ? gmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -513,9 +515,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const 
             for (int l = 0; l < L; l++) {
                 const V xv = xr[l];
                 if (xv != (V)0) {
-                    if (write && lane_out_off[g * L + l] >= 0) {
-                        out_idx[pos[l]] = u;
-                        out_val[pos[l]] = xv;
+                    const long long lo = lane_out_off[g * L + l];
+                    if (write && lo >= 0) {
+                        if (lane_idx) {  // straight into the query's own buffers
+                            lane_idx[g * L + l][pos[l] - lo] = u;
+                            lane_val[g * L + l][pos[l] - lo] = xv;
+                        } else {
+                            out_idx[pos[l]] = u;
+                            out_val[pos[l]] = xv;
+                        }
                     }
                     pos[l]++;
                     xr[l] = (V)0;
@@ -610,7 +618,7 @@ hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, i
 template <typename V>
 hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, int nblk, long long *lane_nnz,
                          const long long *lane_out_off, int32_t *out_idx, V *out_val, int write, hipStream_t s,
-                         const int32_t *gmap, int ngroups) {
+                         const int32_t *gmap, int ngroups, int32_t *const *lane_idx, V *const *lane_val) {
     const int ng = gmap ? ngroups : a.G;
     if (ng <= 0) return hipSuccess;
     dim3 grid((unsigned)nblk, (unsigned)ng);
@@ -623,7 +631,7 @@ hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, 
                                gmap);                                                                               \
         } else {                                                                                                    \
             hipLaunchKernelGGL((k_batch_ex_emit<V, LL>), grid, dim3(kBlock), 0, s, a, cnt, nblk, lane_out_off,      \
-                               out_idx, out_val, write, gmap);                                                      \
+                               out_idx, out_val, write, gmap, lane_idx, lane_val);                                  \
         }                                                                                                           \
         break;
         GDE_BE(8)
@@ -651,7 +659,7 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
                                         const int32_t *, const double *, int32_t, const int32_t *, hipStream_t);   \
     template hipError_t batch_extract<V>(int, const BatchArgs<V> &, int, int32_t *, int, long long *,              \
                                          const long long *, int32_t *, V *, int, hipStream_t, const int32_t *,     \
-                                         int);                                                                     \
+                                         int, int32_t *const *, V *const *);                                       \
     template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);
 
 GDE_BINST(float)

@@ -52,7 +52,7 @@ void launch_ex_count(const uint32_t *bm, int64_t nwords, int32_t *blk, int64_t n
 void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s);
 template <typename V>
 void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
-                    void *out_val, int64_t cap, hipStream_t s);
+                    void *out_val, int64_t cap, const DevState *st, hipStream_t s);
 void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
                       int32_t *dmax, hipStream_t s);
 void launch_lam_step(const int32_t *row_ptr, const int32_t *col_idx, const double *v, double *y, int32_t n,

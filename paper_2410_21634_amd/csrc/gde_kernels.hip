@@ -669,8 +669,11 @@ __global__ void __launch_bounds__(1024) k_ex_scan(int32_t *blk, int64_t nblk, De
 
 template <typename V>
 __global__ void __launch_bounds__(kBlock) k_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *__restrict__ blk,
-                                                     V *x, int32_t *out_idx, V *out_val, int64_t cap) {
+                                                     V *x, int32_t *out_idx, V *out_val, int64_t cap,
+                                                     const DevState *st) {
     __shared__ int s[kBlock];
+    // with st: write only if the whole support fits (else nothing is written)
+    if (st && (int64_t)st->pushed_count > cap) cap = 0;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     uint32_t word = i < nwords ? bm[i] : 0u;
     int c = __popc(word);
@@ -853,9 +856,9 @@ void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s) {
 }
 template <typename V>
 void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
-                    void *out_val, int64_t cap, hipStream_t s) {
+                    void *out_val, int64_t cap, const DevState *st, hipStream_t s) {
     hipLaunchKernelGGL(k_ex_emit<V>, dim3((unsigned)nblk), dim3(kBlock), 0, s, bm, nwords, blk, (V *)x, out_idx,
-                       (V *)out_val, cap);
+                       (V *)out_val, cap, st);
 }
 
 void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
@@ -891,8 +894,8 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
     template void launch_final_residual<V>(uint32_t *, int64_t, void *, DevState *, double, hipStream_t);         \
     template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
     template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \
-    template void launch_ex_emit<V>(uint32_t *, int64_t, const int32_t *, int64_t, void *, int32_t *, void *,     \
-                                    int64_t, hipStream_t);
+    template void launch_ex_emit<V>(uint32_t *, int64_t, const int32_t *, int64_t, void *, int32_t *, void *,   \
+                                    int64_t, const DevState *, hipStream_t);
 
 GDE_INST(float)
 GDE_INST(double)

@@ -158,6 +158,16 @@ def test_device_output_and_torch_graph(gde, ctx, c1):
     assert len(res.idx) == len(host.idx)
     np.testing.assert_array_equal(res.idx.cpu().numpy(), host.idx)
     np.testing.assert_allclose(res.val.cpu().numpy(), host.val, rtol=1e-5, atol=1e-9)
+    # device buffers too small: CAPACITY with the size needed, and nothing written
+    need = len(host.idx)
+    oi.fill_(-7)
+    ov.fill_(-7.0)
+    small = gde.solve(ctx, g, p, [s], out=(oi, ov), capacity=need - 1, raise_on_error=False)
+    assert small.status == gde.CAPACITY and small.extra["nnz_needed"] == need
+    assert int((oi != -7).sum()) == 0 and int((ov != -7.0).sum()) == 0
+    # and the workspace is clean afterwards: the same solve again gives the same answer
+    again = gde.solve(ctx, g, p, [s], out=(oi, ov))
+    np.testing.assert_array_equal(again.idx.cpu().numpy(), host.idx)
 
 
 def test_lambda_bounds(gde, ctx, g2k):
