@@ -497,6 +497,17 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         bins.nranges = w->bin_nranges;
         bins.min_edges = (p->flags & GDE_SCATTER_BINNED) ? 0 : kBinMinEdges;
         if (p->flags & GDE_SCATTER_ATOMIC) bins.nranges = 0;
+        // PPR LocalGD: no iteration can reach the binning threshold when the whole
+        // work bound vol(supp s) + ||s||_1 / (alpha eps) (Corollary 3.5) stays below
+        // it; then neither the binned path nor the range-reduction launches are needed
+        if (bins.nranges > 0 && !(p->flags & GDE_SCATTER_BINNED) && p->kind == GDE_PPR &&
+            p->method == GDE_LOCAL_GD) {
+            GraphHost *gh = graph_host(g);
+            double bound = 0.0;
+            for (int32_t i = 0; i < sd->nnz; i++)
+                bound += (gh ? (double)gh->deg[sd->idx[i]] : (double)g->nnz) + sd->val[i] / (p->alpha * p->eps);
+            if (bound < (double)kBinMinEdges) bins.nranges = 0;
+        }
         bins.base = w->bin_base;
         bins.cursor = w->bin_cursor;
         bins.bw = w->bin_w;

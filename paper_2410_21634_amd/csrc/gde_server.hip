@@ -82,12 +82,21 @@ __global__ void __launch_bounds__(kBlock) k_srv_residual(const uint64_t *__restr
                                                           const int32_t *__restrict__ harvest, float *R, uint32_t *TM,
                                                           const float *__restrict__ deg,
                                                           const float *__restrict__ rscale, double *lane_l1,
-                                                          unsigned long long *lane_dinf) {
+                                                          unsigned long long *lane_dinf, int lds_lanes) {
+    // per-lane partial norms in LDS (G*L lanes when they fit), one global add per lane and workgroup
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_res[];
+    double *s_l1 = (double *)s_res;
+    unsigned long long *s_dm = (unsigned long long *)(s_l1 + lds_lanes);
     constexpr int PPW = kWave / L;
     const int lane = (int)__lane_id();
     const int sub = lane / L, l = lane % L;
     const int n_in = min(*cnt_in, cap);
     const int wpb = (int)blockDim.x / kWave;
+    for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
+        s_l1[j] = 0.0;
+        s_dm[j] = 0ull;
+    }
+    __syncthreads();
     for (int bbase = blockIdx.x * wpb * PPW; bbase < n_in; bbase += gridDim.x * wpb * PPW) {
         const int i = bbase + ((int)threadIdx.x / kWave) * PPW + sub;
         bool keep = false;
@@ -103,9 +112,14 @@ __global__ void __launch_bounds__(kBlock) k_srv_residual(const uint64_t *__restr
                 const double av = fabs((double)val) * (double)rscale[g];
                 if (av > 0.0) {
                     const int lane_id = g * L + l;
-                    atomicAdd(&lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
                     const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)deg[w]);
-                    if (lane_dinf[lane_id] < bits) atomicMax(&lane_dinf[lane_id], bits);
+                    if (lds_lanes) {
+                        atomicAdd(&s_l1[lane_id], av);
+                        if (s_dm[lane_id] < bits) atomicMax(&s_dm[lane_id], bits);
+                    } else {
+                        atomicAdd(&lane_l1[(size_t)lane_id * kStatShards + (blockIdx.x & (kStatShards - 1))], av);
+                        if (lane_dinf[lane_id] < bits) atomicMax(&lane_dinf[lane_id], bits);
+                    }
                 }
             } else {
                 keep = l == 0;
@@ -113,6 +127,11 @@ __global__ void __launch_bounds__(kBlock) k_srv_residual(const uint64_t *__restr
         }
         const int s = block_reserve(keep ? 1 : 0, cnt_out);
         if (keep && s < cap) out[s] = p;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
+        if (s_l1[j] != 0.0) atomicAdd(&lane_l1[(size_t)j * kStatShards + (blockIdx.x & (kStatShards - 1))], s_l1[j]);
+        if (s_dm[j] != 0ull && lane_dinf[j] < s_dm[j]) atomicMax(&lane_dinf[j], s_dm[j]);
     }
 }
 
@@ -495,10 +514,12 @@ static int srv_harvest(gde_server *sv, const std::vector<int> &hv_groups, const 
     int32_t *tcnt = batch_ws_touch_count(w);
     GDE_HIP(hipMemsetAsync(sv->d_cnt, 0, 4, sv->s));
     const int grid = 1024;
+    const int lds_lanes = G * L <= kResLdsLanes ? G * L : 0;
+    const size_t dyn = 16 * (size_t)lds_lanes;
     switch (L) {
-    case 8: hipLaunchKernelGGL(k_srv_residual<8>, dim3(grid), dim3(256), 0, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf); break;
-    case 16: hipLaunchKernelGGL(k_srv_residual<16>, dim3(grid), dim3(256), 0, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf); break;
-    default: hipLaunchKernelGGL(k_srv_residual<32>, dim3(grid), dim3(256), 0, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf); break;
+    case 8: hipLaunchKernelGGL(k_srv_residual<8>, dim3(grid), dim3(kBlock), dyn, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf, lds_lanes); break;
+    case 16: hipLaunchKernelGGL(k_srv_residual<16>, dim3(grid), dim3(kBlock), dyn, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf, lds_lanes); break;
+    default: hipLaunchKernelGGL(k_srv_residual<32>, dim3(grid), dim3(kBlock), dyn, sv->s, a.touched, tcnt, sv->d_touch_tmp, sv->d_cnt, a.touch_cap, G, sv->d_drop, a.R, a.TM, a.deg, sv->d_rscale, a.lane_l1, a.lane_dinf, lds_lanes); break;
     }
     GDE_HIP(hipGetLastError());
     // the compacted list becomes the touched list
