@@ -595,20 +595,93 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, bscale, w->front[0], nullptr,
                             ch ? w->cstamp : nullptr, base, w->tbm, w->st, s);
         a.rd = w->rd;
+        // LocalCH scalars (c_t, m_t) of iteration t: delta_{t+1} = 1 / (2 sigma - delta_t),
+        // c_t = 2 sigma delta_{t+1}, m_t = delta_t delta_{t+1}; t = 0 is the forced first step
+        std::vector<std::pair<V, V>> chs;
+        auto ch_at = [&](int tt) {
+            while ((int)chs.size() <= tt) {
+                if (chs.empty()) {
+                    chs.push_back({(V)1, (V)0});
+                } else {
+                    const double dnext = 1.0 / (2.0 * sigma - dlt);
+                    chs.push_back({(V)(2.0 * sigma * dnext), (V)(dlt * dnext)});
+                    dlt = dnext;
+                }
+            }
+            return chs[tt];
+        };
         int t = 0, chunk = 8;
-        while (t < p->max_iters) {
+        if (!(p->flags & GDE_SCATTER_BINNED)) {
+            // small frontiers first: one workgroup, many iterations, one launch
+            SmallArgs<V> sa{};
+            sa.row_ptr = g->row_ptr;
+            sa.col_idx = g->col_idx;
+            sa.rd = w->rd;
+            sa.x = w->x;
+            sa.bitmap = w->bitmap;
+            sa.tbm = w->tbm;
+            sa.st = w->st;
+            sa.pushed = w->pushed;
+            sa.front0 = w->front[0];
+            sa.front1 = w->front[1];
+            sa.wl_node = w->wl_node;
+            sa.wl_beg = w->wl_beg;
+            sa.wl_off = w->wl_off;
+            sa.wl_sv = w->wl_sv;
+            sa.tile_start = w->tile_start;
+            sa.tr_nodes = d_trn;
+            sa.tr_ncap = tr_ncap;
+            sa.tr_size = d_trs;
+            sa.tr_vol = d_trv;
+            sa.tr_cap = tr_cap;
+            sa.wscale = wscale;
+            sa.eps_eff = eps_eff;
+            sa.w_div_deg = w_div_deg;
+            sa.delta = w->delta;
+            sa.dstamp = w->dstamp;
+            sa.cstamp = w->cstamp;
+            sa.stamp_base = base;
+            sa.cap = g->n;
+            sa.nnz = (int32_t)g->nnz;
+            sa.t0 = 0;
+            sa.t_end = std::min(p->max_iters, kSmallIters);
+            if (ch)
+                for (int k = 0; k < sa.t_end; k++) {
+                    const auto cm = ch_at(k);
+                    sa.c_seq[k] = cm.first;
+                    sa.m_seq[k] = cm.second;
+                }
+            if ((rc = prof_mark(ctx, s))) return rc;
+            launch_small<V>(sa, ch, s);
+            if ((rc = prof_mark(ctx, s))) return rc;
+            GDE_HIP(hipGetLastError());
+            GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            GDE_HIP(hipStreamSynchronize(s));
+            t = w->hst->small_t;
+            if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) {
+                converged = true;
+            } else if (w->hst->small_phase == 1) {  // S_t is snapshot; its volume needs the grid-wide push
+                if ((rc = prof_mark(ctx, s))) return rc;
+                if (ch)
+                    launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
+                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
+                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                else
+                    launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
+                                   w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
+                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                if ((rc = prof_mark(ctx, s))) return rc;
+                t++;
+            }
+        }
+        while (!converged && t < p->max_iters) {
             int end = std::min(p->max_iters, t + chunk);
             for (; t < end; t++) {
                 a.F = w->front[t & 1];
                 a.cur = t & 1;
                 if (ch) {
-                    V c_t = (V)1, m_t = (V)0;
-                    if (t > 0) {
-                        double dnext = 1.0 / (2.0 * sigma - dlt);
-                        c_t = (V)(2.0 * sigma * dnext);
-                        m_t = (V)(dlt * dnext);
-                        dlt = dnext;
-                    }
+                    const auto cm = ch_at(t);
+                    const V c_t = cm.first, m_t = cm.second;
                     launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
                                       w->cstamp, base + t, w->front[(t + 1) & 1], s);
                     if ((rc = prof_mark(ctx, s))) return rc;

@@ -23,6 +23,12 @@ constexpr int kSnapBlock = 1024;  // threads per snapshot workgroup
 constexpr int kPushBlock = 1024;  // threads per push workgroup
 constexpr int kPushTile = 4096;   // edges per push tile (4 per thread, issued together)
 constexpr int kBatchSnapBlock = 1024;  // threads per batched snapshot workgroup
+// Small frontiers: one workgroup runs consecutive iterations in one launch
+// (workgroup barriers in place of kernel boundaries) while the frontier stays
+// within these limits; larger frontiers hand over to the grid-wide kernels.
+constexpr int kSmallIters = 32;             // iterations one single-workgroup launch may run
+constexpr int kSmallMaxNodes = 4096;        // frontier / candidate list it accepts
+constexpr long long kSmallMaxEdges = 16384; // frontier volume it accepts
 // Binned scatter for large frontiers: updates are written, grouped by
 // destination range of 2^S nodes, into per-range bins and then summed in LDS
 // by one workgroup per range (no global atomic per edge).
@@ -67,6 +73,8 @@ struct DevState {
     int32_t empty_seen;            // an iteration found S_t empty (converged)
     int32_t probe;                 // LocalCH: active candidates at the iteration cap
     int32_t overflow;              // a list append found its capacity exhausted (invariant broken)
+    int32_t small_t;               // single-workgroup launch: next iteration to run
+    int32_t small_phase;           // 1: the snapshot of iteration small_t is done, its push is not
 };
 
 // Solver workspace for one (graph, value type).  All node-indexed arrays are

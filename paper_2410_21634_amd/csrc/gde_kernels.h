@@ -24,6 +24,33 @@ struct SnapArgs {
     int32_t cap;          // capacity of every node list (n)
 };
 
+// Everything the single-workgroup iteration kernel needs (LocalGD or LocalCH).
+template <typename V>
+struct SmallArgs {
+    const int32_t *row_ptr, *col_idx;
+    void *rd, *x;
+    uint32_t *bitmap, *tbm;
+    DevState *st;
+    int32_t *pushed, *front0, *front1;
+    int32_t *wl_node, *wl_beg, *wl_off;
+    void *wl_sv;
+    int32_t *tile_start;
+    int32_t *tr_nodes;
+    long long tr_ncap;
+    long long *tr_size, *tr_vol;
+    long long tr_cap;
+    V wscale, eps_eff;
+    int w_div_deg;
+    void *delta;
+    int32_t *dstamp, *cstamp;
+    int32_t stamp_base;
+    V c_seq[kSmallIters], m_seq[kSmallIters];  // LocalCH scalars of iterations t0 .. t0 + kSmallIters - 1
+    int32_t cap, nnz;
+    int t0, t_end;
+};
+
+template <typename V> void launch_small(const SmallArgs<V> &a, bool ch, hipStream_t s);
+
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
 template <typename V>
 void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,

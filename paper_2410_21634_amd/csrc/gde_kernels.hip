@@ -151,17 +151,16 @@ __device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, i
 // LocalGD: v = r_u, r_u = 0, x_u += v, scatter value W_u v with
 // W_u = wscale / d_u (PPR, wscale = 1 - alpha) or wscale (Katz, beta).
 template <typename V>
-__global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
-                                                     uint32_t *bitmap, const int32_t *__restrict__ F, DevState *st,
-                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
-                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
-                                                     int w_div_deg, int32_t *tr_nodes, long long tr_cap, int32_t cap) {
+__device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, uint32_t *bitmap,
+                        const int32_t *__restrict__ F, DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                        int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale, int w_div_deg,
+                        int32_t *tr_nodes, long long tr_cap, int32_t cap, int bid, int nblocks) {
     const int nxt = cur ^ 1;
     const int n_f = min(st->fcount[cur], cap);
     const long long push_base = st->pushes;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < n_f; base += stride) {
+    if (bid == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
+    const int stride = nblocks * blockDim.x;
+    for (int base = bid * blockDim.x; base < n_f; base += stride) {
         int i = base + threadIdx.x;
         bool act = i < n_f;
         int32_t u = 0, beg = 0, deg = 0;
@@ -179,6 +178,16 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restric
         emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
     }
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+                                                     uint32_t *bitmap, const int32_t *__restrict__ F, DevState *st,
+                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
+                                                     int w_div_deg, int32_t *tr_nodes, long long tr_cap, int32_t cap) {
+    snap_gd<V>(row_ptr, rd, x, bitmap, F, st, cur, pushed, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
+               w_div_deg, tr_nodes, tr_cap, cap, blockIdx.x, gridDim.x);
 }
 
 // Heat kernel, level k: snapshot of S_k from plane k (scatter value
@@ -236,20 +245,18 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restric
 // (all of C_0 = supp(s) at t = 0); h_u = c_t r_u + m_t Delta_u with Delta_u
 // the previous update if u was in S_{t-1}; x_u += h_u, r_u -= h_u, Delta_u = h_u.
 template <typename V>
-__global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
-                                                     uint32_t *bitmap, const int32_t *__restrict__ C, DevState *st,
-                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
-                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
-                                                     int w_div_deg, V eps_eff, V c_t, V m_t, int force, V *delta,
-                                                     int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur,
-                                                     int32_t *next_list, int32_t *tr_nodes, long long tr_cap,
-                                                     int32_t cap) {
+__device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, uint32_t *bitmap,
+                        const int32_t *__restrict__ C, DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                        int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale, int w_div_deg,
+                        V eps_eff, V c_t, V m_t, int force, V *delta, int32_t *dstamp, int32_t *cstamp,
+                        int32_t stamp_cur, int32_t *next_list, int32_t *tr_nodes, long long tr_cap, int32_t cap,
+                        int bid, int nblocks) {
     const int nxt = cur ^ 1;
     const int n_c = min(st->fcount[cur], cap);
     const long long push_base = st->pushes;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < n_c; base += stride) {
+    if (bid == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
+    const int stride = nblocks * blockDim.x;
+    for (int base = bid * blockDim.x; base < n_c; base += stride) {
         int i = base + threadIdx.x;
         bool valid = i < n_c;
         bool act = false;
@@ -279,6 +286,20 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restric
     }
 }
 
+template <typename V>
+__global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
+                                                     uint32_t *bitmap, const int32_t *__restrict__ C, DevState *st,
+                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
+                                                     int w_div_deg, V eps_eff, V c_t, V m_t, int force, V *delta,
+                                                     int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur,
+                                                     int32_t *next_list, int32_t *tr_nodes, long long tr_cap,
+                                                     int32_t cap) {
+    snap_ch<V>(row_ptr, rd, x, bitmap, C, st, cur, pushed, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
+               w_div_deg, eps_eff, c_t, m_t, force, delta, dstamp, cstamp, stamp_cur, next_list, tr_nodes, tr_cap, cap,
+               blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------------------------ push (A3 + A4)
 // MODE 0: LocalGD / monotone residual -- returned old value, crossing test.
 // MODE 1: heat kernel -- crossing test on plane k+1 and first-touch list.
@@ -290,14 +311,12 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restric
 // added when an add finds its residual at zero (MODE 0) or when it is first
 // marked as a candidate in an iteration (MODE 2).
 template <typename V, int MODE>
-__global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st,
-                                                      int cur, const int32_t *__restrict__ wl_beg,
-                                                      const int32_t *__restrict__ wl_off, const V *__restrict__ wl_sv,
-                                                      const int32_t *__restrict__ tile_start, V eps_eff,
-                                                      int32_t *next_list, int32_t *touched, int tslot,
-                                                      int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
-                                                      long long *tr_size, long long *tr_vol, long long tr_cap,
-                                                      int scatter, int32_t cap, int32_t nnz, BinArgs<V> bins) {
+__device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st, int cur,
+                           const int32_t *__restrict__ wl_beg, const int32_t *__restrict__ wl_off,
+                           const V *__restrict__ wl_sv, const int32_t *__restrict__ tile_start, V eps_eff,
+                           int32_t *next_list, int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next,
+                           uint32_t *tbm, long long *tr_size, long long *tr_vol, long long tr_cap, int scatter,
+                           int32_t cap, int32_t nnz, const BinArgs<V> &bins, int bid, int nblocks) {
     constexpr int kPer = kPushTile / kPushBlock;
     __shared__ int32_t s_off[kPushTile + 1];
     __shared__ int32_t s_beg[kPushTile + 1];
@@ -309,9 +328,9 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
     const int total = (int)(pk & 0xffffffffull);
     // S_t (or C_t) has been consumed by the snapshot: its list becomes the
     // next-but-one append target, which the snapshot of t+1 may append to.
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->fcount[cur] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && count == 0) st->empty_seen = 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && count > 0) {
+    if (bid == 0 && threadIdx.x == 0) st->fcount[cur] = 0;
+    if (bid == 0 && threadIdx.x == 0 && count == 0) st->empty_seen = 1;
+    if (bid == 0 && threadIdx.x == 0 && count > 0) {
         int it = st->iters;
         if (tr_size && it < tr_cap) {
             tr_size[it] = count;
@@ -329,7 +348,7 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
     int32_t *s_rbase = s_bin + bins.nranges;
     if (binned)
         for (int r = threadIdx.x; r < bins.nranges; r += blockDim.x) s_cnt[r] = 0;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int tile = bid; tile < ntiles; tile += nblocks) {
         const int e0 = tile * kPushTile;
         const int e1 = min(e0 + kPushTile, total);
         const int i0 = tile_start[tile];
@@ -456,6 +475,79 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                 }
         }
     }
+}
+
+template <typename V, int MODE>
+__global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st,
+                                                      int cur, const int32_t *__restrict__ wl_beg,
+                                                      const int32_t *__restrict__ wl_off, const V *__restrict__ wl_sv,
+                                                      const int32_t *__restrict__ tile_start, V eps_eff,
+                                                      int32_t *next_list, int32_t *touched, int tslot,
+                                                      int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
+                                                      long long *tr_size, long long *tr_vol, long long tr_cap,
+                                                      int scatter, int32_t cap, int32_t nnz, BinArgs<V> bins) {
+    push_edges<V, MODE>(col_idx, dst, st, cur, wl_beg, wl_off, wl_sv, tile_start, eps_eff, next_list, touched, tslot,
+                        cstamp, stamp_next, tbm, tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins, blockIdx.x,
+                        gridDim.x);
+}
+
+// Small frontiers: iterations t0 .. t_end-1 of LocalGD (CH = false) or LocalCH
+// run by ONE workgroup in one launch, the same snapshot and push code as the
+// grid-wide kernels with a device-scope fence and a workgroup barrier where a
+// kernel boundary would be.  The launch stops before the snapshot of t when
+// the list of t exceeds kSmallMaxNodes (small_phase 0), after the snapshot
+// when the volume of S_t exceeds kSmallMaxEdges (small_phase 1: the grid-wide
+// push of t follows), or when the iteration converges; small_t records where.
+template <typename V, bool CH>
+__global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
+    DevState *st = a.st;
+    RD<V> *rd = (RD<V> *)a.rd;
+    const BinArgs<V> nobins{};
+    int t = a.t0;
+    int phase = 0;
+    for (; t < a.t_end; t++) {
+        const int cur = t & 1;
+        int32_t *F = cur ? a.front1 : a.front0;
+        int32_t *Fn = cur ? a.front0 : a.front1;
+        const int n_f = __hip_atomic_load(&st->fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n_f > kSmallMaxNodes) break;
+        if (CH)
+            snap_ch<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off,
+                       (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.eps_eff, a.c_seq[t - a.t0],
+                       a.m_seq[t - a.t0], t == 0 ? 1 : 0, (V *)a.delta, a.dstamp, a.cstamp, a.stamp_base + t, Fn,
+                       a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
+        else
+            snap_gd<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off,
+                       (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
+        __threadfence();
+        __syncthreads();
+        const unsigned long long pk = __hip_atomic_load(&st->packed[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int count = (int)(pk >> 32);
+        if (count > 0 && (long long)(pk & 0xffffffffull) > kSmallMaxEdges) {
+            phase = 1;
+            break;
+        }
+        push_edges<V, CH ? 2 : 0>(a.col_idx, rd, st, cur, a.wl_beg, a.wl_off, (const V *)a.wl_sv, a.tile_start,
+                                  a.eps_eff, Fn, nullptr, 0, a.cstamp, a.stamp_base + t + 1, a.tbm, a.tr_size,
+                                  a.tr_vol, a.tr_cap, 1, a.cap, a.nnz, nobins, 0, 1);
+        __threadfence();
+        __syncthreads();
+        if (count == 0) { t++; break; }  // S_t was empty: converged (recorded by the push)
+        if (!CH && __hip_atomic_load(&st->fcount[cur ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            t++;  // LocalGD: S_{t+1} is empty
+            break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->small_t = t;
+        st->small_phase = phase;
+    }
+}
+
+template <typename V>
+void launch_small(const SmallArgs<V> &a, bool ch, hipStream_t s) {
+    if (ch) hipLaunchKernelGGL((k_small<V, true>), dim3(1), dim3(kSnapBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_small<V, false>), dim3(1), dim3(kSnapBlock), 0, s, a);
 }
 
 // Binned scatter, second half: workgroup r sums the updates of bin r into an
@@ -879,6 +971,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
 }
 
 #define GDE_INST(V)                                                                                               \
+    template void launch_small<V>(const SmallArgs<V> &, bool, hipStream_t);                                       \
     template void launch_init_rd<V>(const int32_t *, void *, int32_t, hipStream_t);                               \
     template void launch_seed_init<V>(void *, const int32_t *, const double *, int32_t, double, int32_t *,        \
                                       int32_t *, int32_t *, int32_t, uint32_t *, DevState *, hipStream_t);        \
