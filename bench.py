@@ -220,8 +220,8 @@ def run_c2(args):
         bprof = ctx.profile(False, reset=True)
         plain_gd = [r for r in recs if r[0] == "gd"]
         plain_gd_rate = len(plain_gd) / sum(r[3] for r in plain_gd)
-        bops = sum(r.ops for r in bres)
-        bpush = sum(r.pushes for r in bres)
+        bops = int(bres.ops.sum())
+        bpush = int(bres.pushes.sum())
         batched = dict(queries=len(gd_q), solves_per_s=round(len(gd_q) * args.steps / tb, 2),
                        ms_per_batch=round(1e3 * tb / args.steps, 3),
                        plain_solves_per_s_same_queries=round(plain_gd_rate, 2),
@@ -230,7 +230,7 @@ def run_c2(args):
                        kernel_ms=round(bprof["batch_ms"] / max(bprof["batch_launches"], 1), 3),
                        lane_edges_per_batch=int(bprof["batch_lane_edges"] // max(args.steps, 1)),
                        entries_per_batch=int(bprof["batch_entries"] // max(args.steps, 1)),
-                       schedule=sched or "default", not_converged=int(sum(r.status != 0 for r in bres)))
+                       schedule=sched or "default", not_converged=int((bres.status != 0).sum()))
         log(f"batched: {batched}")
 
     nq = len(queries)
@@ -317,8 +317,8 @@ def run_c4(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = ctx.profile(False, reset=True)
-    ops = sum(r.ops for r in res)
-    pushes = sum(r.pushes for r in res)
+    ops = int(res.ops.sum())
+    pushes = int(res.pushes.sum())
     value = B * args.steps / el
     gbs = alg_bytes(ops, pushes) * args.steps / el / 1e9
     kms = prof["batch_ms"] / max(prof["batch_launches"], 1)
@@ -350,8 +350,7 @@ def run_c4(args):
                plain=dict(sample=len(samp), solves_per_s=round(plain_rate, 2),
                           batched_speedup=round(value / plain_rate, 2)),
                stats=dict(total_edge_updates=int(ops), total_pushes=int(pushes),
-                          not_converged=int(sum(r.status != 0 for r in res)),
-                          mean_iters=float(np.mean([r.iters for r in res]))))
+                          not_converged=int((res.status != 0).sum()), mean_iters=float(res.iters.mean())))
     g.close()
     ctx.close()
     return out

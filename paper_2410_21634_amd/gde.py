@@ -311,54 +311,138 @@ def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *
     return res
 
 
+def _np_dtype(struct):
+    """numpy view of a ctypes Structure (pointers as uint64), for vectorised filling."""
+    conv = {C.c_int32: "<i4", C.c_uint32: "<u4", C.c_int64: "<i8", C.c_uint64: "<u8", C.c_double: "<f8"}
+    names, formats, offsets = [], [], []
+    for name, ctype in struct._fields_:
+        names.append(name)
+        formats.append(conv.get(ctype, "<u8"))
+        offsets.append(getattr(struct, name).offset)
+    return np.dtype({"names": names, "formats": formats, "offsets": offsets, "itemsize": C.sizeof(struct)})
+
+
+_PAR_DT, _SEED_DT, _RES_DT = _np_dtype(Params), _np_dtype(Seed), _np_dtype(Result)
+
+
+class BatchResults:
+    """Results of one gde_solve_batch call.  Per-query fields are numpy arrays
+    (status, nnz, iters, ops, pushes, residual_l1, residual_dinf); indexing or
+    iterating gives SolveResult objects, built on first access."""
+
+    def __init__(self, rv, idx_of, val_of, traces):
+        self._rv = rv
+        self._idx_of, self._val_of, self._traces = idx_of, val_of, traces
+        self._cache = {}
+        self.status = rv["status"].copy()
+        self.nnz = rv["nnz"].copy()
+        self.iters = rv["iters"].copy()
+        self.ops = rv["ops"].copy()
+        self.pushes = rv["pushes"].copy()
+        self.residual_l1 = rv["residual_l1"].copy()
+        self.residual_dinf = rv["residual_dinf"].copy()
+
+    def __len__(self):
+        return len(self.status)
+
+    def __getitem__(self, i):
+        if i < 0:
+            i += len(self)
+        if i not in self._cache:
+            st = int(self.status[i])
+            nnz = int(self.nnz[i]) if st in (OK, NOT_CONVERGED) else 0
+            sr = SolveResult(self._idx_of(i, nnz), self._val_of(i, nnz), st, float(self.residual_l1[i]),
+                             float(self.residual_dinf[i]), int(self.iters[i]), int(self.ops[i]), int(self.pushes[i]))
+            sr.extra["nnz_needed"] = int(self.nnz[i])
+            if i in self._traces:
+                ts, tv, tn, tcap, ncap = self._traces[i]
+                m = min(int(self._rv["trace_len"][i]), tcap)
+                sr.trace_size = ts[:m].copy()
+                sr.trace_vol = tv[:m].copy()
+                if ncap:
+                    sr.trace_nodes = tn[: min(int(self._rv["trace_nodes_len"][i]), ncap)].copy()
+            self._cache[i] = sr
+        return self._cache[i]
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+
 def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None, schedule=None, stream=None,
-                raise_on_error=True, trace_cap=4096, nodes_cap=0, out=None):
-    """B queries in one call.  ``seeds``: list of (idx, val) pairs.  ``out``: optional
-    flat (idx, val) torch device tensors split evenly between the queries (the
-    results stay in HBM).  Returns a list of SolveResult."""
+                raise_on_error=True, trace_cap=4096, nodes_cap=0, out=None) -> BatchResults:
+    """B queries in one call.  ``seeds``: list of (idx, val) pairs (val None = ones).
+    ``out``: optional flat (idx, val) torch device tensors split evenly between the
+    queries (the results stay in HBM).  Argument structs are filled vectorised."""
     B = len(params_list)
-    P = (Params * B)(*[Params.from_buffer_copy(p) for p in params_list])
+    P = (Params * B)(*params_list)
+    pv = np.frombuffer(P, dtype=_PAR_DT)
     if out is not None:
-        for p in P:
-            p.flags |= RESULT_DEVICE
-    holders = [_SeedHolder(i, v) for i, v in seeds]
-    S = (Seed * B)(*[h.seed for h in holders])
+        pv["flags"] |= RESULT_DEVICE
+    idx_l = [np.atleast_1d(np.asarray(i, dtype=np.int32)) for i, _ in seeds]
+    lens = np.fromiter((len(x) for x in idx_l), dtype=np.int64, count=B)
+    offs = np.zeros(B, np.int64)
+    offs[1:] = np.cumsum(lens)[:-1]
+    cat_idx = np.ascontiguousarray(np.concatenate(idx_l), dtype=np.int32)
+    cat_val = np.ascontiguousarray(np.concatenate([np.ones(len(x)) if v is None else np.atleast_1d(np.asarray(v, np.float64))
+                                                   for x, (_, v) in zip(idx_l, seeds)]), dtype=np.float64)
+    S = (Seed * B)()
+    sv = np.frombuffer(S, dtype=_SEED_DT)
+    sv["nnz"] = lens
+    sv["idx"] = cat_idx.ctypes.data + 4 * offs
+    sv["val"] = cat_val.ctypes.data + 8 * offs
     R = (Result * B)()
-    bufs = []
-    keeps = []
-    for i, p in enumerate(P):
-        if out is not None:
-            cap = out[0].numel() // B if capacity is None else capacity
-            oi, ov = out[0][i * cap:(i + 1) * cap], out[1][i * cap:(i + 1) * cap]
-            r, keep = _result_struct(p, cap, oi.data_ptr(), ov.data_ptr(), trace_cap, nodes_cap)
-        else:
-            vdt = np.float64 if p.value_type == F64 else np.float32
-            cap = graph.n if capacity is None else capacity
-            oi = np.zeros(max(cap, 1), np.int32)
-            ov = np.zeros(max(cap, 1), vdt)
-            r, keep = _result_struct(p, cap, oi.ctypes.data, ov.ctypes.data, trace_cap, nodes_cap)
-        R[i] = r
-        bufs.append((oi, ov))
-        keeps.append(keep)
+    rv = np.frombuffer(R, dtype=_RES_DT)
+    vt = np.array([p.value_type for p in params_list])
+    if out is not None:
+        cap = out[0].numel() // B if capacity is None else capacity
+        esize = out[1].element_size()
+        rv["capacity"] = cap
+        rv["idx"] = out[0].data_ptr() + 4 * cap * np.arange(B, dtype=np.uint64)
+        rv["val"] = out[1].data_ptr() + esize * cap * np.arange(B, dtype=np.uint64)
+
+        def idx_of(i, nnz):
+            return out[0][i * cap:i * cap + nnz]
+
+        def val_of(i, nnz):
+            return out[1][i * cap:i * cap + nnz]
+        host = None
+    else:
+        cap = graph.n if capacity is None else capacity
+        rv["capacity"] = cap
+        if (vt == vt[0]).all():  # one block of host buffers
+            vdt = np.float64 if vt[0] == F64 else np.float32
+            host = (np.zeros((B, max(cap, 1)), np.int32), np.zeros((B, max(cap, 1)), vdt))
+            rv["idx"] = host[0].ctypes.data + 4 * max(cap, 1) * np.arange(B, dtype=np.uint64)
+            rv["val"] = host[1].ctypes.data + host[1].itemsize * max(cap, 1) * np.arange(B, dtype=np.uint64)
+        else:  # mixed value types: one buffer pair per query
+            host = ([np.zeros(max(cap, 1), np.int32) for _ in range(B)],
+                    [np.zeros(max(cap, 1), np.float64 if t == F64 else np.float32) for t in vt])
+            rv["idx"] = [a.ctypes.data for a in host[0]]
+            rv["val"] = [a.ctypes.data for a in host[1]]
+
+        def idx_of(i, nnz):
+            return host[0][i][:nnz]
+
+        def val_of(i, nnz):
+            return host[1][i][:nnz]
+    traces = {}
+    for i in np.flatnonzero(pv["flags"] & TRACE):
+        ts = np.zeros(max(trace_cap, 1), np.int64)
+        tv = np.zeros(max(trace_cap, 1), np.int64)
+        tn = np.zeros(max(nodes_cap, 1), np.int32)
+        R[i].trace_capacity = trace_cap
+        R[i].trace_size = ts.ctypes.data
+        R[i].trace_vol = tv.ctypes.data
+        R[i].trace_nodes_capacity = nodes_cap
+        R[i].trace_nodes = tn.ctypes.data if nodes_cap else None
+        traces[int(i)] = (ts, tv, tn, trace_cap, nodes_cap)
     sched = schedule.encode() if isinstance(schedule, str) else schedule
     rc = _lib.gde_solve_batch(ctx.handle, graph.handle, B, P, S, R, sched, _stream_ptr(stream))
     if raise_on_error:
         _check(rc, (OK, NOT_CONVERGED))
-    out = []
-    for i in range(B):
-        r = R[i]
-        nnz = int(r.nnz) if r.status in (OK, NOT_CONVERGED) else 0
-        sr = SolveResult(bufs[i][0][:nnz], bufs[i][1][:nnz], r.status, r.residual_l1, r.residual_dinf, r.iters,
-                         r.ops, r.pushes)
-        sr.extra["nnz_needed"] = int(r.nnz)
-        if params_list[i].flags & TRACE:
-            m = min(int(r.trace_len), trace_cap)
-            sr.trace_size = keeps[i][0][:m].copy()
-            sr.trace_vol = keeps[i][1][:m].copy()
-            if nodes_cap:
-                sr.trace_nodes = keeps[i][2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
-        out.append(sr)
-    return out
+    res = BatchResults(rv, idx_of, val_of, traces)
+    res._keep = (P, S, R, cat_idx, cat_val, host)
+    return res
 
 
 class Server:
