@@ -354,16 +354,32 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
         s_dm[j] = 0ull;
     }
     __syncthreads();
-    for (int base = wave_id * PPW; base < nt; base += nwaves * PPW) {
-        const int i = base + sub;
-        if (i < nt) {
-            const uint64_t p = a.touched[i];
-            const int32_t g = (int32_t)(p >> 32), w = (int32_t)(p & 0xffffffffull);
-            const size_t ri = ((size_t)w * a.G + g) * L + l;
-            const V val = a.R[ri];
-            a.R[ri] = (V)0;
+    // kU pairs per lane group and step: their list entries, then their residual
+    // lines, are loaded before any is used (the loop is latency-bound otherwise)
+    constexpr int kU = 4;
+    for (int base = wave_id * PPW * kU; base < nt; base += nwaves * PPW * kU) {
+        uint64_t pr[kU];
+        V val[kU];
+#pragma unroll
+        for (int q = 0; q < kU; q++) {
+            const int i = base + q * PPW + sub;
+            pr[q] = i < nt ? a.touched[i] : ~0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kU; q++) {
+            val[q] = (V)0;
+            if (pr[q] != ~0ull) {
+                const int32_t g = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
+                val[q] = a.R[((size_t)w * a.G + g) * L + l];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kU; q++) {
+            if (pr[q] == ~0ull) continue;
+            const int32_t g = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
+            a.R[((size_t)w * a.G + g) * L + l] = (V)0;
             if (l == 0) a.TM[(size_t)w * a.G + g] = 0u;
-            const double av = fabs((double)val) * rscale;
+            const double av = fabs((double)val[q]) * rscale;
             if (av > 0.0) {
                 const int lane_id = g * L + l;
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)a.deg[w]);
