@@ -168,11 +168,19 @@ def run_c2(args):
               for m in methods for eps in EPS_C2}
 
     def step(record=None):
-        for m, eps, s in queries:
+        # the scatter launches of every profile_every-th solve are timed with HIP
+        # events (a uniform sample of the step, so that event records do not
+        # slow the step they measure)
+        for k, (m, eps, s) in enumerate(queries):
+            timed = record is not None and k % args.profile_every == 0
+            if timed:
+                ctx.profile(True, reset=False)
             t = time.perf_counter()
             r = gde.solve(ctx, g, params[(m, eps)], [s], out=(oi, ov))
             if record is not None:
                 record.append((m, eps, s, time.perf_counter() - t, r.iters, r.ops, r.pushes, r.status))
+            if timed:
+                ctx.profile(False, reset=False)
 
     if args.phase == "batch":  # profiling aid: only the batched call below
         queries_run = [q for q in queries if q[0] == "gd"][:1]
@@ -182,7 +190,7 @@ def run_c2(args):
         step()
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    ctx.profile(True, reset=True)
+    ctx.profile(False, reset=True)
     recs = []
     t_start = time.perf_counter()
     for i in range(args.steps if args.phase != "batch" else 0):
@@ -257,7 +265,8 @@ def run_c2(args):
     roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic, kernel="k_push<float,0|2> (residual scatter)",
                 launches=prof["launches"], avg_launch_us=round(avg_ms * 1e3, 3),
-                alg_bytes_per_launch=round(pb / launches, 1))
+                alg_bytes_per_launch=round(pb / launches, 1),
+                timed_launches=f"scatter launches of every {args.profile_every}th solve of the timed steps")
     out = dict(
         metric=METRIC, value=round(value, 3), unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(ms_per_step, 3), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -471,6 +480,8 @@ def main():
     ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="write the per-launch push traffic from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time the scatter launches of every k-th plain solve with HIP events")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with one 256 MiB device-to-device copy kernel, the calibration for HBM byte counters")
     args = ap.parse_args()
