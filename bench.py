@@ -89,17 +89,24 @@ def pmc_summary(fetch_dir, write_dir, out_path):
                     rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
         return rows
 
+    # one scatter step = one push launch with its range reduction, or one
+    # single-workgroup launch (what the HIP-event timing of bench.py brackets)
     res = {}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = load(d, counter)
         calib = [v for k, v in rows if "MulFunctor" in k]
         push = [v for k, v in rows if "k_push<" in k]
+        red = [v for k, v in rows if "k_reduce<" in k]
+        small = [v for k, v in rows if "k_small<" in k]
         if not calib or not push:
             raise SystemExit(f"{d}: no calibration or push dispatches with {counter}")
         factor = CALIB_BYTES / max(calib)
-        res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor,
-                        launches=len(push), bytes_per_launch=factor * sum(push) / len(push))
-    out = dict(kernel="k_push<float,0|2>", workload="ppr-plain-n1M (bench.py --phase plain)",
+        steps = len(push) + len(small)
+        res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor, push_launches=len(push),
+                        reduce_launches=len(red), small_launches=len(small),
+                        bytes_per_launch=factor * (sum(push) + sum(red) + sum(small)) / steps)
+    out = dict(kernel="k_push<float,0|2> + k_reduce + k_small (scatter step)",
+               workload="ppr-plain-n1M (bench.py --phase plain)",
                kernel_source_sha=kernel_source_hash(),
                bytes_per_launch=round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"], 1),
                fetch=res["fetch"], write=res["write"])

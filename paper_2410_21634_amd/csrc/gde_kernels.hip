@@ -620,7 +620,6 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
             const RD<V> e = dst[w];
             const V nr = e.r + acc;
             dst[w].r = nr;
-            if (tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
             if (nr != (V)0 && fabs(nr) >= eps_eff * e.d && cstamp[w] != stamp_next) {
                 cstamp[w] = stamp_next;
                 hits |= 1u << k;
@@ -631,12 +630,15 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
             dst[w].r = nw;
             const V th = eps_eff * e.d;
             if (e.r < th && nw >= th) hits |= 1u << k;
-            if (e.r == (V)0) {
-                firsts |= 1u << k;
-                if (MODE == 0 && tbm) atomicOr(&tbm[w >> 5], 1u << (w & 31));
-            }
+            if (e.r == (V)0) firsts |= 1u << k;
         }
     }
+    // the range's words of the touched-residual bitmap: every node with an update
+    // (a superset of the first touches), one plain read-modify-write per word --
+    // the words of a range belong to this workgroup alone
+    if (MODE != 1 && tbm)
+        for (int k = threadIdx.x; k < (span + 31) / 32; k += blockDim.x)
+            if (s_bits[k]) tbm[(lo >> 5) + k] |= s_bits[k];
     int slot = block_reserve(__popc(hits), &st->fcount[cur ^ 1]);
     for (uint32_t h = hits; h; h &= h - 1u) {
         const int32_t w = lo + j0 + (__ffs((int)h) - 1);
