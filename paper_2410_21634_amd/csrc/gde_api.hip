@@ -129,7 +129,7 @@ static GraphHost *graph_host(const gde_graph *g) {
 }
 
 static void ws_free(Workspace *w) {
-    void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->pushed, w->touched[0], w->touched[1],
+    void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->touched[0], w->touched[1],
                    w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
                    w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
                    w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_w, w->bin_v};
@@ -215,7 +215,6 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     WS_ALLOC(w->tbm, 4 * nwords);
     WS_ALLOC(w->blk, 4 * (w->nblk + 1));
     for (int i = 0; i < 2; i++) WS_ALLOC(w->front[i], 4 * n);
-    WS_ALLOC(w->pushed, 4 * n);
     WS_ALLOC(w->wl_node, 4 * n);
     WS_ALLOC(w->wl_beg, 4 * n);
     WS_ALLOC(w->wl_off, 4 * n);
@@ -519,7 +518,6 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     a.x = w->x;
     a.bitmap = w->bitmap;
     a.st = w->st;
-    a.pushed = w->pushed;
     a.wl_node = w->wl_node;
     a.wl_beg = w->wl_beg;
     a.wl_off = w->wl_off;
@@ -621,7 +619,6 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             sa.bitmap = w->bitmap;
             sa.tbm = w->tbm;
             sa.st = w->st;
-            sa.pushed = w->pushed;
             sa.front0 = w->front[0];
             sa.front1 = w->front[1];
             sa.wl_node = w->wl_node;
@@ -738,12 +735,15 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         GDE_HIP(hipGetLastError());
         GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
-        nnz = w->hst->pushed_count;
+        nnz = w->hst->out_count;
         fits = bufs && nnz <= res->capacity;
     } else {
+        // host buffers: the support size (from the output scan) decides the staging size
+        launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
+        launch_ex_scan(w->blk, w->nblk, w->st, s);
         GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
-        nnz = w->hst->pushed_count;
+        nnz = w->hst->out_count;
         fits = nnz <= res->capacity && res->idx && res->val;
         int32_t *o_idx = nullptr;
         void *o_val = nullptr;
@@ -752,8 +752,6 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             o_idx = w->out_idx;
             o_val = w->out_val;
         }
-        launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
-        launch_ex_scan(w->blk, w->nblk, w->st, s);
         launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, nullptr, s);
         GDE_HIP(hipGetLastError());
         if (fits && nnz > 0) {

@@ -62,14 +62,13 @@ struct DevState {
     unsigned long long packed[2];  // work-list reservation: (entries << 32) | edges
     int32_t fcount[2];             // frontier / candidate list lengths
     int32_t tcount[3];             // heat-kernel touched-list lengths (level mod 3)
-    int32_t pushed_count;          // |union of S_t|, length of the pushed list
     int32_t iters;                 // iterations with a nonempty active set
     int32_t pad0;
     long long ops;                 // sum vol(S_t)
     long long pushes;              // sum |S_t|
     double res_l1;                 // reported residual l1 norm
     unsigned long long res_dinf;   // bit pattern of the reported ||D^-1 r||_inf (>= 0)
-    int32_t out_count;             // entries emitted by the extraction
+    int32_t out_count;             // |union of S_t|: the pushed-set size found by the output scan
     int32_t empty_seen;            // an iteration found S_t empty (converged)
     int32_t probe;                 // LocalCH: active candidates at the iteration cap
     int32_t overflow;              // a list append found its capacity exhausted (invariant broken)
@@ -92,7 +91,6 @@ struct Workspace {
     uint32_t *bitmap = nullptr;    // pushed set, ceil(n/32) words
     uint32_t *tbm = nullptr;       // nodes whose residual may be nonzero (LocalGD / LocalCH), ceil(n/32) words
     int32_t *front[2] = {nullptr, nullptr};
-    int32_t *pushed = nullptr;
     int32_t *touched[3] = {nullptr, nullptr, nullptr};
     int32_t *wl_node = nullptr, *wl_beg = nullptr, *wl_off = nullptr;
     void *wl_sv = nullptr;

@@ -15,7 +15,6 @@ struct SnapArgs {
     const int32_t *F;     // S_t (GD, HK) or the candidates C_t (CH)
     DevState *st;
     int cur;
-    int32_t *pushed;
     int32_t *wl_node, *wl_beg, *wl_off;
     void *wl_sv;
     int32_t *tile_start;
@@ -31,7 +30,7 @@ struct SmallArgs {
     void *rd, *x;
     uint32_t *bitmap, *tbm;
     DevState *st;
-    int32_t *pushed, *front0, *front1;
+    int32_t *front0, *front1;
     int32_t *wl_node, *wl_beg, *wl_off;
     void *wl_sv;
     int32_t *tile_start;

@@ -102,7 +102,6 @@ __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const d
         st->fcount[1] = 0;
         st->tcount[0] = touched0 ? nnz : 0;
         st->tcount[1] = st->tcount[2] = 0;
-        st->pushed_count = 0;
         st->iters = 0;
         st->ops = st->pushes = 0;
         st->res_l1 = 0.0;
@@ -122,16 +121,11 @@ __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const d
 // slots and edge offsets for the active lanes of the wave, write the entries.
 template <typename V>
 __device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, int32_t deg, V sv, uint32_t *bitmap,
-                                             int32_t *pushed, DevState *st, int cur, int32_t *wl_node,
+                                             DevState *st, int cur, int32_t *wl_node,
                                              int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start,
                                              int32_t *tr_nodes, long long push_base, long long tr_cap, int32_t cap) {
-    bool first = false;
-    if (act) {
-        uint32_t bit = 1u << (u & 31);
-        uint32_t old = atomicOr(&bitmap[u >> 5], bit);
-        first = (old & bit) == 0u;
-    }
-    block_list_append(first, u, &st->pushed_count, pushed, cap, st);
+    // the pushed set, counted by the output kernels (no return value needed)
+    if (act) atomicOr(&bitmap[u >> 5], 1u << (u & 31));
     const unsigned long long mine = act ? ((1ull << 32) | (unsigned long long)(unsigned)deg) : 0ull;
     const unsigned long long res = block_reserve64(mine, &st->packed[cur]);
     if (act) {
@@ -152,7 +146,7 @@ __device__ __forceinline__ void emit_entries(bool act, int32_t u, int32_t beg, i
 // W_u = wscale / d_u (PPR, wscale = 1 - alpha) or wscale (Katz, beta).
 template <typename V>
 __device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, uint32_t *bitmap,
-                        const int32_t *__restrict__ F, DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                        const int32_t *__restrict__ F, DevState *st, int cur, int32_t *wl_node,
                         int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale, int w_div_deg,
                         int32_t *tr_nodes, long long tr_cap, int32_t cap, int bid, int nblocks) {
     const int nxt = cur ^ 1;
@@ -175,7 +169,7 @@ __device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
             V w = w_div_deg ? wscale / (V)deg : wscale;
             sv = w * v;
         }
-        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
     }
 }
@@ -183,10 +177,10 @@ __device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
 template <typename V>
 __global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
                                                      uint32_t *bitmap, const int32_t *__restrict__ F, DevState *st,
-                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int cur, int32_t *wl_node, int32_t *wl_beg,
                                                      int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
                                                      int w_div_deg, int32_t *tr_nodes, long long tr_cap, int32_t cap) {
-    snap_gd<V>(row_ptr, rd, x, bitmap, F, st, cur, pushed, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
+    snap_gd<V>(row_ptr, rd, x, bitmap, F, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
                w_div_deg, tr_nodes, tr_cap, cap, blockIdx.x, gridDim.x);
 }
 
@@ -197,7 +191,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_gd(const int32_t *__restric
 template <typename V>
 __global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restrict__ row_ptr, RD<V> *plane, RD<V> *prev,
                                                      V *x, uint32_t *bitmap, const int32_t *__restrict__ F,
-                                                     DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                                                     DevState *st, int cur, int32_t *wl_node,
                                                      int32_t *wl_beg, int32_t *wl_off, V *wl_sv,
                                                      int32_t *tile_start, V wmul, int last_level, int frontier_on,
                                                      const int32_t *__restrict__ prev_touched, int prev_tslot,
@@ -226,7 +220,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restric
             deg = row_ptr[u + 1] - beg;
             sv = last_level ? (V)0 : wmul * v / plane[u].d;
         }
-        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
     }
     double l1 = 0.0, mx = 0.0;
@@ -246,7 +240,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restric
 // the previous update if u was in S_{t-1}; x_u += h_u, r_u -= h_u, Delta_u = h_u.
 template <typename V>
 __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, uint32_t *bitmap,
-                        const int32_t *__restrict__ C, DevState *st, int cur, int32_t *pushed, int32_t *wl_node,
+                        const int32_t *__restrict__ C, DevState *st, int cur, int32_t *wl_node,
                         int32_t *wl_beg, int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale, int w_div_deg,
                         V eps_eff, V c_t, V m_t, int force, V *delta, int32_t *dstamp, int32_t *cstamp,
                         int32_t stamp_cur, int32_t *next_list, int32_t *tr_nodes, long long tr_cap, int32_t cap,
@@ -278,10 +272,13 @@ __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
                 sv = w * h;
             }
         }
-        // u's own residual changed: it is a candidate of the next iteration
-        bool mark = act && atomicExch(&cstamp[u], stamp_cur + 1) != stamp_cur + 1;
+        // u's own residual changed: it is a candidate of the next iteration.  u appears
+        // once in C_t and only this iteration's push stamps stamp_cur + 1, later: a
+        // plain store marks it
+        const bool mark = act;
+        if (act) cstamp[u] = stamp_cur + 1;
         block_list_append(mark, u, &st->fcount[nxt], next_list, cap, st);
-        emit_entries<V>(act, u, beg, deg, sv, bitmap, pushed, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
+        emit_entries<V>(act, u, beg, deg, sv, bitmap, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
     }
 }
@@ -289,13 +286,13 @@ __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
 template <typename V>
 __global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x,
                                                      uint32_t *bitmap, const int32_t *__restrict__ C, DevState *st,
-                                                     int cur, int32_t *pushed, int32_t *wl_node, int32_t *wl_beg,
+                                                     int cur, int32_t *wl_node, int32_t *wl_beg,
                                                      int32_t *wl_off, V *wl_sv, int32_t *tile_start, V wscale,
                                                      int w_div_deg, V eps_eff, V c_t, V m_t, int force, V *delta,
                                                      int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur,
                                                      int32_t *next_list, int32_t *tr_nodes, long long tr_cap,
                                                      int32_t cap) {
-    snap_ch<V>(row_ptr, rd, x, bitmap, C, st, cur, pushed, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
+    snap_ch<V>(row_ptr, rd, x, bitmap, C, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start, wscale,
                w_div_deg, eps_eff, c_t, m_t, force, delta, dstamp, cstamp, stamp_cur, next_list, tr_nodes, tr_cap, cap,
                blockIdx.x, gridDim.x);
 }
@@ -512,12 +509,12 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
         const int n_f = __hip_atomic_load(&st->fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (n_f > kSmallMaxNodes) break;
         if (CH)
-            snap_ch<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off,
+            snap_ch<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.wl_node, a.wl_beg, a.wl_off,
                        (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.eps_eff, a.c_seq[t - a.t0],
                        a.m_seq[t - a.t0], t == 0 ? 1 : 0, (V *)a.delta, a.dstamp, a.cstamp, a.stamp_base + t, Fn,
                        a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
         else
-            snap_gd<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off,
+            snap_gd<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.wl_node, a.wl_beg, a.wl_off,
                        (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
         __threadfence();
         __syncthreads();
@@ -767,7 +764,7 @@ __global__ void __launch_bounds__(kBlock) k_ex_emit(uint32_t *bm, int64_t nwords
                                                      const DevState *st) {
     __shared__ int s[kBlock];
     // with st: write only if the whole support fits (else nothing is written)
-    if (st && (int64_t)st->pushed_count > cap) cap = 0;
+    if (st && (int64_t)st->out_count > cap) cap = 0;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     uint32_t word = i < nwords ? bm[i] : 0u;
     int c = __popc(word);
@@ -879,7 +876,7 @@ void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t
 template <typename V>
 void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s) {
     hipLaunchKernelGGL(k_snap_gd<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
-                       a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
+                       a.F, a.st, a.cur, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
                        w_div_deg, a.tr_nodes, a.tr_cap, a.cap);
 }
 
@@ -887,7 +884,7 @@ template <typename V>
 void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
                     int prev_tslot, int next_tslot, double psi_prev, double wdinf_prev, hipStream_t s) {
     hipLaunchKernelGGL(k_snap_hk<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (RD<V> *)prev,
-                       (V *)a.x, a.bitmap, a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv,
+                       (V *)a.x, a.bitmap, a.F, a.st, a.cur, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv,
                        a.tile_start, wmul, last_level, frontier_on, prev_touched, prev_tslot, next_tslot, psi_prev,
                        wdinf_prev, a.tr_nodes, a.tr_cap, a.cap);
 }
@@ -896,7 +893,7 @@ template <typename V>
 void launch_snap_ch(const SnapArgs &a, V wscale, int w_div_deg, V eps_eff, V c_t, V m_t, int force, void *delta,
                     int32_t *dstamp, int32_t *cstamp, int32_t stamp_cur, int32_t *next_list, hipStream_t s) {
     hipLaunchKernelGGL(k_snap_ch<V>, dim3(a.grid), dim3(kSnapBlock), 0, s, a.row_ptr, (RD<V> *)a.rd, (V *)a.x, a.bitmap,
-                       a.F, a.st, a.cur, a.pushed, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
+                       a.F, a.st, a.cur, a.wl_node, a.wl_beg, a.wl_off, (V *)a.wl_sv, a.tile_start, wscale,
                        w_div_deg, eps_eff, c_t, m_t, force, (V *)delta, dstamp, cstamp, stamp_cur, next_list,
                        a.tr_nodes, a.tr_cap, a.cap);
 }
