@@ -35,7 +35,7 @@ constexpr long long kSmallMaxEdges = 16384; // frontier volume it accepts
 constexpr int kBinMaxRanges = 4096;     // ranges a graph may have for the binned scatter
 constexpr int kBinLdsBytes = 16384;     // LDS accumulator bytes of one range (2^S values)
 constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
-constexpr long long kBinMinEdges = 131072;  // frontier volume from which the scatter is binned
+constexpr long long kBinMinEdges = 8192;    // frontier volume from which the scatter is binned
 
 // Device description of the bins of one workspace (value type V).
 template <typename V>
