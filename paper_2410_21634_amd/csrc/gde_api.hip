@@ -132,7 +132,7 @@ static void ws_free(Workspace *w) {
     void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->touched[0], w->touched[1],
                    w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
                    w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
-                   w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_w, w->bin_v};
+                   w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_e};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (w->hst) (void)hipHostFree(w->hst);
@@ -158,16 +158,14 @@ static int ws_graph_state(Workspace *w, const gde_graph *g, hipStream_t s) {
     const size_t vs = w->vsize;
     if (g->nnz > w->nnz_cap) {
         (void)hipFree(w->tile_start);
-        (void)hipFree(w->bin_w);
-        (void)hipFree(w->bin_v);
+        (void)hipFree(w->bin_e);
         w->tile_start = nullptr;
-        w->bin_w = nullptr;
-        w->bin_v = nullptr;
+        w->bin_e = nullptr;
         const int64_t cap = g->nnz + g->nnz / 8 + 65536;
         GDE_HIP(hipMalloc((void **)&w->tile_start, 4 * (size_t)(cap / kPushTile + 2)));
         if (w->bin_nranges > 0) {
-            GDE_HIP(hipMalloc((void **)&w->bin_w, 4 * (size_t)cap));
-            GDE_HIP(hipMalloc(&w->bin_v, vs * (size_t)cap));
+            const size_t es = vs == 8 ? sizeof(BinEnt<double>) : sizeof(BinEnt<float>);
+            GDE_HIP(hipMalloc(&w->bin_e, es * (size_t)cap));
         }
         w->nnz_cap = cap;
     }
@@ -509,8 +507,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         }
         bins.base = w->bin_base;
         bins.cursor = w->bin_cursor;
-        bins.bw = w->bin_w;
-        bins.bv = (V *)w->bin_v;
+        bins.be = (BinEnt<V> *)w->bin_e;
     }
     SnapArgs a{};
     a.grid = sgrid;
@@ -608,10 +605,10 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             }
             return chs[tt];
         };
-        int t = 0, chunk = 8;
-        if (!(p->flags & GDE_SCATTER_BINNED)) {
-            // small frontiers first: one workgroup, many iterations, one launch
-            SmallArgs<V> sa{};
+        int t = 0;
+        const bool small_ok = !(p->flags & GDE_SCATTER_BINNED);
+        SmallArgs<V> sa{};
+        if (small_ok) {
             sa.row_ptr = g->row_ptr;
             sa.col_idx = g->col_idx;
             sa.rd = w->rd;
@@ -640,17 +637,24 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             sa.stamp_base = base;
             sa.cap = g->n;
             sa.nnz = (int32_t)g->nnz;
-            sa.t0 = 0;
-            sa.t_end = std::min(p->max_iters, kSmallIters);
+        }
+        // Small frontiers: one workgroup runs iterations t .. until the frontier
+        // outgrows it, the solve converges or kSmallIters have run; then the host
+        // reads where it stopped.  Used for the first iterations and again for the
+        // tail, whenever a synchronisation finds the frontier small.
+        auto run_small = [&]() -> int {
+            sa.t0 = t;
+            sa.t_end = std::min(p->max_iters, t + kSmallIters);
             if (ch)
-                for (int k = 0; k < sa.t_end; k++) {
+                for (int k = t; k < sa.t_end; k++) {
                     const auto cm = ch_at(k);
-                    sa.c_seq[k] = cm.first;
-                    sa.m_seq[k] = cm.second;
+                    sa.c_seq[k - t] = cm.first;
+                    sa.m_seq[k - t] = cm.second;
                 }
-            if ((rc = prof_mark(ctx, s))) return rc;
+            int e = prof_mark(ctx, s);
+            if (e) return e;
             launch_small<V>(sa, ch, s);
-            if ((rc = prof_mark(ctx, s))) return rc;
+            if ((e = prof_mark(ctx, s))) return e;
             GDE_HIP(hipGetLastError());
             GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
             GDE_HIP(hipStreamSynchronize(s));
@@ -658,7 +662,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) {
                 converged = true;
             } else if (w->hst->small_phase == 1) {  // S_t is snapshot; its volume needs the grid-wide push
-                if ((rc = prof_mark(ctx, s))) return rc;
+                if ((e = prof_mark(ctx, s))) return e;
                 if (ch)
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
@@ -667,10 +671,15 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
                                    d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
-                if ((rc = prof_mark(ctx, s))) return rc;
+                if ((e = prof_mark(ctx, s))) return e;
                 t++;
             }
-        }
+            return GDE_OK;
+        };
+        if (small_ok && (rc = run_small())) return rc;
+        // grid-wide iterations in chunks between host synchronisations: 8, then
+        // doubling up to 32 while the frontier stays large
+        int chunk = 8;
         while (!converged && t < p->max_iters) {
             int end = std::min(p->max_iters, t + chunk);
             for (; t < end; t++) {
@@ -699,7 +708,12 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
             GDE_HIP(hipStreamSynchronize(s));
             if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) { converged = true; break; }
-            chunk = std::min(chunk * 2, 32);
+            if (small_ok && t < p->max_iters && w->hst->fcount[t & 1] <= kSmallMaxNodes) {
+                if ((rc = run_small())) return rc;
+                chunk = 8;
+            } else {
+                chunk = std::min(chunk * 2, 32);
+            }
         }
         if (!converged) {
             if (ch) {

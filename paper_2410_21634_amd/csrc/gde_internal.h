@@ -37,6 +37,15 @@ constexpr int kBinLdsBytes = 16384;     // LDS accumulator bytes of one range (2
 constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
 constexpr long long kBinMinEdges = 8192;    // frontier volume from which the scatter is binned
 
+// One binned update: destination node and value side by side, so that a tile's
+// run of updates to one range is a single contiguous stream of 8-byte (FP32) or
+// 16-byte (FP64) stores.
+template <typename V>
+struct alignas(sizeof(V) == 8 ? 16 : 8) BinEnt {
+    int32_t w;
+    V v;
+};
+
 // Device description of the bins of one workspace (value type V).
 template <typename V>
 struct BinArgs {
@@ -45,8 +54,7 @@ struct BinArgs {
     long long min_edges;     // frontier volume from which the binned scatter runs
     const long long *base;   // [nranges + 1]: bin r occupies [base[r], base[r + 1])
     int32_t *cursor;         // [nranges]: entries written to bin r this iteration
-    int32_t *bw;             // destination node of each binned update
-    V *bv;                   // value of each binned update
+    BinEnt<V> *be;           // the binned updates (destination node, value)
 };
 
 // Residual and degree of one node side by side, so that the atomic update of
@@ -120,8 +128,7 @@ struct Workspace {
     int bin_nranges = 0;
     long long *bin_base = nullptr; // device [nranges + 1]
     int32_t *bin_cursor = nullptr; // device [nranges], zero between iterations
-    int32_t *bin_w = nullptr;      // device [nnz_cap]
-    void *bin_v = nullptr;         // device [nnz_cap] values
+    void *bin_e = nullptr;         // device [nnz_cap] BinEnt<V> entries
     int64_t nnz_cap = 0;           // CSR entries the tile table and bins can hold
 };
 

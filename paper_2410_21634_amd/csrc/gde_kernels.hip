@@ -412,8 +412,10 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
                 if (rb[q] >= 0) {
                     const long long pos = bins.base[rb[q]] + s_rbase[rb[q]] + rk[q];
                     if (pos < bins.base[rb[q] + 1]) {
-                        bins.bw[pos] = w[q];
-                        bins.bv[pos] = dv[q];
+                        BinEnt<V> e;
+                        e.w = w[q];
+                        e.v = dv[q];
+                        bins.be[pos] = e;
                     } else {
                         st->overflow = 1;
                     }
@@ -588,8 +590,10 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
         for (int q = 0; q < kRedUnroll; q++) {
             const int i = i0 + q * (int)blockDim.x + (int)threadIdx.x;
             ok[q] = i < m;
-            jj[q] = ok[q] ? bins.bw[b0 + i] - lo : 0;
-            vv[q] = ok[q] ? bins.bv[b0 + i] : (V)0;
+            BinEnt<V> e{};
+            if (ok[q]) e = bins.be[b0 + i];
+            jj[q] = e.w - lo;
+            vv[q] = e.v;
         }
 #pragma unroll
         for (int q = 0; q < kRedUnroll; q++) {
