@@ -491,53 +491,289 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
 }
 
 // Small frontiers: iterations t0 .. t_end-1 of LocalGD (CH = false) or LocalCH
-// run by ONE workgroup in one launch, the same snapshot and push code as the
-// grid-wide kernels with a device-scope fence and a workgroup barrier where a
-// kernel boundary would be.  The launch stops before the snapshot of t when
-// the list of t exceeds kSmallMaxNodes (small_phase 0), after the snapshot
-// when the volume of S_t exceeds kSmallMaxEdges (small_phase 1: the grid-wide
-// push of t follows), or when the iteration converges; small_t records where.
+// run by ONE workgroup in one launch.  The frontier / candidate lists, the work
+// list (row start, edge offset, scatter value) and every counter live in LDS;
+// global memory is touched only for node state (r, d, x, Delta, stamps, the
+// pushed and touched bitmaps), the CSR, and fire-and-forget copies of the next
+// list that a grid-wide continuation reads.  A device-scope fence and a
+// workgroup barrier stand where a kernel boundary would be (the stores of the
+// snapshot must land before the adds of the push, and the adds before the
+// next snapshot reads r).  The arithmetic and every decision are those of
+// snap_gd / snap_ch followed by push_edges, iteration by iteration.
+//
+// The launch stops before the snapshot of t when the list of t exceeds
+// kSmallMaxNodes (small_phase 0: the list is in global memory), after the
+// snapshot when vol(S_t) exceeds kSmallMaxEdges (small_phase 1: the work list,
+// its tile table and packed[t & 1] are written out for the grid-wide push of
+// t), or when the iteration converges; small_t records where.
+__device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long long v, unsigned long long *total) {
+    __shared__ unsigned long long s_w[kMaxWaves];
+    __shared__ unsigned long long s_tot;
+    const unsigned long long incl = wave_incl_scan64(v);
+    const int wid = threadIdx.x / kWave;
+    if (lane() == kWave - 1) s_w[wid] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0ull;
+        for (int i = 0; i < (int)(blockDim.x / kWave); i++) {
+            const unsigned long long x = s_w[i];
+            s_w[i] = tot;
+            tot += x;
+        }
+        s_tot = tot;
+    }
+    __syncthreads();
+    const unsigned long long r = s_w[wid] + incl - v;
+    *total = s_tot;
+    __syncthreads();
+    return r;
+}
+
 template <typename V, bool CH>
 __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
+    constexpr int kNodesPer = kSmallMaxNodes / kSnapBlock;  // list entries per thread in the snapshot
+    constexpr int kEdgesPer = 4;                            // edges per thread and push round
+    static_assert(kNodesPer * kSnapBlock == kSmallMaxNodes, "list entries must split evenly");
+    __shared__ int32_t s_list[2][kSmallMaxNodes];
+    __shared__ int32_t s_beg[kSmallMaxNodes];
+    __shared__ int32_t s_off[kSmallMaxNodes + 1];
+    __shared__ V s_sv[kSmallMaxNodes];
+    __shared__ int s_cnt[2];
+    __shared__ int s_ovf;
     DevState *st = a.st;
     RD<V> *rd = (RD<V> *)a.rd;
-    const BinArgs<V> nobins{};
+    V *x = (V *)a.x;
+    V *delta = (V *)a.delta;
+    const int tid = threadIdx.x;
+    // iteration counters: thread 0 keeps them and writes them back at the end
+    int iters = 0;
+    long long ops = 0, pushes = 0;
+    if (tid == 0) {
+        iters = st->iters;
+        ops = st->ops;
+        pushes = st->pushes;
+        s_cnt[0] = st->fcount[0];
+        s_cnt[1] = st->fcount[1];
+        s_ovf = 0;
+    }
+    __syncthreads();
     int t = a.t0;
     int phase = 0;
+    bool empty_seen = false;
+    {
+        const int c0 = s_cnt[t & 1];
+        const int32_t *F = (t & 1) ? a.front1 : a.front0;
+        if (c0 <= kSmallMaxNodes)
+            for (int i = tid; i < c0; i += blockDim.x) s_list[t & 1][i] = F[i];
+    }
+    __syncthreads();
+    __shared__ long long s_push_base;
     for (; t < a.t_end; t++) {
-        const int cur = t & 1;
-        int32_t *F = cur ? a.front1 : a.front0;
-        int32_t *Fn = cur ? a.front0 : a.front1;
-        const int n_f = __hip_atomic_load(&st->fcount[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int cur = t & 1, nxt = cur ^ 1;
+        int32_t *Fn = nxt ? a.front1 : a.front0;
+        const int n_f = s_cnt[cur];
         if (n_f > kSmallMaxNodes) break;
-        if (CH)
-            snap_ch<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.wl_node, a.wl_beg, a.wl_off,
-                       (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.eps_eff, a.c_seq[t - a.t0],
-                       a.m_seq[t - a.t0], t == 0 ? 1 : 0, (V *)a.delta, a.dstamp, a.cstamp, a.stamp_base + t, Fn,
-                       a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
-        else
-            snap_gd<V>(a.row_ptr, rd, (V *)a.x, a.bitmap, F, st, cur, a.wl_node, a.wl_beg, a.wl_off,
-                       (V *)a.wl_sv, a.tile_start, a.wscale, a.w_div_deg, a.tr_nodes, a.tr_ncap, a.cap, 0, 1);
+        if (tid == 0) s_push_base = pushes;
+        // ---------------------------------------------------------- snapshot of t
+        const V c_t = CH ? a.c_seq[t - a.t0] : (V)0;
+        const V m_t = CH ? a.m_seq[t - a.t0] : (V)0;
+        const bool force = CH && t == 0;
+        const int32_t stamp_cur = a.stamp_base + t;
+        int32_t u[kNodesPer], beg[kNodesPer], deg[kNodesPer];
+        bool act[kNodesPer];
+        V sv[kNodesPer];
+        unsigned long long mine = 0ull;
+#pragma unroll
+        for (int k = 0; k < kNodesPer; k++) {
+            const int i = tid * kNodesPer + k;
+            act[k] = false;
+            u[k] = 0;
+            beg[k] = deg[k] = 0;
+            sv[k] = (V)0;
+            if (i < n_f) u[k] = s_list[cur][i];
+        }
+        // every load of the entries is issued before any is used
+        RD<V> e[kNodesPer];
+        V xo[kNodesPer], dl[kNodesPer];
+        int32_t ds[kNodesPer], rp0[kNodesPer], rp1[kNodesPer];
+#pragma unroll
+        for (int k = 0; k < kNodesPer; k++) {
+            const bool v = tid * kNodesPer + k < n_f;
+            e[k] = v ? rd[u[k]] : RD<V>{};
+            xo[k] = v ? x[u[k]] : (V)0;
+            rp0[k] = v ? a.row_ptr[u[k]] : 0;
+            rp1[k] = v ? a.row_ptr[u[k] + 1] : 0;
+            ds[k] = (CH && v) ? a.dstamp[u[k]] : 0;
+            dl[k] = (CH && v) ? delta[u[k]] : (V)0;
+        }
+#pragma unroll
+        for (int k = 0; k < kNodesPer; k++) {
+            if (tid * kNodesPer + k >= n_f) continue;
+            V h;
+            if (CH) {
+                act[k] = force || (e[k].r != (V)0 && fabs(e[k].r) >= a.eps_eff * e[k].d);
+                if (!act[k]) continue;
+                h = force ? e[k].r : c_t * e[k].r + m_t * (ds[k] == stamp_cur - 1 ? dl[k] : (V)0);
+                rd[u[k]].r = e[k].r - h;
+                delta[u[k]] = h;
+                a.dstamp[u[k]] = stamp_cur;
+                a.cstamp[u[k]] = stamp_cur + 1;  // u's residual changed: a candidate of t+1
+            } else {
+                act[k] = true;
+                h = e[k].r;
+                rd[u[k]].r = (V)0;
+            }
+            x[u[k]] = xo[k] + h;
+            beg[k] = rp0[k];
+            deg[k] = rp1[k] - rp0[k];
+            const V w = a.w_div_deg ? a.wscale / (V)deg[k] : a.wscale;
+            sv[k] = w * h;
+            atomicOr(&a.bitmap[u[k] >> 5], 1u << (u[k] & 31));
+            mine += (1ull << 32) | (unsigned long long)(unsigned)deg[k];
+        }
+        unsigned long long tot;
+        const unsigned long long pre = block_excl_scan64(mine, &tot);
+        const int count = (int)(tot >> 32);
+        const int total = (int)(tot & 0xffffffffull);
+        {
+            int slot = (int)(pre >> 32);
+            int off = (int)(pre & 0xffffffffull);
+            const long long pb = s_push_base;
+#pragma unroll
+            for (int k = 0; k < kNodesPer; k++) {
+                if (!act[k]) continue;
+                s_beg[slot] = beg[k];
+                s_off[slot] = off;
+                s_sv[slot] = sv[k];
+                if (a.tr_nodes && pb + slot < a.tr_ncap) a.tr_nodes[pb + slot] = u[k];
+                if (CH) {  // self-mark into the candidates of t+1
+                    const int c = atomicAdd(&s_cnt[nxt], 1);
+                    if (c < kSmallMaxNodes) s_list[nxt][c] = u[k];
+                    if (c < a.cap) Fn[c] = u[k];
+                    else s_ovf = 1;
+                }
+                slot++;
+                off += deg[k];
+            }
+        }
+        if (tid == 0) s_off[count] = total;
         __threadfence();
         __syncthreads();
-        const unsigned long long pk = __hip_atomic_load(&st->packed[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int count = (int)(pk >> 32);
-        if (count > 0 && (long long)(pk & 0xffffffffull) > kSmallMaxEdges) {
+        if (count > 0 && (long long)total > kSmallMaxEdges) {
+            // hand the push of t to the grid-wide kernel: work list, tile table, counters
+            for (int i = tid; i < count; i += blockDim.x) {
+                const int off = s_off[i], d = s_off[i + 1] - off;
+                a.wl_beg[i] = s_beg[i];
+                a.wl_off[i] = off;
+                ((V *)a.wl_sv)[i] = s_sv[i];
+                for (int k = (off + kPushTile - 1) / kPushTile; (long long)k * kPushTile < (long long)off + d; k++)
+                    a.tile_start[k] = i;
+            }
+            if (tid == 0) {
+                st->packed[cur] = ((unsigned long long)count << 32) | (unsigned long long)(unsigned)total;
+                st->packed[nxt] = 0ull;
+            }
             phase = 1;
             break;
         }
-        push_edges<V, CH ? 2 : 0>(a.col_idx, rd, st, cur, a.wl_beg, a.wl_off, (const V *)a.wl_sv, a.tile_start,
-                                  a.eps_eff, Fn, nullptr, 0, a.cstamp, a.stamp_base + t + 1, a.tbm, a.tr_size,
-                                  a.tr_vol, a.tr_cap, 1, a.cap, a.nnz, nobins, 0, 1);
+        // ---------------------------------------------------------- push of t
+        const int32_t stamp_next = stamp_cur + 1;
+        for (int e0 = 0; e0 < total; e0 += kEdgesPer * (int)blockDim.x) {
+            int32_t w[kEdgesPer];
+            V dv[kEdgesPer];
+#pragma unroll
+            for (int q = 0; q < kEdgesPer; q++) {
+                const int ee = e0 + q * (int)blockDim.x + tid;
+                w[q] = -1;
+                dv[q] = (V)0;
+                if (ee < total) {
+                    int lo = 0, hi = count - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_off[mid] <= ee) lo = mid; else hi = mid - 1;
+                    }
+                    const int kk = s_beg[lo] + (ee - s_off[lo]);
+                    if (kk >= 0 && kk < a.nnz) {
+                        w[q] = a.col_idx[kk];
+                        dv[q] = s_sv[lo];
+                    } else {
+                        s_ovf = 1;
+                    }
+                }
+            }
+            bool hit[kEdgesPer];
+            if (CH) {
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++)
+                    if (w[q] >= 0) unsafeAtomicAdd(&rd[w[q]].r, dv[q]);
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++)
+                    hit[q] = w[q] >= 0 && a.cstamp[w[q]] != stamp_next &&
+                             atomicExch(&a.cstamp[w[q]], stamp_next) != stamp_next;
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++)
+                    if (hit[q] && a.tbm) atomicOr(&a.tbm[w[q] >> 5], 1u << (w[q] & 31));
+            } else {
+                V th[kEdgesPer], old[kEdgesPer];
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++)
+                    th[q] = (w[q] >= 0 && dv[q] != (V)0) ? a.eps_eff * rd[w[q]].d : (V)0;
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++)
+                    old[q] = (w[q] >= 0 && dv[q] != (V)0) ? unsafeAtomicAdd(&rd[w[q]].r, dv[q]) : (V)0;
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++) {
+                    hit[q] = false;
+                    if (w[q] >= 0 && dv[q] != (V)0) {
+                        hit[q] = (old[q] < th[q]) && (old[q] + dv[q] >= th[q]);
+                        if (old[q] == (V)0 && a.tbm) atomicOr(&a.tbm[w[q] >> 5], 1u << (w[q] & 31));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kEdgesPer; q++)
+                if (hit[q]) {
+                    const int c = atomicAdd(&s_cnt[nxt], 1);
+                    if (c < kSmallMaxNodes) s_list[nxt][c] = w[q];
+                    if (c < a.cap) Fn[c] = w[q];
+                    else s_ovf = 1;
+                }
+        }
         __threadfence();
         __syncthreads();
-        if (count == 0) { t++; break; }  // S_t was empty: converged (recorded by the push)
-        if (!CH && __hip_atomic_load(&st->fcount[cur ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            t++;  // LocalGD: S_{t+1} is empty
+        if (tid == 0) {
+            if (count > 0) {
+                if (a.tr_size && iters < a.tr_cap) {
+                    a.tr_size[iters] = count;
+                    a.tr_vol[iters] = total;
+                }
+                ops += total;
+                pushes += count;
+                iters++;
+            }
+            s_cnt[cur] = 0;  // S_t consumed: the list becomes the append target of t+1
+        }
+        __syncthreads();
+        if (count == 0) {  // S_t was empty: converged
+            empty_seen = true;
+            t++;
+            break;
+        }
+        if (!CH && s_cnt[nxt] == 0) {  // LocalGD: S_{t+1} is empty
+            t++;
             break;
         }
     }
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    if (tid == 0) {
+        st->iters = iters;
+        st->ops = ops;
+        st->pushes = pushes;
+        st->fcount[0] = s_cnt[0];
+        st->fcount[1] = s_cnt[1];
+        if (phase == 0) st->packed[0] = st->packed[1] = 0ull;
+        if (empty_seen) st->empty_seen = 1;
+        if (s_ovf) st->overflow = 1;
         st->small_t = t;
         st->small_phase = phase;
     }
