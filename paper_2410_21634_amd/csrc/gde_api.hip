@@ -482,10 +482,24 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     long long *d_trv = trace && tr_cap > 0 ? (long long *)w->tr_vol : nullptr;
     int32_t *d_trn = trace && tr_ncap > 0 ? w->tr_nodes : nullptr;
 
-    std::memcpy(w->h_seed_idx, sd->idx, 4 * (size_t)sd->nnz);
-    std::memcpy(w->h_seed_val, sd->val, 8 * (size_t)sd->nnz);
-    GDE_HIP(hipMemcpyAsync(w->seed_idx, w->h_seed_idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
-    GDE_HIP(hipMemcpyAsync(w->seed_val, w->h_seed_val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+    // a small seed travels in the seed kernel's arguments; a larger one (or one
+    // the Katz seed subtraction reads again) through the device seed buffers
+    const bool sub_seed = p->kind == GDE_KATZ && (p->flags & GDE_KATZ_SUBTRACT_SEED);
+    SeedInline inl{};
+    const SeedInline *pinl = nullptr;
+    if (sd->nnz <= kSeedInline && !sub_seed) {
+        inl.n = sd->nnz;
+        for (int32_t i = 0; i < sd->nnz; i++) {
+            inl.idx[i] = sd->idx[i];
+            inl.val[i] = sd->val[i];
+        }
+        pinl = &inl;
+    } else {
+        std::memcpy(w->h_seed_idx, sd->idx, 4 * (size_t)sd->nnz);
+        std::memcpy(w->h_seed_val, sd->val, 8 * (size_t)sd->nnz);
+        GDE_HIP(hipMemcpyAsync(w->seed_idx, w->h_seed_idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->seed_val, w->h_seed_val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+    }
 
     const int pgrid = push_grid(g), sgrid = snap_grid(g);
     BinArgs<V> bins{};
@@ -540,7 +554,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             psi[k] = acc;
         }
         void *plane[2] = {w->rd, w->rd2};
-        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
                             nullptr, 0, nullptr, w->st, s);
         for (int k = 0; k <= K; k++) {
             a.rd = plane[k & 1];
@@ -587,7 +601,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             }
             base = w->stamp_base;
         }
-        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, sd->nnz, bscale, w->front[0], nullptr,
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, bscale, w->front[0], nullptr,
                             ch ? w->cstamp : nullptr, base, w->tbm, w->st, s);
         a.rd = w->rd;
         // LocalCH scalars (c_t, m_t) of iteration t: delta_{t+1} = 1 / (2 sigma - delta_t),

@@ -51,8 +51,17 @@ struct SmallArgs {
 template <typename V> void launch_small(const SmallArgs<V> &a, bool ch, hipStream_t s);
 
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
+// A seed small enough to travel in the kernel arguments.
+constexpr int kSeedInline = 8;
+struct SeedInline {
+    int32_t n;  // 0: the seed is in the device buffers
+    int32_t idx[kSeedInline];
+    double val[kSeedInline];
+};
+
 template <typename V>
-void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
+void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, const SeedInline *inl, int32_t nnz,
+                      double bscale, int32_t *f0,
                       int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s);
 template <typename V> void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s);
 template <typename V>

@@ -83,14 +83,16 @@ __global__ void k_init_rd(const int32_t *__restrict__ row_ptr, RD<V> *rd, int32_
 }
 
 // r <- b on supp(s); S_0 = supp(s) (forced, Definition 3.1); counters reset.
+// A seed of at most kSeedInline entries arrives in the kernel arguments (inl.n
+// > 0) instead of device buffers, which saves two host-to-device copies.
 template <typename V>
 __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const double *__restrict__ sval, int32_t nnz,
-                            double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp, int32_t stamp0,
-                            uint32_t *tbm, DevState *st) {
+                            SeedInline inl, double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp,
+                            int32_t stamp0, uint32_t *tbm, DevState *st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nnz) {
-        int32_t u = sidx[i];
-        rd[u].r = (V)(bscale * sval[i]);
+        const int32_t u = inl.n ? inl.idx[i] : sidx[i];
+        rd[u].r = (V)(bscale * (inl.n ? inl.val[i] : sval[i]));
         f0[i] = u;
         if (touched0) touched0[i] = u;
         if (cstamp) cstamp[u] = stamp0;
@@ -1107,10 +1109,12 @@ void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s) 
 }
 
 template <typename V>
-void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, int32_t nnz, double bscale, int32_t *f0,
-                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s) {
+void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, const SeedInline *inl, int32_t nnz,
+                      double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm,
+                      DevState *st, hipStream_t s) {
+    SeedInline none{};
     hipLaunchKernelGGL(k_seed_init<V>, dim3(grid_for(nnz, 256, 65535)), dim3(256), 0, s, (RD<V> *)rd, sidx, sval, nnz,
-                       bscale, f0, touched0, cstamp, stamp0, tbm, st);
+                       inl ? *inl : none, bscale, f0, touched0, cstamp, stamp0, tbm, st);
 }
 
 template <typename V>
@@ -1212,7 +1216,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
 #define GDE_INST(V)                                                                                               \
     template void launch_small<V>(const SmallArgs<V> &, bool, hipStream_t);                                       \
     template void launch_init_rd<V>(const int32_t *, void *, int32_t, hipStream_t);                               \
-    template void launch_seed_init<V>(void *, const int32_t *, const double *, int32_t, double, int32_t *,        \
+    template void launch_seed_init<V>(void *, const int32_t *, const double *, const SeedInline *, int32_t, double, int32_t *,        \
                                       int32_t *, int32_t *, int32_t, uint32_t *, DevState *, hipStream_t);        \
     template void launch_snap_gd<V>(const SnapArgs &, V, int, hipStream_t);                                       \
     template void launch_snap_hk<V>(const SnapArgs &, void *, V, int, int, const int32_t *, int, int, double,    \
