@@ -497,11 +497,14 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
 // list (row start, edge offset, scatter value) and every counter live in LDS;
 // global memory is touched only for node state (r, d, x, Delta, stamps, the
 // pushed and touched bitmaps), the CSR, and fire-and-forget copies of the next
-// list that a grid-wide continuation reads.  A device-scope fence and a
-// workgroup barrier stand where a kernel boundary would be (the stores of the
-// snapshot must land before the adds of the push, and the adds before the
-// next snapshot reads r).  The arithmetic and every decision are those of
-// snap_gd / snap_ch followed by push_edges, iteration by iteration.
+// list that a grid-wide continuation reads.  Every access comes from this one
+// workgroup, so a workgroup barrier (with its workgroup-scope fences) stands
+// where a kernel boundary would be: the stores of the snapshot are ordered
+// before the adds of the push, and the adds before the next snapshot, which
+// reads r past L1 because atomics are performed in L2.  No device-scope fence
+// (an L2 write-back on this part) is needed inside the loop.  The arithmetic
+// and every decision are those of snap_gd / snap_ch followed by push_edges,
+// iteration by iteration.
 //
 // The launch stops before the snapshot of t when the list of t exceeds
 // kSmallMaxNodes (small_phase 0: the list is in global memory), after the
@@ -531,6 +534,13 @@ __device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long lo
     return r;
 }
 
+// Stages a touched-bitmap mark in LDS; a full stage marks at once instead.
+__device__ __forceinline__ void small_mark_later(int32_t w, uint32_t *tbm, int32_t *pend, int *npend) {
+    const int i = atomicAdd(npend, 1);
+    if (i < kSmallPendMarks) pend[i] = w;
+    else atomicOr(&tbm[w >> 5], 1u << (w & 31));
+}
+
 template <typename V, bool CH>
 __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
     constexpr int kNodesPer = kSmallMaxNodes / kSnapBlock;  // list entries per thread in the snapshot
@@ -542,6 +552,10 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
     __shared__ V s_sv[kSmallMaxNodes];
     __shared__ int s_cnt[2];
     __shared__ int s_ovf;
+    // touched-bitmap marks of a push, issued after the fence that ends it (the
+    // fence would otherwise wait for these memory-side atomics)
+    __shared__ int32_t s_tpend[kSmallPendMarks];
+    __shared__ int s_tpn;
     DevState *st = a.st;
     RD<V> *rd = (RD<V> *)a.rd;
     V *x = (V *)a.x;
@@ -557,6 +571,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
         s_cnt[0] = st->fcount[0];
         s_cnt[1] = st->fcount[1];
         s_ovf = 0;
+        s_tpn = 0;
     }
     __syncthreads();
     int t = a.t0;
@@ -574,6 +589,13 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
         const int cur = t & 1, nxt = cur ^ 1;
         int32_t *Fn = nxt ? a.front1 : a.front0;
         const int n_f = s_cnt[cur];
+        {
+            const int np = min(s_tpn, kSmallPendMarks);
+            for (int i = tid; i < np; i += blockDim.x)
+                atomicOr(&a.tbm[s_tpend[i] >> 5], 1u << (s_tpend[i] & 31));
+        }
+        __syncthreads();
+        if (tid == 0) s_tpn = 0;
         if (n_f > kSmallMaxNodes) break;
         if (tid == 0) s_push_base = pushes;
         // ---------------------------------------------------------- snapshot of t
@@ -601,7 +623,9 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
 #pragma unroll
         for (int k = 0; k < kNodesPer; k++) {
             const bool v = tid * kNodesPer + k < n_f;
-            e[k] = v ? rd[u[k]] : RD<V>{};
+            // r is updated by atomics, which are performed in L2: read it past L1
+            e[k].r = v ? __hip_atomic_load(&rd[u[k]].r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (V)0;
+            e[k].d = v ? rd[u[k]].d : (V)0;
             xo[k] = v ? x[u[k]] : (V)0;
             rp0[k] = v ? a.row_ptr[u[k]] : 0;
             rp1[k] = v ? a.row_ptr[u[k] + 1] : 0;
@@ -630,7 +654,6 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
             deg[k] = rp1[k] - rp0[k];
             const V w = a.w_div_deg ? a.wscale / (V)deg[k] : a.wscale;
             sv[k] = w * h;
-            atomicOr(&a.bitmap[u[k] >> 5], 1u << (u[k] & 31));
             mine += (1ull << 32) | (unsigned long long)(unsigned)deg[k];
         }
         unsigned long long tot;
@@ -659,8 +682,11 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
             }
         }
         if (tid == 0) s_off[count] = total;
-        __threadfence();
         __syncthreads();
+        // the pushed set (read only by the output kernels): marked after the fence
+#pragma unroll
+        for (int k = 0; k < kNodesPer; k++)
+            if (act[k]) atomicOr(&a.bitmap[u[k] >> 5], 1u << (u[k] & 31));
         if (count > 0 && (long long)total > kSmallMaxEdges) {
             // hand the push of t to the grid-wide kernel: work list, tile table, counters
             for (int i = tid; i < count; i += blockDim.x) {
@@ -714,7 +740,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
                              atomicExch(&a.cstamp[w[q]], stamp_next) != stamp_next;
 #pragma unroll
                 for (int q = 0; q < kEdgesPer; q++)
-                    if (hit[q] && a.tbm) atomicOr(&a.tbm[w[q] >> 5], 1u << (w[q] & 31));
+                    if (hit[q]) small_mark_later(w[q], a.tbm, s_tpend, &s_tpn);
             } else {
                 V th[kEdgesPer], old[kEdgesPer];
 #pragma unroll
@@ -728,7 +754,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
                     hit[q] = false;
                     if (w[q] >= 0 && dv[q] != (V)0) {
                         hit[q] = (old[q] < th[q]) && (old[q] + dv[q] >= th[q]);
-                        if (old[q] == (V)0 && a.tbm) atomicOr(&a.tbm[w[q] >> 5], 1u << (w[q] & 31));
+                        if (old[q] == (V)0) small_mark_later(w[q], a.tbm, s_tpend, &s_tpn);
                     }
                 }
             }
@@ -741,7 +767,6 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
                     else s_ovf = 1;
                 }
         }
-        __threadfence();
         __syncthreads();
         if (tid == 0) {
             if (count > 0) {
@@ -767,6 +792,10 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
         }
     }
     __syncthreads();
+    {
+        const int np = min(s_tpn, kSmallPendMarks);
+        for (int i = tid; i < np; i += blockDim.x) atomicOr(&a.tbm[s_tpend[i] >> 5], 1u << (s_tpend[i] & 31));
+    }
     if (tid == 0) {
         st->iters = iters;
         st->ops = ops;
