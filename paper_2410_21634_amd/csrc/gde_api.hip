@@ -454,7 +454,7 @@ int plain_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s) {
 // ------------------------------------------------------------------ the plain solver
 static int push_grid(const gde_graph *g) {
     int64_t tiles = g->nnz / kPushTile + 1;
-    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 1024);
+    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 512);
 }
 static int snap_grid(const gde_graph *g) {
     return (int)std::max<int64_t>(std::min<int64_t>((g->n + kSnapBlock - 1) / kSnapBlock, 512), 1);

@@ -21,7 +21,11 @@ constexpr int kMaxWaves = 16;  // wavefronts of the largest workgroup (1024 thre
 // wavefront keeps the counters off the critical path.
 constexpr int kSnapBlock = 1024;  // threads per snapshot workgroup
 constexpr int kPushBlock = 1024;  // threads per push workgroup
-constexpr int kPushTile = 4096;   // edges per push tile (4 per thread, issued together)
+constexpr int kPushTile = 1024;   // edges per push base tile (one per thread)
+// A large frontier is pushed in tiles of kMacroTiles base tiles (kMacroTiles edges
+// per thread, their loads issued together).
+constexpr int kMacroTiles = 4;
+constexpr long long kMacroMinEdges = 262144;
 constexpr int kBatchSnapBlock = 1024;  // threads per batched snapshot workgroup
 // Small frontiers: one workgroup runs consecutive iterations in one launch
 // (workgroup barriers in place of kernel boundaries) while the frontier stays

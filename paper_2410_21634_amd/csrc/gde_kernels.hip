@@ -309,6 +309,61 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_ch(const int32_t *__restric
 // tbm (MODE 0 and 2): the set of nodes whose residual may be nonzero; a node is
 // added when an add finds its residual at zero (MODE 0) or when it is first
 // marked as a candidate in an iteration (MODE 2).
+// Gather of one tile of M base tiles (M * kPushTile edges): the work-list
+// entries of the tile staged in LDS, then for each of the thread's M edges
+// (strided by kPushBlock) the entry by binary search and the destination from
+// col_idx (w = -1 past the end).  Returns false, with the overflow flag set, on
+// a broken work list.  Every thread of the workgroup calls it (it holds barriers).
+template <typename V>
+__device__ __forceinline__ bool gather_tile(int tile, int M, int nbase, int count, int total, int32_t cap,
+                                            int32_t nnz, const int32_t *__restrict__ tile_start,
+                                            const int32_t *__restrict__ wl_off, const int32_t *__restrict__ wl_beg,
+                                            const V *__restrict__ wl_sv, const int32_t *__restrict__ col_idx,
+                                            int32_t *s_off, int32_t *s_beg, V *s_sv, DevState *st,
+                                            int32_t (&w)[kMacroTiles], V (&dv)[kMacroTiles]) {
+#pragma unroll
+    for (int q = 0; q < kMacroTiles; q++) {
+        w[q] = -1;
+        dv[q] = (V)0;
+    }
+    const int b0 = tile * M;
+    const int e0 = b0 * kPushTile;
+    const int e1 = min(e0 + M * kPushTile, total);
+    const int i0 = tile_start[b0];
+    const int i1 = (b0 + M < nbase) ? tile_start[b0 + M] : count - 1;
+    const int m = min(i1 - i0 + 1, kMacroTiles * kPushTile + 1);
+    if (m <= 0 || i0 < 0 || i1 >= cap) {  // a broken work list: never index with it
+        if (threadIdx.x == 0) st->overflow = 1;
+        return false;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        s_off[j] = wl_off[i0 + j];
+        s_beg[j] = wl_beg[i0 + j];
+        s_sv[j] = wl_sv[i0 + j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMacroTiles; q++) {
+        const int e = e0 + q * kPushBlock + threadIdx.x;
+        if (q < M && e < e1) {
+            int lo = 0, hi = m - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int k = s_beg[lo] + (e - s_off[lo]);
+            if (k >= 0 && k < nnz) {
+                w[q] = col_idx[k];
+                dv[q] = s_sv[lo];
+            } else {
+                st->overflow = 1;
+            }
+        }
+    }
+    return true;
+}
+
 template <typename V, int MODE>
 __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevState *st, int cur,
                            const int32_t *__restrict__ wl_beg, const int32_t *__restrict__ wl_off,
@@ -316,10 +371,11 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
                            int32_t *next_list, int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next,
                            uint32_t *tbm, long long *tr_size, long long *tr_vol, long long tr_cap, int scatter,
                            int32_t cap, int32_t nnz, const BinArgs<V> &bins, int bid, int nblocks) {
-    constexpr int kPer = kPushTile / kPushBlock;
-    __shared__ int32_t s_off[kPushTile + 1];
-    __shared__ int32_t s_beg[kPushTile + 1];
-    __shared__ V s_sv[kPushTile + 1];
+    constexpr int kPer = kMacroTiles;  // edges per thread in a tile of kMacroTiles base tiles
+    static_assert(kPushTile == kPushBlock, "a base tile holds one edge per thread");
+    __shared__ int32_t s_off[kMacroTiles * kPushTile + 1];
+    __shared__ int32_t s_beg[kMacroTiles * kPushTile + 1];
+    __shared__ V s_sv[kMacroTiles * kPushTile + 1];
     extern __shared__ int32_t s_bin[];  // binned scatter: [nranges] counts, then [nranges] bases
     const int nxt = cur ^ 1;
     const unsigned long long pk = st->packed[cur];
@@ -339,7 +395,12 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
         st->pushes += count;
         st->iters = it + 1;
     }
-    const int ntiles = scatter ? (total + kPushTile - 1) / kPushTile : 0;
+    // tiles: kMacroTiles base tiles (kMacroTiles edges per thread, loads issued
+    // together) for a large frontier, one base tile (one edge per thread, four
+    // times as many workgroups) otherwise
+    const int nbase = scatter ? (total + kPushTile - 1) / kPushTile : 0;
+    const int M = (long long)total >= kMacroMinEdges ? kMacroTiles : 1;
+    const int ntiles = (nbase + M - 1) / M;
     // large frontier: write the updates into the destination-range bins (summed
     // by k_reduce); small frontier: atomic scatter with the crossing test here
     const bool binned = bins.nranges > 0 && (long long)total >= bins.min_edges && scatter;
@@ -348,46 +409,14 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
     if (binned)
         for (int r = threadIdx.x; r < bins.nranges; r += blockDim.x) s_cnt[r] = 0;
     for (int tile = bid; tile < ntiles; tile += nblocks) {
-        const int e0 = tile * kPushTile;
-        const int e1 = min(e0 + kPushTile, total);
-        const int i0 = tile_start[tile];
-        const int i1 = (tile + 1 < ntiles) ? tile_start[tile + 1] : count - 1;
-        const int m = min(i1 - i0 + 1, kPushTile + 1);
-        if (m <= 0 || i0 < 0 || i1 >= cap) {  // a broken work list: never index with it
-            if (threadIdx.x == 0) st->overflow = 1;
-            continue;
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < m; j += blockDim.x) {
-            s_off[j] = wl_off[i0 + j];
-            s_beg[j] = wl_beg[i0 + j];
-            s_sv[j] = wl_sv[i0 + j];
-        }
-        __syncthreads();
         int32_t w[kPer];
         V dv[kPer];
         bool hit[kPer], first[kPer];
 #pragma unroll
-        for (int q = 0; q < kPer; q++) {  // gather: work-list entry by binary search, then col_idx
-            const int e = e0 + q * kPushBlock + threadIdx.x;
-            w[q] = -1;
-            dv[q] = (V)0;
-            hit[q] = first[q] = false;
-            if (e < e1) {
-                int lo = 0, hi = m - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
-                }
-                const int k = s_beg[lo] + (e - s_off[lo]);
-                if (k >= 0 && k < nnz) {
-                    w[q] = col_idx[k];
-                    dv[q] = s_sv[lo];
-                } else {
-                    st->overflow = 1;
-                }
-            }
-        }
+        for (int q = 0; q < kPer; q++) hit[q] = first[q] = false;
+        if (!gather_tile<V>(tile, M, nbase, count, total, cap, nnz, tile_start, wl_off, wl_beg, wl_sv, col_idx,
+                            s_off, s_beg, s_sv, st, w, dv))
+            continue;
         if (binned) {
             // rank of each update inside its range for this tile (LDS), one global
             // reservation per nonempty range, then the writes
@@ -395,6 +424,7 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
 #pragma unroll
             for (int q = 0; q < kPer; q++) {
                 rb[q] = -1;
+                rk[q] = 0;
                 if (w[q] >= 0 && (MODE == 2 || dv[q] != (V)0)) {
                     rb[q] = w[q] >> bins.shift;
                     rk[q] = atomicAdd(&s_cnt[rb[q]], 1);
@@ -865,23 +895,24 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
 #pragma unroll
         for (int q = 0; q < kRedUnroll; q++) {
             if (!ok[q]) continue;
-            if (jj[q] >= 0 && jj[q] < span) {
-                atomicAdd(&s_acc[jj[q]], vv[q]);
-                atomicOr(&s_bits[jj[q] >> 5], 1u << (jj[q] & 31));
-            } else {
-                st->overflow = 1;
-            }
+            if (jj[q] >= 0 && jj[q] < span) atomicAdd(&s_acc[jj[q]], vv[q]);
+            else st->overflow = 1;
         }
     }
     __syncthreads();
+    // a node needs an update iff its binned sum is nonzero: the gathered values
+    // are positive in MODE 0/1, and in MODE 2 a zero sum leaves r_w unchanged,
+    // so w is neither newly nonzero nor a node whose test could change
     const int per = span_max / (int)blockDim.x;  // nodes per thread (power of two, <= 32)
     const int j0 = (int)threadIdx.x * per;
-    uint32_t hits = 0u, firsts = 0u;
+    uint32_t hits = 0u, firsts = 0u, tmask = 0u;
     for (int k = 0; k < per; k++) {
         const int j = j0 + k;
-        if (j >= span || !((s_bits[j >> 5] >> (j & 31)) & 1u)) continue;
-        const int32_t w = lo + j;
+        if (j >= span) continue;
         const V acc = s_acc[j];
+        if (acc == (V)0) continue;
+        tmask |= 1u << k;
+        const int32_t w = lo + j;
         if (MODE == 2) {
             // the residual of w is final for this iteration: only an active w joins
             // the candidates of t+1 (nodes of S_t were added by the snapshot)
@@ -904,9 +935,12 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     // the range's words of the touched-residual bitmap: every node with an update
     // (a superset of the first touches), one plain read-modify-write per word --
     // the words of a range belong to this workgroup alone
-    if (MODE != 1 && tbm)
+    if (MODE != 1 && tbm) {
+        if (tmask) atomicOr(&s_bits[j0 >> 5], tmask << (j0 & 31));
+        __syncthreads();
         for (int k = threadIdx.x; k < (span + 31) / 32; k += blockDim.x)
             if (s_bits[k]) tbm[(lo >> 5) + k] |= s_bits[k];
+    }
     int slot = block_reserve(__popc(hits), &st->fcount[cur ^ 1]);
     for (uint32_t h = hits; h; h &= h - 1u) {
         const int32_t w = lo + j0 + (__ffs((int)h) - 1);
