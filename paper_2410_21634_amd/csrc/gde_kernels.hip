@@ -870,13 +870,19 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     const int r = blockIdx.x;
     const int lo = r << bins.shift;
     const int span = min(span_max, n - lo);
-    const int cnt = bins.cursor[r];
+    // one thread reads the bin's cursor, hands it on through LDS and resets it
+    // (a load by every thread could still be in flight at the reset)
+    __shared__ int s_cnt0;
+    if (threadIdx.x == 0) {
+        s_cnt0 = bins.cursor[r];
+        bins.cursor[r] = 0;
+    }
     const long long b0 = bins.base[r];
     const long long avail = bins.base[r + 1] - b0;
     for (int j = threadIdx.x; j < span_max; j += blockDim.x) s_acc[j] = (V)0;
     for (int j = threadIdx.x; j < span_max / 32; j += blockDim.x) s_bits[j] = 0u;
     __syncthreads();
-    if (threadIdx.x == 0) bins.cursor[r] = 0;
+    const int cnt = s_cnt0;
     const int m = (int)min((long long)cnt, avail);
     constexpr int kRedUnroll = 4;  // bin entries per thread and step, loaded before any LDS update
     for (int i0 = 0; i0 < m; i0 += kRedUnroll * (int)blockDim.x) {
