@@ -20,6 +20,7 @@ namespace gde {
 // node-indexed array is zero; a batch leaves it zero again.
 struct BatchWS {
     uint64_t guid = 0;
+    uint32_t epoch = 0;  // touched-pair tag of the current solve (TM == epoch); 0 = never
     int vtype = 0, L = 0, Gcap = 0;
     int64_t n = 0, nwords = 0;
     size_t vs = 4;
@@ -299,6 +300,14 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.X = (V *)w->X;
     a.NM = w->NM;
     a.TM = w->TM;
+    // a new tag per solve marks the touched pairs, so the residual pass needs no
+    // clearing writes; on wrap-around the flags are reset once
+    if (++w->epoch == 0u) {
+        GDE_HIP(hipMemsetAsync(w->TM, 0, (size_t)g->n * G * 4, s));
+        w->epoch = 1u;
+    }
+    a.epoch = w->epoch;
+    a.g_epoch = nullptr;
     a.PB = w->PB;
     a.act[0] = w->act[0];
     a.act[1] = w->act[1];

@@ -40,7 +40,9 @@ struct BatchArgs {
     V *R;
     V *X;
     uint32_t *NM;  // [n][G] lanes crossing their threshold this iteration
-    uint32_t *TM;  // [n][G] pair touched flag
+    uint32_t *TM;  // [n][G] pair touched: TM == the group's epoch (never 0), so no clearing pass
+    uint32_t epoch;             // epoch of every group (batched solves)
+    const uint32_t *g_epoch;    // optional [G] per-group epochs (serving); replaces epoch
     uint32_t *PB;  // [G][nwords] pushed bitmap
     uint64_t *act[2];
     int32_t act_cap;

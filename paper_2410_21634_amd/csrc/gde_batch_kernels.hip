@@ -257,7 +257,8 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                 if (hit[q]) new_act[q] = atomicOr(&a.NM[(size_t)wq[q] * a.G + gq[q]], 1u << lq[q]) == 0u;
                 if (first[q]) {
                     uint32_t *tm = &a.TM[(size_t)wq[q] * a.G + gq[q]];
-                    if (*tm == 0u) new_touch[q] = atomicOr(tm, 1u) == 0u;
+                    const uint32_t ep = a.g_epoch ? a.g_epoch[gq[q]] : a.epoch;
+                    if (*tm != ep) new_touch[q] = atomicExch(tm, ep) != ep;
                 }
             }
             n_act += new_act[q] ? 1 : 0;
@@ -378,7 +379,6 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
             if (pr[q] == ~0ull) continue;
             const int32_t g = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
             a.R[((size_t)w * a.G + g) * L + l] = (V)0;
-            if (l == 0) a.TM[(size_t)w * a.G + g] = 0u;
             const double av = fabs((double)val[q]) * rscale;
             if (av > 0.0) {
                 const int lane_id = g * L + l;

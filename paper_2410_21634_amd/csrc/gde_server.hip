@@ -108,7 +108,6 @@ __global__ void __launch_bounds__(kBlock) k_srv_residual(const uint64_t *__restr
                 const size_t ri = ((size_t)w * G + g) * L + l;
                 const float val = R[ri];
                 R[ri] = 0.0f;
-                if (l == 0) TM[(size_t)w * G + g] = 0u;
                 const double av = fabs((double)val) * (double)rscale[g];
                 if (av > 0.0) {
                     const int lane_id = g * L + l;
@@ -273,8 +272,9 @@ __global__ void k_srv_correct_edges(const int32_t *__restrict__ src, const int32
 __global__ void k_srv_correct_nodes(const int32_t *__restrict__ nodes, int32_t nn, const int32_t *__restrict__ add,
                                     const int32_t *__restrict__ old_deg, int32_t G, int L,
                                     const int32_t *__restrict__ busy_kind, float *R, float *X, uint32_t *NM,
-                                    uint32_t *TM, uint64_t *act, int32_t *acount, int32_t act_cap, uint64_t *touched,
-                                    int32_t *tcount, int32_t touch_cap) {
+                                    uint32_t *TM, const uint32_t *__restrict__ g_epoch, uint64_t *act,
+                                    int32_t *acount, int32_t act_cap, uint64_t *touched, int32_t *tcount,
+                                    int32_t touch_cap) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nn * G) return;
     const int j = (int)(idx / G), g = (int)(idx % G);
@@ -297,7 +297,7 @@ __global__ void k_srv_correct_nodes(const int32_t *__restrict__ nodes, int32_t n
         const int s = atomicAdd(acount, 1);
         if (s < act_cap) act[s] = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
     }
-    if (atomicOr(&TM[(size_t)u * G + g], 1u) == 0u) {
+    if (atomicExch(&TM[(size_t)u * G + g], g_epoch[g]) != g_epoch[g]) {
         const int s = atomicAdd(tcount, 1);
         if (s < touch_cap) touched[s] = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
     }
@@ -320,6 +320,7 @@ struct SGroup {
     bool busy = false;
     int kind = -1;
     double param = 0.0;  // alpha (PPR) or beta (Katz)
+    uint32_t epoch = 0;  // touched-pair tag of the group's current occupants
     int start_t = 0;
     int max_iters = 0;
     bool cand = false;
@@ -349,6 +350,8 @@ struct gde_server {
     // device scratch for the server
     int32_t *d_drop = nullptr, *d_gactive = nullptr, *d_kind = nullptr, *d_mode = nullptr, *d_cnt = nullptr;
     float *d_gws = nullptr, *d_gparam = nullptr, *d_rscale = nullptr;
+    uint32_t *d_gepoch = nullptr;  // [G] touched-pair tags
+    uint32_t epoch_next = 1;
     uint64_t *d_act_tmp = nullptr;    // compaction target of the active list (capacity act_cap)
     uint64_t *d_touch_tmp = nullptr;  // compaction target of the touched list (capacity touch_cap)
     float *d_seed_b = nullptr;
@@ -384,6 +387,7 @@ int graph_replace_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const
 static int srv_args(gde_server *sv, BatchArgs<float> *a) {
     batch_args_from_ws(sv->w, sv->g, sv->G, a);
     a->g_wscale = sv->d_gws;
+    a->g_epoch = sv->d_gepoch;
     a->g_mode = sv->d_mode;
     a->max_iters = 1 << 30;
     return GDE_OK;
@@ -392,10 +396,12 @@ static int srv_args(gde_server *sv, BatchArgs<float> *a) {
 static int srv_upload_group_params(gde_server *sv) {
     std::vector<int32_t> kind(sv->G, -1), mode(sv->G, 0);
     std::vector<float> ws(sv->G, 0.f), prm(sv->G, 0.f), rsc(sv->G, 1.f);
+    std::vector<uint32_t> ep(sv->G, 0u);
     for (int gi = 0; gi < sv->G; gi++) {
         const SGroup &gr = sv->groups[gi];
         if (!gr.busy) continue;
         kind[gi] = gr.kind;
+        ep[gi] = gr.epoch;
         prm[gi] = (float)gr.param;
         ws[gi] = (float)(gr.kind == GDE_PPR ? 1.0 - gr.param : gr.param);
         mode[gi] = (gr.kind == GDE_PPR ? 1 : 0) | (gr.cand ? 2 : 0);
@@ -406,6 +412,7 @@ static int srv_upload_group_params(gde_server *sv) {
     GDE_HIP(hipMemcpyAsync(sv->d_gws, ws.data(), 4 * sv->G, hipMemcpyHostToDevice, sv->s));
     GDE_HIP(hipMemcpyAsync(sv->d_gparam, prm.data(), 4 * sv->G, hipMemcpyHostToDevice, sv->s));
     GDE_HIP(hipMemcpyAsync(sv->d_rscale, rsc.data(), 4 * sv->G, hipMemcpyHostToDevice, sv->s));
+    GDE_HIP(hipMemcpyAsync(sv->d_gepoch, ep.data(), 4 * sv->G, hipMemcpyHostToDevice, sv->s));
     return GDE_OK;
 }
 
@@ -424,6 +431,14 @@ static int srv_admit(gde_server *sv) {
         if (it == sv->pending.end()) break;
         gr = SGroup();
         gr.busy = true;
+        // a fresh tag: pairs the previous occupants touched read as untouched
+        if (sv->epoch_next == 0u) {
+            BatchArgs<float> ta{};
+            batch_args_from_ws(sv->w, sv->g, sv->G, &ta);
+            GDE_HIP(hipMemsetAsync(ta.TM, 0, (size_t)sv->g->n * sv->G * 4, sv->s));
+            sv->epoch_next = 1u;
+        }
+        gr.epoch = sv->epoch_next++;
         gr.kind = it->p.kind;
         gr.param = gr.kind == GDE_PPR ? it->p.alpha : it->p.beta;
         gr.start_t = sv->t;
@@ -787,7 +802,7 @@ static int srv_apply_inserts(gde_server *sv) {
         const int cur = sv->t & 1;
         int32_t *tcnt = batch_ws_touch_count(sv->w);
         hipLaunchKernelGGL(k_srv_correct_nodes, dim3((unsigned)((tn + 255) / 256)), dim3(256), 0, sv->s, nodes,
-                           (int32_t)hnodes.size(), add, olddeg, sv->G, sv->L, sv->d_kind, a.R, a.X, a.NM, a.TM,
+                           (int32_t)hnodes.size(), add, olddeg, sv->G, sv->L, sv->d_kind, a.R, a.X, a.NM, a.TM, sv->d_gepoch,
                            a.act[cur], &a.st->acount[cur], a.act_cap, a.touched, tcnt, a.touch_cap);
         GDE_HIP(hipGetLastError());
     }
@@ -862,6 +877,8 @@ int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cf
     if (e == hipSuccess) e = hipMalloc((void **)&sv->d_gws, 4 * (size_t)sv->G);
     if (e == hipSuccess) e = hipMalloc((void **)&sv->d_gparam, 4 * (size_t)sv->G);
     if (e == hipSuccess) e = hipMalloc((void **)&sv->d_rscale, 4 * (size_t)sv->G);
+    if (e == hipSuccess) e = hipMalloc((void **)&sv->d_gepoch, 4 * (size_t)sv->G);
+    if (e == hipSuccess) e = hipMemset(sv->d_gepoch, 0, 4 * (size_t)sv->G);
     if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchDev), sv->s);
     if (e != hipSuccess) return bail(hip_fail(e, "server buffers"));
     rc = srv_upload_group_params(sv);
@@ -929,7 +946,7 @@ int gde_server_insert_edges(gde_server *sv, int32_t k, const int32_t *u, const i
 int gde_server_destroy(gde_server *sv) {
     if (!sv) return fail(GDE_ERR_INVALID_ARG, "null server");
     if (sv->s) (void)hipStreamSynchronize(sv->s);
-    void *p[] = {sv->d_drop, sv->d_gactive, sv->d_kind, sv->d_mode, sv->d_cnt, sv->d_gws, sv->d_gparam, sv->d_rscale,
+    void *p[] = {sv->d_drop, sv->d_gactive, sv->d_kind, sv->d_mode, sv->d_cnt, sv->d_gws, sv->d_gparam, sv->d_rscale, sv->d_gepoch,
                  sv->d_act_tmp, sv->d_touch_tmp, sv->d_seed_b, sv->d_seed_lane, sv->d_seed_node, sv->d_out_idx, sv->d_out_val,
                  sv->spare_rp, sv->spare_ci, sv->t_add, sv->t_olddeg, sv->t_cursor, sv->t_bsum, sv->t_src, sv->t_dst,
                  sv->t_flag};
