@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -218,7 +219,21 @@ static int ws_create(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s,
     WS_ALLOC(w->wl_off, 4 * n);
     WS_ALLOC(w->wl_sv, vs * n);
     WS_ALLOC(w->st, sizeof(DevState));
-    hipError_t e = hipHostMalloc((void **)&w->hst, sizeof(DevState), hipHostMallocDefault);
+    // host-coherent: the publication kernel writes it while the host polls it
+    hipError_t e = hipHostMalloc((void **)&w->hst, sizeof(DevState) + 128, hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        const size_t off = ((sizeof(DevState) + 63) / 64) * 64;
+        w->hseq = (uint32_t *)((char *)w->hst + off);
+        *w->hseq = 0u;
+        w->seq = 0u;
+        void *dp = nullptr;
+        e = hipHostGetDevicePointer(&dp, w->hst, 0);
+        if (e == hipSuccess && !dp) e = hipErrorInvalidValue;
+        if (e == hipSuccess) {
+            w->hst_dev = (DevState *)dp;
+            w->hseq_dev = (uint32_t *)((char *)dp + off);
+        }
+    }
     if (e != hipSuccess) { ws_free(w); return hip_fail(e, "hipHostMalloc"); }
     // bins of the binned scatter: one per range of 2^S nodes, sized by the range's in-volume
     int shift = 0;
@@ -460,6 +475,28 @@ static int snap_grid(const gde_graph *g) {
     return (int)std::max<int64_t>(std::min<int64_t>((g->n + kSnapBlock - 1) / kSnapBlock, 512), 1);
 }
 
+// Makes the device state of w visible in w->hst: the publication kernel is
+// enqueued after everything on s and the host polls its sequence number for a
+// short while (the runtime's blocking wait resumes later than a polling host);
+// a longer wait, or a stream that failed, falls back to the blocking wait.
+static int sync_state(Workspace *w, hipStream_t s) {
+    constexpr double kSpinSeconds = 2e-3;
+    const uint32_t want = ++w->seq;
+    launch_publish(w->st, w->hst_dev, w->hseq_dev, want, s);
+    GDE_HIP(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0;; k++) {
+        if (__atomic_load_n(w->hseq, __ATOMIC_ACQUIRE) == want) return GDE_OK;
+        if ((k & 255) == 255 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > kSpinSeconds)
+            break;
+        __builtin_ia32_pause();
+    }
+    GDE_HIP(hipStreamSynchronize(s));
+    if (__atomic_load_n(w->hseq, __ATOMIC_ACQUIRE) != want) return fail(GDE_ERR_DEVICE, "state publication missing");
+    return GDE_OK;
+}
+
 template <typename V>
 static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
                        hipStream_t s) {
@@ -670,8 +707,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             launch_small<V>(sa, ch, s);
             if ((e = prof_mark(ctx, s))) return e;
             GDE_HIP(hipGetLastError());
-            GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-            GDE_HIP(hipStreamSynchronize(s));
+            if ((e = sync_state(w, s))) return e;
             t = w->hst->small_t;
             if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) {
                 converged = true;
@@ -719,8 +755,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                 }
             }
             GDE_HIP(hipGetLastError());
-            GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-            GDE_HIP(hipStreamSynchronize(s));
+            if ((rc = sync_state(w, s))) return rc;
             if (w->hst->empty_seen || (!ch && w->hst->fcount[t & 1] == 0)) { converged = true; break; }
             if (small_ok && t < p->max_iters && w->hst->fcount[t & 1] <= kSmallMaxNodes) {
                 if ((rc = run_small())) return rc;
@@ -732,8 +767,8 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         if (!converged) {
             if (ch) {
                 launch_ch_probe<V>(w->rd, w->front[t & 1], w->st, t & 1, eps_eff, g->n, s);
-                GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-                GDE_HIP(hipStreamSynchronize(s));
+                GDE_HIP(hipGetLastError());
+                if ((rc = sync_state(w, s))) return rc;
                 converged = w->hst->probe == 0;
             } else {
                 converged = w->hst->fcount[t & 1] == 0;
@@ -761,8 +796,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, bufs ? res->idx : nullptr,
                           bufs ? res->val : nullptr, bufs ? res->capacity : 0, w->st, s);
         GDE_HIP(hipGetLastError());
-        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-        GDE_HIP(hipStreamSynchronize(s));
+        if ((rc = sync_state(w, s))) return rc;
         nnz = w->hst->out_count;
         fits = bufs && nnz <= res->capacity;
     } else {

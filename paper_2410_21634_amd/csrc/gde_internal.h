@@ -114,7 +114,11 @@ struct Workspace {
     int32_t *blk = nullptr;        // extraction block sums
     int64_t nblk = 0;
     DevState *st = nullptr;        // device
-    DevState *hst = nullptr;       // pinned host mirror
+    DevState *hst = nullptr;       // pinned, host-coherent mirror of st
+    uint32_t *hseq = nullptr;      // in the same allocation: sequence number of the last publication
+    DevState *hst_dev = nullptr;   // device address of hst (for the publication kernel)
+    uint32_t *hseq_dev = nullptr;  // device address of hseq
+    uint32_t seq = 0;              // last sequence number asked for
     int32_t *seed_idx = nullptr;   // device staging for seeds
     double *seed_val = nullptr;
     int32_t seed_cap = 0;

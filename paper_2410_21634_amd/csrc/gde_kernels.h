@@ -49,6 +49,7 @@ struct SmallArgs {
 };
 
 template <typename V> void launch_small(const SmallArgs<V> &a, bool ch, hipStream_t s);
+void launch_publish(const DevState *st, DevState *out, uint32_t *seq, uint32_t val, hipStream_t s);
 
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
 // A seed small enough to travel in the kernel arguments.

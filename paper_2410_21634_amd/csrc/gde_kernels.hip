@@ -163,11 +163,14 @@ __device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
         V sv = (V)0;
         if (act) {
             u = F[i];
-            V v = rd[u].r;
+            // every load before the first store: one round trip, not three
+            const V v = rd[u].r;
+            const V xo = x[u];
+            const int32_t rp0 = row_ptr[u], rp1 = row_ptr[u + 1];
             rd[u].r = (V)0;
-            x[u] += v;
-            beg = row_ptr[u];
-            deg = row_ptr[u + 1] - beg;
+            x[u] = xo + v;
+            beg = rp0;
+            deg = rp1 - rp0;
             V w = w_div_deg ? wscale / (V)deg : wscale;
             sv = w * v;
         }
@@ -215,12 +218,15 @@ __global__ void __launch_bounds__(kSnapBlock) k_snap_hk(const int32_t *__restric
         V sv = (V)0;
         if (act) {
             u = F[i];
-            V v = plane[u].r;
+            // every load before the first store: one round trip, not three
+            const RD<V> e = plane[u];
+            const V xo = x[u];
+            const int32_t rp0 = row_ptr[u], rp1 = row_ptr[u + 1];
             plane[u].r = (V)0;
-            x[u] += v;
-            beg = row_ptr[u];
-            deg = row_ptr[u + 1] - beg;
-            sv = last_level ? (V)0 : wmul * v / plane[u].d;
+            x[u] = xo + e.r;
+            beg = rp0;
+            deg = rp1 - rp0;
+            sv = last_level ? (V)0 : wmul * e.r / e.d;
         }
         emit_entries<V>(act, u, beg, deg, sv, bitmap, st, cur, wl_node, wl_beg, wl_off, wl_sv, tile_start,
                         tr_nodes, push_base, tr_cap, cap);
@@ -263,13 +269,19 @@ __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
             RD<V> e = rd[u];
             act = force || (e.r != (V)0 && fabs(e.r) >= eps_eff * e.d);
             if (act) {
-                V h = force ? e.r : c_t * e.r + m_t * (dstamp[u] == stamp_cur - 1 ? delta[u] : (V)0);
-                x[u] += h;
+                // the node's other state in one round of loads (Delta is read even
+                // when its stamp will say it is stale)
+                const int32_t ds = dstamp[u];
+                const V dl = delta[u];
+                const V xo = x[u];
+                const int32_t rp0 = row_ptr[u], rp1 = row_ptr[u + 1];
+                V h = force ? e.r : c_t * e.r + m_t * (ds == stamp_cur - 1 ? dl : (V)0);
+                x[u] = xo + h;
                 rd[u].r = e.r - h;
                 delta[u] = h;
                 dstamp[u] = stamp_cur;
-                beg = row_ptr[u];
-                deg = row_ptr[u + 1] - beg;
+                beg = rp0;
+                deg = rp1 - rp0;
                 V w = w_div_deg ? wscale / (V)deg : wscale;
                 sv = w * h;
             }
@@ -1166,6 +1178,26 @@ __global__ void k_fill_f64(double *v, int64_t n, double val) {
 }
 
 // ------------------------------------------------------------------ launchers
+// Publication of the solver state to host memory: every word of *st is copied
+// into the host-coherent mirror, made visible at system scope, and then the
+// sequence number is released; a host that reads the number reads the state.
+__global__ void __launch_bounds__(64) k_publish(const DevState *__restrict__ st, DevState *out, uint32_t *seq,
+                                                uint32_t val) {
+    constexpr int kWords = (int)(sizeof(DevState) / 4);
+    static_assert(kWords <= 64, "one wavefront copies the state");
+    const int i = threadIdx.x;
+    if (i < kWords) {
+        ((uint32_t *)out)[i] = ((const uint32_t *)st)[i];
+        __threadfence_system();
+    }
+    __syncthreads();
+    if (i == 0) __hip_atomic_store(seq, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const DevState *st, DevState *out, uint32_t *seq, uint32_t val, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, st, out, seq, val);
+}
+
 static inline int grid_for(int64_t items, int block, int cap) {
     int64_t g = (items + block - 1) / block;
     if (g < 1) g = 1;
