@@ -605,7 +605,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             if ((rc = prof_mark(ctx, s))) return rc;
             launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
                            w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
-                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, bins, s);
+                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, bins, nullptr, s);
             if ((rc = prof_mark(ctx, s))) return rc;
         }
         // clean-up of the last level
@@ -716,11 +716,11 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                 if (ch)
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
-                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, nullptr, s);
                 else
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
-                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, nullptr, s);
                 if ((e = prof_mark(ctx, s))) return e;
                 t++;
             }
@@ -728,7 +728,26 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         };
         if (small_ok && (rc = run_small())) return rc;
         // grid-wide iterations in chunks between host synchronisations: 8, then
-        // doubling up to 32 while the frontier stays large
+        // doubling up to 32 while the frontier stays large.  Inside a chunk the
+        // range reduction of a binned LocalGD iteration also takes the snapshot of
+        // the next one for the nodes it activates; the last reduction of a chunk
+        // does not, so that every synchronisation sees an iteration boundary.
+        FuseArgs<V> fz{};
+        fz.row_ptr = g->row_ptr;
+        fz.x = (V *)w->x;
+        fz.bitmap = w->bitmap;
+        fz.wl_node = w->wl_node;
+        fz.wl_beg = w->wl_beg;
+        fz.wl_off = w->wl_off;
+        fz.wl_sv = (V *)w->wl_sv;
+        fz.tile_start = w->tile_start;
+        fz.tr_nodes = d_trn;
+        fz.tr_cap = tr_ncap;
+        fz.wscale = wscale;
+        fz.w_div_deg = w_div_deg;
+        fz.delta = (V *)w->delta;
+        fz.dstamp = w->dstamp;
+        fz.cap = g->n;
         int chunk = 8;
         while (!converged && t < p->max_iters) {
             int end = std::min(p->max_iters, t + chunk);
@@ -741,16 +760,20 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
                                       w->cstamp, base + t, w->front[(t + 1) & 1], s);
                     if ((rc = prof_mark(ctx, s))) return rc;
+                    // LocalCH keeps its separate snapshot (its self-marked nodes need it
+                    // anyway; measured slower fused)
+                    fz.on = 0;
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
-                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                                   w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, &fz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 } else {
                     launch_snap_gd<V>(a, wscale, w_div_deg, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
+                    fz.on = t + 1 < end ? 1 : 0;
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, nullptr, 0, w->tbm, d_trs,
-                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, s);
+                                   d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, &fz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 }
             }

@@ -23,6 +23,30 @@ struct SnapArgs {
     int32_t cap;          // capacity of every node list (n)
 };
 
+// The snapshot of t+1 taken inside the range reduction of a binned iteration t,
+// for the nodes the reduction itself activates: every crossing of LocalGD, and
+// the LocalCH candidates that were not in S_t (so their momentum term is zero).
+// Their residuals are final in registers and their state is range-local there.
+template <typename V>
+struct FuseArgs {
+    int on;                      // 0: plain reduction (appends S_{t+1} / C_{t+1} to the list)
+    const int32_t *row_ptr;
+    V *x;
+    uint32_t *bitmap;            // pushed set
+    int32_t *wl_node, *wl_beg, *wl_off;
+    V *wl_sv;
+    int32_t *tile_start;
+    int32_t *tr_nodes;
+    long long tr_cap;
+    V wscale;
+    int w_div_deg;
+    V c_next;                    // LocalCH: c_{t+1}
+    V *delta;
+    int32_t *dstamp;
+    int32_t *list2;              // LocalCH: candidates of t+2 (self-marks of S_{t+1})
+    int32_t cap;
+};
+
 // Everything the single-workgroup iteration kernel needs (LocalGD or LocalCH).
 template <typename V>
 struct SmallArgs {
@@ -76,7 +100,7 @@ void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
                  int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
                  long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, const BinArgs<V> &bins,
-                 hipStream_t s);
+                 const FuseArgs<V> *fz, hipStream_t s);
 void launch_bin_count(const int32_t *col_idx, long long nnz, int shift, int nranges, unsigned long long *counts,
                       hipStream_t s);
 template <typename V>

@@ -871,7 +871,7 @@ template <typename V, int MODE>
 __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> *dst, DevState *st, int cur,
                                                           V eps_eff, int32_t *next_list, int32_t *touched, int tslot,
                                                           int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
-                                                          int scatter, int32_t cap, int32_t n) {
+                                                          int scatter, int32_t cap, int32_t n, FuseArgs<V> fz) {
     // 16-byte aligned: the FP64 accumulator takes 64-bit LDS atomics, which need natural alignment
     extern __shared__ __attribute__((aligned(16))) unsigned char s_red[];
     const int span_max = 1 << bins.shift;
@@ -921,10 +921,20 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     // a node needs an update iff its binned sum is nonzero: the gathered values
     // are positive in MODE 0/1, and in MODE 2 a zero sum leaves r_w unchanged,
     // so w is neither newly nonzero nor a node whose test could change
-    const int per = span_max / (int)blockDim.x;  // nodes per thread (power of two, <= 32)
+    // nodes per thread: the range of kBinLdsBytes / sizeof(V) nodes over the workgroup
+    constexpr int per = kBinLdsBytes / (int)sizeof(V) / kReduceBlock;
+    static_assert(per >= 1 && per <= 32, "one hit bit per node of a thread");
+    if (span_max != per * (int)blockDim.x) {  // the host sized the ranges differently: never index with it
+        if (threadIdx.x == 0) st->overflow = 1;
+        return;
+    }
     const int j0 = (int)threadIdx.x * per;
+    const bool fuse = MODE != 1 && fz.on;
     uint32_t hits = 0u, firsts = 0u, tmask = 0u;
+    V hval[per];  // fused snapshot: the amount moved into x for each hit (v or h)
+#pragma unroll
     for (int k = 0; k < per; k++) {
+        hval[k] = (V)0;
         const int j = j0 + k;
         if (j >= span) continue;
         const V acc = s_acc[j];
@@ -936,18 +946,38 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
             // the candidates of t+1 (nodes of S_t were added by the snapshot)
             const RD<V> e = dst[w];
             const V nr = e.r + acc;
-            dst[w].r = nr;
             if (nr != (V)0 && fabs(nr) >= eps_eff * e.d && cstamp[w] != stamp_next) {
-                cstamp[w] = stamp_next;
                 hits |= 1u << k;
+                if (fuse) {
+                    // w is not in S_t: h = c_{t+1} r_w (no momentum term)
+                    const V h = fz.c_next * nr;
+                    hval[k] = h;
+                    dst[w].r = nr - h;
+                    fz.x[w] += h;
+                    fz.delta[w] = h;
+                    fz.dstamp[w] = stamp_next;
+                    cstamp[w] = stamp_next + 1;  // its residual changed again: a candidate of t+2
+                } else {
+                    dst[w].r = nr;
+                    cstamp[w] = stamp_next;
+                }
+            } else {
+                dst[w].r = nr;
             }
         } else {
             const RD<V> e = dst[w];
             const V nw = e.r + acc;
-            dst[w].r = nw;
             const V th = eps_eff * e.d;
-            if (e.r < th && nw >= th) hits |= 1u << k;
+            const bool hit = e.r < th && nw >= th;
+            if (hit) hits |= 1u << k;
             if (e.r == (V)0) firsts |= 1u << k;
+            if (hit && fuse) {  // snapshot of t+1: v = r_w, r_w = 0, x_w += v
+                hval[k] = nw;
+                dst[w].r = (V)0;
+                fz.x[w] += nw;
+            } else {
+                dst[w].r = nw;
+            }
         }
     }
     // the range's words of the touched-residual bitmap: every node with an update
@@ -958,6 +988,54 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
         __syncthreads();
         for (int k = threadIdx.x; k < (span + 31) / 32; k += blockDim.x)
             if (s_bits[k]) tbm[(lo >> 5) + k] |= s_bits[k];
+    }
+    if (fuse) {
+        // work-list entries of the hits (the list of t+1 is not needed for them)
+        const long long push_base = st->pushes;
+        int32_t begs[per], degs[per];
+        unsigned long long mine = 0ull;
+#pragma unroll
+        for (int k = 0; k < per; k++) {
+            begs[k] = degs[k] = 0;
+            if (!((hits >> k) & 1u)) continue;
+            const int32_t w = lo + j0 + k;
+            begs[k] = fz.row_ptr[w];
+            degs[k] = fz.row_ptr[w + 1] - begs[k];
+            mine += (1ull << 32) | (unsigned long long)(unsigned)degs[k];
+        }
+        const unsigned long long res = block_reserve64(mine, &st->packed[cur ^ 1]);
+        int slot = (int)(res >> 32);
+        int off = (int)(res & 0xffffffffull);
+#pragma unroll
+        for (int k = 0; k < per; k++) {
+            if (!((hits >> k) & 1u)) continue;
+            const int32_t w = lo + j0 + k;
+            if (slot >= fz.cap) {
+                st->overflow = 1;
+                continue;
+            }
+            const V wgt = fz.w_div_deg ? fz.wscale / (V)degs[k] : fz.wscale;
+            fz.wl_node[slot] = w;
+            fz.wl_beg[slot] = begs[k];
+            fz.wl_off[slot] = off;
+            fz.wl_sv[slot] = wgt * hval[k];
+            for (int q = (off + kPushTile - 1) / kPushTile; (long long)q * kPushTile < (long long)off + degs[k]; q++)
+                fz.tile_start[q] = slot;
+            if (fz.tr_nodes && push_base + slot < fz.tr_cap) fz.tr_nodes[push_base + slot] = w;
+            atomicOr(&fz.bitmap[w >> 5], 1u << (w & 31));
+            slot++;
+            off += degs[k];
+        }
+        if (MODE == 2) {  // the fused nodes are candidates of t+2
+            int s2 = block_reserve(__popc(hits), &st->fcount[cur]);
+            for (uint32_t hm = hits; hm; hm &= hm - 1u) {
+                const int32_t w = lo + j0 + (__ffs((int)hm) - 1);
+                if (s2 < cap) fz.list2[s2] = w;
+                else st->overflow = 1;
+                s2++;
+            }
+        }
+        return;
     }
     int slot = block_reserve(__popc(hits), &st->fcount[cur ^ 1]);
     for (uint32_t h = hits; h; h &= h - 1u) {
@@ -1248,7 +1326,7 @@ void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState
                  const int32_t *wl_off, const void *wl_sv, const int32_t *tile_start, V eps_eff, int32_t *next_list,
                  int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next, uint32_t *tbm, long long *tr_size,
                  long long *tr_vol, long long tr_cap, int scatter, int32_t cap, int32_t nnz, const BinArgs<V> &bins,
-                 hipStream_t s) {
+                 const FuseArgs<V> *fz, hipStream_t s) {
     auto kern = mode == 0 ? k_push<V, 0> : mode == 1 ? k_push<V, 1> : k_push<V, 2>;
     const size_t dyn = 2 * sizeof(int32_t) * (size_t)bins.nranges;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kPushBlock), dyn, s, col_idx, (RD<V> *)dst, st, cur, wl_beg, wl_off,
@@ -1258,7 +1336,8 @@ void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState
         auto red = mode == 0 ? k_reduce<V, 0> : mode == 1 ? k_reduce<V, 1> : k_reduce<V, 2>;
         const size_t rdyn = sizeof(V) * ((size_t)1 << bins.shift) + sizeof(uint32_t) * (((size_t)1 << bins.shift) / 32);
         hipLaunchKernelGGL(red, dim3(bins.nranges), dim3(kReduceBlock), rdyn, s, bins, (RD<V> *)dst, st, cur, eps_eff,
-                           next_list, touched, tslot, cstamp, stamp_next, tbm, scatter, cap, (int32_t)(cap));
+                           next_list, touched, tslot, cstamp, stamp_next, tbm, scatter, cap, (int32_t)(cap),
+                           fz ? *fz : FuseArgs<V>{});
     }
 }
 
@@ -1327,7 +1406,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
     template void launch_push<V>(int, int, const int32_t *, void *, DevState *, int, const int32_t *,            \
                                  const int32_t *, const void *, const int32_t *, V, int32_t *, int32_t *, int,    \
                                  int32_t *, int32_t, uint32_t *, long long *, long long *, long long, int,        \
-                                 int32_t, int32_t, const BinArgs<V> &, hipStream_t);                              \
+                                 int32_t, int32_t, const BinArgs<V> &, const FuseArgs<V> *, hipStream_t);                              \
     template void launch_final_residual<V>(uint32_t *, int64_t, void *, DevState *, double, hipStream_t);         \
     template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
     template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \
