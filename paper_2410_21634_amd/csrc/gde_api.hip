@@ -593,7 +593,9 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         void *plane[2] = {w->rd, w->rd2};
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
                             nullptr, 0, nullptr, w->st, s);
-        for (int k = 0; k <= K; k++) {
+        auto eps_at = [&](int k) { return k >= K ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]); };
+        // level k on the grid-wide kernels: clean-up of k-1 and snapshot of k, then the push into k+1
+        auto grid_level = [&](int k) -> int {
             a.rd = plane[k & 1];
             a.F = w->front[k & 1];
             a.cur = k & 1;
@@ -601,19 +603,86 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             launch_snap_hk<V>(a, plane[(k + 1) & 1], (V)(tau / (double)(k + 1)), last ? 1 : 0, 1,
                               k >= 1 ? w->touched[(k + 2) % 3] : nullptr, (k + 2) % 3, (k + 1) % 3,
                               k >= 1 ? psi[k - 1] : 0.0, k >= 1 ? (double)(K + 1) * psi[k - 1] : 0.0, s);
-            const double eps_next = last ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]);
-            if ((rc = prof_mark(ctx, s))) return rc;
+            int e = prof_mark(ctx, s);
+            if (e) return e;
             launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off, w->wl_sv,
-                           w->tile_start, (V)eps_next, w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
-                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, bins, nullptr, s);
-            if ((rc = prof_mark(ctx, s))) return rc;
+                           w->tile_start, (V)eps_at(k), w->front[(k + 1) & 1], w->touched[(k + 1) % 3], (k + 1) % 3,
+                           nullptr, 0, nullptr, d_trs, d_trv, tr_cap, last ? 0 : 1, g->n, (int32_t)g->nnz, bins, nullptr,
+                           s);
+            return prof_mark(ctx, s);
+        };
+        // small frontiers: one workgroup runs levels k .. (and the final clean-up)
+        const bool small_ok = !(p->flags & GDE_SCATTER_BINNED);
+        HkSmallArgs<V> ha{};
+        ha.row_ptr = g->row_ptr;
+        ha.col_idx = g->col_idx;
+        ha.plane[0] = plane[0];
+        ha.plane[1] = plane[1];
+        ha.x = w->x;
+        ha.bitmap = w->bitmap;
+        ha.st = w->st;
+        for (int i = 0; i < 2; i++) ha.front[i] = w->front[i];
+        for (int i = 0; i < 3; i++) ha.touched[i] = w->touched[i];
+        ha.wl_beg = w->wl_beg;
+        ha.wl_off = w->wl_off;
+        ha.wl_sv = w->wl_sv;
+        ha.tile_start = w->tile_start;
+        ha.tr_nodes = d_trn;
+        ha.tr_ncap = tr_ncap;
+        ha.tr_size = d_trs;
+        ha.tr_vol = d_trv;
+        ha.tr_cap = tr_cap;
+        ha.tau = tau;
+        ha.eps = p->eps;
+        ha.K = K;
+        ha.cap = g->n;
+        ha.nnz = (int32_t)g->nnz;
+        int k = 0;
+        bool done = false;
+        auto run_small_hk = [&]() -> int {
+            ha.k0 = k;
+            int e = prof_mark(ctx, s);
+            if (e) return e;
+            launch_small_hk<V>(ha, s);
+            if ((e = prof_mark(ctx, s))) return e;
+            GDE_HIP(hipGetLastError());
+            if ((e = sync_state(w, s))) return e;
+            k = w->hst->small_t;
+            if (w->hst->small_phase == 2) {
+                done = true;
+            } else if (w->hst->small_phase == 1) {  // the snapshot of level k is done; its push is not
+                if ((e = prof_mark(ctx, s))) return e;
+                launch_push<V>(1, pgrid, g->col_idx, plane[(k + 1) & 1], w->st, k & 1, w->wl_beg, w->wl_off,
+                               w->wl_sv, w->tile_start, (V)eps_at(k), w->front[(k + 1) & 1], w->touched[(k + 1) % 3],
+                               (k + 1) % 3, nullptr, 0, nullptr, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz,
+                               bins, nullptr, s);
+                if ((e = prof_mark(ctx, s))) return e;
+                k++;
+            }
+            return GDE_OK;
+        };
+        if (small_ok && (rc = run_small_hk())) return rc;
+        // grid-wide levels: eight, then one synchronisation that hands a frontier
+        // which has shrunk back to the single workgroup, then the rest back to
+        // back (a synchronisation per chunk of levels measured slower than it saved)
+        for (int pass = 0; pass < 2 && !done && k <= K; pass++) {
+            const int end = pass == 0 && small_ok ? std::min(K + 1, k + 8) : K + 1;
+            for (; k < end; k++)
+                if ((rc = grid_level(k))) return rc;
+            if (pass == 0 && small_ok && k <= K) {
+                if ((rc = sync_state(w, s))) return rc;
+                if (w->hst->fcount[k & 1] <= kSmallMaxNodes && w->hst->tcount[(k + 2) % 3] <= kSmallMaxEdges &&
+                    (rc = run_small_hk()))
+                    return rc;
+            }
         }
-        // clean-up of the last level
-        a.rd = plane[(K + 1) & 1];
-        a.F = w->front[(K + 1) & 1];
-        a.cur = (K + 1) & 1;
-        launch_snap_hk<V>(a, plane[K & 1], (V)0, 1, 0, w->touched[K % 3], K % 3, -1, psi[K], (double)(K + 1) * psi[K],
-                          s);
+        if (!done) {  // clean-up of the last level
+            a.rd = plane[(K + 1) & 1];
+            a.F = w->front[(K + 1) & 1];
+            a.cur = (K + 1) & 1;
+            launch_snap_hk<V>(a, plane[K & 1], (V)0, 1, 0, w->touched[K % 3], K % 3, -1, psi[K],
+                              (double)(K + 1) * psi[K], s);
+        }
         GDE_HIP(hipGetLastError());
         converged = true;
     } else {

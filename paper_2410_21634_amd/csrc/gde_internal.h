@@ -34,6 +34,7 @@ constexpr int kSmallIters = 32;             // iterations one single-workgroup l
 constexpr int kSmallMaxNodes = 4096;        // frontier / candidate list it accepts
 constexpr long long kSmallMaxEdges = 16384; // frontier volume it accepts
 constexpr int kSmallPendMarks = 8192;      // touched-bitmap marks it stages in LDS per push
+constexpr int kHkMaxLevels = 256;          // largest heat-kernel truncation K
 // Binned scatter for large frontiers: updates are written, grouped by
 // destination range of 2^S nodes, into per-range bins and then summed in LDS
 // by one workgroup per range (no global atomic per edge).

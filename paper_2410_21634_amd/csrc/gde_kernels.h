@@ -73,6 +73,31 @@ struct SmallArgs {
 };
 
 template <typename V> void launch_small(const SmallArgs<V> &a, bool ch, hipStream_t s);
+
+// The heat-kernel level push of small frontiers, one workgroup over consecutive
+// levels k0 .. K (and the final clean-up).
+template <typename V>
+struct HkSmallArgs {
+    const int32_t *row_ptr, *col_idx;
+    void *plane[2];              // RD<V> planes: level k uses plane[k & 1]
+    void *x;
+    uint32_t *bitmap;
+    DevState *st;
+    int32_t *front[2];           // S_k in front[k & 1]
+    int32_t *touched[3];         // nodes of level k with a nonzero residual in touched[k % 3]
+    int32_t *wl_beg, *wl_off;
+    void *wl_sv;
+    int32_t *tile_start;
+    int32_t *tr_nodes;
+    long long tr_ncap;
+    long long *tr_size, *tr_vol;
+    long long tr_cap;
+    double tau, eps;
+    int K, k0;
+    int32_t cap, nnz;
+};
+
+template <typename V> void launch_small_hk(const HkSmallArgs<V> &a, hipStream_t s);
 void launch_publish(const DevState *st, DevState *out, uint32_t *seq, uint32_t val, hipStream_t s);
 
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);
