@@ -895,8 +895,8 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         // host buffers: the support size (from the output scan) decides the staging size
         launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
         launch_ex_scan(w->blk, w->nblk, w->st, s);
-        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-        GDE_HIP(hipStreamSynchronize(s));
+        GDE_HIP(hipGetLastError());
+        if ((rc = sync_state(w, s))) return rc;
         nnz = w->hst->out_count;
         fits = nnz <= res->capacity && res->idx && res->val;
         int32_t *o_idx = nullptr;
@@ -912,6 +912,8 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             GDE_HIP(hipMemcpyAsync(res->idx, w->out_idx, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
             GDE_HIP(hipMemcpyAsync(res->val, w->out_val, w->vsize * (size_t)nnz, hipMemcpyDeviceToHost, s));
         }
+        // the caller's buffers may be pageable (filled by the runtime's staging),
+        // so the final wait is the runtime's own
         GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
     }
