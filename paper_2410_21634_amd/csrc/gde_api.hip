@@ -165,8 +165,9 @@ static int ws_graph_state(Workspace *w, const gde_graph *g, hipStream_t s) {
         const int64_t cap = g->nnz + g->nnz / 8 + 65536;
         GDE_HIP(hipMalloc((void **)&w->tile_start, 4 * (size_t)(cap / kPushTile + 2)));
         if (w->bin_nranges > 0) {
+            // in-volume of every range plus one LocalCH self-mark per node
             const size_t es = vs == 8 ? sizeof(BinEnt<double>) : sizeof(BinEnt<float>);
-            GDE_HIP(hipMalloc(&w->bin_e, es * (size_t)cap));
+            GDE_HIP(hipMalloc(&w->bin_e, es * (size_t)(cap + n)));
         }
         w->nnz_cap = cap;
     }
@@ -188,8 +189,14 @@ static int ws_graph_state(Workspace *w, const gde_graph *g, hipStream_t s) {
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         (void)hipFree(cnt);
         if (e != hipSuccess) return hip_fail(e, "bin counts");
+        // a bin holds its range's in-volume (one update per CSR entry and iteration)
+        // and one LocalCH self-mark per node of the range
         std::vector<long long> base(nr + 1, 0);
-        for (int64_t r = 0; r < nr; r++) base[r + 1] = base[r] + (long long)h[r];
+        for (int64_t r = 0; r < nr; r++) {
+            const int64_t lo = r << w->bin_shift;
+            const int64_t nodes = std::min<int64_t>((int64_t)1 << w->bin_shift, n - lo);
+            base[r + 1] = base[r] + (long long)h[r] + (long long)nodes;
+        }
         GDE_HIP(hipMemcpyAsync(w->bin_base, base.data(), 8 * (nr + 1), hipMemcpyHostToDevice, s));
         GDE_HIP(hipStreamSynchronize(s));
     }
@@ -798,9 +805,9 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         if (small_ok && (rc = run_small())) return rc;
         // grid-wide iterations in chunks between host synchronisations: 8, then
         // doubling up to 32 while the frontier stays large.  Inside a chunk the
-        // range reduction of a binned LocalGD iteration also takes the snapshot of
-        // the next one for the nodes it activates; the last reduction of a chunk
-        // does not, so that every synchronisation sees an iteration boundary.
+        // range reduction of a binned iteration also takes the snapshot of the
+        // next one; the last reduction of a chunk does not, so that every
+        // synchronisation sees an iteration boundary.
         FuseArgs<V> fz{};
         fz.row_ptr = g->row_ptr;
         fz.x = (V *)w->x;
@@ -829,9 +836,10 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                     launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
                                       w->cstamp, base + t, w->front[(t + 1) & 1], s);
                     if ((rc = prof_mark(ctx, s))) return rc;
-                    // LocalCH keeps its separate snapshot (its self-marked nodes need it
-                    // anyway; measured slower fused)
-                    fz.on = 0;
+                    fz.on = t + 1 < end ? 1 : 0;
+                    fz.c_next = ch_at(t + 1).first;
+                    fz.m_next = ch_at(t + 1).second;
+                    fz.list2 = w->front[t & 1];
                     launch_push<V>(2, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
                                    w->tile_start, eps_eff, w->front[(t + 1) & 1], nullptr, 0, w->cstamp, base + t + 1,
                                    w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, &fz, s);

@@ -42,6 +42,7 @@ constexpr int kBinMaxRanges = 4096;     // ranges a graph may have for the binne
 constexpr int kBinLdsBytes = 16384;     // LDS accumulator bytes of one range (2^S values)
 constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
 constexpr long long kBinMinEdges = 8192;    // frontier volume from which the scatter is binned
+constexpr uint32_t kSelfMarkBit = 0x80000000u;  // a bin entry that marks a node of S_t (LocalCH)
 
 // One binned update: destination node and value side by side, so that a tile's
 // run of updates to one range is a single contiguous stream of 8-byte (FP32) or
@@ -88,6 +89,7 @@ struct DevState {
     int32_t overflow;              // a list append found its capacity exhausted (invariant broken)
     int32_t small_t;               // single-workgroup launch: next iteration to run
     int32_t small_phase;           // 1: the snapshot of iteration small_t is done, its push is not
+    int32_t fused_stamp;           // LocalCH: the range reduction took the snapshot of the iteration with this stamp
 };
 
 // Solver workspace for one (graph, value type).  All node-indexed arrays are

@@ -23,10 +23,12 @@ struct SnapArgs {
     int32_t cap;          // capacity of every node list (n)
 };
 
-// The snapshot of t+1 taken inside the range reduction of a binned iteration t,
-// for the nodes the reduction itself activates: every crossing of LocalGD, and
-// the LocalCH candidates that were not in S_t (so their momentum term is zero).
-// Their residuals are final in registers and their state is range-local there.
+// The snapshot of t+1 taken inside the range reduction of a binned iteration t.
+// LocalGD: every crossing (S_{t+1} is exactly the set of nodes that crossed).
+// LocalCH: every candidate of t+1 (a node touched by the push of t, or a node of
+// S_t, which the push marks in the bins with a zero-valued entry), so the
+// separate snapshot of t+1 has nothing left to do.  Residuals are final in
+// registers there and the node state is range-local.
 template <typename V>
 struct FuseArgs {
     int on;                      // 0: plain reduction (appends S_{t+1} / C_{t+1} to the list)
@@ -40,7 +42,7 @@ struct FuseArgs {
     long long tr_cap;
     V wscale;
     int w_div_deg;
-    V c_next;                    // LocalCH: c_{t+1}
+    V c_next, m_next;            // LocalCH: c_{t+1}, m_{t+1}
     V *delta;
     int32_t *dstamp;
     int32_t *list2;              // LocalCH: candidates of t+2 (self-marks of S_{t+1})

@@ -112,6 +112,7 @@ __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const d
         st->empty_seen = 0;
         st->probe = 0;
         st->overflow = 0;
+        st->fused_stamp = 0;
     }
 }
 
@@ -254,7 +255,10 @@ __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
                         int32_t stamp_cur, int32_t *next_list, int32_t *tr_nodes, long long tr_cap, int32_t cap,
                         int bid, int nblocks) {
     const int nxt = cur ^ 1;
-    const int n_c = min(st->fcount[cur], cap);
+    // the range reduction of t-1 may have taken this snapshot already (binned
+    // iteration with a fused reduction): then the candidate list is spent
+    const bool fused = st->fused_stamp == stamp_cur;
+    const int n_c = fused ? 0 : min(st->fcount[cur], cap);
     const long long push_base = st->pushes;
     if (bid == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
     const int stride = nblocks * blockDim.x;
@@ -332,11 +336,13 @@ __device__ __forceinline__ bool gather_tile(int tile, int M, int nbase, int coun
                                             const int32_t *__restrict__ wl_off, const int32_t *__restrict__ wl_beg,
                                             const V *__restrict__ wl_sv, const int32_t *__restrict__ col_idx,
                                             int32_t *s_off, int32_t *s_beg, V *s_sv, DevState *st,
-                                            int32_t (&w)[kMacroTiles], V (&dv)[kMacroTiles]) {
+                                            int32_t (&w)[kMacroTiles], V (&dv)[kMacroTiles],
+                                            const int32_t *__restrict__ wl_node, int32_t (&su)[kMacroTiles]) {
 #pragma unroll
     for (int q = 0; q < kMacroTiles; q++) {
         w[q] = -1;
         dv[q] = (V)0;
+        su[q] = -1;
     }
     const int b0 = tile * M;
     const int e0 = b0 * kPushTile;
@@ -371,6 +377,8 @@ __device__ __forceinline__ bool gather_tile(int tile, int M, int nbase, int coun
             } else {
                 st->overflow = 1;
             }
+            // the first edge of an entry also names the entry's node (LocalCH self-marks)
+            if (wl_node && e == s_off[lo]) su[q] = wl_node[i0 + lo];
         }
     }
     return true;
@@ -382,7 +390,8 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
                            const V *__restrict__ wl_sv, const int32_t *__restrict__ tile_start, V eps_eff,
                            int32_t *next_list, int32_t *touched, int tslot, int32_t *cstamp, int32_t stamp_next,
                            uint32_t *tbm, long long *tr_size, long long *tr_vol, long long tr_cap, int scatter,
-                           int32_t cap, int32_t nnz, const BinArgs<V> &bins, int bid, int nblocks) {
+                           int32_t cap, int32_t nnz, const BinArgs<V> &bins, const int32_t *wl_node, int self_marks,
+                           int bid, int nblocks) {
     constexpr int kPer = kMacroTiles;  // edges per thread in a tile of kMacroTiles base tiles
     static_assert(kPushTile == kPushBlock, "a base tile holds one edge per thread");
     __shared__ int32_t s_off[kMacroTiles * kPushTile + 1];
@@ -421,25 +430,31 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
     if (binned)
         for (int r = threadIdx.x; r < bins.nranges; r += blockDim.x) s_cnt[r] = 0;
     for (int tile = bid; tile < ntiles; tile += nblocks) {
-        int32_t w[kPer];
+        int32_t w[kPer], su[kPer];
         V dv[kPer];
         bool hit[kPer], first[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; q++) hit[q] = first[q] = false;
+        const bool marks = MODE == 2 && binned && self_marks;
         if (!gather_tile<V>(tile, M, nbase, count, total, cap, nnz, tile_start, wl_off, wl_beg, wl_sv, col_idx,
-                            s_off, s_beg, s_sv, st, w, dv))
+                            s_off, s_beg, s_sv, st, w, dv, marks ? wl_node : nullptr, su))
             continue;
         if (binned) {
             // rank of each update inside its range for this tile (LDS), one global
-            // reservation per nonempty range, then the writes
-            int rb[kPer], rk[kPer];
+            // reservation per nonempty range, then the writes; LocalCH with a fused
+            // reduction also bins each node of S_t once, flagged, with value zero
+            int rb[kPer], rk[kPer], sb[kPer], sk[kPer];
 #pragma unroll
             for (int q = 0; q < kPer; q++) {
-                rb[q] = -1;
-                rk[q] = 0;
+                rb[q] = sb[q] = -1;
+                rk[q] = sk[q] = 0;
                 if (w[q] >= 0 && (MODE == 2 || dv[q] != (V)0)) {
                     rb[q] = w[q] >> bins.shift;
                     rk[q] = atomicAdd(&s_cnt[rb[q]], 1);
+                }
+                if (su[q] >= 0) {
+                    sb[q] = su[q] >> bins.shift;
+                    sk[q] = atomicAdd(&s_cnt[sb[q]], 1);
                 }
             }
             __syncthreads();
@@ -452,7 +467,7 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < kPer; q++)
+            for (int q = 0; q < kPer; q++) {
                 if (rb[q] >= 0) {
                     const long long pos = bins.base[rb[q]] + s_rbase[rb[q]] + rk[q];
                     if (pos < bins.base[rb[q] + 1]) {
@@ -464,6 +479,18 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
                         st->overflow = 1;
                     }
                 }
+                if (sb[q] >= 0) {
+                    const long long pos = bins.base[sb[q]] + s_rbase[sb[q]] + sk[q];
+                    if (pos < bins.base[sb[q] + 1]) {
+                        BinEnt<V> e;
+                        e.w = (int32_t)((uint32_t)su[q] | kSelfMarkBit);
+                        e.v = (V)0;
+                        bins.be[pos] = e;
+                    } else {
+                        st->overflow = 1;
+                    }
+                }
+            }
             continue;
         }
         if (MODE == 2) {
@@ -528,10 +555,11 @@ __global__ void __launch_bounds__(kPushBlock) k_push(const int32_t *__restrict__
                                                       int32_t *next_list, int32_t *touched, int tslot,
                                                       int32_t *cstamp, int32_t stamp_next, uint32_t *tbm,
                                                       long long *tr_size, long long *tr_vol, long long tr_cap,
-                                                      int scatter, int32_t cap, int32_t nnz, BinArgs<V> bins) {
+                                                      int scatter, int32_t cap, int32_t nnz, BinArgs<V> bins,
+                                                      const int32_t *wl_node, int self_marks) {
     push_edges<V, MODE>(col_idx, dst, st, cur, wl_beg, wl_off, wl_sv, tile_start, eps_eff, next_list, touched, tslot,
-                        cstamp, stamp_next, tbm, tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins, blockIdx.x,
-                        gridDim.x);
+                        cstamp, stamp_next, tbm, tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins, wl_node, self_marks,
+                        blockIdx.x, gridDim.x);
 }
 
 // Small frontiers: iterations t0 .. t_end-1 of LocalGD (CH = false) or LocalCH
@@ -877,6 +905,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     const int span_max = 1 << bins.shift;
     V *s_acc = (V *)s_red;
     uint32_t *s_bits = (uint32_t *)(s_acc + span_max);
+    uint32_t *s_self = s_bits + span_max / 32;  // LocalCH fused: nodes of S_t (flagged bin entries)
     const int total = (int)(st->packed[cur] & 0xffffffffull);
     if (!(bins.nranges > 0 && (long long)total >= bins.min_edges && scatter)) return;
     const int r = blockIdx.x;
@@ -892,7 +921,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     const long long b0 = bins.base[r];
     const long long avail = bins.base[r + 1] - b0;
     for (int j = threadIdx.x; j < span_max; j += blockDim.x) s_acc[j] = (V)0;
-    for (int j = threadIdx.x; j < span_max / 32; j += blockDim.x) s_bits[j] = 0u;
+    for (int j = threadIdx.x; j < span_max / 32; j += blockDim.x) s_bits[j] = s_self[j] = 0u;
     __syncthreads();
     const int cnt = s_cnt0;
     const int m = (int)min((long long)cnt, avail);
@@ -900,21 +929,23 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     for (int i0 = 0; i0 < m; i0 += kRedUnroll * (int)blockDim.x) {
         int jj[kRedUnroll];
         V vv[kRedUnroll];
-        bool ok[kRedUnroll];
+        bool ok[kRedUnroll], self[kRedUnroll];
 #pragma unroll
         for (int q = 0; q < kRedUnroll; q++) {
             const int i = i0 + q * (int)blockDim.x + (int)threadIdx.x;
             ok[q] = i < m;
             BinEnt<V> e{};
             if (ok[q]) e = bins.be[b0 + i];
-            jj[q] = e.w - lo;
+            jj[q] = (int)((uint32_t)e.w & ~kSelfMarkBit) - lo;
             vv[q] = e.v;
+            self[q] = MODE == 2 && ((uint32_t)e.w & kSelfMarkBit) != 0u;
         }
 #pragma unroll
         for (int q = 0; q < kRedUnroll; q++) {
             if (!ok[q]) continue;
-            if (jj[q] >= 0 && jj[q] < span) atomicAdd(&s_acc[jj[q]], vv[q]);
-            else st->overflow = 1;
+            if (jj[q] < 0 || jj[q] >= span) st->overflow = 1;
+            else if (self[q]) atomicOr(&s_self[jj[q] >> 5], 1u << (jj[q] & 31));
+            else atomicAdd(&s_acc[jj[q]], vv[q]);
         }
     }
     __syncthreads();
@@ -938,31 +969,36 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
         const int j = j0 + k;
         if (j >= span) continue;
         const V acc = s_acc[j];
-        if (acc == (V)0) continue;
-        tmask |= 1u << k;
+        const bool in_s = MODE == 2 && fuse && ((s_self[j >> 5] >> (j & 31)) & 1u);
+        if (acc == (V)0 && !in_s) continue;
+        if (acc != (V)0) tmask |= 1u << k;
         const int32_t w = lo + j;
-        if (MODE == 2) {
+        if (MODE == 2 && fuse) {
+            // every candidate of t+1 in the range is here (touched, or in S_t):
+            // the snapshot of t+1 on its final residual, momentum for nodes of S_t
+            const RD<V> e = dst[w];
+            const V nr = e.r + acc;
+            if (nr != (V)0 && fabs(nr) >= eps_eff * e.d) {
+                hits |= 1u << k;
+                const V h = fz.c_next * nr + (in_s ? fz.m_next * fz.delta[w] : (V)0);
+                hval[k] = h;
+                dst[w].r = nr - h;
+                fz.x[w] += h;
+                fz.delta[w] = h;
+                fz.dstamp[w] = stamp_next;
+                cstamp[w] = stamp_next + 1;  // its residual changed again: a candidate of t+2
+            } else if (acc != (V)0) {
+                dst[w].r = nr;
+            }
+        } else if (MODE == 2) {
             // the residual of w is final for this iteration: only an active w joins
             // the candidates of t+1 (nodes of S_t were added by the snapshot)
             const RD<V> e = dst[w];
             const V nr = e.r + acc;
+            dst[w].r = nr;
             if (nr != (V)0 && fabs(nr) >= eps_eff * e.d && cstamp[w] != stamp_next) {
                 hits |= 1u << k;
-                if (fuse) {
-                    // w is not in S_t: h = c_{t+1} r_w (no momentum term)
-                    const V h = fz.c_next * nr;
-                    hval[k] = h;
-                    dst[w].r = nr - h;
-                    fz.x[w] += h;
-                    fz.delta[w] = h;
-                    fz.dstamp[w] = stamp_next;
-                    cstamp[w] = stamp_next + 1;  // its residual changed again: a candidate of t+2
-                } else {
-                    dst[w].r = nr;
-                    cstamp[w] = stamp_next;
-                }
-            } else {
-                dst[w].r = nr;
+                cstamp[w] = stamp_next;
             }
         } else {
             const RD<V> e = dst[w];
@@ -990,6 +1026,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
             if (s_bits[k]) tbm[(lo >> 5) + k] |= s_bits[k];
     }
     if (fuse) {
+        if (MODE == 2 && blockIdx.x == 0 && threadIdx.x == 0) st->fused_stamp = stamp_next;
         // work-list entries of the hits (the list of t+1 is not needed for them)
         const long long push_base = st->pushes;
         int32_t begs[per], degs[per];
@@ -1329,12 +1366,13 @@ void launch_push(int mode, int grid, const int32_t *col_idx, void *dst, DevState
                  const FuseArgs<V> *fz, hipStream_t s) {
     auto kern = mode == 0 ? k_push<V, 0> : mode == 1 ? k_push<V, 1> : k_push<V, 2>;
     const size_t dyn = 2 * sizeof(int32_t) * (size_t)bins.nranges;
+    const int marks = (mode == 2 && fz && fz->on) ? 1 : 0;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kPushBlock), dyn, s, col_idx, (RD<V> *)dst, st, cur, wl_beg, wl_off,
                        (const V *)wl_sv, tile_start, eps_eff, next_list, touched, tslot, cstamp, stamp_next, tbm,
-                       tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins);
+                       tr_size, tr_vol, tr_cap, scatter, cap, nnz, bins, fz ? fz->wl_node : nullptr, marks);
     if (bins.nranges > 0) {
         auto red = mode == 0 ? k_reduce<V, 0> : mode == 1 ? k_reduce<V, 1> : k_reduce<V, 2>;
-        const size_t rdyn = sizeof(V) * ((size_t)1 << bins.shift) + sizeof(uint32_t) * (((size_t)1 << bins.shift) / 32);
+        const size_t rdyn = sizeof(V) * ((size_t)1 << bins.shift) + 2 * sizeof(uint32_t) * (((size_t)1 << bins.shift) / 32);
         hipLaunchKernelGGL(red, dim3(bins.nranges), dim3(kReduceBlock), rdyn, s, bins, (RD<V> *)dst, st, cur, eps_eff,
                            next_list, touched, tslot, cstamp, stamp_next, tbm, scatter, cap, (int32_t)(cap),
                            fz ? *fz : FuseArgs<V>{});
