@@ -1059,10 +1059,18 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
             for (int q = (off + kPushTile - 1) / kPushTile; (long long)q * kPushTile < (long long)off + degs[k]; q++)
                 fz.tile_start[q] = slot;
             if (fz.tr_nodes && push_base + slot < fz.tr_cap) fz.tr_nodes[push_base + slot] = w;
-            atomicOr(&fz.bitmap[w >> 5], 1u << (w & 31));
             slot++;
             off += degs[k];
         }
+        // the pushed set: the range's bitmap words belong to this workgroup, so the
+        // hits are gathered in LDS and written with one plain OR per word
+        __syncthreads();  // the touched-bitmap words have been read out of s_bits
+        for (int q = threadIdx.x; q < span_max / 32; q += blockDim.x) s_bits[q] = 0u;
+        __syncthreads();
+        if (hits) atomicOr(&s_bits[j0 >> 5], hits << (j0 & 31));
+        __syncthreads();
+        for (int q = threadIdx.x; q < (span + 31) / 32; q += blockDim.x)
+            if (s_bits[q]) fz.bitmap[(lo >> 5) + q] |= s_bits[q];
         if (MODE == 2) {  // the fused nodes are candidates of t+2
             int s2 = block_reserve(__popc(hits), &st->fcount[cur]);
             for (uint32_t hm = hits; hm; hm &= hm - 1u) {
