@@ -805,9 +805,10 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         if (small_ok && (rc = run_small())) return rc;
         // grid-wide iterations in chunks between host synchronisations: 8, then
         // doubling up to 32 while the frontier stays large.  Inside a chunk the
-        // range reduction of a binned iteration also takes the snapshot of the
-        // next one; the last reduction of a chunk does not, so that every
-        // synchronisation sees an iteration boundary.
+        // range reduction of iteration t also takes the snapshot of t+1 (fused
+        // into the reduction when t is binned, over the list otherwise), so an
+        // iteration is two launches; the last reduction of a chunk does not, so
+        // that every synchronisation sees an iteration boundary.
         FuseArgs<V> fz{};
         fz.row_ptr = g->row_ptr;
         fz.x = (V *)w->x;
@@ -827,14 +828,16 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
         int chunk = 8;
         while (!converged && t < p->max_iters) {
             int end = std::min(p->max_iters, t + chunk);
+            bool taken = false;  // the range reduction of t-1 took the snapshot of t
             for (; t < end; t++) {
                 a.F = w->front[t & 1];
                 a.cur = t & 1;
                 if (ch) {
                     const auto cm = ch_at(t);
                     const V c_t = cm.first, m_t = cm.second;
-                    launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta, w->dstamp,
-                                      w->cstamp, base + t, w->front[(t + 1) & 1], s);
+                    if (!taken)
+                        launch_snap_ch<V>(a, wscale, w_div_deg, eps_eff, c_t, m_t, t == 0 ? 1 : 0, w->delta,
+                                          w->dstamp, w->cstamp, base + t, w->front[(t + 1) & 1], s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                     fz.on = t + 1 < end ? 1 : 0;
                     fz.c_next = ch_at(t + 1).first;
@@ -845,7 +848,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                                    w->tbm, d_trs, d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, &fz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 } else {
-                    launch_snap_gd<V>(a, wscale, w_div_deg, s);
+                    if (!taken) launch_snap_gd<V>(a, wscale, w_div_deg, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                     fz.on = t + 1 < end ? 1 : 0;
                     launch_push<V>(0, pgrid, g->col_idx, w->rd, w->st, t & 1, w->wl_beg, w->wl_off, w->wl_sv,
@@ -853,6 +856,9 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
                                    d_trv, tr_cap, 1, g->n, (int32_t)g->nnz, bins, &fz, s);
                     if ((rc = prof_mark(ctx, s))) return rc;
                 }
+                // a launched range reduction with fusion on takes the next snapshot,
+                // binned (fused) or over the list (atomic iteration)
+                taken = fz.on && bins.nranges > 0;
             }
             GDE_HIP(hipGetLastError());
             if ((rc = sync_state(w, s))) return rc;

@@ -155,7 +155,6 @@ __device__ void snap_gd(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
     const int nxt = cur ^ 1;
     const int n_f = min(st->fcount[cur], cap);
     const long long push_base = st->pushes;
-    if (bid == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
     const int stride = nblocks * blockDim.x;
     for (int base = bid * blockDim.x; base < n_f; base += stride) {
         int i = base + threadIdx.x;
@@ -260,7 +259,6 @@ __device__ void snap_ch(const int32_t *__restrict__ row_ptr, RD<V> *rd, V *x, ui
     const bool fused = st->fused_stamp == stamp_cur;
     const int n_c = fused ? 0 : min(st->fcount[cur], cap);
     const long long push_base = st->pushes;
-    if (bid == 0 && threadIdx.x == 0) st->packed[nxt] = 0ull;
     const int stride = nblocks * blockDim.x;
     for (int base = bid * blockDim.x; base < n_c; base += stride) {
         int i = base + threadIdx.x;
@@ -403,8 +401,13 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
     const int count = min((int)(pk >> 32), cap);
     const int total = (int)(pk & 0xffffffffull);
     // S_t (or C_t) has been consumed by the snapshot: its list becomes the
-    // next-but-one append target, which the snapshot of t+1 may append to.
-    if (bid == 0 && threadIdx.x == 0) st->fcount[cur] = 0;
+    // next-but-one append target, which the snapshot of t+1 may append to.  The
+    // reservation counter of t+1 is cleared here (the snapshot of t+1 may run in
+    // the range reduction of t, whose other workgroups still read the one of t).
+    if (bid == 0 && threadIdx.x == 0) {
+        st->fcount[cur] = 0;
+        st->packed[nxt] = 0ull;
+    }
     if (bid == 0 && threadIdx.x == 0 && count == 0) st->empty_seen = 1;
     if (bid == 0 && threadIdx.x == 0 && count > 0) {
         int it = st->iters;
@@ -907,7 +910,20 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     uint32_t *s_bits = (uint32_t *)(s_acc + span_max);
     uint32_t *s_self = s_bits + span_max / 32;  // LocalCH fused: nodes of S_t (flagged bin entries)
     const int total = (int)(st->packed[cur] & 0xffffffffull);
-    if (!(bins.nranges > 0 && (long long)total >= bins.min_edges && scatter)) return;
+    if (!(bins.nranges > 0 && (long long)total >= bins.min_edges && scatter)) {
+        // an atomic iteration: with a fused reduction the snapshot of t+1 is taken
+        // here over its list, so that no separate launch is needed
+        if (MODE == 0 && fz.on)
+            snap_gd<V>(fz.row_ptr, dst, fz.x, fz.bitmap, next_list, st, cur ^ 1, fz.wl_node, fz.wl_beg, fz.wl_off,
+                       fz.wl_sv, fz.tile_start, fz.wscale, fz.w_div_deg, fz.tr_nodes, fz.tr_cap, fz.cap, blockIdx.x,
+                       gridDim.x);
+        if (MODE == 2 && fz.on)
+            snap_ch<V>(fz.row_ptr, dst, fz.x, fz.bitmap, next_list, st, cur ^ 1, fz.wl_node, fz.wl_beg, fz.wl_off,
+                       fz.wl_sv, fz.tile_start, fz.wscale, fz.w_div_deg, eps_eff, fz.c_next, fz.m_next, 0, fz.delta,
+                       fz.dstamp, cstamp, stamp_next, fz.list2, fz.tr_nodes, fz.tr_cap, fz.cap, blockIdx.x,
+                       gridDim.x);
+        return;
+    }
     const int r = blockIdx.x;
     const int lo = r << bins.shift;
     const int span = min(span_max, n - lo);
