@@ -979,54 +979,65 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(BinArgs<V> bins, RD<V> 
     const bool fuse = MODE != 1 && fz.on;
     uint32_t hits = 0u, firsts = 0u, tmask = 0u;
     V hval[per];  // fused snapshot: the amount moved into x for each hit (v or h)
+    // every load of the thread's nodes first (their stores would otherwise order
+    // each node's loads after the previous node's stores), then the arithmetic
+    V acc[per], xo[per], dl[per];
+    RD<V> e[per];
+    int32_t cs[per];
+    bool need[per], in_s[per];
 #pragma unroll
     for (int k = 0; k < per; k++) {
-        hval[k] = (V)0;
         const int j = j0 + k;
-        if (j >= span) continue;
-        const V acc = s_acc[j];
-        const bool in_s = MODE == 2 && fuse && ((s_self[j >> 5] >> (j & 31)) & 1u);
-        if (acc == (V)0 && !in_s) continue;
-        if (acc != (V)0) tmask |= 1u << k;
+        hval[k] = (V)0;
+        acc[k] = j < span ? s_acc[j] : (V)0;
+        in_s[k] = MODE == 2 && fuse && j < span && ((s_self[j >> 5] >> (j & 31)) & 1u);
+        need[k] = j < span && (acc[k] != (V)0 || in_s[k]);
         const int32_t w = lo + j;
+        e[k] = need[k] ? dst[w] : RD<V>{};
+        xo[k] = (need[k] && fuse) ? fz.x[w] : (V)0;
+        dl[k] = in_s[k] ? fz.delta[w] : (V)0;
+        cs[k] = (need[k] && MODE == 2 && !fuse) ? cstamp[w] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < per; k++) {
+        if (!need[k]) continue;
+        if (acc[k] != (V)0) tmask |= 1u << k;
+        const int32_t w = lo + j0 + k;
         if (MODE == 2 && fuse) {
             // every candidate of t+1 in the range is here (touched, or in S_t):
             // the snapshot of t+1 on its final residual, momentum for nodes of S_t
-            const RD<V> e = dst[w];
-            const V nr = e.r + acc;
-            if (nr != (V)0 && fabs(nr) >= eps_eff * e.d) {
+            const V nr = e[k].r + acc[k];
+            if (nr != (V)0 && fabs(nr) >= eps_eff * e[k].d) {
                 hits |= 1u << k;
-                const V h = fz.c_next * nr + (in_s ? fz.m_next * fz.delta[w] : (V)0);
+                const V h = fz.c_next * nr + (in_s[k] ? fz.m_next * dl[k] : (V)0);
                 hval[k] = h;
                 dst[w].r = nr - h;
-                fz.x[w] += h;
+                fz.x[w] = xo[k] + h;
                 fz.delta[w] = h;
                 fz.dstamp[w] = stamp_next;
                 cstamp[w] = stamp_next + 1;  // its residual changed again: a candidate of t+2
-            } else if (acc != (V)0) {
+            } else if (acc[k] != (V)0) {
                 dst[w].r = nr;
             }
         } else if (MODE == 2) {
             // the residual of w is final for this iteration: only an active w joins
             // the candidates of t+1 (nodes of S_t were added by the snapshot)
-            const RD<V> e = dst[w];
-            const V nr = e.r + acc;
+            const V nr = e[k].r + acc[k];
             dst[w].r = nr;
-            if (nr != (V)0 && fabs(nr) >= eps_eff * e.d && cstamp[w] != stamp_next) {
+            if (nr != (V)0 && fabs(nr) >= eps_eff * e[k].d && cs[k] != stamp_next) {
                 hits |= 1u << k;
                 cstamp[w] = stamp_next;
             }
         } else {
-            const RD<V> e = dst[w];
-            const V nw = e.r + acc;
-            const V th = eps_eff * e.d;
-            const bool hit = e.r < th && nw >= th;
+            const V nw = e[k].r + acc[k];
+            const V th = eps_eff * e[k].d;
+            const bool hit = e[k].r < th && nw >= th;
             if (hit) hits |= 1u << k;
-            if (e.r == (V)0) firsts |= 1u << k;
+            if (e[k].r == (V)0) firsts |= 1u << k;
             if (hit && fuse) {  // snapshot of t+1: v = r_w, r_w = 0, x_w += v
                 hval[k] = nw;
                 dst[w].r = (V)0;
-                fz.x[w] += nw;
+                fz.x[w] = xo[k] + nw;
             } else {
                 dst[w].r = nw;
             }

@@ -48,16 +48,17 @@ def device_graph(gde, ctx, torch, G):
     return gde.Graph(ctx, rp, ci), (rp, ci)
 
 
-def check_device(gde, ctx, torch, g, G, kind, method, prm, seed_idx, seed_val=None):
-    """One FP32 solve with device outputs and a trace, graded as in the small tests."""
+def check_device(gde, ctx, torch, g, G, kind, method, prm, seed_idx, seed_val=None, vt=None):
+    """One solve (FP32 unless vt says otherwise) with device outputs and a trace,
+    graded as in the small tests."""
     seed_idx = np.atleast_1d(np.asarray(seed_idx, dtype=np.int32))
     seed_val = np.ones(len(seed_idx)) if seed_val is None else np.asarray(seed_val, dtype=np.float64)
     s1 = float(seed_val.sum())
-    vt = gde.F32
+    vt = gde.F32 if vt is None else vt
     p = gde.make_params(kind, method, value_type=vt, flags=gde.TRACE, **prm)
     dev = torch.device("cuda:0")
     oi = torch.empty(G.n, dtype=torch.int32, device=dev)
-    ov = torch.empty(G.n, dtype=torch.float32, device=dev)
+    ov = torch.empty(G.n, dtype=torch.float64 if vt == gde.F64 else torch.float32, device=dev)
     res = gde.solve(ctx, g, p, seed_idx, seed_val, out=(oi, ov), trace_cap=100000, nodes_cap=30_000_000)
     torch.cuda.synchronize()
     idx = res.idx.cpu().numpy()
@@ -67,7 +68,8 @@ def check_device(gde, ctx, torch, g, G, kind, method, prm, seed_idx, seed_val=No
     same = (res.iters == ref["iters"] and res.ops == ref["ops"] and res.pushes == ref["pushes"]
             and np.array_equal(res.trace_size, ref["trace_size"]) and np.array_equal(res.trace_vol, ref["trace_vol"]))
     rep = dict(iters=res.iters, ops=res.ops, trace_equal=same, nnz=len(idx),
-               l1_err_vs_oracle=float(np.abs(x_gpu - ref["x"]).sum()) / s1)
+               l1_err_vs_oracle=float(np.abs(x_gpu - ref["x"]).sum()) / s1,
+               max_vol=int(np.max(res.trace_vol)) if len(res.trace_vol) else 0)
     if same:
         assert rep["l1_err_vs_oracle"] <= TOL[vt], rep
         np.testing.assert_allclose(res.residual_l1, ref["residual_l1"], rtol=RTOL[vt])
@@ -99,6 +101,23 @@ def test_c2_ppr_sampled(gde, ctx, torch, c2, method):
     for i, eps in ((0, 1e-4), (21, 1e-6), (42, 1e-4), (63, 1e-6)):
         rep = check_device(gde, ctx, torch, g, G, gde.PPR, m, dict(alpha=0.1, eps=eps), [int(seeds[i])])
         print("c2", method, eps, int(seeds[i]), rep, flush=True)
+
+
+def test_c2_fp64_large_frontiers(gde, ctx, torch, c2):
+    """FP64 at eps 1e-7: frontiers of several 10^5 edges, so 4,096-edge tiles,
+    16-byte bin entries and range reductions that take the next snapshot; with
+    FP64 the traces must equal the oracle's (free run)."""
+    G, g = c2
+    seeds = W.uniform_seeds(G, 64, seed=42)
+    largest = 0
+    for method in (gde.LOCAL_GD, gde.LOCAL_CH):
+        for i in (5, 50):
+            rep = check_device(gde, ctx, torch, g, G, gde.PPR, method, dict(alpha=0.1, eps=1e-7), [int(seeds[i])],
+                               vt=gde.F64)
+            print("c2 fp64", method, int(seeds[i]), rep, flush=True)
+            assert rep["mode"] == "free-run", rep  # FP64: the same iteration as the oracle
+            largest = max(largest, rep["max_vol"])
+    assert largest >= 262144, largest  # the large-frontier tiles ran
 
 
 @pytest.fixture(scope="module")
