@@ -10,7 +10,9 @@ outputs left in HBM.
 
 Printed: one JSON line with solves/s (value), the algorithmic HBM GB/s of the
 whole step, per-solve latency p50 / p99, the roofline of the dominant kernel
-(the push / residual scatter, timed live with HIP events on the solve stream)
+(the scatter step: a push with its range reduction -- which also takes the
+next snapshot inside a host chunk -- or a single-workgroup launch, timed live
+with HIP events on the solve stream)
 and the FP64 CPU oracle timed on a bounded sample of the same queries.
 """
 from __future__ import annotations
@@ -270,7 +272,7 @@ def run_c2(args):
     achieved = pb / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
     traffic = traffic_from_profile("bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic, kernel="k_push<float,0|2> (residual scatter)",
+                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic, kernel="scatter step: k_push + k_reduce, or k_small",
                 launches=prof["launches"], avg_launch_us=round(avg_ms * 1e3, 3),
                 alg_bytes_per_launch=round(pb / launches, 1),
                 timed_launches=f"scatter launches of every {args.profile_every}th solve of the timed steps")
