@@ -261,6 +261,8 @@ def run_c2(args):
     for m in methods:
         for eps in EPS_C2:
             sel = [r for r in recs if r[0] == m and r[1] == eps]
+            if not sel:  # --phase batch times one plain query only
+                continue
             per[f"{m}@{eps:g}"] = dict(
                 solves_per_s=len(sel) / sum(r[3] for r in sel), p50_ms=float(np.percentile([r[3] * 1e3 for r in sel], 50)),
                 mean_iters=float(np.mean([r[4] for r in sel])), mean_ops=float(np.mean([r[5] for r in sel])),
