@@ -73,12 +73,14 @@ typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
 #define GDE_KATZ_SUBTRACT_SEED 0x1u /* Katz: return x - s, the centrality ((I - beta A)^-1 - I) s */
 #define GDE_TRACE 0x2u              /* record |S_t|, vol(S_t) and the S_t lists into the result */
 #define GDE_RESULT_DEVICE 0x4u      /* result idx / val are device pointers (else host) */
-/* Scatter strategy of the plain solver (gde_solve).  By default an iteration
- * whose frontier volume reaches a fixed threshold writes its updates into
- * destination-range bins that are summed in on-chip memory; smaller frontiers
- * use one atomic add per edge.  Both compute the same iteration (Eq. (9)); only
- * the order of floating-point additions differs.  Setting both is INVALID_ARG. */
-#define GDE_SCATTER_BINNED 0x8u     /* bin every iteration's scatter */
+/* Scatter strategy of the plain solver (gde_solve).  By default small frontiers
+ * run in one workgroup (several iterations per launch); larger ones run on the
+ * whole device, where an iteration whose frontier volume reaches a fixed
+ * threshold writes its updates into destination-range bins that are summed in
+ * on-chip memory, and smaller ones use one atomic add per edge.  All compute the
+ * same iteration (Eq. (9)); only the order of floating-point additions differs.
+ * Setting both is INVALID_ARG. */
+#define GDE_SCATTER_BINNED 0x8u     /* bin every iteration's scatter (no single-workgroup launches) */
 #define GDE_SCATTER_ATOMIC 0x10u    /* never bin: one atomic add per edge */
 
 typedef struct gde_ctx gde_ctx;
