@@ -418,10 +418,11 @@ def run_serve(args):
                 p = gde.make_params("katz", beta=beta, eps=max(e, 1e-6), lambda_bound=hi)
             else:
                 p = gde.make_params("hk", tau=5.0, K=30, eps=max(e, 1e-6))
-            qs.append((p, idx, val))
+            qs.append((p, idx, val, kind))
         srv = gde.Server(ctx, g, lanes_per_group=16, max_groups=args.groups, iters_per_step=args.iters_per_step,
                          result_capacity=2_000_000)
-        lat, sub_at = [], {}
+        lat, sub_at, sub_kind = [], {}, {}
+        kinds = {k: [0, 0, []] for k in ("ppr", "katz", "hk")}  # completed, submitted, latencies
         submitted = completed = i = ins = 0
         t0 = time.perf_counter()
         deadline = total_s + 2.0
@@ -430,9 +431,11 @@ def run_serve(args):
             if now > deadline:
                 break
             while i < len(arr) and arr[i] <= now:
-                t = srv.submit(*qs[i])
+                t = srv.submit(*qs[i][:3])
                 sub_at[t] = arr[i]
+                sub_kind[t] = qs[i][3]
                 submitted += arr[i] >= args.warm_s
+                kinds[qs[i][3]][1] += int(arr[i] >= args.warm_s)
                 i += 1
             while ins < len(inserts) and (ins + 1) * 0.1 <= now:
                 srv.insert_edges(*inserts[ins])
@@ -441,9 +444,12 @@ def run_serve(args):
             tn = time.perf_counter() - t0
             for c in done:
                 t_arr = sub_at.pop(c["ticket"])
+                kd = kinds[sub_kind.pop(c["ticket"])]
                 if t_arr >= args.warm_s:
                     lat.append(tn - t_arr)
                     completed += 1
+                    kd[0] += 1
+                    kd[2].append((tn - t_arr) * 1e3)
             if i >= len(arr) and not sub_at:
                 break
         srv.close()
@@ -452,7 +458,11 @@ def run_serve(args):
                    completion_ratio=round(completed / max(submitted, 1), 4),
                    solves_per_s=round(completed / args.serve_s, 2), inserted_edges=ins * args.insert_k,
                    p50_ms=round(float(np.percentile(lat_ms, 50)), 3) if len(lat_ms) else None,
-                   p99_ms=round(float(np.percentile(lat_ms, 99)), 3) if len(lat_ms) else None)
+                   p99_ms=round(float(np.percentile(lat_ms, 99)), 3) if len(lat_ms) else None,
+                   by_kind={k: dict(completed=int(v[0]), submitted=int(v[1]),
+                                    p50_ms=round(float(np.percentile(v[2], 50)), 3) if v[2] else None,
+                                    p99_ms=round(float(np.percentile(v[2], 99)), 3) if v[2] else None)
+                            for k, v in kinds.items()})
         log(f"serve {rec}")
         results.append(rec)
     ok = [r for r in results if r["completion_ratio"] >= 0.99]

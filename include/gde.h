@@ -231,12 +231,14 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
               hipStream_t stream);
 
 /*
- * B independent queries on one graph solved together in one persistent
- * launch: seeds are packed into lanes of node-major residual tiles, so a
- * CSR row that several queries push in the same round is read once.
- * Queries may differ in eps; they must share kind, method (LocalGD), value
- * type and kind parameters.  schedule_json: NULL = the tuned schedule for
- * this device/graph shape, else a JSON object {"lanes":L,"blocks":G,...}.
+ * B independent queries on one graph solved together, every iteration of all
+ * of them in the same launches: seeds are packed into lanes of node-major
+ * residual tiles, so a CSR row that several queries push in the same round is
+ * read once.  Queries may differ in eps; they must share kind, method
+ * (LocalGD), value type and kind parameters.  schedule_json: NULL = the
+ * default schedule (16 lanes, full occupancy), else a JSON object
+ * {"lanes":L,"blocks":G,...}; "persistent":1 (one cooperative launch for all
+ * iterations) is GDE_ERR_UNSUPPORTED.
  * res[i].status holds each query's own status; the call returns the first
  * non-OK status, or GDE_OK.
  */
@@ -245,7 +247,7 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
 
 /* ---------------------------------------------------------------- serving */
 typedef struct gde_server_cfg {
-    int32_t lanes_per_group;   /* queries per node-major residual tile (8, 16, 32 or 64) */
+    int32_t lanes_per_group;   /* queries per node-major residual tile (8, 16 or 32) */
     int32_t max_groups;        /* tiles per kind resident at once (memory admission) */
     int32_t iters_per_step;    /* local iterations per engine step */
     int32_t queue_capacity;    /* pending queries beyond which submit returns GDE_ERR_BUSY */
@@ -267,11 +269,18 @@ typedef struct gde_completion {
     double done_time_s;   /* server clock when the completion was harvested */
 } gde_completion;
 
-/* A continuous-batching server on a private dynamic copy of the graph. */
+/* A continuous-batching server on a private dynamic copy of the graph.
+ * PPR and Katz queries (LocalGD) advance in node-major lane groups on the
+ * server's stream; heat-kernel queries are solved one each by the plain
+ * level-push solver on three worker threads, each with its own context and
+ * stream, and always on one graph version (a rebuild waits for running
+ * solves).  The handle is used by one thread at a time. */
 int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cfg, gde_server **out);
 /* Enqueue a query (non-blocking); *ticket identifies its completion. */
 int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, uint64_t *ticket);
-/* Run engine steps while work is in flight and return up to cap completions (non-blocking when idle). */
+/* Apply queued insertions, admit, run one engine step and return up to cap
+ * completions.  With no group in flight and heat-kernel queries running it
+ * waits up to 2 ms for one of them; with nothing in flight it returns at once. */
 int gde_server_poll(gde_server *sv, gde_completion *out, int32_t cap, int32_t *n_out);
 /* Insert k undirected edges (u[i], v[i]); applied between engine steps, with the
  * warm-start corrections of the dynamic GDE (Sec. 4) to every in-flight query. */

@@ -27,6 +27,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <mutex>
+#include <shared_mutex>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -327,6 +331,25 @@ struct SGroup {
     std::vector<SReq> lanes;
 };
 
+// Heat-kernel queries are solved by the plain level-push solver on worker
+// threads, each with a private context (its own dense workspace) and stream,
+// so that several run at once beside the batched groups.
+constexpr int kHkWorkers = 3;
+
+struct HkWorker {
+    gde_ctx *ctx = nullptr;
+    hipStream_t s = nullptr;
+    std::thread th;
+    std::vector<int32_t> idx;
+    std::vector<float> val;
+};
+
+struct HkDone {
+    gde_completion c{};
+    std::vector<int32_t> idx;
+    std::vector<float> val;
+};
+
 }  // namespace gde
 
 struct gde_server {
@@ -368,9 +391,22 @@ struct gde_server {
     int32_t *t_add = nullptr, *t_olddeg = nullptr, *t_cursor = nullptr, *t_bsum = nullptr;
     int32_t *t_src = nullptr, *t_dst = nullptr, *t_flag = nullptr;
     int64_t t_cap = 0;
-    // host staging of heat-kernel results (result_capacity entries)
-    std::vector<int32_t> hk_idx;
-    std::vector<float> hk_val;
+    // heat-kernel workers: a queue of queries, their completions, and a lock that
+    // solves hold shared and graph rebuilds hold exclusive
+    std::vector<gde::HkWorker *> hk_w;
+    std::mutex hk_mu;
+    std::condition_variable hk_cv;       // workers wait for a query or for stop
+    std::condition_variable hk_done_cv;  // poll waits for a completion
+    std::deque<gde::SReq> hk_queue;
+    std::vector<gde::HkDone> hk_done;
+    int64_t hk_running = 0;
+    bool hk_stop = false;
+    bool hk_gate = false;                // a rebuild waits: workers start no new solve
+    int hk_err = 0;                      // a worker's solve failed with a device error
+    std::shared_mutex graph_mu;
+    // the step enqueued by srv_step_launch and not yet finished
+    bool step_open = false;
+    std::vector<int32_t> step_drop;
 };
 
 namespace gde {
@@ -620,7 +656,10 @@ static int srv_harvest(gde_server *sv, const std::vector<int> &hv_groups, const 
 }
 
 // one engine step: iters_per_step iterations of every busy group, then harvest
-static int srv_step(gde_server *sv) {
+// Enqueue iters_per_step batched iterations and the per-group activity count
+// on the server's stream without waiting for them; srv_step_finish reads the
+// result.  Heat-kernel solves run on their own stream in between.
+static int srv_step_launch(gde_server *sv) {
     bool any = false;
     for (const SGroup &gr : sv->groups) any = any || gr.busy;
     if (!any) return GDE_OK;
@@ -636,7 +675,8 @@ static int srv_step(gde_server *sv) {
         GDE_HIP(batch_launch<float>(2, sv->L, a, grid, sv->t, sv->s));
     }
     // per-group active pairs; groups over their iteration cap are dropped
-    std::vector<int32_t> drop(sv->G, 0);
+    std::vector<int32_t> &drop = sv->step_drop;
+    drop.assign(sv->G, 0);
     for (int gi = 0; gi < sv->G; gi++)
         if (sv->groups[gi].busy && sv->t - sv->groups[gi].start_t >= sv->groups[gi].max_iters) drop[gi] = 1;
     const int cur = sv->t & 1;
@@ -648,12 +688,24 @@ static int srv_step(gde_server *sv) {
     GDE_HIP(hipGetLastError());
     batch_ws_swap_list(sv->w, cur, &sv->d_act_tmp);
     GDE_HIP(hipMemcpyAsync(&a.st->acount[cur], sv->d_cnt, 4, hipMemcpyDeviceToDevice, sv->s));
+    sv->step_open = true;
+    return GDE_OK;
+}
+
+// Wait for the enqueued step and harvest the groups that converged or reached
+// their iteration cap.
+static int srv_step_finish(gde_server *sv) {
+    if (!sv->step_open) return GDE_OK;
+    sv->step_open = false;
+    BatchArgs<float> a{};
+    srv_args(sv, &a);
     std::vector<int32_t> gact(sv->G);
     BatchDev hst{};
     GDE_HIP(hipMemcpyAsync(gact.data(), sv->d_gactive, 4 * sv->G, hipMemcpyDeviceToHost, sv->s));
     GDE_HIP(hipMemcpyAsync(&hst, a.st, sizeof(BatchDev), hipMemcpyDeviceToHost, sv->s));
     GDE_HIP(hipStreamSynchronize(sv->s));
     if (hst.ovf[0] || hst.ovf[1]) return fail(GDE_ERR_OOM, "server work lists exceeded their capacity");
+    const std::vector<int32_t> &drop = sv->step_drop;
     std::vector<int> hv;
     std::vector<int32_t> flag(sv->G, 0);
     for (int gi = 0; gi < sv->G; gi++)
@@ -661,50 +713,95 @@ static int srv_step(gde_server *sv) {
     return srv_harvest(sv, hv, flag);
 }
 
-static int srv_hk(gde_server *sv) {
-    // heat-kernel queries: the plain level-push solver on the server's stream,
-    // oldest first, at most kHkPerPoll per call so that the batched groups keep
-    // advancing between them
-    constexpr int kHkPerPoll = 4;
-    int done = 0;
+// One heat-kernel worker: takes the oldest queued query, solves it on its own
+// context and stream while holding the graph lock shared, and queues the
+// completion for the next poll.
+static void hk_worker_main(gde_server *sv, HkWorker *wk) {
+    (void)hipSetDevice(wk->ctx->device);
     const int64_t cap = std::max<int32_t>(sv->cfg.result_capacity, 1);
-    if ((int64_t)sv->hk_idx.size() < cap) {
-        sv->hk_idx.resize(cap);
-        sv->hk_val.resize(cap);
+    for (;;) {
+        SReq q;
+        {
+            std::unique_lock<std::mutex> lk(sv->hk_mu);
+            sv->hk_cv.wait(lk, [&] { return sv->hk_stop || (!sv->hk_queue.empty() && !sv->hk_gate); });
+            if (sv->hk_stop) return;
+            q = std::move(sv->hk_queue.front());
+            sv->hk_queue.pop_front();
+            sv->hk_running++;
+        }
+        HkDone d;
+        {
+            std::shared_lock<std::shared_mutex> gl(sv->graph_mu);
+            gde_seed sd{(int32_t)q.idx.size(), q.idx.data(), q.val.data()};
+            gde_params p = q.p;
+            p.value_type = GDE_F32;
+            p.flags &= ~(uint32_t)(GDE_RESULT_DEVICE | GDE_TRACE);
+            gde_result r{};
+            r.capacity = cap;
+            r.idx = wk->idx.data();
+            r.val = wk->val.data();
+            const int rc = gde_solve(wk->ctx, sv->g, &p, &sd, &r, wk->s);
+            // nothing of this solve may still run when a rebuild takes the lock
+            const hipError_t e = hipStreamSynchronize(wk->s);
+            d.c.ticket = q.ticket;
+            d.c.submit_time_s = q.t_sub;
+            d.c.status = (rc == GDE_OK && e != hipSuccess) ? GDE_ERR_DEVICE : rc;
+            d.c.iters = r.iters;
+            d.c.residual_l1 = r.residual_l1;
+            d.c.residual_dinf = r.residual_dinf;
+            d.c.nnz = (d.c.status == GDE_OK || d.c.status == GDE_ERR_NOT_CONVERGED) ? r.nnz : 0;
+            d.idx.assign(wk->idx.begin(), wk->idx.begin() + d.c.nnz);
+            d.val.assign(wk->val.begin(), wk->val.begin() + d.c.nnz);
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->hk_mu);
+            if (d.c.status == GDE_ERR_DEVICE) sv->hk_err = GDE_ERR_DEVICE;
+            sv->hk_done.push_back(std::move(d));
+            sv->hk_running--;
+        }
+        sv->hk_done_cv.notify_all();
     }
-    for (auto it = sv->pending.begin(); it != sv->pending.end() && done < kHkPerPoll;) {
-        if (it->p.kind != GDE_HK) { ++it; continue; }
-        gde_seed sd{(int32_t)it->idx.size(), it->idx.data(), it->val.data()};
-        gde_params p = it->p;
-        p.value_type = GDE_F32;
-        p.flags &= ~(uint32_t)(GDE_RESULT_DEVICE | GDE_TRACE);
-        gde_result r{};
-        r.capacity = cap;
-        r.idx = sv->hk_idx.data();
-        r.val = sv->hk_val.data();
-        const int rc = gde_solve(sv->ctx, sv->g, &p, &sd, &r, sv->s);
-        gde_completion c{};
-        c.ticket = it->ticket;
-        c.submit_time_s = it->t_sub;
-        c.done_time_s = now_s(sv->t0);
-        c.status = rc;
-        c.iters = r.iters;
-        c.residual_l1 = r.residual_l1;
-        c.residual_dinf = r.residual_dinf;
-        c.nnz = (rc == GDE_OK || rc == GDE_ERR_NOT_CONVERGED) ? r.nnz : 0;
-        sv->done.push_back(c);
-        sv->done_idx.emplace_back(sv->hk_idx.begin(), sv->hk_idx.begin() + c.nnz);
-        sv->done_val.emplace_back(sv->hk_val.begin(), sv->hk_val.begin() + c.nnz);
-        it = sv->pending.erase(it);
-        done++;
-        if (rc == GDE_ERR_DEVICE) return rc;
+}
+
+// Move finished heat-kernel queries to the completions.  When this poll found
+// nothing else to do and heat-kernel queries are still running, wait briefly
+// for one of them.
+static int srv_hk_collect(gde_server *sv, bool idle) {
+    std::unique_lock<std::mutex> lk(sv->hk_mu);
+    if (idle && sv->done.empty() && sv->hk_done.empty() && (sv->hk_running > 0 || !sv->hk_queue.empty()))
+        sv->hk_done_cv.wait_for(lk, std::chrono::milliseconds(2), [&] { return !sv->hk_done.empty(); });
+    const double t = now_s(sv->t0);
+    for (HkDone &d : sv->hk_done) {
+        d.c.done_time_s = t;
+        sv->done.push_back(d.c);
+        sv->done_idx.push_back(std::move(d.idx));
+        sv->done_val.push_back(std::move(d.val));
     }
-    return GDE_OK;
+    sv->hk_done.clear();
+    return sv->hk_err;
 }
 
 // apply the queued insertions: rebuild the CSR, correct in-flight lanes
 static int srv_apply_inserts(gde_server *sv) {
     if (sv->inserts.empty()) return GDE_OK;
+    // Heat-kernel solves read the CSR and the plain workspaces that this
+    // rebuilds.  The gate keeps workers from starting new solves meanwhile (the
+    // shared mutex alone may keep admitting readers ahead of this writer).
+    struct Gate {
+        gde_server *sv;
+        explicit Gate(gde_server *v) : sv(v) {
+            std::lock_guard<std::mutex> lk(sv->hk_mu);
+            sv->hk_gate = true;
+        }
+        ~Gate() {
+            {
+                std::lock_guard<std::mutex> lk(sv->hk_mu);
+                sv->hk_gate = false;
+            }
+            sv->hk_cv.notify_all();
+        }
+    } gate(sv);
+    std::unique_lock<std::shared_mutex> gl(sv->graph_mu);
     // host: drop self-loops and repeats within the batch, keep canonical pairs
     std::set<std::pair<int32_t, int32_t>> uniq;
     for (auto &e : sv->inserts)
@@ -818,6 +915,8 @@ static int srv_apply_inserts(gde_server *sv) {
     sv->spare_ci = old_ci;
     sv->spare_ci_cap = old_cap;
     if ((rc = plain_workspaces_refresh(sv->g, sv->ctx, sv->s))) return rc;
+    for (HkWorker *wk : sv->hk_w)
+        if ((rc = plain_workspaces_refresh(sv->g, wk->ctx, sv->s))) return rc;
     GDE_HIP(batch_init_deg<float>(sv->g->row_ptr, (float *)a.deg, n, sv->s));
     GDE_HIP(hipStreamSynchronize(sv->s));
     sv->inserted_edges += m / 2;
@@ -885,6 +984,18 @@ int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cf
     if (rc) return bail(rc);
     e = hipStreamSynchronize(sv->s);
     if (e != hipSuccess) return bail(hip_fail(e, "server init"));
+    for (int i = 0; i < kHkWorkers; i++) {
+        HkWorker *wk = new HkWorker();
+        sv->hk_w.push_back(wk);
+        wk->ctx = new gde_ctx();
+        wk->ctx->device = ctx->device;
+        e = hipStreamCreateWithFlags(&wk->s, hipStreamNonBlocking);
+        if (e != hipSuccess) { wk->s = nullptr; return bail(hip_fail(e, "hipStreamCreate")); }
+        const size_t cap = (size_t)std::max<int32_t>(cfg->result_capacity, 1);
+        wk->idx.resize(cap);
+        wk->val.resize(cap);
+        wk->th = std::thread(hk_worker_main, sv, wk);
+    }
     *out = sv;
     return GDE_OK;
 }
@@ -894,7 +1005,10 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     int rc = gde_validate_query(sv->g, p, s);
     if (rc) return rc;
     if (p->method != GDE_LOCAL_GD) return fail(GDE_ERR_UNSUPPORTED, "the server runs LocalGD");
-    if ((int)sv->pending.size() >= sv->cfg.queue_capacity) return fail(GDE_ERR_BUSY, "server queue is full");
+    std::unique_lock<std::mutex> lk(sv->hk_mu);
+    if ((int64_t)sv->pending.size() + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
+        return fail(GDE_ERR_BUSY, "server queue is full");
+    if (p->kind != GDE_HK) lk.unlock();
     SReq r;
     r.ticket = sv->next_ticket++;
     r.p = *p;
@@ -902,6 +1016,12 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     r.val.assign(s->val, s->val + s->nnz);
     r.t_sub = now_s(sv->t0);
     *ticket = r.ticket;
+    if (p->kind == GDE_HK) {
+        sv->hk_queue.push_back(std::move(r));
+        lk.unlock();
+        sv->hk_cv.notify_one();
+        return GDE_OK;
+    }
     sv->pending.push_back(std::move(r));
     return GDE_OK;
 }
@@ -919,8 +1039,10 @@ int gde_server_poll(gde_server *sv, gde_completion *out, int32_t cap, int32_t *n
     int rc = srv_apply_inserts(sv);
     if (rc) return rc;
     if ((rc = srv_admit(sv))) return rc;
-    if ((rc = srv_step(sv))) return rc;
-    if ((rc = srv_hk(sv))) return rc;
+    if ((rc = srv_step_launch(sv))) return rc;
+    const bool stepped = sv->step_open;
+    if ((rc = srv_step_finish(sv))) return rc;
+    if ((rc = srv_hk_collect(sv, !stepped))) return fail(rc, "a heat-kernel solve failed on the device");
     const int32_t k = (int32_t)std::min<size_t>(sv->done.size(), (size_t)std::max(cap, 0));
     for (int32_t i = 0; i < k; i++) {
         out[i] = sv->done[i];
@@ -945,6 +1067,18 @@ int gde_server_insert_edges(gde_server *sv, int32_t k, const int32_t *u, const i
 
 int gde_server_destroy(gde_server *sv) {
     if (!sv) return fail(GDE_ERR_INVALID_ARG, "null server");
+    {
+        std::lock_guard<std::mutex> lk(sv->hk_mu);
+        sv->hk_stop = true;
+    }
+    sv->hk_cv.notify_all();
+    for (HkWorker *wk : sv->hk_w) {
+        if (wk->th.joinable()) wk->th.join();
+        if (wk->s) (void)hipStreamDestroy(wk->s);
+        if (wk->ctx) gde_ctx_destroy(wk->ctx);
+        delete wk;
+    }
+    sv->hk_w.clear();
     if (sv->s) (void)hipStreamSynchronize(sv->s);
     void *p[] = {sv->d_drop, sv->d_gactive, sv->d_kind, sv->d_mode, sv->d_cnt, sv->d_gws, sv->d_gparam, sv->d_rscale, sv->d_gepoch,
                  sv->d_act_tmp, sv->d_touch_tmp, sv->d_seed_b, sv->d_seed_lane, sv->d_seed_node, sv->d_out_idx, sv->d_out_val,

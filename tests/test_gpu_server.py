@@ -222,3 +222,59 @@ def test_server_dynamic_inserts(gde, ctx):
         assert (np.abs(f - x) <= eps * d * (1 + 1e-3) + 1e-6 * np.abs(f) + 1e-9).all()
     srv.close()
     g.close()
+
+
+def _hk_ok(row_ptr, col_idx, eps, idx, val, x):
+    """x is the level-push answer on this graph: it agrees with the FP64 oracle,
+    or (an FP32 threshold flip at some level) it meets the level-push guarantee
+    0 <= f_K - x and ||D^-1 (f_K - x)||_inf <= eps."""
+    s1 = float(np.sum(val))
+    ref = O.hk(row_ptr, col_idx, 5.0, 30, eps, idx, val)["x"]
+    if np.abs(x - ref).sum() / s1 <= 1e-6:
+        return True
+    fK = hk_truncated(row_ptr, col_idx, 5.0, 30, idx, val)
+    dd = np.diff(row_ptr).astype(float)
+    gap = fK - x
+    return bool((gap >= -1e-6 * fK - 1e-9).all()
+                and (gap[dd > 0] <= eps * dd[dd > 0] * (1 + 1e-3) + 1e-6 * fK[dd > 0] + 1e-9).all())
+
+
+def test_server_hk_with_inserts(gde, ctx):
+    """Heat-kernel queries run on worker threads while an insert batch is applied:
+    each is solved on one graph version, the old or the new one for queries that
+    were queued before the batch, the new one for queries submitted after the
+    poll that applied it."""
+    G = W.chung_lu(10000, 50000, 2.5, seed=9)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    rng = np.random.default_rng(9)
+    seeds = W.uniform_seeds(G, 16, seed=9)
+    eps = 1e-5
+    srv = gde.Server(ctx, g, lanes_per_group=8, max_groups=2, iters_per_step=2)
+    p = gde.make_params("hk", tau=5.0, K=30, eps=eps)
+    early = {srv.submit(p, [int(s)]): int(s) for s in seeds[:8]}
+    u, v = W.insert_batch(G, 500, rng, set())
+    srv.insert_edges(u, v)
+    got = {c["ticket"]: c for c in srv.poll()}  # applies the batch
+    late = {srv.submit(p, [int(s)]): int(s) for s in seeds[8:]}
+    got.update(drain(srv, len(seeds) - len(got)))
+    assert len(got) == len(seeds)
+    edges = set()
+    for a in range(G.n):
+        for b in G.col_idx[G.row_ptr[a]:G.row_ptr[a + 1]]:
+            if a < b:
+                edges.add((a, int(b)))
+    edges.update(zip(u.tolist(), v.tolist()))
+    Gn = W.from_edges(G.n, sorted(edges))
+    one = np.ones(1)
+    for t, c in got.items():
+        assert c["status"] == gde.OK, c["status"]
+        x = np.zeros(G.n)
+        x[c["idx"]] = c["val"]
+        if t in late:
+            assert _hk_ok(Gn.row_ptr, Gn.col_idx, eps, [late[t]], one, x), late[t]
+        else:
+            s = early[t]
+            assert (_hk_ok(Gn.row_ptr, Gn.col_idx, eps, [s], one, x)
+                    or _hk_ok(G.row_ptr, G.col_idx, eps, [s], one, x)), s
+    srv.close()
+    g.close()
