@@ -272,7 +272,7 @@ typedef struct gde_completion {
 /* A continuous-batching server on a private dynamic copy of the graph.
  * PPR and Katz queries (LocalGD) advance in node-major lane groups on the
  * server's stream; heat-kernel queries are solved one each by the plain
- * level-push solver on three worker threads, each with its own context and
+ * level-push solver on five worker threads, each with its own context and
  * stream, and always on one graph version (a rebuild waits for running
  * solves).  The handle is used by one thread at a time. */
 int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cfg, gde_server **out);

@@ -334,7 +334,7 @@ struct SGroup {
 // Heat-kernel queries are solved by the plain level-push solver on worker
 // threads, each with a private context (its own dense workspace) and stream,
 // so that several run at once beside the batched groups.
-constexpr int kHkWorkers = 3;
+constexpr int kHkWorkers = 5;
 
 struct HkWorker {
     gde_ctx *ctx = nullptr;
