@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <set>
 #include <string>
 #include <unordered_set>
@@ -362,7 +363,10 @@ struct gde_server {
     int t = 0;  // global iteration counter (list parity)
     uint64_t next_ticket = 1;
     std::chrono::steady_clock::time_point t0;
-    std::deque<gde::SReq> pending;
+    // pending PPR / Katz queries, one FIFO per (kind, alpha or beta): a free group
+    // takes the key whose head is the oldest and fills its lanes from that FIFO
+    std::map<std::pair<int, double>, std::deque<gde::SReq>> pending;
+    int64_t n_pending = 0;
     std::vector<gde::SGroup> groups;
     std::vector<std::pair<int32_t, int32_t>> inserts;
     std::vector<gde_completion> done;
@@ -458,13 +462,15 @@ static int srv_admit(gde_server *sv) {
     std::vector<float> s_b;
     std::vector<float> eps_upd;
     std::vector<int> admitted;
-    for (int gi = 0; gi < sv->G && !sv->pending.empty(); gi++) {
+    for (int gi = 0; gi < sv->G && sv->n_pending > 0; gi++) {
         SGroup &gr = sv->groups[gi];
         if (gr.busy) continue;
-        // the oldest batchable request decides the group's kind
-        auto it = std::find_if(sv->pending.begin(), sv->pending.end(),
-                               [](const SReq &r) { return r.p.kind != GDE_HK; });
-        if (it == sv->pending.end()) break;
+        // the oldest pending request decides the group's kind and parameter
+        auto best = sv->pending.end();
+        for (auto qt = sv->pending.begin(); qt != sv->pending.end(); ++qt)
+            if (best == sv->pending.end() || qt->second.front().ticket < best->second.front().ticket) best = qt;
+        if (best == sv->pending.end()) break;
+        std::deque<SReq> &q = best->second;
         gr = SGroup();
         gr.busy = true;
         // a fresh tag: pairs the previous occupants touched read as untouched
@@ -475,20 +481,17 @@ static int srv_admit(gde_server *sv) {
             sv->epoch_next = 1u;
         }
         gr.epoch = sv->epoch_next++;
-        gr.kind = it->p.kind;
-        gr.param = gr.kind == GDE_PPR ? it->p.alpha : it->p.beta;
+        gr.kind = best->first.first;
+        gr.param = best->first.second;
         gr.start_t = sv->t;
         gr.max_iters = 0;
-        for (auto jt = sv->pending.begin(); jt != sv->pending.end() && (int)gr.lanes.size() < sv->L;) {
-            const double prm = jt->p.kind == GDE_PPR ? jt->p.alpha : jt->p.beta;
-            if (jt->p.kind == gr.kind && prm == gr.param) {
-                gr.max_iters = std::max(gr.max_iters, jt->p.max_iters);
-                gr.lanes.push_back(std::move(*jt));
-                jt = sv->pending.erase(jt);
-            } else {
-                ++jt;
-            }
+        while (!q.empty() && (int)gr.lanes.size() < sv->L) {
+            gr.max_iters = std::max(gr.max_iters, q.front().p.max_iters);
+            gr.lanes.push_back(std::move(q.front()));
+            q.pop_front();
+            sv->n_pending--;
         }
+        if (q.empty()) sv->pending.erase(best);
         admitted.push_back(gi);
         for (int l = 0; l < (int)gr.lanes.size(); l++) {
             const SReq &r = gr.lanes[l];
@@ -1006,7 +1009,7 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     if (rc) return rc;
     if (p->method != GDE_LOCAL_GD) return fail(GDE_ERR_UNSUPPORTED, "the server runs LocalGD");
     std::unique_lock<std::mutex> lk(sv->hk_mu);
-    if ((int64_t)sv->pending.size() + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
+    if (sv->n_pending + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
         return fail(GDE_ERR_BUSY, "server queue is full");
     if (p->kind != GDE_HK) lk.unlock();
     SReq r;
@@ -1022,7 +1025,8 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
         sv->hk_cv.notify_one();
         return GDE_OK;
     }
-    sv->pending.push_back(std::move(r));
+    sv->pending[{p->kind, p->kind == GDE_PPR ? p->alpha : p->beta}].push_back(std::move(r));
+    sv->n_pending++;
     return GDE_OK;
 }
 
