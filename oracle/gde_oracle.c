@@ -18,7 +18,7 @@
  *   HK  : Taylor-truncated heat kernel solved level by level (the AHK push of
  *         Sec. 2 on the Kronecker system), see oracle_hk below.
  *
- * Readings of the paper that this file adopts (all listed in the design doc):
+ * Readings of the paper that this file adopts:
  *   - S_0 = supp(s) is forced (Definition 3.1), whatever the threshold says.
  *   - active iff |r_u| >= theta_u AND r_u != 0; stop iff every |r_u| < theta_u.
  *   - theta_u = eps_eff * d_u with eps_eff = alpha*eps (PPR) or eps (Katz),
