@@ -515,7 +515,7 @@ def main():
         pmc_summary(*args.pmc_summary)
         return
     if args.gpus != 1:
-        print(json.dumps(dict(error="this build measures one GPU only; multi-GPU sharding is by query "
+        print(json.dumps(dict(error="bench.py measures one GPU only; multi-GPU sharding is by query "
                                     "(replicated graph) and is described, not run")), flush=True)
         sys.exit(2)
     out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
