@@ -278,3 +278,32 @@ def test_server_hk_with_inserts(gde, ctx):
                     or _hk_ok(G.row_ptr, G.col_idx, eps, [s], one, x)), s
     srv.close()
     g.close()
+
+
+def test_server_admission_errors(gde, ctx):
+    """Submit-time errors: a full queue is BUSY (and accepts again once polled
+    empty), LocalCH is UNSUPPORTED, a seed of degree 0 is ISOLATED_SEED."""
+    G = W.chung_lu(2000, 10000, 2.5, seed=3)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    srv = gde.Server(ctx, g, lanes_per_group=8, max_groups=1, iters_per_step=2, queue_capacity=4)
+    deg = np.diff(G.row_ptr)
+    seeds = [int(u) for u in np.flatnonzero(deg > 0)[:5]]
+    p = gde.make_params("ppr", alpha=0.1, eps=1e-4)
+    tickets = [srv.submit(p, [s]) for s in seeds[:4]]
+    with pytest.raises(gde.GDEError) as e:
+        srv.submit(p, [seeds[4]])
+    assert e.value.status == gde.BUSY
+    with pytest.raises(gde.GDEError) as e:
+        srv.submit(gde.make_params("ppr", alpha=0.1, eps=1e-4, method="ch"), [seeds[0]])
+    assert e.value.status == gde.UNSUPPORTED
+    iso = np.flatnonzero(deg == 0)
+    if len(iso):
+        with pytest.raises(gde.GDEError) as e:
+            srv.submit(p, [int(iso[0])])
+        assert e.value.status == gde.ISOLATED_SEED
+    got = drain(srv, 4)
+    assert sorted(got) == sorted(tickets) and all(c["status"] == gde.OK for c in got.values())
+    t = srv.submit(p, [seeds[4]])
+    assert drain(srv, 1)[t]["status"] == gde.OK
+    srv.close()
+    g.close()
