@@ -550,7 +550,9 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     if (w->bin_nranges > 0) {
         bins.shift = w->bin_shift;
         bins.nranges = w->bin_nranges;
-        bins.min_edges = (p->flags & GDE_SCATTER_BINNED) ? 0 : kBinMinEdges;
+        const long long nr = w->bin_nranges;
+        const long long min_binned = std::max(kBinMinEdges, nr * nr / kBinRangeSqDiv);
+        bins.min_edges = (p->flags & GDE_SCATTER_BINNED) ? 0 : min_binned;
         if (p->flags & GDE_SCATTER_ATOMIC) bins.nranges = 0;
         // PPR LocalGD: no iteration can reach the binning threshold when the whole
         // work bound vol(supp s) + ||s||_1 / (alpha eps) (Corollary 3.5) stays below
@@ -561,7 +563,7 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             double bound = 0.0;
             for (int32_t i = 0; i < sd->nnz; i++)
                 bound += (gh ? (double)gh->deg[sd->idx[i]] : (double)g->nnz) + sd->val[i] / (p->alpha * p->eps);
-            if (bound < (double)kBinMinEdges) bins.nranges = 0;
+            if (bound < (double)min_binned) bins.nranges = 0;
         }
         bins.base = w->bin_base;
         bins.cursor = w->bin_cursor;

@@ -41,7 +41,12 @@ constexpr int kHkMaxLevels = 256;          // largest heat-kernel truncation K
 constexpr int kBinMaxRanges = 4096;     // ranges a graph may have for the binned scatter
 constexpr int kBinLdsBytes = 16384;     // LDS accumulator bytes of one range (2^S values)
 constexpr int kReduceBlock = 1024;      // threads per range-reduction workgroup
-constexpr long long kBinMinEdges = 8192;    // frontier volume from which the scatter is binned
+// The range reduction launches one workgroup per range, so a graph with more
+// ranges needs a larger frontier before binning pays: the threshold is
+// max(kBinMinEdges, ranges^2 / kBinRangeSqDiv) edges (measured: 8,192 on a
+// 245-range graph, 128 to 512 edges per range on a 2,442-range graph).
+constexpr long long kBinMinEdges = 8192;  // smallest frontier volume whose scatter is binned
+constexpr long long kBinRangeSqDiv = 8;
 constexpr uint32_t kSelfMarkBit = 0x80000000u;  // a bin entry that marks a node of S_t (LocalCH)
 
 // One binned update: destination node and value side by side, so that a tile's
