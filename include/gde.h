@@ -237,8 +237,9 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
  * read once.  Queries may differ in eps; they must share kind, method
  * (LocalGD), value type and kind parameters.  schedule_json: NULL = the
  * default schedule (16 lanes, full occupancy), else a JSON object
- * {"lanes":L,"blocks":G,...}; "persistent":1 (one cooperative launch for all
- * iterations) is GDE_ERR_UNSUPPORTED.
+ * {"lanes":L,"blocks_per_cu":G,"sort":0|1}.  Every iteration is one snapshot
+ * and one push launch; "persistent":1 (a single launch for all iterations) is
+ * not provided and gives GDE_ERR_UNSUPPORTED.
  * res[i].status holds each query's own status; the call returns the first
  * non-OK status, or GDE_OK.
  */

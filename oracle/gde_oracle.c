@@ -227,9 +227,9 @@ static int check_seed(const graph_t *g, int32_t nnz, const int32_t *idx, const d
  */
 static int run_gd_ch(const graph_t *g, const form_t *f, int method, double lam, int32_t seed_nnz,
                      const int32_t *seed_idx, const double *seed_val, int32_t max_iters, double *x, double *r,
-                     int64_t *stats, double *norms, trace_t *tr, replay_t *rp) {
+                     int64_t *stats, double *norms, trace_t *tr, replay_t *rp, int warm) {
     int64_t n = g->n;
-    int rc = check_seed(g, seed_nnz, seed_idx, seed_val);
+    int rc = warm ? OR_OK : check_seed(g, seed_nnz, seed_idx, seed_val);
     if (rc) return rc;
     touched_t tch = {0};
     int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -241,11 +241,16 @@ static int run_gd_ch(const graph_t *g, const form_t *f, int method, double lam, 
         free(S); free(h); free(delta); free(prevS); free(mark); touched_free(&tch);
         return OR_OOM;
     }
-    memset(x, 0, sizeof(double) * (size_t)n);
-    memset(r, 0, sizeof(double) * (size_t)n);
-    for (int32_t i = 0; i < seed_nnz; i++) {
-        r[seed_idx[i]] = form_b(f, seed_val[i]);
-        touch(&tch, seed_idx[i]);
+    if (warm) { /* continue from the given (x, r): every node with r_u != 0 may be active */
+        for (int64_t u = 0; u < n; u++)
+            if (r[u] != 0.0) touch(&tch, u);
+    } else {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        memset(r, 0, sizeof(double) * (size_t)n);
+        for (int32_t i = 0; i < seed_nnz; i++) {
+            r[seed_idx[i]] = form_b(f, seed_val[i]);
+            touch(&tch, seed_idx[i]);
+        }
     }
     double sigma = 1.0, dlt = 0.0; /* Chebyshev state */
     if (method == 1) {
@@ -260,7 +265,7 @@ static int run_gd_ch(const graph_t *g, const form_t *f, int method, double lam, 
     int status = OR_NOT_CONVERGED;
     for (int64_t t = 0;; t++) {
         int64_t ns;
-        if (t == 0) { /* S_0 = supp(s), forced (Definition 3.1) */
+        if (t == 0 && !warm) { /* S_0 = supp(s), forced (Definition 3.1) */
             ns = seed_nnz;
             for (int32_t i = 0; i < seed_nnz; i++) S[i] = seed_idx[i];
             if (rp && rp->T_rec > 0) {
@@ -282,7 +287,8 @@ static int run_gd_ch(const graph_t *g, const form_t *f, int method, double lam, 
         /* the update h on S_t, from the residual at the start of iteration t */
         int64_t vol = 0;
         double rs = 0.0, r1 = 0.0;
-        for (int64_t i = 0; i < tch.len; i++) r1 += fabs(r[tch.list[i]]);
+        if (tr && tr->r_l1) /* only the trace reads ||r||_1; it feeds no arithmetic */
+            for (int64_t i = 0; i < tch.len; i++) r1 += fabs(r[tch.list[i]]);
         for (int64_t i = 0; i < ns; i++) {
             int64_t u = S[i];
             vol += (int64_t)deg(g, u);
@@ -335,7 +341,7 @@ int oracle_localgd(int64_t n, const int64_t *rp, const int32_t *ci, int kind, do
     form_t f;
     if (make_form(kind, param, eps, &f)) return OR_INVALID;
     trace_t tr = {trace_cap, tr_size, tr_vol, tr_rs, tr_r1, nodes_cap, tr_nodes, 0};
-    int rc = run_gd_ch(&g, &f, 0, 0.0, seed_nnz, seed_idx, seed_val, max_iters, x, r, stats, norms, &tr, NULL);
+    int rc = run_gd_ch(&g, &f, 0, 0.0, seed_nnz, seed_idx, seed_val, max_iters, x, r, stats, norms, &tr, NULL, 0);
     if (nodes_len) *nodes_len = tr.nodes_len;
     return rc;
 }
@@ -349,7 +355,7 @@ int oracle_localch(int64_t n, const int64_t *rp, const int32_t *ci, int kind, do
     if (make_form(kind, param, eps, &f)) return OR_INVALID;
     if (kind == KIND_KATZ && !(param * lam > 0.0 && param * lam < 1.0)) return OR_INVALID;
     trace_t tr = {trace_cap, tr_size, tr_vol, NULL, NULL, nodes_cap, tr_nodes, 0};
-    int rc = run_gd_ch(&g, &f, 1, lam, seed_nnz, seed_idx, seed_val, max_iters, x, r, stats, norms, &tr, NULL);
+    int rc = run_gd_ch(&g, &f, 1, lam, seed_nnz, seed_idx, seed_val, max_iters, x, r, stats, norms, &tr, NULL, 0);
     if (nodes_len) *nodes_len = tr.nodes_len;
     return rc;
 }
@@ -365,10 +371,76 @@ int oracle_replay_gd_ch(int64_t n, const int64_t *rp, const int32_t *ci, int met
     if (make_form(kind, param, eps, &f)) return OR_INVALID;
     replay_t rpl = {off, nodes, T_rec, kappa, 0, 0};
     int rc = run_gd_ch(&g, &f, method, lam, seed_nnz, seed_idx, seed_val, (int32_t)(T_rec + 1), x, r, stats, norms,
-                       NULL, &rpl);
+                       NULL, &rpl, 0);
     out_fv[0] = rpl.flips;
     out_fv[1] = rpl.violations;
     return rc;
+}
+
+/*
+ * LocalGD continued from a given state (x, r) on the current graph: the
+ * re-solve step of the dynamic algorithms of Sec. 4 (LocalGS(Dynamic) and
+ * LocalSOR(Dynamic) return to their local solver after the Insert / Delete
+ * corrections).  There is no forced S_0: S_t = {u : |r_u| >= theta_u, r_u != 0}
+ * from t = 0, with signed residuals (a deletion can make r negative).
+ * x, r: in / out, dense n-vectors in the generic form r = b - Q x.
+ */
+int oracle_localgd_warm(int64_t n, const int64_t *rp, const int32_t *ci, int kind, double param, double eps,
+                        int32_t max_iters, double *x, double *r, int64_t *stats, double *norms) {
+    graph_t g = {n, rp, ci};
+    form_t f;
+    if (make_form(kind, param, eps, &f)) return OR_INVALID;
+    return run_gd_ch(&g, &f, 0, 0.0, 0, NULL, NULL, max_iters, x, r, stats, norms, NULL, NULL, 1);
+}
+
+/*
+ * Edge events on (x, r) in the generic form r = b - Q x (Sec. 4, the Insert and
+ * Delete procedures of LocalGS(Dynamic) / LocalSOR(Dynamic)).  Each undirected
+ * edge {a, c} is applied as the directed event a -> c and then c -> a; deg is the
+ * current degree of every node and is updated event by event.
+ *
+ * PPR (Q = I - (1-alpha) A D^-1): a directed event a -> c changes column a of
+ * A D^-1.  With d0 = deg[a] before and d1 after the event, x_a is rescaled to
+ * x_a d1 / d0 so that the old neighbours keep receiving (1-alpha) x_a / d0;
+ * with D = x_a / d0 (the change of x_a in magnitude):
+ *   insert : x_a += D, r_a -= D, r_c += (1-alpha) D
+ *   delete : x_a -= D, r_a += D, r_c -= (1-alpha) D
+ * (the paper's procedures, written with the degree before the event, so that a
+ * node left with degree 0 gets x_a = 0 instead of 0/0).  An isolated node's
+ * column of A D^-1 is zero, so the first edge of a node with d0 = 0 only adds
+ * (1-alpha) x_a to r_c.
+ * Katz (Q = I - beta A, derived): the directed event a -> c adds or removes
+ * A[c][a], so r_c += beta x_a (insert) or r_c -= beta x_a (delete).
+ * sign: +1 insert, -1 delete.  The events must be valid for the graph they
+ * are applied to (an inserted edge is new, a deleted edge exists).
+ */
+int oracle_edge_events(int64_t n, int kind, double param, double *x, double *r, int64_t *deg, int64_t k,
+                       const int32_t *eu, const int32_t *ev, int sign) {
+    if ((kind != KIND_PPR && kind != KIND_KATZ) || (sign != 1 && sign != -1)) return OR_INVALID;
+    for (int64_t i = 0; i < k; i++) {
+        for (int dir = 0; dir < 2; dir++) {
+            int64_t a = dir == 0 ? eu[i] : ev[i];
+            int64_t c = dir == 0 ? ev[i] : eu[i];
+            if (a < 0 || a >= n || c < 0 || c >= n || a == c) return OR_INVALID;
+            int64_t d0 = deg[a];
+            if (sign < 0 && d0 < 1) return OR_INVALID;
+            if (kind == KIND_PPR) {
+                double alpha = param;
+                if (d0 == 0) {
+                    r[c] += (1.0 - alpha) * x[a];
+                } else {
+                    double D = x[a] / (double)d0;
+                    x[a] += sign * D;
+                    r[a] -= sign * D;
+                    r[c] += sign * (1.0 - alpha) * D;
+                }
+            } else {
+                r[c] += sign * param * x[a];
+            }
+            deg[a] = d0 + sign;
+        }
+    }
+    return OR_OK;
 }
 
 /*

@@ -53,8 +53,10 @@ def _load():
                                              _p64, _pf]
             lib.oracle_hk.argtypes = [i64, _p64, _p32, d, i32, d, i32, _p32, _pf, _pf, _p64, _pf, _pf, i64, vp,
                                       vp, i64, vp, vp, i64, vp, vp, d, vp]
+            lib.oracle_localgd_warm.argtypes = [i64, _p64, _p32, C.c_int, d, d, i32, _pf, _pf, _p64, _pf]
+            lib.oracle_edge_events.argtypes = [i64, C.c_int, d, _pf, _pf, _p64, i64, _p32, _p32, C.c_int]
             for f in (lib.oracle_localgd, lib.oracle_localch, lib.oracle_replay_gd_ch, lib.oracle_push_fifo,
-                      lib.oracle_hk):
+                      lib.oracle_hk, lib.oracle_localgd_warm, lib.oracle_edge_events):
                 f.restype = C.c_int
             _lib = lib
     return _lib
@@ -207,3 +209,35 @@ def replay_gd_ch(row_ptr, col_idx, method, kind, param, eps, seed_idx, seed_val,
     _check(rc)
     return dict(x=x, r=r, status=rc, iters=int(stats[0]), ops=int(stats[1]), pushes=int(stats[2]),
                 residual_l1=norms[0], residual_dinf=norms[1], flips=int(fv[0]), violations=int(fv[1]))
+
+
+def localgd_warm(row_ptr, col_idx, kind, param, eps, x, r, max_iters=100000):
+    """LocalGD continued from a given (x, r) (no forced S_0, signed residuals): the
+    re-solve after the edge-event corrections of the dynamic algorithms (Sec. 4).
+    Returns new arrays; the inputs are not modified."""
+    lib = _load()
+    n, rp, ci = _graph(row_ptr, col_idx)
+    x = np.array(x, dtype=np.float64, copy=True)
+    r = np.array(r, dtype=np.float64, copy=True)
+    stats, norms = np.zeros(4, np.int64), np.zeros(2)
+    rc = lib.oracle_localgd_warm(n, rp, ci, kind, param, eps, max_iters, x, r, stats, norms)
+    _check(rc)
+    return dict(x=x, r=r, status=rc, iters=int(stats[0]), ops=int(stats[1]), pushes=int(stats[2]),
+                residual_l1=norms[0], residual_dinf=norms[1])
+
+
+def edge_events(kind, param, x, r, deg, u, v, sign):
+    """Insert (sign=+1) or delete (sign=-1) the undirected edges (u[i], v[i]) in
+    (x, r) (generic form r = b - Q x), each as the directed events u->v then v->u
+    (the Insert / Delete procedures of Sec. 4; Katz derived).  ``deg`` holds the
+    degrees before the batch.  Returns new (x, r, deg)."""
+    lib = _load()
+    x = np.array(x, dtype=np.float64, copy=True)
+    r = np.array(r, dtype=np.float64, copy=True)
+    deg = np.array(deg, dtype=np.int64, copy=True)
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    rc = lib.oracle_edge_events(len(x), kind, param, x, r, deg, len(u), u, v, int(sign))
+    if rc != OK:
+        raise ValueError(f"oracle rejected the edge events (status {rc})")
+    return x, r, deg

@@ -74,7 +74,6 @@ struct DevBuf {  // device scratch released on every return path
 struct Schedule {
     int lanes = 16;
     int blocks_per_cu = 0;  // 0: the occupancy limit
-    int persistent = 0;
     int sort = 1;           // order queries by eps, then seed degree, before packing lanes
 };
 
@@ -91,15 +90,13 @@ static int json_int(const char *js, const char *key, int dflt) {
 static int parse_schedule(const char *js, Schedule *sc) {
     sc->lanes = json_int(js, "lanes", 16);
     sc->blocks_per_cu = json_int(js, "blocks_per_cu", 0);
-    sc->persistent = json_int(js, "persistent", 0);
     sc->sort = json_int(js, "sort", 1);
     if (sc->lanes != 8 && sc->lanes != 16 && sc->lanes != 32)
         return fail(GDE_ERR_INVALID_ARG, "schedule.lanes must be 8, 16 or 32");
     if (sc->blocks_per_cu < 0 || sc->blocks_per_cu > 64) return fail(GDE_ERR_INVALID_ARG, "bad schedule.blocks_per_cu");
-    // The single cooperative launch with grid-wide barriers stopped making
-    // progress on its first GPU run and its cause has not been shown; it stays
-    // switched off.  Iterations run as per-iteration launches of the same phases.
-    if (sc->persistent) return fail(GDE_ERR_UNSUPPORTED, "schedule.persistent=1 is disabled");
+    // every iteration runs as one snapshot and one push launch; a single
+    // cooperative launch for all iterations is not provided
+    if (json_int(js, "persistent", 0)) return fail(GDE_ERR_UNSUPPORTED, "schedule.persistent is not provided");
     return GDE_OK;
 }
 
@@ -388,29 +385,21 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     const int grid = bpc * cus;
     BatchDev hst{};
     if ((rc = prof_mark_batch(ctx, s))) return rc;
-    if (sc.persistent) {
-        GDE_HIP(batch_launch<V>(0, L, a, grid, 0, s));
-        if ((rc = prof_mark_batch(ctx, s))) return rc;
+    int t = 0, chunk = 8;
+    bool done = false;
+    while (t < a.max_iters && !done) {
+        int end = std::min(a.max_iters, t + chunk);
+        for (; t < end; t++) {
+            GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
+            GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
+        }
         GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
-    } else {
-        int t = 0, chunk = 8;
-        bool done = false;
-        while (t < a.max_iters && !done) {
-            int end = std::min(a.max_iters, t + chunk);
-            for (; t < end; t++) {
-                GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
-                GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
-            }
-            GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
-            GDE_HIP(hipStreamSynchronize(s));
-            done = hst.acount[t & 1] == 0 || hst.ovf[0] || hst.ovf[1];
-            chunk = std::min(chunk * 2, 32);
-        }
-        if ((rc = prof_mark_batch(ctx, s))) return rc;
-        hst.iters_run = t;
-        hst.final_parity = t & 1;
+        done = hst.acount[t & 1] == 0 || hst.ovf[0] || hst.ovf[1];
+        chunk = std::min(chunk * 2, 32);
     }
+    if ((rc = prof_mark_batch(ctx, s))) return rc;
+    const int final_parity = t & 1;
     if (hst.ovf[0] || hst.ovf[1]) {
         // the kernels stopped on a capacity limit: restore the rest state by brute force
         GDE_HIP(hipMemsetAsync(w->R, 0, (size_t)g->n * GL * w->vs, s));
@@ -423,7 +412,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     }
     // residual norms, unconverged lanes, Katz seed subtraction
     const bool any_sub = std::any_of(h_flag.begin(), h_flag.end(), [](int32_t f) { return f != 0; });
-    GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, hst.final_parity, w->s_lane, w->s_node,
+    GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, final_parity, w->s_lane, w->s_node,
                             w->s_val, (int32_t)ns, any_sub ? w->sub_flag : nullptr, s));
     // extraction: counts per lane, then the sorted sparse outputs
     GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));

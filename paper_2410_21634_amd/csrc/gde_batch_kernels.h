@@ -19,8 +19,7 @@ struct BatchDev {
     int32_t ovf[2];                // a capacity was exceeded during an iteration of this parity
                                    // (per parity, so the stop test after iteration t reads a
                                    // flag that no block can still be writing)
-    int32_t iters_run;             // iterations executed by the persistent kernel
-    int32_t final_parity;          // parity of the last (possibly non-empty) active list
+    int32_t pad0[2];
     long long lane_edges;          // sum over iterations of the lane-edges pushed
     long long entries;             // sum over iterations of the (group, node) entries
 };
@@ -77,7 +76,7 @@ struct BatchArgs {
     int32_t max_iters;
 };
 
-// which: 0 persistent cooperative launch, 1 snap(t), 2 push(t)
+// which: 1 snap(t), 2 push(t)
 template <typename V> hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t, hipStream_t s);
 template <typename V> hipError_t batch_occupancy(int L, int *blocks_per_cu);
 template <typename V>

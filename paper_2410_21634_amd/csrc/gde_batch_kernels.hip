@@ -15,15 +15,10 @@
 //          active list.  A returned zero marks the pair as touched (the
 //          residual clean-up at the end reads only touched pairs).  List
 //          appends are aggregated per workgroup and tile (one counter atomic).
-// The persistent kernel runs both phases for all iterations in one
-// cooperative launch, separated by grid barriers.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "gde_batch_kernels.h"
 #include "gde_device.h"
-
-namespace cg = cooperative_groups;
 
 namespace gde {
 
@@ -285,28 +280,6 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
 
 // ------------------------------------------------------------------ launches
 template <typename V, int L>
-__global__ void __launch_bounds__(kBlock) k_batch_persistent(BatchArgs<V> a) {
-    cg::grid_group grid = cg::this_grid();
-    const int nb = gridDim.x, bid = blockIdx.x;
-    for (int t = 0; t < a.max_iters; t++) {
-        batch_snap<V, L>(a, t, bid, nb);
-        grid.sync();
-        batch_push<V, L>(a, t, bid, nb);
-        grid.sync();
-        const int nxt_count = __hip_atomic_load(&a.st->acount[(t + 1) & 1], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-        const int ovf = __hip_atomic_load(&a.st->ovf[t & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (nxt_count == 0 || ovf != 0 || t + 1 == a.max_iters) {
-            if (bid == 0 && threadIdx.x == 0) {
-                a.st->iters_run = t + 1;
-                a.st->final_parity = (t + 1) & 1;
-            }
-            break;
-        }
-    }
-}
-
-template <typename V, int L>
 __global__ void __launch_bounds__(kBatchSnapBlock) k_batch_snap(BatchArgs<V> a, int t) {
     batch_snap<V, L>(a, t, blockIdx.x, gridDim.x);
 }
@@ -557,18 +530,10 @@ __global__ void k_batch_init_deg(const int32_t *__restrict__ row_ptr, V *deg, in
 }
 
 // ------------------------------------------------------------------ host-side launchers
-template <typename V, int L>
-static hipError_t launch_persistent_t(const BatchArgs<V> &a, int grid, hipStream_t s) {
-    BatchArgs<V> copy = a;
-    void *args[] = {&copy};
-    return hipLaunchCooperativeKernel((const void *)k_batch_persistent<V, L>, dim3(grid), dim3(kBlock), args, 0, s);
-}
-
 template <typename V>
 hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t, hipStream_t s) {
 #define GDE_BL(LL)                                                                                       \
     case LL:                                                                                             \
-        if (which == 0) return launch_persistent_t<V, LL>(a, grid, s);                                    \
         if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL>),                                         \
                                            dim3((grid * kBlock + kBatchSnapBlock - 1) / kBatchSnapBlock),   \
                                            dim3(kBatchSnapBlock), 0, s, a, t);                            \
@@ -587,9 +552,9 @@ hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t
 template <typename V>
 hipError_t batch_occupancy(int L, int *blocks_per_cu) {
     switch (L) {
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 8>, kBlock, 0);
-    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 16>, kBlock, 0);
-    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<V, 32>, kBlock, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 8>, kBlock, 0);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 16>, kBlock, 0);
+    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 32>, kBlock, 0);
     default: return hipErrorInvalidValue;
     }
 }

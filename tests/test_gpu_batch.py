@@ -92,14 +92,8 @@ def run_and_check(gde, ctx, g, G, queries, kind, vt, schedule, param, lam=0.0):
     return worst
 
 
-PERSISTENT_SKIP = pytest.mark.skip(reason="the cooperative persistent launch stopped making progress on its first "
-                                          "GPU run; its cause is not shown, so the path is disabled")
-
-
 @pytest.mark.parametrize("vt", [1, 0])
-@pytest.mark.parametrize("schedule", [pytest.param('{"lanes":16,"persistent":1}', marks=PERSISTENT_SKIP),
-                                      '{"lanes":16}', '{"lanes":8,"persistent":0}',
-                                      '{"lanes":32,"blocks_per_cu":2}'])
+@pytest.mark.parametrize("schedule", ['{"lanes":16}', '{"lanes":8,"persistent":0}', '{"lanes":32,"blocks_per_cu":2}'])
 def test_batch_ppr_matches_oracle(gde, ctx, c1, vt, schedule):
     G, g = c1
     queries = make_queries(G, 40, seed=1)
@@ -163,7 +157,7 @@ def test_batch_status_paths(gde, ctx, c1):
     capped = [gde.make_params("ppr", alpha=0.1, eps=1e-7, value_type=gde.F64, max_iters=3) for _ in range(4)]
     out = gde.solve_batch(ctx, g, capped, [(q[0], q[1]) for q in queries[:4]], raise_on_error=False)
     assert all(r.status == gde.NOT_CONVERGED and r.iters == 3 for r in out)
-    # the disabled persistent launch is refused, not run
+    # a single launch for all iterations is not provided: refused, not run
     with pytest.raises(gde.GDEError):
         gde.solve_batch(ctx, g, params[:2], [(q[0], q[1]) for q in queries[:2]], schedule='{"persistent":1}')
     # mixed kinds fall back to query-by-query solves
