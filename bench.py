@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the local diffusion solvers on one MI355X.
 
-Default workload (PPR on the n = 10^6 power-law graph): undirected Chung-Lu
-graph, n = 1,000,000, 10,000,000 edges (nnz 2e7), degree exponent 2.5, RNG seed
-42, int32 CSR, FP32 x / r.  One step = 64 seed nodes (uniform over the largest
-component) x eps in {1e-4, 1e-5, 1e-6, 1e-7} x {LocalGD, LocalCH}, PPR
-alpha = 0.1, each query solved on its own through the C ABI (the plain path),
-outputs left in HBM.
+Default workload (the batched configuration on the n = 10^7 power-law graph):
+undirected Chung-Lu graph, n = 10,000,000, 200,000,000 edges (nnz 4e8), degree
+exponent 2.2, RNG seed 42, int32 CSR, FP32 x / r.  One step = ONE
+gde_solve_batch call over 1,024 PPR queries (alpha 0.1, LocalGD): seeds
+degree-stratified over 16 log2-spaced degree bins, eps log-uniform in
+[1e-7, 1e-4]; inputs and outputs stay in HBM.  The same 1,024 queries are also
+solved one at a time (the plain path) for the batched/plain ratio.
 
-Printed: one JSON line with solves/s (value), the algorithmic HBM GB/s of the
-whole step, per-solve latency p50 / p99, the roofline of the dominant kernel
-(the scatter step: a push with its range reduction -- which also takes the
-next snapshot inside a host chunk -- or a single-workgroup launch, timed live
-with HIP events on the solve stream)
-and the FP64 CPU oracle timed on a bounded sample of the same queries.
+Printed: one JSON line with solves/s of the batched step (value), the
+algorithmic HBM GB/s of the whole batch, the roofline of its dominant kernel
+(the batched push, each launch timed live with HIP events on the solve stream),
+the FP64 CPU oracle timed on a bounded, eps-stratified sample of the same
+queries, and sub-records for the other configurations: the plain 512-solve
+mix on the n = 10^6 graph, the n = 10^4 FP64 latency, Katz and heat-kernel
+throughput on the n = 2.4 * 10^6 graph, and a short serving run on the n = 10^7
+graph with edge insertions.
 """
 from __future__ import annotations
 
@@ -54,34 +57,50 @@ def push_alg_bytes(edges, entries, vsize=4):
     return (4 + 2 * vsize) * edges + (8 + vsize) * entries
 
 
-def kernel_source_hash():
+def kernel_source_hash(source="gde_kernels.hip"):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2410_21634_amd", "csrc", "gde_kernels.hip"), "rb") as fh:
+    with open(os.path.join(ROOT, "paper_2410_21634_amd", "csrc", source), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(entry_name):
-    """HBM traffic per launch from a committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "push_traffic_c2.json")
+def traffic_from_profile(fname, source, entry_name):
+    """HBM traffic per launch from a committed rocprofv3 --pmc summary
+    (profiles/<fname>), if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", fname)
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha") != kernel_source_hash():
+    if d.get("kernel_source_sha") != kernel_source_hash(source):
         return None
     return d.get(entry_name)
 
 
-def pmc_summary(fetch_dir, write_dir, out_path):
-    """HBM traffic per push launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch) of `bench.py --phase plain --copy-calib`, each
+# --pmc-summary targets: which dispatches make up one timed launch of the
+# roofline kernel, its source file, and where the summary is kept
+PMC_TARGETS = {
+    "plain": dict(source="gde_kernels.hip", out="push_traffic_c2.json",
+                  kernel="k_push<float,0|2> + k_reduce + k_small (scatter step)",
+                  workload="ppr-plain-n1M (bench.py --workload c2 --phase plain)",
+                  step=("k_push<", "k_small<"), extra=("k_reduce<",)),
+    "batch": dict(source="gde_batch_kernels.hip", out="batch_push_traffic_c4.json",
+                  kernel="k_batch_push<float,16> (batched residual scatter)",
+                  workload="ppr-batched-n10M (bench.py --workload c4 --no-sub)",
+                  step=("k_batch_push<",), extra=()),
+}
+
+
+def pmc_summary(target, fetch_dir, write_dir):
+    """HBM traffic per timed launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) of a bench run ending with --copy-calib, each
     scaled by what the same counter read for the calibration kernel (a 2 GiB
     elementwise multiply: CALIB_BYTES read and CALIB_BYTES written)."""
     import csv
     import glob
+
+    tg = PMC_TARGETS[target]
 
     def load(d, counter):
         rows = []
@@ -91,28 +110,21 @@ def pmc_summary(fetch_dir, write_dir, out_path):
                     rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
         return rows
 
-    # one scatter step = one push launch with its range reduction, or one
-    # single-workgroup launch (what the HIP-event timing of bench.py brackets)
     res = {}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = load(d, counter)
         calib = [v for k, v in rows if "MulFunctor" in k]
-        push = [v for k, v in rows if "k_push<" in k]
-        red = [v for k, v in rows if "k_reduce<" in k]
-        small = [v for k, v in rows if "k_small<" in k]
-        if not calib or not push:
-            raise SystemExit(f"{d}: no calibration or push dispatches with {counter}")
+        step = [v for k, v in rows if any(m in k for m in tg["step"])]
+        extra = [v for k, v in rows if any(m in k for m in tg["extra"])]
+        if not calib or not step:
+            raise SystemExit(f"{d}: no calibration or timed dispatches with {counter}")
         factor = CALIB_BYTES / max(calib)
-        steps = len(push) + len(small)
-        res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor, push_launches=len(push),
-                        reduce_launches=len(red), small_launches=len(small),
-                        bytes_per_launch=factor * (sum(push) + sum(red) + sum(small)) / steps)
-    out = dict(kernel="k_push<float,0|2> + k_reduce + k_small (scatter step)",
-               workload="ppr-plain-n1M (bench.py --phase plain)",
-               kernel_source_sha=kernel_source_hash(),
+        res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor, launches=len(step),
+                        extra_dispatches=len(extra), bytes_per_launch=factor * (sum(step) + sum(extra)) / len(step))
+    out = dict(kernel=tg["kernel"], workload=tg["workload"], kernel_source_sha=kernel_source_hash(tg["source"]),
                bytes_per_launch=round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"], 1),
                fetch=res["fetch"], write=res["write"])
-    with open(out_path, "w") as fh:
+    with open(os.path.join(ROOT, "profiles", tg["out"]), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
@@ -272,7 +284,7 @@ def run_c2(args):
     pb = push_alg_bytes(prof["edges"], prof["entries"])
     avg_ms = prof["total_ms"] / launches
     achieved = pb / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
-    traffic = traffic_from_profile("bytes_per_launch")
+    traffic = traffic_from_profile("push_traffic_c2.json", "gde_kernels.hip", "bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic, kernel="scatter step: k_push + k_reduce, or k_small",
                 launches=prof["launches"], avg_launch_us=round(avg_ms * 1e3, 3),
@@ -296,38 +308,108 @@ def run_c2(args):
     return out
 
 
-def build_graph_device(W, n, E, gamma, seed, gde, ctx, torch):
+def host_cpu():
+    """CPU model and logical core count of this host (for the baseline record)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline_c4(G, seeds, eps, budget_s=30.0, threads=16):
+    """The FP64 LocalGD oracle, as it stands, on the batched queries: (1) every
+    query of the batch spread over a thread pool, one single-threaded solve per
+    thread (ctypes releases the GIL), and (2) one solve at a time on one core,
+    median latency over every 16th query in eps order.  The pool is capped at the
+    host CPU share of one GPU (16 threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import solvers as O
+
+    O._load()
+    model, ncpu = host_cpu()
+    cores = max(1, min(threads, ncpu))
+    order = np.argsort(eps, kind="stable")
+    rp64 = G.row_ptr.astype(np.int64)
+
+    def one(i):
+        t = time.perf_counter()
+        O.localgd(rp64, G.col_idx, O.PPR, 0.1, float(eps[i]), [int(seeds[i])])
+        return time.perf_counter() - t
+
+    t1 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        done = len(list(ex.map(one, range(len(seeds)))))
+    wall = time.perf_counter() - t1
+    lat = []
     t0 = time.perf_counter()
-    G = W.chung_lu(n, E, gamma, seed=seed)
+    for i in order[8::16]:
+        lat.append(one(int(i)))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return dict(value=round(done / wall, 3), unit="solves/s", cores=cores, kind="oracle",
+                host_cpu=model, host_logical_cpus=ncpu,
+                latency_1core_ms=dict(median=round(1e3 * float(np.median(lat)), 3),
+                                      p99=round(1e3 * float(np.percentile(lat, 99)), 3), solves=len(lat)),
+                sample=(f"FP64 LocalGD oracle, PPR alpha=0.1, same n=1e7 graph: all {done} queries of the batch on "
+                        f"{cores} threads, one single-threaded solve per thread, in {wall:.1f}s; 1-core latency over "
+                        f"{len(lat)} queries (every 16th in eps order)"))
+
+
+def c4_inputs(W):
+    t0 = time.perf_counter()
+    G = W.chung_lu(10_000_000, 200_000_000, 2.2, seed=42)
     log(f"graph {G.summary()} built in {time.perf_counter() - t0:.1f}s")
-    dev = torch.device("cuda:0")
-    rp = torch.from_numpy(G.row_ptr).to(dev)
-    ci = torch.from_numpy(G.col_idx).to(dev)
-    return G, gde.Graph(ctx, rp, ci), (rp, ci)
+    B = 1024
+    seeds = W.stratified_seeds(G, B, bins=16, seed=42)
+    eps = W.log_uniform_eps(B, 1e-7, 1e-4, seed=42)
+    return G, seeds, eps
+
+
+def batch_push_bytes(prof, vsize=4):
+    """Algorithmic bytes of the batched push launches (the batched rule): the
+    column indices of every distinct CSR row pushed in a round, once, whatever
+    the number of queries pushing it; per (edge, query) update the residual
+    read-modify-write."""
+    return 4 * prof["batch_row_vol"] + 2 * vsize * prof["batch_lane_edges"]
+
+
+def batch_alg_bytes(prof, lane_pushes, vsize=4):
+    """Algorithmic bytes of whole batched solves: the push bytes above, plus per
+    distinct row and round its row pointers, plus per (node, query) push the
+    residual snapshot and reset and the x read-modify-write."""
+    return batch_push_bytes(prof, vsize) + 8 * prof["batch_rows"] + 4 * vsize * lane_pushes
 
 
 def run_c4(args):
     """Batched: 1,024 degree-stratified seeds, eps log-uniform in [1e-7, 1e-4], PPR
     alpha 0.1, on the n = 10^7, 2e8-edge, gamma 2.2 graph; one gde_solve_batch call
-    against the same queries solved one at a time (the plain path, on a sample)."""
+    per step, against the same queries solved one at a time (the plain path)."""
     import torch
 
     from paper_2410_21634_amd import gde
     from paper_2410_21634_amd import workloads as W
 
+    G, seeds, eps = c4_inputs(W)
+    B = len(seeds)
     ctx = gde.Context(0)
-    G, g, keep = build_graph_device(W, 10_000_000, 200_000_000, 2.2, 42, gde, ctx, torch)
-    B = 1024
-    seeds = W.stratified_seeds(G, B, bins=16, seed=42)
-    eps = W.log_uniform_eps(B, 1e-7, 1e-4, seed=42)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
     params = [gde.make_params("ppr", alpha=0.1, eps=float(e), value_type=gde.F32) for e in eps]
     bseeds = [([int(s)], None) for s in seeds]
     cap = 2_000_000
-    dev = torch.device("cuda:0")
     bout = (torch.empty(B * cap, dtype=torch.int32, device=dev), torch.empty(B * cap, dtype=torch.float32, device=dev))
     for i in range(args.warmup):
         gde.solve_batch(ctx, g, params, bseeds, schedule=args.schedule, out=bout)
-        log(f"warmup batch {i + 1} done")
+        log(f"warmup batch {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True, reset=True)
     t0 = time.perf_counter()
@@ -340,60 +422,166 @@ def run_c4(args):
     ops = int(res.ops.sum())
     pushes = int(res.pushes.sum())
     value = B * args.steps / el
-    gbs = alg_bytes(ops, pushes) * args.steps / el / 1e9
+    K = max(args.steps, 1)
+    whole = batch_alg_bytes(prof, pushes * K) / K  # per batch
+    gbs = whole * args.steps / el / 1e9
+    pl = max(prof["batch_push_launches"], 1)
+    push_ms = prof["batch_push_ms"] / pl
+    push_bytes = batch_push_bytes(prof) / pl
+    achieved = push_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
+    traffic = traffic_from_profile("batch_push_traffic_c4.json", "gde_batch_kernels.hip", "bytes_per_launch")
+    roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic,
+                kernel="k_batch_push<float,16> (batched residual scatter)", launches=prof["batch_push_launches"],
+                avg_launch_us=round(push_ms * 1e3, 3), alg_bytes_per_launch=round(push_bytes, 1),
+                timed_launches="every push launch of the timed batches, HIP events on the solve stream",
+                byte_rule="4 B per column index of each distinct row pushed in a round + 8 B per (edge, query) "
+                          "residual read-modify-write")
     kms = prof["batch_ms"] / max(prof["batch_launches"], 1)
-    # batched kernel roofline: per (edge, query) update 12 B, per (query, node) push 24 B
-    kb = alg_bytes(ops, pushes) / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    # the plain path on a stratified sample of the same queries (one at a time)
+    # the plain path on the same queries, one at a time
     oi = torch.empty(G.n, dtype=torch.int32, device=dev)
     ov = torch.empty(G.n, dtype=torch.float32, device=dev)
     samp = list(range(0, B, max(1, B // args.plain_sample)))
     gde.solve(ctx, g, params[samp[0]], [int(seeds[samp[0]])], out=(oi, ov))
     torch.cuda.synchronize()
     tp = time.perf_counter()
+    nconv_plain = 0
     for j in samp:
-        gde.solve(ctx, g, params[j], [int(seeds[j])], out=(oi, ov))
+        r = gde.solve(ctx, g, params[j], [int(seeds[j])], out=(oi, ov))
+        nconv_plain += int(r.status != gde.OK)
     torch.cuda.synchronize()
     tp = time.perf_counter() - tp
     plain_rate = len(samp) / tp
+    log(f"c4: batched {value:.1f} solves/s, plain {plain_rate:.1f} solves/s")
     out = dict(metric=METRIC, value=round(value, 2), unit="solves/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(1e3 * el / args.steps, 3), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload="ppr-batched-n10M: Chung-Lu n=1e7, 2e8 edges, gamma 2.2, seed 42; 1,024 "
-                                    "degree-stratified seeds, eps log-uniform [1e-7,1e-4], PPR alpha 0.1, one "
-                                    "gde_solve_batch call", n=G.n, edges=G.nnz // 2, queries=B, path="batched",
+                                    "degree-stratified seeds (16 log2 degree bins), eps log-uniform [1e-7,1e-4] "
+                                    "(seed 42), PPR alpha 0.1, LocalGD, FP32; one gde_solve_batch call per step",
+                           n=G.n, edges=G.nnz // 2, d_max=int(G.degrees.max()), queries=B, path="batched",
                            schedule=args.schedule or "default"),
                hbm_gbs_alg=round(gbs, 2), hbm_frac_alg=round(gbs / PEAK_HBM_GBS, 5),
-               roofline=dict(bound="hbm", achieved=round(kb, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                             frac=round(kb / PEAK_HBM_GBS, 5), traffic=None,
-                             kernel="batched snap+push launches (whole solve)", kernel_ms=round(kms, 3)),
-               plain=dict(sample=len(samp), solves_per_s=round(plain_rate, 2),
-                          batched_speedup=round(value / plain_rate, 2)),
-               stats=dict(total_edge_updates=int(ops), total_pushes=int(pushes),
-                          not_converged=int((res.status != 0).sum()), mean_iters=float(res.iters.mean())))
+               roofline=roof,
+               batch=dict(ms_per_batch=round(1e3 * el / args.steps, 3), solve_span_ms=round(kms, 3),
+                          push_ms_per_batch=round(prof["batch_push_ms"] / K, 3),
+                          lane_edges=int(prof["batch_lane_edges"] // K), entries=int(prof["batch_entries"] // K),
+                          distinct_rows=int(prof["batch_rows"] // K), distinct_row_vol=int(prof["batch_row_vol"] // K),
+                          lane_pushes=pushes, alg_bytes=int(whole), not_converged=int((res.status != 0).sum()),
+                          mean_iters=round(float(res.iters.mean()), 3), max_iters=int(res.iters.max())),
+               plain=dict(queries=len(samp), solves_per_s=round(plain_rate, 2), not_converged=nconv_plain,
+                          batched_speedup=round(value / plain_rate, 2)))
+    if not args.no_sub:
+        out["serving"] = run_serve_sub(args, ctx, g, G)
     g.close()
     ctx.close()
+    del rp, ci, bout
+    torch.cuda.empty_cache()
+    if not args.no_sub:
+        out["sub"] = dict(c2_plain=sub_c2(args), c1_latency=sub_c1(), c3_katz_hk=sub_c3())
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_c4(G, seeds, eps, budget_s=args.cpu_budget)
     return out
 
 
-def run_serve(args):
-    """Serving: open-loop Poisson arrivals of mixed PPR / Katz / HK queries (half
-    single seeds, half 8-node seed sets, eps log-uniform [1e-7, 1e-4]) with a
-    10,000-edge insert batch every 100 ms, swept over arrival rates.  Queries and
-    insert batches are drawn before the clock starts; latency is completion time
-    minus scheduled arrival time."""
+def sub_c2(args):
+    """One step of the plain 512-solve mix on the n = 10^6 graph (and the batched
+    call over its LocalGD queries), as a sub-record."""
+    sub_args = argparse.Namespace(**vars(args))
+    sub_args.steps, sub_args.warmup, sub_args.no_cpu_baseline, sub_args.phase = 1, 1, True, "all"
+    r = run_c2(sub_args)
+    keep = ("value", "unit", "ms_per_step", "hbm_gbs_alg", "hbm_frac_alg", "latency_ms", "per_query", "roofline",
+            "batched")
+    return dict(config=r["config"], **{k: r[k] for k in keep})
+
+
+def sub_c1():
+    """Latency of one FP64 PPR LocalGD solve on the n = 10^4 graph (median / p99
+    over 100 repeats, device outputs)."""
     import torch
 
     from paper_2410_21634_amd import gde
     from paper_2410_21634_amd import workloads as W
 
+    G = W.chung_lu(10_000, 50_000, 2.5, seed=42)
+    seed = int(W.uniform_seeds(G, 1, seed=42)[0])
     ctx = gde.Context(0)
-    n, E = (10_000_000, 200_000_000) if not args.small else (1_000_000, 10_000_000)
-    G, g, keep = build_graph_device(W, n, E, 2.2, 42, gde, ctx, torch)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
+    p = gde.make_params("ppr", alpha=0.1, eps=1e-6, value_type=gde.F64)
+    oi = torch.empty(G.n, dtype=torch.int32, device=dev)
+    ov = torch.empty(G.n, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        r = gde.solve(ctx, g, p, [seed], out=(oi, ov))
+    lat = []
+    for _ in range(100):
+        t = time.perf_counter()
+        r = gde.solve(ctx, g, p, [seed], out=(oi, ov))
+        lat.append(time.perf_counter() - t)
+    g.close()
+    ctx.close()
+    lat = np.array(lat) * 1e6
+    return dict(workload="Chung-Lu n=1e4, 5e4 edges, gamma 2.5, seed 42; one uniform seed; PPR alpha 0.1, "
+                         "eps 1e-6, LocalGD, FP64", seed=seed, iters=r.iters, ops=r.ops,
+                latency_us=dict(median=round(float(np.median(lat)), 2), p99=round(float(np.percentile(lat, 99)), 2)))
+
+
+def sub_c3():
+    """Katz (beta = 0.5 / lambda_lower) and heat kernel (tau 5, K 30) at eps 1e-6,
+    32 uniform seeds, FP32, on the n = 2.4 * 10^6 graph: solves/s of each."""
+    import torch
+
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
+    t0 = time.perf_counter()
+    G = W.chung_lu(2_400_000, 62_000_000, 2.3, seed=42)
+    log(f"graph {G.summary()} built in {time.perf_counter() - t0:.1f}s")
+    seeds = W.uniform_seeds(G, 32, seed=42)
+    ctx = gde.Context(0)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
+    lo, hi = g.lambda_max(max_iters=300, rtol=1e-3)
+    beta = 0.5 / lo
+    oi = torch.empty(G.n, dtype=torch.int32, device=dev)
+    ov = torch.empty(G.n, dtype=torch.float32, device=dev)
+    out = dict(workload="Chung-Lu n=2.4e6, 6.2e7 edges, gamma 2.3, seed 42; 32 uniform seeds, eps 1e-6, FP32",
+               lambda_bounds=[round(lo, 4), round(hi, 4)], beta=beta)
+    for name, p in (("katz", gde.make_params("katz", beta=beta, eps=1e-6, lambda_bound=hi, value_type=gde.F32)),
+                    ("hk", gde.make_params("hk", tau=5.0, K=30, eps=1e-6, value_type=gde.F32))):
+        gde.solve(ctx, g, p, [int(seeds[0])], out=(oi, ov))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ops = 0
+        for s in seeds:
+            r = gde.solve(ctx, g, p, [int(s)], out=(oi, ov))
+            ops += r.ops
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        out[name] = dict(solves_per_s=round(len(seeds) / t, 2), mean_ops=round(ops / len(seeds), 1))
+    g.close()
+    ctx.close()
+    return out
+
+
+def serve_sweep(args, ctx, g, G, qps_list, warm_s, serve_s):
+    """Open-loop Poisson arrivals of mixed PPR / Katz / HK queries (kind uniform,
+    half single seeds, half 8-node seed sets, eps log-uniform [1e-7, 1e-4] for
+    every kind) with a 10,000-edge insert batch every 100 ms, at each rate of
+    qps_list.  Queries and insert batches are drawn before the clock starts;
+    latency is harvest time minus scheduled arrival time."""
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
     lo, hi = g.lambda_max(max_iters=300, rtol=1e-3)
     beta = 0.5 / hi
     log(f"lambda bounds [{lo:.3f}, {hi:.3f}], beta {beta:.4g}")
-    total_s = args.warm_s + args.serve_s
+    total_s = warm_s + serve_s
     rng = np.random.default_rng(7)
     t0 = time.perf_counter()
     existing = set()
@@ -402,7 +590,7 @@ def run_serve(args):
     pool = W.stratified_seeds(G, 4096, bins=16, seed=7)
     sets = [W.seed_set(G, int(a), 8, rng) for a in pool[::4]]
     results = []
-    for qps in args.qps:
+    for qps in qps_list:
         arr = W.poisson_arrivals(qps, total_s, seed=int(qps))
         qs = []
         for _ in range(len(arr)):
@@ -415,9 +603,9 @@ def run_serve(args):
             if kind == "ppr":
                 p = gde.make_params("ppr", alpha=0.1, eps=e)
             elif kind == "katz":
-                p = gde.make_params("katz", beta=beta, eps=max(e, 1e-6), lambda_bound=hi)
+                p = gde.make_params("katz", beta=beta, eps=e, lambda_bound=hi)
             else:
-                p = gde.make_params("hk", tau=5.0, K=30, eps=max(e, 1e-6))
+                p = gde.make_params("hk", tau=5.0, K=30, eps=e)
             qs.append((p, idx, val, kind))
         srv = gde.Server(ctx, g, lanes_per_group=16, max_groups=args.groups, iters_per_step=args.iters_per_step,
                          result_capacity=2_000_000)
@@ -438,8 +626,8 @@ def run_serve(args):
                 t = srv.submit(*qs[i][:3])
                 sub_at[t] = arr[i]
                 sub_kind[t] = qs[i][3]
-                submitted += arr[i] >= args.warm_s
-                kinds[qs[i][3]][1] += int(arr[i] >= args.warm_s)
+                submitted += arr[i] >= warm_s
+                kinds[qs[i][3]][1] += int(arr[i] >= warm_s)
                 i += 1
             while ins < len(inserts) and (ins + 1) * 0.1 <= now:
                 srv.insert_edges(*inserts[ins])
@@ -449,7 +637,7 @@ def run_serve(args):
             for c in done:
                 t_arr = sub_at.pop(c["ticket"])
                 kd = kinds[sub_kind.pop(c["ticket"])]
-                if t_arr >= args.warm_s:
+                if t_arr >= warm_s:
                     lat.append(tn - t_arr)
                     completed += 1
                     kd[0] += 1
@@ -458,10 +646,10 @@ def run_serve(args):
                 break
         srv.close()
         lat_ms = np.array(lat) * 1e3
-        rec = dict(qps=qps, submitted=int(submitted), completed=int(completed),
-                   offered=int(np.sum(arr >= args.warm_s)),
-                   completion_ratio=round(completed / max(int(np.sum(arr >= args.warm_s)), 1), 4),
-                   solves_per_s=round(completed / args.serve_s, 2), inserted_edges=ins * args.insert_k,
+        offered = int(np.sum(arr >= warm_s))
+        rec = dict(qps=qps, submitted=int(submitted), completed=int(completed), offered=offered,
+                   completion_ratio=round(completed / max(offered, 1), 4),
+                   solves_per_s=round(completed / serve_s, 2), inserted_edges=ins * args.insert_k,
                    p50_ms=round(float(np.percentile(lat_ms, 50)), 3) if len(lat_ms) else None,
                    p99_ms=round(float(np.percentile(lat_ms, 99)), 3) if len(lat_ms) else None,
                    by_kind={k: dict(completed=int(v[0]), submitted=int(v[1]),
@@ -471,14 +659,48 @@ def run_serve(args):
         log(f"serve {rec}")
         results.append(rec)
     ok = [r for r in results if r["completion_ratio"] >= 0.99]
-    stated = max(ok, key=lambda r: r["qps"]) if ok else results[0]
-    out = dict(metric=METRIC, value=stated["solves_per_s"], unit="solves/s", n_gpus=1, steps=len(results),
+    stated = max(ok, key=lambda r: r["qps"]) if ok else None
+    return stated, results
+
+
+def run_serve_sub(args, ctx, g, G):
+    """A short serving sweep on the n = 10^7 graph already on the device: each
+    rate of --serve-sub-qps for 1 s of warm-up and --serve-sub-s seconds measured."""
+    stated, results = serve_sweep(args, ctx, g, G, args.serve_sub_qps, 1.0, args.serve_sub_s)
+    return dict(workload=f"serving: the n=1e7 graph; Poisson arrivals of mixed PPR/Katz/HK (kind uniform, half single "
+                         f"seeds, half 8-node seed sets, eps log-uniform [1e-7,1e-4]), {args.insert_k}-edge inserts "
+                         f"every 100 ms; 1 s warm-up + {args.serve_sub_s:g} s measured per rate",
+                stated_qps=stated["qps"] if stated else None,
+                stated_rule="highest swept rate with >= 99% of the offered queries completed",
+                latency_ms=dict(p50=stated["p50_ms"], p99=stated["p99_ms"]) if stated else None, sweep=results)
+
+
+def run_serve(args):
+    """Serving sweep as its own JSON line (--workload serve)."""
+    import torch
+
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
+    ctx = gde.Context(0)
+    n, E = (10_000_000, 200_000_000) if not args.small else (1_000_000, 10_000_000)
+    t0 = time.perf_counter()
+    G = W.chung_lu(n, E, 2.2, seed=42)
+    log(f"graph {G.summary()} built in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
+    stated, results = serve_sweep(args, ctx, g, G, args.qps, args.warm_s, args.serve_s)
+    head = stated or results[0]
+    out = dict(metric=METRIC, value=head["solves_per_s"], unit="solves/s", n_gpus=1, steps=len(results),
                warmup=0, ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic",
                config=dict(workload=f"serving: Chung-Lu n={n}, {E} edges, gamma 2.2; Poisson arrivals of mixed "
-                                    f"PPR/Katz/HK, {args.insert_k}-edge inserts every 100 ms",
-                           stated_qps=stated["qps"], serve_s=args.serve_s, warm_s=args.warm_s),
-               latency_ms=dict(p50=stated["p50_ms"], p99=stated["p99_ms"]), sweep=results)
+                                    f"PPR/Katz/HK (eps log-uniform [1e-7,1e-4] for every kind), {args.insert_k}-edge "
+                                    f"inserts every 100 ms",
+                           stated_qps=stated["qps"] if stated else None, serve_s=args.serve_s, warm_s=args.warm_s),
+               latency_ms=dict(p50=head["p50_ms"], p99=head["p99_ms"]), sweep=results)
     g.close()
     ctx.close()
     return out
@@ -487,10 +709,14 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "serve"])
-    ap.add_argument("--plain-sample", type=int, default=64, help="c4: plain solves timed for the comparison")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve"])
+    ap.add_argument("--plain-sample", type=int, default=1024,
+                    help="c4: plain solves timed for the comparison (1,024 = every query of the batch)")
+    ap.add_argument("--no-sub", action="store_true", help="c4: skip the serving and other-config sub-records")
+    ap.add_argument("--serve-sub-qps", type=float, nargs="+", default=[2000, 5000, 10000])
+    ap.add_argument("--serve-sub-s", type=float, default=4.0)
     ap.add_argument("--qps", type=float, nargs="+", default=[1000, 2000, 5000, 10000, 20000, 50000])
     ap.add_argument("--warm-s", type=float, default=2.0)
     ap.add_argument("--serve-s", type=float, default=10.0)
@@ -499,13 +725,14 @@ def main():
     ap.add_argument("--iters-per-step", type=int, default=4)
     ap.add_argument("--small", action="store_true", help="serve: the n=1e6 graph instead of n=1e7")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--phase", default="all", choices=["all", "plain", "batch"],
                     help="profiling aid: run only one path (the JSON line then covers that path only)")
     ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
-    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
-                    help="write the per-launch push traffic from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("TARGET", "FETCH_DIR", "WRITE_DIR"),
+                    help="TARGET plain|batch: write profiles/<target summary>.json, the per-launch traffic from "
+                         "two rocprofv3 --pmc runs, and exit")
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time the scatter launches of every k-th plain solve with HIP events")
     ap.add_argument("--copy-calib", action="store_true",

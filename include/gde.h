@@ -82,6 +82,18 @@ typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
  * Setting both is INVALID_ARG. */
 #define GDE_SCATTER_BINNED 0x8u     /* bin every iteration's scatter (no single-workgroup launches) */
 #define GDE_SCATTER_ATOMIC 0x10u    /* never bin: one atomic add per edge */
+/* Deterministic mode (for checking and A/B bisection, not speed).  The same
+ * iterations (Eq. (9); Sec. 3.3; the level push of Sec. 2) with every
+ * floating-point operation in a fixed order: at each node the updates of an
+ * iteration are added one after another in ascending order of the pushed node
+ * they come from, the node's own change at its place in that order -- a
+ * sequential reading of the iteration with S_t taken in ascending ids.  No
+ * floating-point atomics; residual norms are reduced in a fixed tree.  Two runs
+ * give bit-identical x, residual norms and traces; in FP64, x equals a
+ * sequential implementation of those steps bit for bit.  It overrides the
+ * scatter flags.  gde_solve_batch honours it by solving each query in this mode;
+ * the server rejects it (GDE_ERR_UNSUPPORTED). */
+#define GDE_DETERMINISTIC 0x20u
 
 typedef struct gde_ctx gde_ctx;
 typedef struct gde_graph gde_graph;
@@ -102,7 +114,7 @@ typedef struct gde_server gde_server;
  *   c                : reserved, must be NULL (coefficients follow from kind)
  *   max_iters        : iteration cap (>= 1); reaching it gives GDE_ERR_NOT_CONVERGED
  *   flags            : GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE |
- *                      GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC
+ *                      GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC | GDE_DETERMINISTIC
  */
 typedef struct gde_params {
     int32_t kind;
@@ -208,6 +220,11 @@ int gde_graph_lambda_max(gde_ctx *ctx, gde_graph *g, int max_iters, double rtol,
  *   batch_launches, batch_ms -- batched-solver kernel launches and their time
  *   batch_lane_edges    -- (edge, query) updates the batched kernel applied
  *   batch_entries       -- (group, node) work entries it processed
+ *   batch_push_launches, batch_push_ms -- the batched push (scatter) launches
+ *                          alone, each bracketed by its own event pair
+ *   batch_rows, batch_row_vol -- distinct CSR rows the batched rounds read (a
+ *                          row pushed by several queries in one round counts
+ *                          once) and their summed degree
  * reset != 0 clears the totals after reading.
  */
 typedef struct gde_kernel_profile {
@@ -219,6 +236,10 @@ typedef struct gde_kernel_profile {
     double batch_ms;
     int64_t batch_lane_edges;
     int64_t batch_entries;
+    int64_t batch_push_launches;
+    double batch_push_ms;
+    int64_t batch_rows;
+    int64_t batch_row_vol;
 } gde_kernel_profile;
 int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset);
 
@@ -273,7 +294,7 @@ typedef struct gde_completion {
 /* A continuous-batching server on a private dynamic copy of the graph.
  * PPR and Katz queries (LocalGD) advance in node-major lane groups on the
  * server's stream; heat-kernel queries are solved one each by the plain
- * level-push solver on five worker threads, each with its own context and
+ * level-push solver on three worker threads, each with its own context and
  * stream, and always on one graph version (a rebuild waits for running
  * solves).  The handle is used by one thread at a time. */
 int gde_server_create(gde_ctx *ctx, const gde_graph *g, const gde_server_cfg *cfg, gde_server **out);

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgde.so")
-SOURCES = ["gde_kernels.hip", "gde_hk_small.hip", "gde_api.hip", "gde_batch_kernels.hip", "gde_batch.hip",
-           "gde_server.hip"]
+SOURCES = ["gde_kernels.hip", "gde_hk_small.hip", "gde_api.hip", "gde_det.hip", "gde_batch_kernels.hip",
+           "gde_batch.hip", "gde_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "gde_batch.h"
+#include "gde_det.h"
 #include "gde_internal.h"
 #include "gde_kernels.h"
 
@@ -59,7 +60,8 @@ static int validate_params(const gde_params *p) {
     if (p->c != nullptr) return fail(GDE_ERR_INVALID_ARG, "params.c is reserved and must be NULL");
     if ((p->flags & GDE_SCATTER_BINNED) && (p->flags & GDE_SCATTER_ATOMIC))
         return fail(GDE_ERR_INVALID_ARG, "GDE_SCATTER_BINNED and GDE_SCATTER_ATOMIC exclude each other");
-    if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE | GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC))
+    if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE | GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC |
+                     GDE_DETERMINISTIC))
         return fail(GDE_ERR_INVALID_ARG, "unknown flag bits");
     switch (p->kind) {
     case GDE_PPR:
@@ -139,6 +141,7 @@ static void ws_free(Workspace *w) {
     if (w->hst) (void)hipHostFree(w->hst);
     if (w->h_seed_idx) (void)hipHostFree(w->h_seed_idx);
     if (w->h_seed_val) (void)hipHostFree(w->h_seed_val);
+    det_ws_free(w->det);
     delete w;
 }
 
@@ -391,7 +394,19 @@ int prof_mark_batch(gde_ctx *ctx, hipStream_t s) {
     return GDE_OK;
 }
 
-int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries) {
+// an event before or after one batched push launch
+int prof_mark_batch_push(gde_ctx *ctx, hipStream_t s) {
+    if (!ctx->prof_on) return GDE_OK;
+    if (ctx->ev_bp_used == ctx->ev_bp.size()) {
+        hipEvent_t e;
+        GDE_HIP(hipEventCreate(&e));
+        ctx->ev_bp.push_back(e);
+    }
+    GDE_HIP(hipEventRecord(ctx->ev_bp[ctx->ev_bp_used++], s));
+    return GDE_OK;
+}
+
+int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries, int64_t rows, int64_t row_vol) {
     if (!ctx->prof_on) return GDE_OK;
     if (ctx->ev_b_used == 2) {
         float ms = 0.f;
@@ -400,8 +415,17 @@ int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries) {
         ctx->prof_b_launches++;
         ctx->prof_b_lane_edges += lane_edges;
         ctx->prof_b_entries += entries;
+        ctx->prof_b_rows += rows;
+        ctx->prof_b_row_vol += row_vol;
+    }
+    for (size_t i = 0; i + 1 < ctx->ev_bp_used; i += 2) {
+        float ms = 0.f;
+        GDE_HIP(hipEventElapsedTime(&ms, ctx->ev_bp[i], ctx->ev_bp[i + 1]));
+        ctx->prof_bp_ms += ms;
+        ctx->prof_bp_launches++;
     }
     ctx->ev_b_used = 0;
+    ctx->ev_bp_used = 0;
     return GDE_OK;
 }
 
@@ -586,7 +610,10 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
 
     bool converged = false;
     int status = GDE_OK;
-    if (hk) {
+    if (p->flags & GDE_DETERMINISTIC) {
+        // fixed-order iterations (pull instead of scatter), any kind and method
+        if ((rc = det_run<V>(g, p, sd, w, pinl, d_trs, d_trv, d_trn, tr_cap, tr_ncap, s, &converged))) return rc;
+    } else if (hk) {
         // ------------------------------------------------ heat kernel, level by level
         const int K = p->K;
         const double tau = p->tau;
@@ -1017,12 +1044,18 @@ int gde_ctx_profile(gde_ctx *ctx, int enable, gde_kernel_profile *out, int reset
         out->batch_ms = ctx->prof_b_ms;
         out->batch_lane_edges = ctx->prof_b_lane_edges;
         out->batch_entries = ctx->prof_b_entries;
+        out->batch_push_launches = ctx->prof_bp_launches;
+        out->batch_push_ms = ctx->prof_bp_ms;
+        out->batch_rows = ctx->prof_b_rows;
+        out->batch_row_vol = ctx->prof_b_row_vol;
     }
     if (reset) {
         ctx->prof_launches = ctx->prof_edges = ctx->prof_entries = 0;
         ctx->prof_ms = 0.0;
         ctx->prof_b_launches = ctx->prof_b_lane_edges = ctx->prof_b_entries = 0;
         ctx->prof_b_ms = 0.0;
+        ctx->prof_bp_launches = ctx->prof_b_rows = ctx->prof_b_row_vol = 0;
+        ctx->prof_bp_ms = 0.0;
     }
     ctx->prof_on = enable != 0;
     ctx->ev_used = 0;

@@ -11,7 +11,8 @@ void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx);
 int prof_mark(gde_ctx *ctx, hipStream_t s);
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries);
 int prof_mark_batch(gde_ctx *ctx, hipStream_t s);
-int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries);
+int prof_mark_batch_push(gde_ctx *ctx, hipStream_t s);
+int prof_collect_batch(gde_ctx *ctx, int64_t lane_edges, int64_t entries, int64_t rows, int64_t row_vol);
 struct BatchWS;
 void batch_ws_extract_buffers(BatchWS *w, int32_t **cnt, long long **lane_nnz, long long **lane_off);
 void batch_ws_swap_list(BatchWS *w, int which, uint64_t **spare);

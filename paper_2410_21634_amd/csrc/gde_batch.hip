@@ -44,6 +44,8 @@ struct BatchWS {
     int64_t out_cap = 0;
     int nblk = 0;
     void **lane_dst = nullptr;  // [2 * Gcap * L]: per-lane output pointers (idx, then val) for device results
+    uint32_t *row_stamp = nullptr;  // [n], measurement only: distinct rows per round
+    uint32_t round = 0;
 };
 
 void batch_ws_free(BatchWS *w) {
@@ -51,7 +53,7 @@ void batch_ws_free(BatchWS *w) {
                  w->act[0], w->act[1], w->touched, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
-                 w->lane_dst};
+                 w->lane_dst, w->row_stamp};
     for (void *q : p)
         if (q) (void)hipFree(q);
     delete w;
@@ -372,6 +374,15 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     }
     a.st = w->st;
     a.max_iters = p[0].max_iters;
+    a.row_stamp = nullptr;
+    if (ctx->prof_on) {  // measurement: count the distinct rows each round reads
+        if (!w->row_stamp) {
+            GDE_HIP(hipMalloc((void **)&w->row_stamp, 4 * (size_t)g->n));
+            GDE_HIP(hipMemsetAsync(w->row_stamp, 0, 4 * (size_t)g->n, s));
+            w->round = 0;
+        }
+        a.row_stamp = w->row_stamp;
+    }
 
     GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns, ppr ? p[0].alpha : 1.0, s));
     int dev = 0;
@@ -390,8 +401,15 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     while (t < a.max_iters && !done) {
         int end = std::min(a.max_iters, t + chunk);
         for (; t < end; t++) {
+            if (a.row_stamp && ++w->round == 0u) {  // tags wrapped: start the stamps afresh
+                GDE_HIP(hipMemsetAsync(w->row_stamp, 0, 4 * (size_t)g->n, s));
+                w->round = 1u;
+            }
+            a.round_tag = w->round;
             GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
+            if ((rc = prof_mark_batch_push(ctx, s))) return rc;
             GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
+            if ((rc = prof_mark_batch_push(ctx, s))) return rc;
         }
         GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
@@ -474,7 +492,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     GDE_HIP(hipMemcpyAsync(unconv.data(), w->group_unconv, 4 * unconv.size(), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipStreamSynchronize(s));
-    if ((rc = prof_collect_batch(ctx, hst.lane_edges, hst.entries))) return rc;
+    if ((rc = prof_collect_batch(ctx, hst.lane_edges, hst.entries, hst.rows, hst.row_vol))) return rc;
     std::vector<unsigned long long> ncount(trace ? GL : 0);
     if (trace) {
         GDE_HIP(hipMemcpy(ncount.data(), a.tr_ncount, 8 * GL, hipMemcpyDeviceToHost));
@@ -558,10 +576,12 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
     }
     // the fused kernels need one kind (PPR or Katz), LocalGD, one value type and
     // shared kind parameters; anything else is solved query by query
-    bool fused = p[0].kind != GDE_HK && p[0].method == GDE_LOCAL_GD;
+    // (deterministic queries are solved one by one in the fixed-order mode)
+    bool fused = p[0].kind != GDE_HK && p[0].method == GDE_LOCAL_GD && !(p[0].flags & GDE_DETERMINISTIC);
     for (int32_t i = 1; i < B && fused; i++) {
         fused = p[i].kind == p[0].kind && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
                 p[i].alpha == p[0].alpha && p[i].beta == p[0].beta && p[i].max_iters == p[0].max_iters &&
+                !(p[i].flags & GDE_DETERMINISTIC) &&
                 (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
     }
     GDE_HIP(hipSetDevice(ctx->device));

@@ -22,6 +22,11 @@ struct BatchDev {
     int32_t pad0[2];
     long long lane_edges;          // sum over iterations of the lane-edges pushed
     long long entries;             // sum over iterations of the (group, node) entries
+    // measurement only (row_stamp set): distinct rows pushed in iteration of
+    // parity p, packed (rows << 40) | their volume, and the sums over iterations
+    unsigned long long rowpack[2];
+    long long rows;
+    long long row_vol;
 };
 
 // Everything a batch kernel needs.  Node-major layout: the L lanes of group g
@@ -74,6 +79,10 @@ struct BatchArgs {
     unsigned long long *tr_ncount;      // [G*L] entries recorded (may exceed the capacity)
     BatchDev *st;
     int32_t max_iters;
+    // measurement only: row_stamp[u] == round_tag once row u was counted in this
+    // iteration (distinct CSR rows read per round, whatever the groups); null = off
+    uint32_t *row_stamp;
+    uint32_t round_tag;
 };
 
 // which: 1 snap(t), 2 push(t)

@@ -61,6 +61,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     if (bid == 0 && threadIdx.x == 0) {
         st->packed[nxt] = 0ull;
         st->acount[nxt] = 0;
+        st->rowpack[nxt] = 0ull;
     }
     int32_t *ovf = &st->ovf[cur];
     if (nact > a.wl_cap) {  // one work-list entry per active pair: refuse rather than wrap
@@ -110,6 +111,11 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             if (c > 0) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
         }
         const bool leader = valid && l == 0 && c > 0;
+        if (a.row_stamp) {  // measurement: count each CSR row once per round (uniform branch)
+            bool fresh_row = false;
+            if (leader) fresh_row = atomicExch(&a.row_stamp[u], a.round_tag) != a.round_tag;
+            block_reserve64(fresh_row ? ((1ull << 40) | (unsigned long long)deg) : 0ull, &st->rowpack[cur]);
+        }
         const long long le = leader ? (long long)deg * c : 0ll;
         const unsigned long long res =
             block_reserve64(leader ? ((1ull << 40) | (unsigned long long)le) : 0ull, &st->packed[cur]);
@@ -174,6 +180,9 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     if (bid == 0 && threadIdx.x == 0 && count > 0) {
         st->lane_edges += total;
         st->entries += count;
+        const unsigned long long rp = st->rowpack[cur];
+        st->rows += (long long)(rp >> 40);
+        st->row_vol += (long long)(rp & kLaneEdgeMask);
     }
     const long long ntiles = min((total + kTile - 1) / kTile, (long long)a.tile_cap - 1);
     for (long long tile = bid; tile < ntiles; tile += nblocks) {

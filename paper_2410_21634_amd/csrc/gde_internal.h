@@ -97,6 +97,8 @@ struct DevState {
     int32_t fused_stamp;           // LocalCH: the range reduction took the snapshot of the iteration with this stamp
 };
 
+struct DetWS;  // buffers of the deterministic mode (gde_det.hip)
+
 // Solver workspace for one (graph, value type).  All node-indexed arrays are
 // dense over n; between solves every entry is back at its rest value (zero),
 // restored by the finalisation kernels, so a solve costs O(work), not O(n).
@@ -147,6 +149,7 @@ struct Workspace {
     int32_t *bin_cursor = nullptr; // device [nranges], zero between iterations
     void *bin_e = nullptr;         // device [nnz_cap] BinEnt<V> entries
     int64_t nnz_cap = 0;           // CSR entries the tile table and bins can hold
+    DetWS *det = nullptr;          // deterministic mode, lazily
 };
 
 struct BatchWS;
@@ -179,6 +182,11 @@ struct gde_ctx {
     std::vector<gde::BatchWS *> bws;  // batched-solver workspaces
     hipEvent_t ev_b[2] = {nullptr, nullptr};
     int ev_b_used = 0;
+    // batched push launches: event pairs of the current solve, and their totals
+    std::vector<hipEvent_t> ev_bp;
+    size_t ev_bp_used = 0;
+    int64_t prof_bp_launches = 0, prof_b_rows = 0, prof_b_row_vol = 0;
+    double prof_bp_ms = 0.0;
 };
 
 namespace gde {

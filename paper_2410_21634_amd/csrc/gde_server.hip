@@ -335,7 +335,9 @@ struct SGroup {
 // Heat-kernel queries are solved by the plain level-push solver on worker
 // threads, each with a private context (its own dense workspace) and stream,
 // so that several run at once beside the batched groups.
-constexpr int kHkWorkers = 5;
+// Three workers plus the engine stream keep the server within the four
+// hardware queues a process gets, so the engine never shares a queue.
+constexpr int kHkWorkers = 3;
 
 struct HkWorker {
     gde_ctx *ctx = nullptr;
@@ -504,7 +506,6 @@ static int srv_admit(gde_server *sv) {
         }
     }
     if (admitted.empty()) return GDE_OK;
-    BatchWS *w = sv->w;
     BatchArgs<float> a{};
     srv_args(sv, &a);
     // lane thresholds and per-lane statistics of the admitted groups
@@ -551,8 +552,10 @@ static int srv_admit(gde_server *sv) {
                            a.act_cap);
         GDE_HIP(hipGetLastError());
     }
-    // the seeds' pairs must also be known as touched (their residual is nonzero)
-    (void)w;
+    // The seeds' pairs are not put on the touched list here: every lane's first
+    // snapshot is forced (S_0 = supp(s)) and takes the whole seed residual, so a
+    // seed pair holds a nonzero residual later only if a push reaches it, and
+    // that push marks it as touched.
     return GDE_OK;
 }
 
@@ -1008,6 +1011,8 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     int rc = gde_validate_query(sv->g, p, s);
     if (rc) return rc;
     if (p->method != GDE_LOCAL_GD) return fail(GDE_ERR_UNSUPPORTED, "the server runs LocalGD");
+    if (p->flags & GDE_DETERMINISTIC)
+        return fail(GDE_ERR_UNSUPPORTED, "the deterministic mode is provided by gde_solve, not by the server");
     std::unique_lock<std::mutex> lk(sv->hk_mu);
     if (sv->n_pending + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
         return fail(GDE_ERR_BUSY, "server queue is full");

@@ -22,7 +22,7 @@ LOCAL_GD, LOCAL_CH = 0, 1
 F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
 KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
-SCATTER_BINNED, SCATTER_ATOMIC = 0x8, 0x10
+SCATTER_BINNED, SCATTER_ATOMIC, DETERMINISTIC = 0x8, 0x10, 0x20
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
 KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK}
@@ -68,7 +68,8 @@ class ServerCfg(C.Structure):
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("edges", C.c_int64), ("entries", C.c_int64),
                 ("batch_launches", C.c_int64), ("batch_ms", C.c_double), ("batch_lane_edges", C.c_int64),
-                ("batch_entries", C.c_int64)]
+                ("batch_entries", C.c_int64), ("batch_push_launches", C.c_int64), ("batch_push_ms", C.c_double),
+                ("batch_rows", C.c_int64), ("batch_row_vol", C.c_int64)]
 
 
 class Completion(C.Structure):

@@ -16,6 +16,7 @@ from oracle import solvers as O
 from paper_2410_21634_amd import gde
 
 TOL = {gde.F64: 1e-12, gde.F32: 1e-6}
+U32 = 2.0 ** -24  # unit roundoff of FP32
 RTOL = {gde.F64: 1e-10, gde.F32: 1e-5}
 KAPPA = {gde.F64: 1e-12, gde.F32: 1e-5}
 
@@ -78,3 +79,44 @@ def check(ctx, g, G, kind, method, vt, prm, seed_idx, seed_val=None, force_repla
         np.testing.assert_allclose(res.residual_l1, rp["residual_l1"], rtol=RTOL[vt] * 10, atol=1e-300)
         rep.update(mode="replay", flips=rp["flips"], l1_err_vs_replay=err_rp / s1)
     return rep
+
+
+def fp32_residual_bound(row_ptr, col_idx, kind, param, eps, x, T, events=0):
+    """Per-node bound on |r_w| (PPR in the reported scale r~ = r/alpha) that an
+    FP32 LocalGD result x after T iterations satisfies when its residual
+    r = b - Q x is recomputed in FP64 on the host.
+
+    Let v be the snapshot values the device actually pushed and x*, r* the exact
+    state they define (x* = sum of v, r* = b - Q x*).
+      * x: in LocalGD a node is pushed at most once per iteration, so the stored
+        x_u is an FP32 sum of at most T values: |x_u - x*_u| <= T u |x_u|
+        (first order, u = 2^-24).  r_host - r* = -Q (x - x*), so at w it is at
+        most T u (|x_w| + sum_{u ~ w} W_u |x_u|), W_u = (1-alpha)/d_u (PPR) or
+        beta (Katz).
+      * r: a push takes v_w = r_w exactly and sets r_w = 0, so only the FP32
+        additions into r_w after its last push are unaccounted for.  Their
+        terms are >= 0 and r_w never crossed theta_w again, so every partial
+        sum is < theta_w; at most d_w additions arrive per iteration:
+        |r_w - r*_w| <= u (d_w T + 1) theta_w (the 1 covers the rounded
+        products W_u v_u).
+      * The stop rule gives |r_w| < theta_w on the device.
+    Together: |r_host_w| < theta_w (1 + u (d_w T + 1)) + T u (|x_w| + sum W_u |x_u|).
+    An edge event (the insert corrections of Sec. 4) adds a few roundings of
+    the same size per node: `events` counts them into T.  The x term is doubled
+    to cover second-order terms and the FP64 recomputation itself.
+    """
+    from oracle import exact as X
+
+    d = np.diff(np.asarray(row_ptr)).astype(float)
+    A = X.sparse_adjacency(row_ptr, col_idx)
+    ax = np.abs(np.asarray(x, dtype=np.float64))
+    Te = T + events
+    if kind == gde.PPR:
+        alpha = param
+        inv = np.where(d > 0, 1.0 / np.maximum(d, 1), 0.0)
+        nb = (1.0 - alpha) * (A @ (inv * ax))
+        scale = 1.0 / alpha  # r -> r~
+    else:
+        nb = param * (A @ ax)
+        scale = 1.0
+    return eps * d * (1.0 + U32 * (d * Te + 1.0)) + 2.0 * Te * U32 * scale * (ax + nb)

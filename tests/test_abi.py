@@ -66,8 +66,10 @@ def test_validation_errors(small):
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
     p = gde.make_params(flags=gde.SCATTER_BINNED | gde.SCATTER_ATOMIC)  # exclusive strategies
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
-    for f in (gde.SCATTER_BINNED, gde.SCATTER_ATOMIC):
+    for f in (gde.SCATTER_BINNED, gde.SCATTER_ATOMIC, gde.DETERMINISTIC, gde.DETERMINISTIC | gde.TRACE):
         assert gde.validate(rp, ci, gde.make_params(flags=f), [0]) == gde.OK
+    p = gde.make_params(flags=gde.DETERMINISTIC << 1)  # the first undefined flag bit
+    assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
     # malformed CSR
     bad = rp.copy()
     bad[-1] += 1

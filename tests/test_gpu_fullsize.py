@@ -2,11 +2,13 @@
 times (sparse results left in device memory, FP32 values):
 
 * PPR LocalGD and LocalCH on the n = 10^6, 10^7-edge, gamma 2.5 graph, sampled
-  seeds at eps 1e-4 and 1e-6;
+  seeds at every eps of the benchmark mix (1e-4, 1e-5, 1e-6, 1e-7), including
+  FP32 frontiers large enough for the 4,096-edge tiles;
 * Katz (beta = 0.5 / lambda_lower) and the heat kernel (tau 5, K 30) on the
   n = 2.4 * 10^6, 6.2 * 10^7-edge, gamma 2.3 graph at eps 1e-6;
 * sampled lanes of the 1,024-query batch on the n = 10^7, 2 * 10^8-edge,
-  gamma 2.2 graph (degree-stratified seeds, eps log-uniform in [1e-7, 1e-4]).
+  gamma 2.2 graph (degree-stratified seeds, eps log-uniform in [1e-7, 1e-4]),
+  over the whole eps range, the smallest eps of the batch included.
 
 Every sampled result is checked against the FP64 oracle: free-run when the
 integer traces agree, else replay of the recorded active sets (band kappa).
@@ -95,12 +97,17 @@ def c2(gde, ctx, torch):
 
 @pytest.mark.parametrize("method", ["gd", "ch"])
 def test_c2_ppr_sampled(gde, ctx, torch, c2, method):
+    """Every eps of the benchmark mix, FP32, as timed; at 1e-7 the frontiers reach
+    the 4,096-edge tiles and the binned scatter (asserted)."""
     G, g = c2
     seeds = W.uniform_seeds(G, 64, seed=42)
     m = gde.LOCAL_GD if method == "gd" else gde.LOCAL_CH
-    for i, eps in ((0, 1e-4), (21, 1e-6), (42, 1e-4), (63, 1e-6)):
+    largest = 0
+    for i, eps in ((0, 1e-4), (10, 1e-5), (21, 1e-6), (31, 1e-7), (42, 1e-4), (52, 1e-5), (63, 1e-6), (7, 1e-7)):
         rep = check_device(gde, ctx, torch, g, G, gde.PPR, m, dict(alpha=0.1, eps=eps), [int(seeds[i])])
         print("c2", method, eps, int(seeds[i]), rep, flush=True)
+        largest = max(largest, rep["max_vol"])
+    assert largest >= 262144, largest  # the FP32 large-frontier tiles ran
 
 
 def test_c2_fp64_large_frontiers(gde, ctx, torch, c2):
@@ -143,8 +150,9 @@ def test_c3_katz_hk_sampled(gde, ctx, torch, c3):
 
 
 def test_c4_batch_sampled_lanes(gde, ctx, torch):
-    """The 1,024-query batch as timed; lanes sampled over the degree bins (eps >= 1e-6
-    so the oracle finishes each in seconds) are traced and graded."""
+    """The 1,024-query batch as timed; lanes sampled over the eps range (six with
+    eps >= 1e-6 spread over the degree bins, four below 1e-6 including the
+    smallest eps of the batch) are traced and graded."""
     G = W.chung_lu(10_000_000, 200_000_000, 2.2, seed=42)
     g, keep = device_graph(gde, ctx, torch, G)
     B = 1024
@@ -152,6 +160,9 @@ def test_c4_batch_sampled_lanes(gde, ctx, torch):
     eps = W.log_uniform_eps(B, 1e-7, 1e-4, seed=42)
     cand = [i for i in range(B) if eps[i] >= 1e-6]
     sample = set(cand[:: max(1, len(cand) // 6)][:6])
+    low = [i for i in range(B) if eps[i] < 1e-6]
+    sample |= {int(np.argmin(eps))} | set(low[:: max(1, len(low) // 3)][:3])
+    assert sum(eps[i] < 1e-6 for i in sample) >= 3
     params = [gde.make_params("ppr", alpha=0.1, eps=float(e), value_type=gde.F32,
                               flags=gde.TRACE if i in sample else 0) for i, e in enumerate(eps)]
     cap = 2_000_000
