@@ -13,7 +13,7 @@ from oracle import exact as X  # noqa: E402
 from oracle import solvers as O  # noqa: E402
 from paper_2410_21634_amd import workloads as W  # noqa: E402
 
-from _parity import KAPPA, oracle_replay  # noqa: E402
+from _parity import KAPPA, mass, oracle_replay  # noqa: E402
 
 TOL = {1: 1e-12, 0: 1e-6}
 
@@ -77,14 +77,14 @@ def run_and_check(gde, ctx, g, G, queries, kind, vt, schedule, param, lam=0.0):
         if vt == 1:
             assert same, (eps, r.iters, ref["iters"])
         if same:
-            err = np.abs(r.dense(G.n) - ref["x"]).sum() / val.sum()
+            err = np.abs(r.dense(G.n) - ref["x"]).sum() / mass(kind, val, ref["x"])
             np.testing.assert_allclose(r.residual_l1, ref["residual_l1"], rtol=1e-5 if vt == 0 else 1e-10)
             np.testing.assert_allclose(r.residual_dinf, ref["residual_dinf"], rtol=1e-5 if vt == 0 else 1e-10)
         else:
             rp = oracle_replay(G, kind, gde.LOCAL_GD, dict(prm, eps=eps), idx, val, r.trace_size, r.trace_nodes,
                                KAPPA[vt])
             assert rp["violations"] == 0, rp
-            err = np.abs(r.dense(G.n) - rp["x"]).sum() / val.sum()
+            err = np.abs(r.dense(G.n) - rp["x"]).sum() / mass(kind, val, rp["x"])
             replays += 1
         assert err <= TOL[vt], (eps, err, same)
         worst = max(worst, err)

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 from oracle import exact as X  # noqa: E402
 from paper_2410_21634_amd import workloads as W  # noqa: E402
 
-from _parity import KAPPA, RTOL, TOL, oracle_replay, oracle_run  # noqa: E402
+from _parity import KAPPA, RTOL, TOL, mass, oracle_replay, oracle_run  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -55,7 +55,6 @@ def check_device(gde, ctx, torch, g, G, kind, method, prm, seed_idx, seed_val=No
     graded as in the small tests."""
     seed_idx = np.atleast_1d(np.asarray(seed_idx, dtype=np.int32))
     seed_val = np.ones(len(seed_idx)) if seed_val is None else np.asarray(seed_val, dtype=np.float64)
-    s1 = float(seed_val.sum())
     vt = gde.F32 if vt is None else vt
     p = gde.make_params(kind, method, value_type=vt, flags=gde.TRACE, **prm)
     dev = torch.device("cuda:0")
@@ -67,6 +66,7 @@ def check_device(gde, ctx, torch, g, G, kind, method, prm, seed_idx, seed_val=No
     assert np.all(np.diff(idx) > 0)
     x_gpu = res.dense(G.n)
     ref = oracle_run(G, kind, method, prm, seed_idx, seed_val)
+    s1 = mass(kind, seed_val, ref["x"])
     same = (res.iters == ref["iters"] and res.ops == ref["ops"] and res.pushes == ref["pushes"]
             and np.array_equal(res.trace_size, ref["trace_size"]) and np.array_equal(res.trace_vol, ref["trace_vol"]))
     rep = dict(iters=res.iters, ops=res.ops, trace_equal=same, nnz=len(idx),

@@ -20,7 +20,7 @@ from oracle import exact as X  # noqa: E402
 from oracle import solvers as O  # noqa: E402
 from paper_2410_21634_amd import workloads as W  # noqa: E402
 
-from _parity import TOL, fp32_residual_bound  # noqa: E402
+from _parity import TOL, fp32_residual_bound, mass  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -154,7 +154,7 @@ def test_server_static_mix(gde, ctx):
             ref = O.localgd(G.row_ptr, G.col_idx, O.KATZ, beta, eps, idx, val)["x"]
         else:
             ref = O.hk(G.row_ptr, G.col_idx, 5.0, 30, eps, idx, val)["x"]
-        s1 = val.sum()
+        s1 = mass({"ppr": gde.PPR, "katz": gde.KATZ, "hk": gde.HK}[kind], val, ref)
         d_mix_alone = np.abs(xm - xa).sum() / s1
         d_oracle = np.abs(xm - ref).sum() / s1
         if kind == "ppr" and (d_mix_alone > 1e-6 or d_oracle > 1e-6):
