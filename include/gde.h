@@ -37,6 +37,7 @@
 #ifndef GDE_H
 #define GDE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include <hip/hip_runtime_api.h>
@@ -250,6 +251,36 @@ int gde_validate(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *
 /* One query (Definition 3.1 with the method of p).  See gde_result. */
 int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
               hipStream_t stream);
+
+/*
+ * gde_solve without any allocation, for callers that cannot allocate device
+ * or pinned host memory during a call (serving loops or harnesses that forbid
+ * it, code run between stream captures).  It runs the iterations of gde_solve
+ * (small frontiers in one workgroup, larger ones with one atomic add per edge;
+ * never the binned scatter) on a workspace carved from one fixed device array
+ * of GDE_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends; no hipMalloc, hipFree or allocating library call
+ * is made.  The device counters are read back with stream synchronisations.
+ *   g      : a graph from gde_graph_create (its CSR is read; its host degree
+ *            copy validates the seed)
+ *   p      : as gde_solve, with GDE_RESULT_DEVICE required (res idx / val are
+ *            device pointers); GDE_TRACE, GDE_DETERMINISTIC and
+ *            GDE_SCATTER_BINNED give GDE_ERR_UNSUPPORTED
+ *   s      : host seed, at most 4096 entries (else GDE_ERR_INVALID_ARG)
+ *   res    : as gde_solve
+ * A graph and query whose workspace (gde_solve_noalloc_bytes) exceeds the
+ * array give GDE_ERR_OOM before any device work: at 64 MiB that is about
+ * 1.2 M nodes for FP32 PPR/Katz LocalGD, 0.5 M nodes for FP64 heat kernel.
+ * Each call clears the part of the array it uses and rebuilds the degree
+ * planes from g (O(n) device work), so calls may alternate graphs.  All calls
+ * on one device share the array: calls that overlap in time on one GPU (from
+ * two threads or on two streams) race and give undefined results.
+ */
+#define GDE_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
+int gde_solve_noalloc(const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
+                      hipStream_t stream);
+/* Bytes of the fixed array gde_solve_noalloc would use for (g, p, s); 0 on a null argument. */
+size_t gde_solve_noalloc_bytes(const gde_graph *g, const gde_params *p, const gde_seed *s);
 
 /*
  * B independent queries on one graph solved together, every iteration of all

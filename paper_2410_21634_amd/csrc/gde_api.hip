@@ -360,7 +360,7 @@ void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
 
 // ------------------------------------------------------------------ kernel timing
 int prof_mark(gde_ctx *ctx, hipStream_t s) {
-    if (!ctx->prof_on) return GDE_OK;
+    if (!ctx || !ctx->prof_on) return GDE_OK;
     if (ctx->ev_used == ctx->ev.size()) {
         hipEvent_t e;
         GDE_HIP(hipEventCreate(&e));
@@ -372,7 +372,7 @@ int prof_mark(gde_ctx *ctx, hipStream_t s) {
 
 // after the stream has been synchronised: fold the recorded pairs into the totals
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries) {
-    if (!ctx->prof_on) return GDE_OK;
+    if (!ctx || !ctx->prof_on) return GDE_OK;
     for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
         float ms = 0.f;
         GDE_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
@@ -512,6 +512,11 @@ static int snap_grid(const gde_graph *g) {
 // a longer wait, or a stream that failed, falls back to the blocking wait.
 static int sync_state(Workspace *w, hipStream_t s) {
     constexpr double kSpinSeconds = 2e-3;
+    if (!w->hst_dev) {  // no host-coherent mirror: copy the state and wait for the stream
+        GDE_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        return GDE_OK;
+    }
     const uint32_t want = ++w->seq;
     launch_publish(w->st, w->hst_dev, w->hseq_dev, want, s);
     GDE_HIP(hipGetLastError());
@@ -528,12 +533,14 @@ static int sync_state(Workspace *w, hipStream_t s) {
     return GDE_OK;
 }
 
+// One plain solve on the workspace w.  ctx may be null (no kernel timing); a
+// workspace whose buffers are all present (a view onto fixed device memory)
+// makes the ws_ensure_* calls no-ops, and one without pinned mirrors reads the
+// device state with a copy and a stream synchronisation.
 template <typename V>
-static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
-                       hipStream_t s) {
-    Workspace *w = nullptr;
-    int rc = get_workspace(ctx, g, p->value_type, s, &w);
-    if (rc) return rc;
+int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
+                   Workspace *w, hipStream_t s) {
+    int rc = GDE_OK;
     const bool hk = p->kind == GDE_HK;
     const bool ch = p->method == GDE_LOCAL_CH;
     if (hk && (rc = ws_ensure_hk(w, g, s))) return rc;
@@ -562,11 +569,14 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
             inl.val[i] = sd->val[i];
         }
         pinl = &inl;
-    } else {
+    } else if (w->h_seed_idx) {
         std::memcpy(w->h_seed_idx, sd->idx, 4 * (size_t)sd->nnz);
         std::memcpy(w->h_seed_val, sd->val, 8 * (size_t)sd->nnz);
         GDE_HIP(hipMemcpyAsync(w->seed_idx, w->h_seed_idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
         GDE_HIP(hipMemcpyAsync(w->seed_val, w->h_seed_val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+    } else {  // no pinned staging: copy from the caller's arrays (the runtime stages pageable memory)
+        GDE_HIP(hipMemcpyAsync(w->seed_idx, sd->idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->seed_val, sd->val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
     }
 
     const int pgrid = push_grid(g), sgrid = snap_grid(g);
@@ -988,6 +998,20 @@ static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, co
     res->status = status;
     if (status == GDE_ERR_NOT_CONVERGED) return fail(status, "max_iters reached before S_t became empty");
     return GDE_OK;
+}
+
+template int solve_plain_ws<float>(gde_ctx *, const gde_graph *, const gde_params *, const gde_seed *, gde_result *,
+                                   Workspace *, hipStream_t);
+template int solve_plain_ws<double>(gde_ctx *, const gde_graph *, const gde_params *, const gde_seed *, gde_result *,
+                                    Workspace *, hipStream_t);
+
+template <typename V>
+static int solve_plain(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
+                       hipStream_t s) {
+    Workspace *w = nullptr;
+    int rc = get_workspace(ctx, g, p->value_type, s, &w);
+    if (rc) return rc;
+    return solve_plain_ws<V>(ctx, g, p, sd, res, w, s);
 }
 
 }  // namespace gde

@@ -23,6 +23,7 @@ F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
 KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
 SCATTER_BINNED, SCATTER_ATOMIC, DETERMINISTIC = 0x8, 0x10, 0x20
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # GDE_NOALLOC_SCRATCH_BYTES of gde.h
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
 KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK}
@@ -92,6 +93,8 @@ _SIGS = {
     "gde_validate": ([_i32, _i64, _vp, _vp, C.POINTER(Params), C.POINTER(Seed)], C.c_int),
     "gde_ctx_profile": ([_vp, C.c_int, C.POINTER(KernelProfile), C.c_int], C.c_int),
     "gde_solve": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
+    "gde_solve_noalloc": ([_vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
+    "gde_solve_noalloc_bytes": ([_vp, C.POINTER(Params), C.POINTER(Seed)], C.c_size_t),
     "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
                         C.c_int),
     "gde_server_create": ([_vp, _vp, C.POINTER(ServerCfg), C.POINTER(_vp)], C.c_int),
@@ -310,6 +313,31 @@ def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *
         if nodes_cap:
             res.trace_nodes = keep[2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
     return res
+
+
+def solve_noalloc(graph: Graph, params: Params, seed_idx, seed_val=None, *, out, capacity=None, stream=None,
+                  raise_on_error=True) -> SolveResult:
+    """gde_solve_noalloc: one query on the library's fixed device array (no
+    allocation in the call).  ``out`` = (idx, val) torch device tensors."""
+    sh = _SeedHolder(seed_idx, seed_val)
+    p = Params.from_buffer_copy(params)
+    p.flags |= RESULT_DEVICE
+    oi, ov = out
+    cap = oi.numel() if capacity is None else capacity
+    r, _ = _result_struct(p, cap, oi.data_ptr(), ov.data_ptr(), 0, 0)
+    rc = _lib.gde_solve_noalloc(graph.handle, C.byref(p), C.byref(sh.seed), C.byref(r), _stream_ptr(stream))
+    if raise_on_error:
+        _check(rc, (OK, NOT_CONVERGED))
+    nnz = int(r.nnz) if rc in (OK, NOT_CONVERGED) else 0
+    res = SolveResult(oi[:nnz], ov[:nnz], rc, r.residual_l1, r.residual_dinf, r.iters, r.ops, r.pushes)
+    res.extra["nnz_needed"] = int(r.nnz)
+    return res
+
+
+def noalloc_bytes(graph: Graph, params: Params, seed_idx, seed_val=None) -> int:
+    """Bytes of the fixed array gde_solve_noalloc would use for this query."""
+    sh = _SeedHolder(seed_idx, seed_val)
+    return int(_lib.gde_solve_noalloc_bytes(graph.handle, C.byref(params), C.byref(sh.seed)))
 
 
 def _np_dtype(struct):
