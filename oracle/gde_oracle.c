@@ -394,6 +394,88 @@ int oracle_localgd_warm(int64_t n, const int64_t *rp, const int32_t *ci, int kin
 }
 
 /*
+ * The standard (global) counterparts of LocalGD and LocalCH that Table 2 and the
+ * eps sweep of Sec. 5 compare against: the same updates with S_t = V, the whole
+ * node set, in every iteration.
+ *
+ *   GD : h = r                                  (Richardson / gradient step)
+ *   CH : t = 0 h = r ; t >= 1 h = c_t r + m_t Delta  (Chebyshev, Sec. 3.3, with
+ *        the coefficients of run_gd_ch above and Delta = the previous h)
+ *   x <- x + h ,  r <- r - Q h   over all nodes
+ *
+ * The first iteration always runs (the forced S_0 of Definition 3.1); after it
+ * the solver stops as soon as no node satisfies |r_u| >= theta_u (r_u != 0),
+ * the stop rule of the local solvers.  Every iteration costs vol(V) = nnz edge
+ * operations and |V| = n node updates (stats[1], stats[2]).
+ * method: 0 = GD, 1 = CH.  x, r: dense outputs (r in the generic form).
+ */
+int oracle_global(int64_t n, const int64_t *rp, const int32_t *ci, int method, int kind, double param,
+                  double lam, double eps, int32_t seed_nnz, const int32_t *seed_idx, const double *seed_val,
+                  int32_t max_iters, double *x, double *r, int64_t *stats, double *norms) {
+    graph_t g = {n, rp, ci};
+    form_t f;
+    if (make_form(kind, param, eps, &f)) return OR_INVALID;
+    if (method == 1 && kind == KIND_KATZ && !(param * lam > 0.0 && param * lam < 1.0)) return OR_INVALID;
+    int rc = check_seed(&g, seed_nnz, seed_idx, seed_val);
+    if (rc) return rc;
+    double *h = (double *)malloc(sizeof(double) * (size_t)n);
+    double *rn = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!h || !rn) { free(h); free(rn); return OR_OOM; }
+    memset(x, 0, sizeof(double) * (size_t)n);
+    memset(r, 0, sizeof(double) * (size_t)n);
+    memset(h, 0, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < seed_nnz; i++) r[seed_idx[i]] = form_b(&f, seed_val[i]);
+    double sigma = 1.0, dlt = 0.0;
+    if (method == 1) {
+        double mu, L;
+        if (kind == KIND_PPR) { mu = param; L = 2.0 - param; }
+        else { mu = 1.0 - param * lam; L = 1.0 + param * lam; }
+        sigma = (L + mu) / (L - mu);
+        dlt = 1.0 / sigma;
+    }
+    int64_t T = 0, nnz = rp[n];
+    int status = OR_NOT_CONVERGED;
+    for (int64_t t = 0;; t++) {
+        if (t > 0) {
+            int any = 0;
+            for (int64_t u = 0; u < n && !any; u++) any = is_active(r[u], form_theta(&f, &g, u));
+            if (!any) { status = OR_OK; break; }
+        }
+        if (t >= max_iters) break;
+        if (method == 0 || t == 0) {
+            for (int64_t u = 0; u < n; u++) h[u] = r[u];
+        } else {
+            double dnext = 1.0 / (2.0 * sigma - dlt);
+            double c = 2.0 * sigma * dnext, m = dlt * dnext;
+            for (int64_t u = 0; u < n; u++) h[u] = c * r[u] + m * h[u]; /* h still holds Delta */
+            dlt = dnext;
+        }
+        /* r_new = r - Q h : r_new_w = r_w - h_w + sum_{u ~ w} w_u h_u */
+        for (int64_t w = 0; w < n; w++) {
+            double acc = r[w] - h[w];
+            for (int64_t e = rp[w]; e < rp[w + 1]; e++) {
+                int64_t u = ci[e];
+                acc += form_w(&f, &g, u) * h[u];
+            }
+            rn[w] = acc;
+        }
+        for (int64_t u = 0; u < n; u++) { x[u] += h[u]; r[u] = rn[u]; }
+        T++;
+    }
+    stats[0] = T; stats[1] = T * nnz; stats[2] = T * n; stats[3] = status;
+    double a = 0.0, mx = 0.0, sc = form_rscale(&f);
+    for (int64_t u = 0; u < n; u++) {
+        double v = fabs(r[u]) * sc, d = deg(&g, u);
+        a += v;
+        if (d > 0 && v / d > mx) mx = v / d;
+    }
+    norms[0] = a;
+    norms[1] = mx;
+    free(h); free(rn);
+    return status;
+}
+
+/*
  * Edge events on (x, r) in the generic form r = b - Q x (Sec. 4, the Insert and
  * Delete procedures of LocalGS(Dynamic) / LocalSOR(Dynamic)).  Each undirected
  * edge {a, c} is applied as the directed event a -> c and then c -> a; deg is the

@@ -55,8 +55,10 @@ def _load():
                                       vp, i64, vp, vp, i64, vp, vp, d, vp]
             lib.oracle_localgd_warm.argtypes = [i64, _p64, _p32, C.c_int, d, d, i32, _pf, _pf, _p64, _pf]
             lib.oracle_edge_events.argtypes = [i64, C.c_int, d, _pf, _pf, _p64, i64, _p32, _p32, C.c_int]
+            lib.oracle_global.argtypes = [i64, _p64, _p32, C.c_int, C.c_int, d, d, d, i32, _p32, _pf, i32, _pf,
+                                          _pf, _p64, _pf]
             for f in (lib.oracle_localgd, lib.oracle_localch, lib.oracle_replay_gd_ch, lib.oracle_push_fifo,
-                      lib.oracle_hk, lib.oracle_localgd_warm, lib.oracle_edge_events):
+                      lib.oracle_hk, lib.oracle_localgd_warm, lib.oracle_edge_events, lib.oracle_global):
                 f.restype = C.c_int
             _lib = lib
     return _lib
@@ -241,3 +243,18 @@ def edge_events(kind, param, x, r, deg, u, v, sign):
     if rc != OK:
         raise ValueError(f"oracle rejected the edge events (status {rc})")
     return x, r, deg
+
+
+def global_gd_ch(row_ptr, col_idx, method, kind, param, eps, seed_idx, seed_val=None, lam=0.0, max_iters=100000):
+    """The standard counterparts of LocalGD / LocalCH (method 0 / 1): the same
+    update with S_t = V in every iteration, until no node is active (Table 2,
+    the eps sweep of Sec. 5).  ops = T * nnz, pushes = T * n."""
+    lib = _load()
+    n, rp, ci = _graph(row_ptr, col_idx)
+    k, idx, val = _seed(seed_idx, seed_val)
+    x, r = np.zeros(n), np.zeros(n)
+    stats, norms = np.zeros(4, np.int64), np.zeros(2)
+    rc = lib.oracle_global(n, rp, ci, method, kind, param, lam, eps, k, idx, val, max_iters, x, r, stats, norms)
+    _check(rc)
+    return dict(x=x, r=r, status=rc, iters=int(stats[0]), ops=int(stats[1]), pushes=int(stats[2]),
+                residual_l1=norms[0], residual_dinf=norms[1])
