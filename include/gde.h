@@ -253,6 +253,22 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
               hipStream_t stream);
 
 /*
+ * The standard (global) counterparts of LocalGD and LocalCH that Table 2 and
+ * the eps sweep of Sec. 5 compare the local solvers against: the same update
+ * with S_t = V, every node, in every iteration -- GD (h = r) or Chebyshev
+ * (p->method = GDE_LOCAL_CH: the Sec. 3.3 recurrence over all nodes) -- until
+ * no node has |r_u| >= theta_u (the first iteration always runs).  Each
+ * iteration is one pass over the whole CSR (a sparse matrix-vector product), so
+ * res.ops = T * nnz and res.pushes = T * n.  PPR and Katz only (the heat
+ * kernel gives GDE_ERR_UNSUPPORTED).  Arguments, result layout, flags
+ * (GDE_RESULT_DEVICE, GDE_TRACE: |S_t| = n, vol(S_t) = nnz) and errors as
+ * gde_solve; every sum runs in a fixed order, so results are bit-identical
+ * from run to run (GDE_DETERMINISTIC changes nothing here).
+ */
+int gde_solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
+                     hipStream_t stream);
+
+/*
  * gde_solve without any allocation, for callers that cannot allocate device
  * or pinned host memory during a call (serving loops or harnesses that forbid
  * it, code run between stream captures).  It runs the iterations of gde_solve

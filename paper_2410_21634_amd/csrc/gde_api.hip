@@ -14,6 +14,7 @@
 
 #include "gde_batch.h"
 #include "gde_det.h"
+#include "gde_global.h"
 #include "gde_internal.h"
 #include "gde_kernels.h"
 
@@ -142,6 +143,7 @@ static void ws_free(Workspace *w) {
     if (w->h_seed_idx) (void)hipHostFree(w->h_seed_idx);
     if (w->h_seed_val) (void)hipHostFree(w->h_seed_val);
     det_ws_free(w->det);
+    glob_ws_free(w->glob);
     delete w;
 }
 
@@ -1239,6 +1241,24 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
     GDE_HIP(hipSetDevice(ctx->device));
     if (p->value_type == GDE_F64) return solve_plain<double>(ctx, g, p, s, res, stream);
     return solve_plain<float>(ctx, g, p, s, res, stream);
+}
+
+int gde_solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *s, gde_result *res,
+                     hipStream_t stream) {
+    if (!ctx || !g || !res) return fail(GDE_ERR_INVALID_ARG, "null ctx, graph or result");
+    int rc = validate_params(p);
+    if (rc) { res->status = rc; return rc; }
+    if (p->kind == GDE_HK) {
+        res->status = GDE_ERR_UNSUPPORTED;
+        return fail(GDE_ERR_UNSUPPORTED, "the global solvers cover PPR and Katz");
+    }
+    GraphHost *gh = graph_host(g);
+    if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");
+    if ((rc = validate_seed_deg(s, g->n, gh->deg))) { res->status = rc; return rc; }
+    if (res->capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
+    if (g->device != ctx->device) return fail(GDE_ERR_INVALID_ARG, "graph and context on different devices");
+    GDE_HIP(hipSetDevice(ctx->device));
+    return solve_global(ctx, g, p, s, res, stream);
 }
 
 }  // extern "C"

@@ -97,7 +97,8 @@ struct DevState {
     int32_t fused_stamp;           // LocalCH: the range reduction took the snapshot of the iteration with this stamp
 };
 
-struct DetWS;  // buffers of the deterministic mode (gde_det.hip)
+struct DetWS;   // buffers of the deterministic mode (gde_det.hip)
+struct GlobWS;  // buffers of the global solvers (gde_global.hip)
 
 // Solver workspace for one (graph, value type).  All node-indexed arrays are
 // dense over n; between solves every entry is back at its rest value (zero),
@@ -150,6 +151,7 @@ struct Workspace {
     void *bin_e = nullptr;         // device [nnz_cap] BinEnt<V> entries
     int64_t nnz_cap = 0;           // CSR entries the tile table and bins can hold
     DetWS *det = nullptr;          // deterministic mode, lazily
+    GlobWS *glob = nullptr;        // global solvers, lazily
 };
 
 struct BatchWS;

@@ -93,6 +93,7 @@ _SIGS = {
     "gde_validate": ([_i32, _i64, _vp, _vp, C.POINTER(Params), C.POINTER(Seed)], C.c_int),
     "gde_ctx_profile": ([_vp, C.c_int, C.POINTER(KernelProfile), C.c_int], C.c_int),
     "gde_solve": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
+    "gde_solve_global": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
     "gde_solve_noalloc": ([_vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
     "gde_solve_noalloc_bytes": ([_vp, C.POINTER(Params), C.POINTER(Seed)], C.c_size_t),
     "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
@@ -284,7 +285,7 @@ def _result_struct(params, capacity, out_idx, out_val, trace_cap, nodes_cap):
 
 
 def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *, capacity=None, out=None,
-          trace_cap=4096, nodes_cap=0, stream=None, raise_on_error=True) -> SolveResult:
+          trace_cap=4096, nodes_cap=0, stream=None, raise_on_error=True, _entry="gde_solve") -> SolveResult:
     """One query.  ``out``: optional (idx, val) torch device tensors (the result
     stays in HBM, GDE_RESULT_DEVICE); otherwise numpy host arrays are returned."""
     sh = _SeedHolder(seed_idx, seed_val)
@@ -300,7 +301,8 @@ def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *
         oi = np.zeros(max(cap, 1), np.int32)
         ov = np.zeros(max(cap, 1), vdt)
         r, keep = _result_struct(p, cap, oi.ctypes.data, ov.ctypes.data, trace_cap, nodes_cap)
-    rc = _lib.gde_solve(ctx.handle, graph.handle, C.byref(p), C.byref(sh.seed), C.byref(r), _stream_ptr(stream))
+    rc = getattr(_lib, _entry)(ctx.handle, graph.handle, C.byref(p), C.byref(sh.seed), C.byref(r),
+                               _stream_ptr(stream))
     if raise_on_error:
         _check(rc, (OK, NOT_CONVERGED))
     nnz = int(r.nnz) if rc in (OK, NOT_CONVERGED) else 0
@@ -313,6 +315,12 @@ def solve(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, *
         if nodes_cap:
             res.trace_nodes = keep[2][: min(int(r.trace_nodes_len), nodes_cap)].copy()
     return res
+
+
+def solve_global(ctx: Context, graph: Graph, params: Params, seed_idx, seed_val=None, **kw) -> SolveResult:
+    """gde_solve_global: GD or Chebyshev (params.method) over all nodes in every
+    iteration; same arguments and result as ``solve``."""
+    return solve(ctx, graph, params, seed_idx, seed_val, _entry="gde_solve_global", **kw)
 
 
 def solve_noalloc(graph: Graph, params: Params, seed_idx, seed_val=None, *, out, capacity=None, stream=None,
