@@ -473,12 +473,14 @@ def run_c4(args):
                           batched_speedup=round(value / plain_rate, 2)))
     if not args.no_sub:
         out["serving"] = run_serve_sub(args, ctx, g, G)
+        out["global_gd"] = sub_global_roofline(ctx, g, G, seeds, dev)
     g.close()
     ctx.close()
     del rp, ci, bout
     torch.cuda.empty_cache()
     if not args.no_sub:
-        out["sub"] = dict(c2_plain=sub_c2(args), c1_latency=sub_c1(), c3_katz_hk=sub_c3())
+        out["sub"] = dict(c2_plain=sub_c2(args), c1_latency=sub_c1(), c3_katz_hk=sub_c3(),
+                          global_vs_local=sub_global_vs_local())
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline_c4(G, seeds, eps, budget_s=args.cpu_budget)
@@ -566,6 +568,116 @@ def sub_c3():
         out[name] = dict(solves_per_s=round(len(seeds) / t, 2), mean_ops=round(ops / len(seeds), 1))
     g.close()
     ctx.close()
+    return out
+
+
+def glob_bytes_per_iter(n, nnz, vsize):
+    """Algorithmic bytes of one global iteration (one pull over the whole CSR):
+    col_idx 4 B per entry, row pointers 4 B per node, and per node x, r, h
+    read-modify-write plus one write and one read of its scatter value z."""
+    return 4 * nnz + 4 * (n + 1) + 8 * vsize * n
+
+
+def sub_global_roofline(ctx, g, G, seeds, dev):
+    """Global GD (every node, every iteration) on the benchmark graph in FP32 at
+    eps 1e-7 from four of the batch's seeds: time per iteration of the pull
+    kernel and its achieved algorithmic bandwidth."""
+    import torch
+
+    from paper_2410_21634_amd import gde
+
+    oi = torch.empty(G.n, dtype=torch.int32, device=dev)
+    ov = torch.empty(G.n, dtype=torch.float32, device=dev)
+    p = gde.make_params("ppr", "gd", alpha=0.1, eps=1e-7, value_type=gde.F32)
+    gde.solve_global(ctx, g, p, [int(seeds[0])], out=(oi, ov))
+    torch.cuda.synchronize()
+    ctx.profile(True, reset=True)
+    iters = 0
+    t = time.perf_counter()
+    for s in seeds[::256][:4]:
+        r = gde.solve_global(ctx, g, p, [int(s)], out=(oi, ov))
+        iters += r.iters
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    prof = ctx.profile(False, reset=True)
+    it_ms = prof["total_ms"] / max(iters, 1)
+    bpi = glob_bytes_per_iter(G.n, G.nnz, 4)
+    ach = bpi / (it_ms * 1e-3) / 1e9 if it_ms > 0 else 0.0
+    return dict(kernel="k_glob_step<float> (one pull over the whole CSR per iteration)", solves=4, iters=iters,
+                us_per_iter=round(it_ms * 1e3, 2), alg_bytes_per_iter=bpi, achieved_gbs=round(ach, 1),
+                frac=round(ach / PEAK_HBM_GBS, 4), ms_per_solve=round(1e3 * wall / 4, 3),
+                timing="HIP events around each chunk of iteration launches (no-op launches after the stop "
+                       "included), divided by the iterations that ran",
+                byte_rule="4 B per CSR entry + 4 B per row pointer + 32 B per node (x, r, h read and written, "
+                          "z written and read)")
+
+
+def sub_global_vs_local(budget_s=90.0):
+    """Local vs global solvers (the Table 2 and eps-sweep comparisons of Sec. 5)
+    on the n = 10^6 power-law graph and the 1000 x 1000 grid, PPR alpha 0.1, FP64,
+    8 uniform sources per graph: operations (sum vol(S_t) vs T * nnz) and median
+    wall time per solve for LocalGD vs GD over eps = 2^-17 ... 2^-32, and the
+    operation ratios GD/LocalGD and CH/LocalCH at eps = 1/n."""
+    import torch
+
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    out = dict(workload="PPR alpha 0.1, FP64, 8 uniform sources per graph; graphs: Chung-Lu n=1e6, 1e7 edges, "
+                        "gamma 2.5, seed 42, and the 1000x1000 4-neighbour grid (1,998,000 edges)",
+               eps_sweep=[2.0 ** -k for k in (17, 20, 23, 26, 29, 32)])
+    t_all = time.perf_counter()
+    for gname, G in (("chung_lu_n1M", W.chung_lu(1_000_000, 10_000_000, 2.5, seed=42)),
+                     ("grid_1000x1000", W.grid_2d(1000, 1000))):
+        ctx = gde.Context(0)
+        rp = torch.from_numpy(G.row_ptr).to(dev)
+        ci = torch.from_numpy(G.col_idx).to(dev)
+        g = gde.Graph(ctx, rp, ci)
+        seeds = [int(s) for s in W.uniform_seeds(G, 8, seed=42)]
+        oi = torch.empty(G.n, dtype=torch.int32, device=dev)
+        ov = torch.empty(G.n, dtype=torch.float64, device=dev)
+
+        def timed(fn, p):
+            ts, ops = [], []
+            for s in seeds:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = fn(ctx, g, p, [s], out=(oi, ov))
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+                ops.append(r.ops)
+            return float(np.median(ts)) * 1e3, float(np.mean(ops))
+
+        rec = dict(n=G.n, nnz=G.nnz, sweep=[])
+        # Table 2 analogue at eps = 1/n: operation ratios of the standard solvers over the local ones
+        e_n = 1.0 / G.n
+        ratios = {}
+        for m in ("gd", "ch"):
+            p = gde.make_params("ppr", m, alpha=0.1, eps=e_n, value_type=gde.F64, max_iters=100000)
+            _, lo = timed(gde.solve, p)
+            _, go = timed(gde.solve_global, p)
+            ratios[m] = round(go / lo, 2)
+        rec["ops_ratio_at_eps_1_over_n"] = dict(gd_over_localgd=ratios["gd"], ch_over_localch=ratios["ch"])
+        for e in out["eps_sweep"]:
+            if time.perf_counter() - t_all > budget_s:
+                rec["sweep"].append(dict(eps=e, skipped="time budget"))
+                continue
+            p = gde.make_params("ppr", "gd", alpha=0.1, eps=e, value_type=gde.F64, max_iters=100000)
+            gde.solve(ctx, g, p, [seeds[0]], out=(oi, ov))
+            l_ms, l_ops = timed(gde.solve, p)
+            g_ms, g_ops = timed(gde.solve_global, p)
+            rec["sweep"].append(dict(eps=e, local_ms=round(l_ms, 3), global_ms=round(g_ms, 3),
+                                     local_ops=round(l_ops), global_ops=round(g_ops),
+                                     time_speedup=round(g_ms / l_ms, 2), ops_ratio=round(g_ops / l_ops, 2)))
+            log(f"global vs local {gname} eps 2^{np.log2(e):.0f}: local {l_ms:.3f} ms, global {g_ms:.3f} ms")
+        faster = [r["eps"] for r in rec["sweep"] if "local_ms" in r and r["local_ms"] <= r["global_ms"]]
+        rec["smallest_eps_local_faster"] = min(faster) if faster else None
+        out[gname] = rec
+        g.close()
+        ctx.close()
+        del rp, ci
+        torch.cuda.empty_cache()
     return out
 
 
@@ -711,7 +823,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve"])
+    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve", "global"],
+                    help="global: only the local-vs-global comparison record")
     ap.add_argument("--plain-sample", type=int, default=1024,
                     help="c4: plain solves timed for the comparison (1,024 = every query of the batch)")
     ap.add_argument("--no-sub", action="store_true", help="c4: skip the serving and other-config sub-records")
@@ -745,7 +858,10 @@ def main():
         print(json.dumps(dict(error="bench.py measures one GPU only; multi-GPU sharding is by query "
                                     "(replicated graph) and is described, not run")), flush=True)
         sys.exit(2)
-    out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
+    if args.workload == "global":
+        out = sub_global_vs_local(budget_s=1e9)
+    else:
+        out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
     print(json.dumps(out), flush=True)
     if args.copy_calib:
         import torch

@@ -13,9 +13,14 @@
 // iteration, so an update is applied only when the stop test has let the
 // iteration run.
 //
-// Rows are split by length: rows of at most kLongRow entries are summed by
-// kLanesPerRow lanes each (strided loads, a fixed shuffle tree); longer rows
-// get a workgroup each (fixed LDS tree).  The order of every sum is fixed, so
+// The solver runs on its own copy of the graph with nodes relabelled by
+// descending degree (made once per graph on the GPU).  On power-law graphs most
+// CSR entries point at the high-degree nodes, so the gathers of z then fall on
+// a short prefix of the array that the L2 caches hold; seeds are mapped in and
+// x is mapped back to the caller's ids in the output pass.  Rows of at most
+// kLongRow entries are summed by kLanesPerRow lanes each (strided loads, a
+// fixed shuffle tree); the longer ones -- the first nlong rows after the
+// relabelling -- get a workgroup each (fixed LDS tree).  The order of every sum is fixed, so
 // two runs give bit-identical results.  The stop test counts active nodes per
 // workgroup into one of three counter slots (iteration t reads slot t mod 3,
 // writes t+1 mod 3, clears t+2 mod 3), and a launch whose iteration has no
@@ -50,8 +55,12 @@ struct GlobWS {
     int64_t n = 0, nnz = 0;
     size_t vs = 4;
     void *x = nullptr, *r = nullptr, *h = nullptr, *z[2] = {nullptr, nullptr};
-    int32_t *long_rows = nullptr;  // ids of rows longer than kLongRow
-    int32_t nlong = 0;
+    int32_t *rp = nullptr;         // the relabelled CSR: node v is the caller's node order[v]
+    int32_t *ci = nullptr;
+    int32_t *order = nullptr;      // [n] new id -> caller's id
+    int32_t *inv = nullptr;        // [n] caller's id -> new id
+    std::vector<int32_t> h_inv;    // host copy of inv (seed mapping)
+    int32_t nlong = 0;             // rows longer than kLongRow: new ids [0, nlong)
     GlobCnt *cnt = nullptr;        // [3] slots
     int32_t *iters = nullptr;      // iterations that ran
     int32_t *blk = nullptr;        // output compaction: per-block counts, then offsets
@@ -67,8 +76,8 @@ struct GlobWS {
 
 void glob_ws_free(GlobWS *w) {
     if (!w) return;
-    void *p[] = {w->x, w->r, w->h, w->z[0], w->z[1], w->long_rows, w->cnt, w->iters, w->blk, w->part, w->nrm,
-                 w->total, w->seed_idx, w->seed_val};
+    void *p[] = {w->x, w->r, w->h, w->z[0], w->z[1], w->rp, w->ci, w->order, w->inv, w->cnt, w->iters, w->blk,
+                 w->part, w->nrm, w->total, w->seed_idx, w->seed_val};
     for (void *q : p)
         if (q) (void)hipFree(q);
     if (w->h_buf) (void)hipHostFree(w->h_buf);
@@ -80,7 +89,6 @@ struct GlobArgs {
     int32_t n;
     const int32_t *row_ptr;
     const int32_t *col_idx;
-    const int32_t *long_rows;
     int32_t nlong;
     V *x, *r, *h;
     const V *z_cur;
@@ -122,7 +130,7 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_step(GlobArgs<V> a, int t, 
     unsigned act = 0u;
     if ((int)blockIdx.x < a.nlong) {
         // one long row per workgroup
-        const int32_t w = a.long_rows[blockIdx.x];
+        const int32_t w = (int32_t)blockIdx.x;
         const int32_t beg = a.row_ptr[w], end = a.row_ptr[w + 1];
         V sum = (V)0;
         for (int32_t e = beg + (int32_t)threadIdx.x; e < end; e += kGlobBlock) sum += a.z_cur[a.col_idx[e]];
@@ -135,17 +143,15 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_step(GlobArgs<V> a, int t, 
         if (threadIdx.x == 0) act = glob_node(a, w, end - beg, s_sum[0], ch, c, m);
     } else {
         const int sub = (int)threadIdx.x / kLanesPerRow, sl = (int)threadIdx.x % kLanesPerRow;
-        const int64_t w64 = (int64_t)((int)blockIdx.x - a.nlong) * kRowsPerBlock + sub;
+        const int64_t w64 = a.nlong + (int64_t)((int)blockIdx.x - a.nlong) * kRowsPerBlock + sub;
         if (w64 < a.n) {
             const int32_t w = (int32_t)w64;
             const int32_t beg = a.row_ptr[w], end = a.row_ptr[w + 1];
-            if (end - beg <= kLongRow) {
-                V sum = (V)0;
-                for (int32_t e = beg + sl; e < end; e += kLanesPerRow) sum += a.z_cur[a.col_idx[e]];
+            V sum = (V)0;
+            for (int32_t e = beg + sl; e < end; e += kLanesPerRow) sum += a.z_cur[a.col_idx[e]];
 #pragma unroll
-                for (int off = kLanesPerRow / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kLanesPerRow);
-                if (sl == 0) act = glob_node(a, w, end - beg, sum, ch, c, m);
-            }
+            for (int off = kLanesPerRow / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kLanesPerRow);
+            if (sl == 0) act = glob_node(a, w, end - beg, sum, ch, c, m);
         }
     }
     // active count: a wave sum, then one atomic per workgroup
@@ -243,11 +249,13 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_norm_final(const double *__
 }
 
 // sparse output: the nodes with x_u != 0 in ascending order
+// (x is read through inv: entry u of the output order is x[inv[u]])
 template <typename V>
-__global__ void __launch_bounds__(kGlobBlock) k_glob_count(const V *__restrict__ x, int64_t n, int32_t *blk) {
+__global__ void __launch_bounds__(kGlobBlock) k_glob_count(const V *__restrict__ x, const int32_t *__restrict__ inv,
+                                                            int64_t n, int32_t *blk) {
     __shared__ int s[kGlobBlock / kWave];
     const int64_t u = blockIdx.x * (int64_t)kGlobBlock + threadIdx.x;
-    int c = (u < n && x[u] != (V)0) ? 1 : 0;
+    int c = (u < n && x[inv[u]] != (V)0) ? 1 : 0;
     for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if (lane() == 0) s[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -283,12 +291,12 @@ __global__ void __launch_bounds__(1024) k_glob_scan(int32_t *blk, int64_t nblk, 
 }
 
 template <typename V>
-__global__ void __launch_bounds__(kGlobBlock) k_glob_emit(const V *__restrict__ x, int64_t n,
-                                                           const int32_t *__restrict__ blk, int32_t *out_idx,
-                                                           V *out_val) {
+__global__ void __launch_bounds__(kGlobBlock) k_glob_emit(const V *__restrict__ x, const int32_t *__restrict__ inv,
+                                                           int64_t n, const int32_t *__restrict__ blk,
+                                                           int32_t *out_idx, V *out_val) {
     __shared__ int s_w[kGlobBlock / kWave];
     const int64_t u = blockIdx.x * (int64_t)kGlobBlock + threadIdx.x;
-    const V v = u < n ? x[u] : (V)0;
+    const V v = u < n ? x[inv[u]] : (V)0;
     const bool nz = v != (V)0;
     const unsigned long long bal = __ballot(nz);
     const int before = __popcll(bal & lanemask_lt());
@@ -299,6 +307,21 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_emit(const V *__restrict__ 
     if (nz) {
         out_idx[off + before] = (int32_t)u;
         out_val[off + before] = v;
+    }
+}
+
+// row v of the relabelled CSR = row order[v] of the caller's, columns mapped by inv
+__global__ void __launch_bounds__(kGlobBlock) k_glob_relabel(const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ ci,
+                                                              const int32_t *__restrict__ order,
+                                                              const int32_t *__restrict__ inv,
+                                                              const int32_t *__restrict__ nrp, int32_t *nci, int32_t n) {
+    const int64_t wid = (blockIdx.x * (int64_t)kGlobBlock + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * kGlobBlock / kWave;
+    for (int64_t v = wid; v < n; v += nw) {
+        const int32_t u = order[v];
+        const int32_t beg = rp[u], len = rp[u + 1] - beg, dst = nrp[v];
+        for (int32_t k = lane(); k < len; k += kWave) nci[dst + k] = inv[ci[beg + k]];
     }
 }
 
@@ -333,22 +356,41 @@ static int glob_ws_get(Workspace *w, const gde_graph *g, hipStream_t s, GlobWS *
     al((void **)&q->nrm, 16);
     al((void **)&q->total, 8);
     if (e == hipSuccess) e = hipHostMalloc(&q->h_buf, 4096, 0);
-    // long rows, from the host copy of the row pointers
-    std::vector<int32_t> rp((size_t)g->n + 1), lr;
-    if (e == hipSuccess) e = hipMemcpy(rp.data(), g->row_ptr, 4 * ((size_t)g->n + 1), hipMemcpyDeviceToHost);
+    // relabelling by descending degree (ties by id), from the host copy of the row pointers
+    const int32_t n = g->n;
+    std::vector<int32_t> rp((size_t)n + 1), order((size_t)n), nrp((size_t)n + 1);
+    q->h_inv.assign((size_t)n, 0);
+    if (e == hipSuccess) e = hipMemcpy(rp.data(), g->row_ptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost);
     if (e == hipSuccess) {
-        for (int32_t u = 0; u < g->n; u++)
-            if (rp[u + 1] - rp[u] > kLongRow) lr.push_back(u);
-        q->nlong = (int32_t)lr.size();
-        al((void **)&q->long_rows, 4 * std::max<size_t>(lr.size(), 1));
-        if (e == hipSuccess && !lr.empty())
-            e = hipMemcpy(q->long_rows, lr.data(), 4 * lr.size(), hipMemcpyHostToDevice);
+        for (int32_t u = 0; u < n; u++) order[u] = u;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a2, int32_t b2) { return rp[a2 + 1] - rp[a2] > rp[b2 + 1] - rp[b2]; });
+        nrp[0] = 0;
+        q->nlong = 0;
+        for (int32_t v = 0; v < n; v++) {
+            const int32_t d = rp[order[v] + 1] - rp[order[v]];
+            nrp[v + 1] = nrp[v] + d;
+            q->h_inv[order[v]] = v;
+            if (d > kLongRow) q->nlong = v + 1;
+        }
+        al((void **)&q->rp, 4 * ((size_t)n + 1));
+        al((void **)&q->ci, 4 * (size_t)g->nnz);
+        al((void **)&q->order, 4 * (size_t)n);
+        al((void **)&q->inv, 4 * (size_t)n);
     }
+    if (e == hipSuccess) e = hipMemcpy(q->rp, nrp.data(), 4 * ((size_t)n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->order, order.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->inv, q->h_inv.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_glob_relabel, dim3(8192), dim3(kGlobBlock), 0, s, g->row_ptr, g->col_idx, q->order,
+                           q->inv, q->rp, q->ci, n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         glob_ws_free(q);
         return hip_fail(e, "global solver workspace");
     }
-    (void)s;
     w->glob = q;
     *out = q;
     return GDE_OK;
@@ -371,16 +413,17 @@ static int glob_run(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const
         GDE_HIP(hipMalloc((void **)&q->seed_val, 8 * (size_t)sd->nnz));
         q->seed_cap = sd->nnz;
     }
-    GDE_HIP(hipMemcpyAsync(q->seed_idx, sd->idx, 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> sidx((size_t)sd->nnz);
+    for (int32_t i = 0; i < sd->nnz; i++) sidx[i] = q->h_inv[sd->idx[i]];
+    GDE_HIP(hipMemcpyAsync(q->seed_idx, sidx.data(), 4 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
     GDE_HIP(hipMemcpyAsync(q->seed_val, sd->val, 8 * (size_t)sd->nnz, hipMemcpyHostToDevice, s));
 
     const bool ppr = p->kind == GDE_PPR;
     const bool ch = p->method == GDE_LOCAL_CH;
     GlobArgs<V> a{};
     a.n = g->n;
-    a.row_ptr = g->row_ptr;
-    a.col_idx = g->col_idx;
-    a.long_rows = q->long_rows;
+    a.row_ptr = q->rp;
+    a.col_idx = q->ci;
     a.nlong = q->nlong;
     a.x = (V *)q->x;
     a.r = (V *)q->r;
@@ -409,7 +452,7 @@ static int glob_run(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const
         sigma = (L + mu) / (L - mu);
         dlt = 1.0 / sigma;
     }
-    const unsigned grid = (unsigned)(q->nlong + (g->n + kRowsPerBlock - 1) / kRowsPerBlock);
+    const unsigned grid = (unsigned)(q->nlong + (g->n - q->nlong + kRowsPerBlock - 1) / kRowsPerBlock);
     int t = 0, chunk = 4;
     int32_t T = 0;
     bool converged = false;
@@ -442,9 +485,9 @@ static int glob_run(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const
     if ((rc = prof_collect(ctx, (int64_t)T * g->nnz, (int64_t)T * g->n))) return rc;
     // residual norms and the sparse output
     hipLaunchKernelGGL(k_glob_norm_part<V>, dim3((unsigned)q->nblk), dim3(kGlobBlock), 0, s, (const V *)q->r,
-                       g->row_ptr, (int64_t)g->n, ppr ? 1.0 / p->alpha : 1.0, q->part, q->nblk);
+                       q->rp, (int64_t)g->n, ppr ? 1.0 / p->alpha : 1.0, q->part, q->nblk);
     hipLaunchKernelGGL(k_glob_norm_final, dim3(1), dim3(kGlobBlock), 0, s, q->part, q->nblk, q->nrm);
-    hipLaunchKernelGGL(k_glob_count<V>, dim3((unsigned)q->nblk), dim3(kGlobBlock), 0, s, (const V *)q->x,
+    hipLaunchKernelGGL(k_glob_count<V>, dim3((unsigned)q->nblk), dim3(kGlobBlock), 0, s, (const V *)q->x, q->inv,
                        (int64_t)g->n, q->blk);
     hipLaunchKernelGGL(k_glob_scan, dim3(1), dim3(1024), 0, s, q->blk, q->nblk, q->total);
     GDE_HIP(hipGetLastError());
@@ -477,13 +520,13 @@ static int glob_run(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const
     if (nnz > 0) {
         if (p->flags & GDE_RESULT_DEVICE) {
             hipLaunchKernelGGL(k_glob_emit<V>, dim3((unsigned)q->nblk), dim3(kGlobBlock), 0, s, (const V *)q->x,
-                               (int64_t)g->n, q->blk, res->idx, (V *)res->val);
+                               q->inv, (int64_t)g->n, q->blk, res->idx, (V *)res->val);
             GDE_HIP(hipGetLastError());
             GDE_HIP(hipStreamSynchronize(s));
         } else {
             // stage through the (free) z buffers: nnz <= n entries of each
             hipLaunchKernelGGL(k_glob_emit<V>, dim3((unsigned)q->nblk), dim3(kGlobBlock), 0, s, (const V *)q->x,
-                               (int64_t)g->n, q->blk, (int32_t *)q->z[0], (V *)q->z[1]);
+                               q->inv, (int64_t)g->n, q->blk, (int32_t *)q->z[0], (V *)q->z[1]);
             GDE_HIP(hipGetLastError());
             GDE_HIP(hipMemcpyAsync(res->idx, q->z[0], 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
             GDE_HIP(hipMemcpyAsync(res->val, q->z[1], q->vs * (size_t)nnz, hipMemcpyDeviceToHost, s));

@@ -148,6 +148,22 @@ def from_edges(n: int, edges) -> Graph:
     return Graph(n, row_ptr, col_idx, 0.0, 0)
 
 
+def grid_2d(rows: int, cols: int) -> Graph:
+    """The rows x cols 4-neighbour grid graph (node (i, j) has id i * cols + j):
+    1000 x 1000 gives 10^6 nodes and 1,998,000 edges, the grid of the paper's
+    App. C experiment on graph types.  Neighbour lists are ascending."""
+    n = rows * cols
+    ids = np.arange(n, dtype=np.int64)
+    i, j = ids // cols, ids % cols
+    cand = np.stack([np.where(i > 0, ids - cols, -1), np.where(j > 0, ids - 1, -1),
+                     np.where(j < cols - 1, ids + 1, -1), np.where(i < rows - 1, ids + cols, -1)], axis=1)
+    valid = cand >= 0
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(valid.sum(axis=1))
+    col_idx = cand[valid].astype(np.int32)
+    return Graph(n, row_ptr, col_idx, 0.0, 0)
+
+
 def components(graph: Graph) -> np.ndarray:
     lib = _load()
     label = np.empty(graph.n, dtype=np.int32)

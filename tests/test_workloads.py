@@ -43,3 +43,14 @@ def test_seed_samplers():
     rng = np.random.default_rng(0)
     u, v = W.insert_batch(g, 100, rng)
     assert (u < v).all() and len(set(zip(u.tolist(), v.tolist()))) == 100
+
+
+def test_grid_2d_matches_edge_list():
+    from paper_2410_21634_amd import workloads as W
+    rows, cols = 5, 7
+    edges = [(i * cols + j, i * cols + j + 1) for i in range(rows) for j in range(cols - 1)]
+    edges += [(i * cols + j, (i + 1) * cols + j) for i in range(rows - 1) for j in range(cols)]
+    G, H = W.grid_2d(rows, cols), W.from_edges(rows * cols, edges)
+    assert np.array_equal(G.row_ptr, H.row_ptr) and np.array_equal(G.col_idx, H.col_idx)
+    big = W.grid_2d(1000, 1000)
+    assert big.n == 10**6 and big.nnz == 2 * 1_998_000
