@@ -601,26 +601,18 @@ int oracle_push_fifo(int64_t n, const int64_t *rp, const int32_t *ci, int kind, 
  * norms[0] = that weighted sum, norms[1] = max_k (K+1) psi_k ||D^-1 leftover_k||_inf
  * (below eps iff every leftover is below its threshold).
  * stats = T (levels with a nonempty active set), ops, pushes, status.
+ * run_level_push takes the series through c_0, the level ratios c_{k+1}/c_k
+ * (ratio[k], k < K) and psi; oracle_hk and oracle_series below supply them.
  */
-int oracle_hk(int64_t n, const int64_t *rp, const int32_t *ci, double tau, int32_t K, double eps, int32_t seed_nnz,
-              const int32_t *seed_idx, const double *seed_val, double *x, int64_t *stats, double *norms,
-              double *psi_out, int64_t trace_cap, int64_t *tr_size, int64_t *tr_vol, int64_t nodes_cap,
-              int32_t *tr_nodes, int64_t *nodes_len, int64_t T_rec, const int64_t *off, const int32_t *nodes,
-              double kappa, int64_t *out_fv) {
+static int run_level_push(int64_t n, const int64_t *rp, const int32_t *ci, int32_t K, double c0,
+                          const double *ratio, const double *psi, double eps, int32_t seed_nnz,
+                          const int32_t *seed_idx, const double *seed_val, double *x, int64_t *stats, double *norms,
+                          int64_t trace_cap, int64_t *tr_size, int64_t *tr_vol, int64_t nodes_cap,
+                          int32_t *tr_nodes, int64_t *nodes_len, int64_t T_rec, const int64_t *off,
+                          const int32_t *nodes, double kappa, int64_t *out_fv) {
     graph_t g = {n, rp, ci};
-    if (!(tau >= 0.0) || !isfinite(tau) || K < 0 || K > 256 || !(eps > 0.0) || !isfinite(eps)) return OR_INVALID;
     int rc = check_seed(&g, seed_nnz, seed_idx, seed_val);
     if (rc) return rc;
-    double *psi = (double *)malloc(sizeof(double) * (size_t)(K + 1));
-    for (int32_t k = 0; k <= K; k++) {
-        double s = 0.0, term = 1.0; /* term = tau^{j-k} k!/j! */
-        for (int32_t j = k; j <= K; j++) {
-            if (j > k) term *= tau / (double)j;
-            s += term;
-        }
-        psi[k] = s;
-        if (psi_out) psi_out[k] = s;
-    }
     double *rk = (double *)calloc((size_t)n, sizeof(double));
     double *rk1 = (double *)calloc((size_t)n, sizeof(double));
     int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -628,8 +620,7 @@ int oracle_hk(int64_t n, const int64_t *rp, const int32_t *ci, double tau, int32
     touched_t tk = {0}, tk1 = {0}; /* touched sets of the current and next level */
     if (!rk || !rk1 || !S || !mark || touched_init(&tk, n) || touched_init(&tk1, n)) return OR_OOM;
     memset(x, 0, sizeof(double) * (size_t)n);
-    double e = exp(-tau);
-    for (int32_t i = 0; i < seed_nnz; i++) { rk[seed_idx[i]] = e * seed_val[i]; touch(&tk, seed_idx[i]); }
+    for (int32_t i = 0; i < seed_nnz; i++) { rk[seed_idx[i]] = c0 * seed_val[i]; touch(&tk, seed_idx[i]); }
     replay_t rpl = {off, nodes, T_rec, kappa, 0, 0};
     int64_t T = 0, ops = 0, pushes = 0, rec = 0;
     double left_l1 = 0.0, left_dinf = 0.0;
@@ -661,7 +652,7 @@ int oracle_hk(int64_t n, const int64_t *rp, const int32_t *ci, double tau, int32
             x[u] += v;
             rk[u] = 0.0;
             if (k < K) {
-                double wgt = (tau / (double)(k + 1)) * v / d;
+                double wgt = ratio[k] * v / d;
                 for (int64_t ee = g.rp[u]; ee < g.rp[u + 1]; ee++) {
                     int64_t w = g.ci[ee];
                     rk1[w] += wgt;
@@ -700,6 +691,68 @@ int oracle_hk(int64_t n, const int64_t *rp, const int32_t *ci, double tau, int32
     norms[0] = left_l1; norms[1] = left_dinf;
     if (out_fv) { out_fv[0] = rpl.flips; out_fv[1] = rpl.violations; }
     if (nodes_len) *nodes_len = rec;
-    free(psi); free(rk); free(rk1); free(S); free(mark); touched_free(&tk); touched_free(&tk1);
+    free(rk); free(rk1); free(S); free(mark); touched_free(&tk); touched_free(&tk1);
     return OR_OK;
+}
+
+/* The heat kernel: c_k = e^{-tau} tau^k / k!, so c_0 = e^{-tau}, the level
+ * ratio c_{k+1}/c_k = tau/(k+1) and psi_k = sum_{j=k..K} tau^{j-k} k!/j!.
+ * psi_out (optional) receives psi. */
+int oracle_hk(int64_t n, const int64_t *rp, const int32_t *ci, double tau, int32_t K, double eps, int32_t seed_nnz,
+              const int32_t *seed_idx, const double *seed_val, double *x, int64_t *stats, double *norms,
+              double *psi_out, int64_t trace_cap, int64_t *tr_size, int64_t *tr_vol, int64_t nodes_cap,
+              int32_t *tr_nodes, int64_t *nodes_len, int64_t T_rec, const int64_t *off, const int32_t *nodes,
+              double kappa, int64_t *out_fv) {
+    if (!(tau >= 0.0) || !isfinite(tau) || K < 0 || K > 256 || !(eps > 0.0) || !isfinite(eps)) return OR_INVALID;
+    double *psi = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    double *ratio = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    if (!psi || !ratio) { free(psi); free(ratio); return OR_OOM; }
+    for (int32_t k = 0; k <= K; k++) {
+        double s = 0.0, term = 1.0; /* term = tau^{j-k} k!/j! */
+        for (int32_t j = k; j <= K; j++) {
+            if (j > k) term *= tau / (double)j;
+            s += term;
+        }
+        psi[k] = s;
+        ratio[k] = tau / (double)(k + 1);
+        if (psi_out) psi_out[k] = s;
+    }
+    int rc = run_level_push(n, rp, ci, K, exp(-tau), ratio, psi, eps, seed_nnz, seed_idx, seed_val, x, stats, norms,
+                            trace_cap, tr_size, tr_vol, nodes_cap, tr_nodes, nodes_len, T_rec, off, nodes, kappa,
+                            out_fv);
+    free(psi); free(ratio);
+    return rc;
+}
+
+/*
+ * A general truncated series f_K = sum_{k=0..K} c_k (A D^-1)^k s (Eq. (1) with
+ * M = A D^-1, Table 1), every c_k > 0 and finite: the same level push with
+ * v_0 = c_0 s, level ratio c_{k+1}/c_k and psi_k = sum_{j=k..K} c_j / c_k (the
+ * l1 weight of a unit of residual left at level k, since A D^-1 keeps mass).
+ * With c_k = e^{-tau} tau^k/k! it is the heat kernel; with c_k = alpha
+ * (1-alpha)^k the truncated PPR series.  psi_out as oracle_hk.
+ */
+int oracle_series(int64_t n, const int64_t *rp, const int32_t *ci, int32_t K, const double *c, double eps,
+                  int32_t seed_nnz, const int32_t *seed_idx, const double *seed_val, double *x, int64_t *stats,
+                  double *norms, double *psi_out, int64_t trace_cap, int64_t *tr_size, int64_t *tr_vol,
+                  int64_t nodes_cap, int32_t *tr_nodes, int64_t *nodes_len, int64_t T_rec, const int64_t *off,
+                  const int32_t *nodes, double kappa, int64_t *out_fv) {
+    if (K < 0 || K > 256 || !c || !(eps > 0.0) || !isfinite(eps)) return OR_INVALID;
+    for (int32_t k = 0; k <= K; k++)
+        if (!(c[k] > 0.0) || !isfinite(c[k])) return OR_INVALID;
+    double *psi = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    double *ratio = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    if (!psi || !ratio) { free(psi); free(ratio); return OR_OOM; }
+    for (int32_t k = 0; k <= K; k++) {
+        double s = 0.0;
+        for (int32_t j = k; j <= K; j++) s += c[j] / c[k];
+        psi[k] = s;
+        ratio[k] = k < K ? c[k + 1] / c[k] : 0.0;
+        if (psi_out) psi_out[k] = s;
+    }
+    int rc = run_level_push(n, rp, ci, K, c[0], ratio, psi, eps, seed_nnz, seed_idx, seed_val, x, stats, norms,
+                            trace_cap, tr_size, tr_vol, nodes_cap, tr_nodes, nodes_len, T_rec, off, nodes, kappa,
+                            out_fv);
+    free(psi); free(ratio);
+    return rc;
 }

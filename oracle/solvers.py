@@ -55,10 +55,13 @@ def _load():
                                       vp, i64, vp, vp, i64, vp, vp, d, vp]
             lib.oracle_localgd_warm.argtypes = [i64, _p64, _p32, C.c_int, d, d, i32, _pf, _pf, _p64, _pf]
             lib.oracle_edge_events.argtypes = [i64, C.c_int, d, _pf, _pf, _p64, i64, _p32, _p32, C.c_int]
+            lib.oracle_series.argtypes = [i64, _p64, _p32, i32, _pf, d, i32, _p32, _pf, _pf, _p64, _pf, _pf, i64,
+                                          vp, vp, i64, vp, vp, i64, vp, vp, d, vp]
             lib.oracle_global.argtypes = [i64, _p64, _p32, C.c_int, C.c_int, d, d, d, i32, _p32, _pf, i32, _pf,
                                           _pf, _p64, _pf]
             for f in (lib.oracle_localgd, lib.oracle_localch, lib.oracle_replay_gd_ch, lib.oracle_push_fifo,
-                      lib.oracle_hk, lib.oracle_localgd_warm, lib.oracle_edge_events, lib.oracle_global):
+                      lib.oracle_hk, lib.oracle_localgd_warm, lib.oracle_edge_events, lib.oracle_global,
+                      lib.oracle_series):
                 f.restype = C.c_int
             _lib = lib
     return _lib
@@ -181,6 +184,43 @@ def hk(row_ptr, col_idx, tau, K, eps, seed_idx, seed_val=None, trace_cap=64, rep
     nlen = np.zeros(1, np.int64)
     rc = lib.oracle_hk(n, rp, ci, tau, K, eps, k, idx, val, x, stats, norms, psi, trace_cap, _ptr(ts), _ptr(tv),
                        nodes_cap, _ptr(nb), _ptr(nlen), T_rec, _ptr(off), _ptr(nodes), kappa, _ptr(fv))
+    _check(rc)
+    T = int(stats[0])
+    m = min(T, trace_cap)
+    out = dict(x=x, status=rc, iters=T, ops=int(stats[1]), pushes=int(stats[2]), residual_l1=norms[0],
+               residual_dinf=norms[1], psi=psi, trace_size=ts[:m], trace_vol=tv[:m], flips=int(fv[0]),
+               violations=int(fv[1]))
+    if nodes_cap and m == T:
+        out["trace_nodes"] = _nodes_result(nb, nlen, ts[:m])
+    return out
+
+
+def series(row_ptr, col_idx, c, eps, seed_idx, seed_val=None, trace_cap=64, replay=None, kappa=0.0, nodes_cap=0):
+    """Level push of f_K = sum_k c_k (A D^-1)^k s for positive coefficients c
+    (length K + 1): the heat-kernel push with general level ratios (Eq. (1),
+    Table 1).  Arguments and result as ``hk``."""
+    lib = _load()
+    n, rp, ci = _graph(row_ptr, col_idx)
+    k, idx, val = _seed(seed_idx, seed_val)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    K = len(cc) - 1
+    x = np.zeros(n)
+    stats, norms, psi = np.zeros(4, np.int64), np.zeros(2), np.zeros(K + 1)
+    ts, tv = np.zeros(trace_cap, np.int64), np.zeros(trace_cap, np.int64)
+    fv = np.zeros(2, np.int64)
+    if replay is not None:
+        off = np.ascontiguousarray(replay[0], dtype=np.int64)
+        nodes = np.ascontiguousarray(replay[1], dtype=np.int32)
+        if len(nodes) == 0:
+            nodes = np.zeros(1, np.int32)
+        T_rec = len(off) - 1
+    else:
+        off = nodes = None
+        T_rec = 0
+    nb = np.zeros(nodes_cap, np.int32) if nodes_cap else None
+    nlen = np.zeros(1, np.int64)
+    rc = lib.oracle_series(n, rp, ci, K, cc, eps, k, idx, val, x, stats, norms, psi, trace_cap, _ptr(ts), _ptr(tv),
+                           nodes_cap, _ptr(nb), _ptr(nlen), T_rec, _ptr(off), _ptr(nodes), kappa, _ptr(fv))
     _check(rc)
     T = int(stats[0])
     m = min(T, trace_cap)
