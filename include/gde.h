@@ -13,10 +13,13 @@
  *   HK   : Taylor truncation f_K = sum_{k<=K} e^-tau tau^k/k! (A D^-1)^k s, solved
  *          level by level on the Kronecker system of the AHK push (Sec. 2);
  *          level-k threshold eps*d_u/((K+1) psi_k), psi_k = sum_{j=k..K} tau^(j-k) k!/j!.
+ *   SERIES : any truncated series f_K = sum_{k<=K} c_k (A D^-1)^k s with given
+ *          c_k > 0 (Eq. (1), Table 1), by the same level push with ratio
+ *          c_{k+1}/c_k and psi_k = sum_{j=k..K} c_j/c_k.
  *
  * Methods: LocalGD (Eq. (9): x += r_S, r -= Q r_S) and LocalCH (Sec. 3.3,
- * Chebyshev update restricted to S_t).  The heat kernel always uses the
- * level push.
+ * Chebyshev update restricted to S_t).  The heat kernel and SERIES always use
+ * the level push.
  *
  * Conventions shared by every entry point
  *   - All sizes and indices are int32 node ids / int64 counts; the graph is a
@@ -60,7 +63,7 @@ typedef enum gde_status {
     GDE_ERR_UNSUPPORTED = 8    /* valid but not provided (LocalCH for the heat kernel) */
 } gde_status;
 
-typedef enum gde_kind { GDE_PPR = 0, GDE_KATZ = 1, GDE_HK = 2 } gde_kind;
+typedef enum gde_kind { GDE_PPR = 0, GDE_KATZ = 1, GDE_HK = 2, GDE_SERIES = 3 } gde_kind;
 typedef enum gde_method { GDE_LOCAL_GD = 0, GDE_LOCAL_CH = 1 } gde_method;
 typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
 
@@ -102,17 +105,24 @@ typedef struct gde_server gde_server;
 
 /*
  * One diffusion query.
- *   kind, method     : gde_kind, gde_method (LocalCH with HK -> GDE_ERR_UNSUPPORTED)
+ *   kind, method     : gde_kind, gde_method (LocalCH with HK or SERIES -> GDE_ERR_UNSUPPORTED)
  *   value_type       : GDE_F32 or GDE_F64 -- the type of x and r on the device
  *   alpha            : PPR damping, 0 < alpha < 1
  *   beta             : Katz weight, beta > 0 and beta * lambda_bound < 1
- *   tau, K           : heat-kernel temperature (tau >= 0) and truncation (0 <= K <= 256)
+ *   tau, K           : heat-kernel temperature (tau >= 0) and truncation (0 <= K <= 256);
+ *                      K is also the truncation of GDE_SERIES
  *   eps              : tolerance, finite and > 0 (stop iff max_u |r~_u|/d_u < eps)
  *   lambda_bound     : an upper bound of the spectral radius of A (Katz).  It is
  *                      required for Katz (validation of beta) and is the
  *                      Chebyshev bound of Katz-LocalCH: mu = 1 - beta*lambda,
  *                      L = 1 + beta*lambda.  gde_graph_lambda_max provides one.
- *   c                : reserved, must be NULL (coefficients follow from kind)
+ *   c                : GDE_SERIES only (NULL for every other kind): K + 1 coefficients
+ *                      c_0 .. c_K in host memory, each finite and > 0; the call
+ *                      solves f_K = sum_k c_k (A D^-1)^k s (Eq. (1), Table 1) by the
+ *                      heat kernel's level push with level ratio c_{k+1}/c_k and
+ *                      level thresholds eps d_u / ((K+1) psi_k), psi_k = sum_{j>=k}
+ *                      c_j / c_k.  The heat kernel is c_k = e^-tau tau^k / k!;
+ *                      alpha (1-alpha)^k is the truncated PPR series.  LocalGD only.
  *   max_iters        : iteration cap (>= 1); reaching it gives GDE_ERR_NOT_CONVERGED
  *   flags            : GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE |
  *                      GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC | GDE_DETERMINISTIC

@@ -53,12 +53,13 @@ static int validate_csr_host(int32_t n, int64_t nnz, const int32_t *rp, const in
 
 static int validate_params(const gde_params *p) {
     if (!p) return fail(GDE_ERR_INVALID_ARG, "null params");
-    if (p->kind < GDE_PPR || p->kind > GDE_HK) return fail(GDE_ERR_INVALID_ARG, "unknown kind");
+    if (p->kind < GDE_PPR || p->kind > GDE_SERIES) return fail(GDE_ERR_INVALID_ARG, "unknown kind");
     if (p->method != GDE_LOCAL_GD && p->method != GDE_LOCAL_CH) return fail(GDE_ERR_INVALID_ARG, "unknown method");
     if (p->value_type != GDE_F32 && p->value_type != GDE_F64) return fail(GDE_ERR_INVALID_ARG, "unknown value_type");
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(GDE_ERR_INVALID_ARG, "eps must be finite and > 0");
     if (p->max_iters < 1) return fail(GDE_ERR_INVALID_ARG, "max_iters must be >= 1");
-    if (p->c != nullptr) return fail(GDE_ERR_INVALID_ARG, "params.c is reserved and must be NULL");
+    if (p->kind != GDE_SERIES && p->c != nullptr)
+        return fail(GDE_ERR_INVALID_ARG, "params.c is for GDE_SERIES only and must be NULL otherwise");
     if ((p->flags & GDE_SCATTER_BINNED) && (p->flags & GDE_SCATTER_ATOMIC))
         return fail(GDE_ERR_INVALID_ARG, "GDE_SCATTER_BINNED and GDE_SCATTER_ATOMIC exclude each other");
     if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE | GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC |
@@ -79,6 +80,14 @@ static int validate_params(const gde_params *p) {
         if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(GDE_ERR_INVALID_ARG, "HK needs tau >= 0");
         if (p->K < 0 || p->K > 256) return fail(GDE_ERR_INVALID_ARG, "HK needs 0 <= K <= 256");
         if (p->method == GDE_LOCAL_CH) return fail(GDE_ERR_UNSUPPORTED, "LocalCH is not defined for the heat kernel");
+        break;
+    case GDE_SERIES:
+        if (p->K < 0 || p->K > 256) return fail(GDE_ERR_INVALID_ARG, "SERIES needs 0 <= K <= 256");
+        if (!p->c) return fail(GDE_ERR_INVALID_ARG, "SERIES needs params.c (K + 1 coefficients)");
+        for (int32_t k = 0; k <= p->K; k++)
+            if (!(p->c[k] > 0.0) || !std::isfinite(p->c[k]))
+                return fail(GDE_ERR_INVALID_ARG, "SERIES coefficients must be finite and > 0");
+        if (p->method == GDE_LOCAL_CH) return fail(GDE_ERR_UNSUPPORTED, "LocalCH is not defined for SERIES");
         break;
     }
     return GDE_OK;
@@ -136,7 +145,7 @@ static void ws_free(Workspace *w) {
     void *dev[] = {w->rd, w->rd2, w->x, w->bitmap, w->tbm, w->front[0], w->front[1], w->touched[0], w->touched[1],
                    w->touched[2], w->wl_node, w->wl_beg, w->wl_off, w->wl_sv, w->tile_start, w->delta, w->dstamp,
                    w->cstamp, w->blk, w->st, w->seed_idx, w->seed_val, w->out_idx, w->out_val, w->tr_size,
-                   w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_e};
+                   w->tr_vol, w->tr_nodes, w->lam_buf, w->bin_base, w->bin_cursor, w->bin_e, w->lvl_tab};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (w->hst) (void)hipHostFree(w->hst);
@@ -278,6 +287,7 @@ static int ws_ensure_hk(Workspace *w, const gde_graph *g, hipStream_t s) {
         if (!w->touched[i]) {
             GDE_HIP(hipMalloc((void **)&w->touched[i], 4 * n));
         }
+    if (!w->lvl_tab) GDE_HIP(hipMalloc((void **)&w->lvl_tab, 16 * (size_t)(kHkMaxLevels + 1)));
     return GDE_OK;
 }
 
@@ -543,7 +553,7 @@ template <typename V>
 int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
                    Workspace *w, hipStream_t s) {
     int rc = GDE_OK;
-    const bool hk = p->kind == GDE_HK;
+    const bool hk = p->kind == GDE_HK || p->kind == GDE_SERIES;  // the level push
     const bool ch = p->method == GDE_LOCAL_CH;
     if (hk && (rc = ws_ensure_hk(w, g, s))) return rc;
     if (ch && (rc = ws_ensure_ch(w, s))) return rc;
@@ -626,20 +636,17 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
         // fixed-order iterations (pull instead of scatter), any kind and method
         if ((rc = det_run<V>(g, p, sd, w, pinl, d_trs, d_trv, d_trn, tr_cap, tr_ncap, s, &converged))) return rc;
     } else if (hk) {
-        // ------------------------------------------------ heat kernel, level by level
+        // ------------------------------------------------ heat kernel or SERIES, level by level
         const int K = p->K;
-        const double tau = p->tau;
-        std::vector<double> psi(K + 1);
-        for (int k = 0; k <= K; k++) {
-            double acc = 0.0, term = 1.0;
-            for (int j = k; j <= K; j++) {
-                if (j > k) term *= tau / (double)j;
-                acc += term;
-            }
-            psi[k] = acc;
-        }
+        const LevelSeries ls = level_series(p);
+        const std::vector<double> &psi = ls.psi;
+        // the single-workgroup kernel reads psi and the level ratios from the device table
+        w->h_lvl.assign(2 * (size_t)(kHkMaxLevels + 1), 0.0);
+        std::copy(ls.psi.begin(), ls.psi.end(), w->h_lvl.begin());
+        std::copy(ls.ratio.begin(), ls.ratio.end(), w->h_lvl.begin() + kHkMaxLevels + 1);
+        GDE_HIP(hipMemcpyAsync(w->lvl_tab, w->h_lvl.data(), 8 * w->h_lvl.size(), hipMemcpyHostToDevice, s));
         void *plane[2] = {w->rd, w->rd2};
-        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, std::exp(-tau), w->front[0], w->touched[0],
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, ls.c0, w->front[0], w->touched[0],
                             nullptr, 0, nullptr, w->st, s);
         auto eps_at = [&](int k) { return k >= K ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]); };
         // level k on the grid-wide kernels: clean-up of k-1 and snapshot of k, then the push into k+1
@@ -648,7 +655,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
             a.F = w->front[k & 1];
             a.cur = k & 1;
             const bool last = k == K;
-            launch_snap_hk<V>(a, plane[(k + 1) & 1], (V)(tau / (double)(k + 1)), last ? 1 : 0, 1,
+            launch_snap_hk<V>(a, plane[(k + 1) & 1], (V)ls.ratio[k], last ? 1 : 0, 1,
                               k >= 1 ? w->touched[(k + 2) % 3] : nullptr, (k + 2) % 3, (k + 1) % 3,
                               k >= 1 ? psi[k - 1] : 0.0, k >= 1 ? (double)(K + 1) * psi[k - 1] : 0.0, s);
             int e = prof_mark(ctx, s);
@@ -680,7 +687,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
         ha.tr_size = d_trs;
         ha.tr_vol = d_trv;
         ha.tr_cap = tr_cap;
-        ha.tau = tau;
+        ha.lvl_tab = w->lvl_tab;
         ha.eps = p->eps;
         ha.K = K;
         ha.cap = g->n;
@@ -1248,7 +1255,7 @@ int gde_solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, cons
     if (!ctx || !g || !res) return fail(GDE_ERR_INVALID_ARG, "null ctx, graph or result");
     int rc = validate_params(p);
     if (rc) { res->status = rc; return rc; }
-    if (p->kind == GDE_HK) {
+    if (p->kind == GDE_HK || p->kind == GDE_SERIES) {
         res->status = GDE_ERR_UNSUPPORTED;
         return fail(GDE_ERR_UNSUPPORTED, "the global solvers cover PPR and Katz");
     }

@@ -577,7 +577,8 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
     // the fused kernels need one kind (PPR or Katz), LocalGD, one value type and
     // shared kind parameters; anything else is solved query by query
     // (deterministic queries are solved one by one in the fixed-order mode)
-    bool fused = p[0].kind != GDE_HK && p[0].method == GDE_LOCAL_GD && !(p[0].flags & GDE_DETERMINISTIC);
+    bool fused = (p[0].kind == GDE_PPR || p[0].kind == GDE_KATZ) && p[0].method == GDE_LOCAL_GD &&
+                 !(p[0].flags & GDE_DETERMINISTIC);
     for (int32_t i = 1; i < B && fused; i++) {
         fused = p[i].kind == p[0].kind && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
                 p[i].alpha == p[0].alpha && p[i].beta == p[0].beta && p[i].max_iters == p[0].max_iters &&

@@ -411,22 +411,14 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
     if (d_trs) GDE_HIP(hipMemsetAsync(d_trs, 0, 8 * (size_t)tr_cap, s));
     if (d_trv) GDE_HIP(hipMemsetAsync(d_trv, 0, 8 * (size_t)tr_cap, s));
 
-    if (p->kind == GDE_HK) {
+    if (p->kind == GDE_HK || p->kind == GDE_SERIES) {
         const int K = p->K;
-        const double tau = p->tau;
-        std::vector<double> psi(K + 1);
-        for (int k = 0; k <= K; k++) {
-            double acc = 0.0, term = 1.0;
-            for (int j = k; j <= K; j++) {
-                if (j > k) term *= tau / (double)j;
-                acc += term;
-            }
-            psi[k] = acc;
-        }
+        const LevelSeries ls = level_series(p);
+        const std::vector<double> &psi = ls.psi;
         void *plane[2] = {w->rd, w->rd2};
         uint32_t *tb[2] = {w->tbm, d->tbm2};
-        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, inl, sd->nnz, std::exp(-tau), S, nullptr, nullptr, 0,
-                            tb[0], w->st, s);
+        launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, inl, sd->nnz, ls.c0, S, nullptr, nullptr, 0, tb[0],
+                            w->st, s);
         double left_l1 = 0.0, left_dinf = 0.0;
         bool stopped = false;
         for (int k = 0; k <= K; k++) {
@@ -446,7 +438,7 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
                     const double eps_next = p->eps / ((double)(K + 1) * psi[k + 1]);
                     hipLaunchKernelGGL(k_det_pull<V>, dim3(pull_grid), dim3(kDetBlock), 0, s, U, d->cnt + 0,
                                        g->row_ptr, g->col_idx, (const RD<V> *)plane[cur], (RD<V> *)plane[nxt],
-                                       (const V *)d->sv[0], d->sbm[0], 1, (V)(tau / (double)(k + 1)), 1,
+                                       (const V *)d->sv[0], d->sbm[0], 1, (V)ls.ratio[k], 1,
                                        (V)eps_next, d->nbm);
                     det_compact(d, d->nbm, S, 1, s);
                 }

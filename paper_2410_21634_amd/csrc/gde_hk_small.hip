@@ -8,7 +8,8 @@
 //              the reported norms, weighted by psi_{k-1}, and their plane is
 //              zeroed, since it becomes plane k+1;
 //   snapshot : for u in S_k, x_u += r_k[u], r_k[u] = 0, scatter value
-//              (tau / (k+1)) r_k[u] / d_u (none at the last level K);
+//              (c_{k+1}/c_k) r_k[u] / d_u (none at the last level K), which
+//              for the heat kernel is (tau / (k+1)) r_k[u] / d_u;
 //   push     : r_{k+1}[w] += value over the rows of S_k; the add that lifts
 //              r_{k+1}[w] over eps d_w / ((K+1) psi_{k+1}) appends w to S_{k+1}
 //              (crossing test, the plane only grows during the push), and the
@@ -91,15 +92,8 @@ __global__ void __launch_bounds__(kSnapBlock) k_small_hk(HkSmallArgs<V> a) {
     V *x = (V *)a.x;
     const int tid = threadIdx.x;
     const int K = a.K;
-    // psi_k = sum_{j=k..K} tau^{j-k} k! / j!, the same double operations as the host
-    for (int k = tid; k <= K; k += blockDim.x) {
-        double acc = 0.0, term = 1.0;
-        for (int j = k; j <= K; j++) {
-            if (j > k) term *= a.tau / (double)j;
-            acc += term;
-        }
-        s_psi[k] = acc;
-    }
+    // psi_k of the series, from the host's table
+    for (int k = tid; k <= K; k += blockDim.x) s_psi[k] = a.lvl_tab[k];
     int iters = 0;
     long long ops = 0, pushes = 0;
     if (tid == 0) {
@@ -154,7 +148,7 @@ __global__ void __launch_bounds__(kSnapBlock) k_small_hk(HkSmallArgs<V> a) {
         const bool last = k == K;
         RD<V> *plane = (RD<V> *)a.plane[cur];
         RD<V> *nplane = (RD<V> *)a.plane[nxt];
-        const V wmul = (V)(a.tau / (double)(k + 1));
+        const V wmul = (V)a.lvl_tab[kHkMaxLevels + 1 + k];  // c_{k+1} / c_k
         if (tid == 0) {
             s_push_base = pushes;
             s_tcnt[(k + 1) % 3] = 0;  // the touched list of level k+1 starts empty

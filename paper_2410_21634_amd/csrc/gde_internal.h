@@ -150,6 +150,8 @@ struct Workspace {
     int32_t *bin_cursor = nullptr; // device [nranges], zero between iterations
     void *bin_e = nullptr;         // device [nnz_cap] BinEnt<V> entries
     int64_t nnz_cap = 0;           // CSR entries the tile table and bins can hold
+    double *lvl_tab = nullptr;     // level push: device [2][kHkMaxLevels + 1], psi then level ratios
+    std::vector<double> h_lvl;     // its host copy for the current solve
     DetWS *det = nullptr;          // deterministic mode, lazily
     GlobWS *glob = nullptr;        // global solvers, lazily
 };

@@ -1,6 +1,9 @@
 // gde_kernels.h -- host-side launch interface of the gfx950 kernels.
 #pragma once
 
+#include <cmath>
+#include <vector>
+
 #include "gde_internal.h"
 
 namespace gde {
@@ -94,12 +97,49 @@ struct HkSmallArgs {
     long long tr_ncap;
     long long *tr_size, *tr_vol;
     long long tr_cap;
-    double tau, eps;
+    const double *lvl_tab;       // device [2][kHkMaxLevels + 1]: psi_k, then the level ratios
+    double eps;
     int K, k0;
     int32_t cap, nnz;
 };
 
 template <typename V> void launch_small_hk(const HkSmallArgs<V> &a, hipStream_t s);
+
+// The series of a level-push query: c_0 (the scale of level 0), the level ratios
+// c_{k+1}/c_k (ratio[k], k < K) and psi_k = sum_{j=k..K} c_j / c_k.  The heat
+// kernel (c_k = e^-tau tau^k/k!) takes them from tau; GDE_SERIES from p->c.
+struct LevelSeries {
+    double c0 = 1.0;
+    std::vector<double> ratio, psi;
+};
+inline LevelSeries level_series(const gde_params *p) {
+    LevelSeries ls;
+    const int K = p->K;
+    ls.ratio.assign((size_t)K + 1, 0.0);
+    ls.psi.assign((size_t)K + 1, 0.0);
+    if (p->kind == GDE_SERIES) {
+        ls.c0 = p->c[0];
+        for (int k = 0; k <= K; k++) {
+            double acc = 0.0;
+            for (int j = k; j <= K; j++) acc += p->c[j] / p->c[k];
+            ls.psi[k] = acc;
+            if (k < K) ls.ratio[k] = p->c[k + 1] / p->c[k];
+        }
+    } else {
+        const double tau = p->tau;
+        ls.c0 = std::exp(-tau);
+        for (int k = 0; k <= K; k++) {
+            double acc = 0.0, term = 1.0;  // term = tau^{j-k} k!/j!
+            for (int j = k; j <= K; j++) {
+                if (j > k) term *= tau / (double)j;
+                acc += term;
+            }
+            ls.psi[k] = acc;
+            if (k < K) ls.ratio[k] = tau / (double)(k + 1);
+        }
+    }
+    return ls;
+}
 void launch_publish(const DevState *st, DevState *out, uint32_t *seq, uint32_t val, hipStream_t s);
 
 template <typename V> void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s);

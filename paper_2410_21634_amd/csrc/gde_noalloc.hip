@@ -89,9 +89,10 @@ void layout(Carve &c, Workspace *w, const gde_graph *g, const gde_params *p, int
     c.take(&w->wl_off, 4 * n);
     c.take(&w->wl_sv, vs * n);
     c.take(&w->tile_start, 4 * (size_t)(g->nnz / kPushTile + 2));
-    if (p->kind == GDE_HK) {
+    if (p->kind == GDE_HK || p->kind == GDE_SERIES) {
         c.take(&w->rd2, 2 * vs * n);
         for (int i = 0; i < 3; i++) c.take(&w->touched[i], 4 * n);
+        c.take(&w->lvl_tab, 16 * (size_t)(kHkMaxLevels + 1));
     }
     if (p->method == GDE_LOCAL_CH) {
         c.take(&w->delta, vs * n);

@@ -318,6 +318,7 @@ struct SReq {
     gde_params p{};
     std::vector<int32_t> idx;
     std::vector<double> val;
+    std::vector<double> coef;  // GDE_SERIES: the server's copy of p.c
     double t_sub = 0.0;
 };
 
@@ -740,6 +741,7 @@ static void hk_worker_main(gde_server *sv, HkWorker *wk) {
             std::shared_lock<std::shared_mutex> gl(sv->graph_mu);
             gde_seed sd{(int32_t)q.idx.size(), q.idx.data(), q.val.data()};
             gde_params p = q.p;
+            if (p.kind == GDE_SERIES) p.c = q.coef.data();
             p.value_type = GDE_F32;
             p.flags &= ~(uint32_t)(GDE_RESULT_DEVICE | GDE_TRACE);
             gde_result r{};
@@ -1016,15 +1018,20 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     std::unique_lock<std::mutex> lk(sv->hk_mu);
     if (sv->n_pending + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
         return fail(GDE_ERR_BUSY, "server queue is full");
-    if (p->kind != GDE_HK) lk.unlock();
+    const bool level = p->kind == GDE_HK || p->kind == GDE_SERIES;  // level-push workers
+    if (!level) lk.unlock();
     SReq r;
     r.ticket = sv->next_ticket++;
     r.p = *p;
+    if (p->kind == GDE_SERIES) {
+        r.coef.assign(p->c, p->c + p->K + 1);
+        r.p.c = nullptr;  // set to the copy when a worker takes the query
+    }
     r.idx.assign(s->idx, s->idx + s->nnz);
     r.val.assign(s->val, s->val + s->nnz);
     r.t_sub = now_s(sv->t0);
     *ticket = r.ticket;
-    if (p->kind == GDE_HK) {
+    if (level) {
         sv->hk_queue.push_back(std::move(r));
         lk.unlock();
         sv->hk_cv.notify_one();

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgde.so")
 
 OK, INVALID_ARG, ISOLATED_SEED, CAPACITY, NOT_CONVERGED, OOM, BUSY, DEVICE, UNSUPPORTED = range(9)
-PPR, KATZ, HK = 0, 1, 2
+PPR, KATZ, HK, SERIES = 0, 1, 2, 3
 LOCAL_GD, LOCAL_CH = 0, 1
 F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
@@ -26,7 +26,7 @@ SCATTER_BINNED, SCATTER_ATOMIC, DETERMINISTIC = 0x8, 0x10, 0x20
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # GDE_NOALLOC_SCRATCH_BYTES of gde.h
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
-KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK}
+KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK, "series": SERIES}
 METHODS = {"gd": LOCAL_GD, "localgd": LOCAL_GD, "ch": LOCAL_CH, "localch": LOCAL_CH}
 
 if not os.path.exists(LIB_PATH):
@@ -146,12 +146,20 @@ def _stream_ptr(stream):
 
 
 def make_params(kind="ppr", method="gd", *, alpha=0.1, beta=0.0, tau=5.0, K=30, eps=1e-6, lambda_bound=0.0,
-                value_type=F32, max_iters=10000, flags=0) -> Params:
+                value_type=F32, max_iters=10000, flags=0, c=None) -> Params:
+    """Query parameters.  ``c``: the K + 1 coefficients of kind "series" (K is
+    taken from their count); the returned struct keeps the array alive."""
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
     m = METHODS[method] if isinstance(method, str) else int(method)
     vt = {"f32": F32, "f64": F64}.get(value_type, value_type) if isinstance(value_type, str) else int(value_type)
-    return Params(k, m, vt, int(K), float(alpha), float(beta), float(tau), float(eps), float(lambda_bound), None,
-                  int(max_iters), int(flags))
+    coef = None
+    if c is not None:
+        coef = np.ascontiguousarray(c, dtype=np.float64)
+        K = len(coef) - 1
+    p = Params(k, m, vt, int(K), float(alpha), float(beta), float(tau), float(eps), float(lambda_bound),
+               coef.ctypes.data_as(C.POINTER(C.c_double)) if coef is not None else None, int(max_iters), int(flags))
+    p._coef = coef
+    return p
 
 
 class _SeedHolder:

@@ -54,6 +54,13 @@ def test_validation_errors(small):
     assert v(kind="hk", tau=-1.0) == gde.INVALID_ARG
     assert v(kind="hk", K=300) == gde.INVALID_ARG
     assert v(kind="hk", method="ch") == gde.UNSUPPORTED
+    assert v(kind="series", c=[0.5, 0.3, 0.2]) == gde.OK
+    assert v(kind="series", c=[0.5, 0.0, 0.2]) == gde.INVALID_ARG         # a zero coefficient
+    assert v(kind="series", c=[0.5, float("inf")]) == gde.INVALID_ARG
+    assert v(kind="series", c=[0.5, 0.3], method="ch") == gde.UNSUPPORTED
+    assert v(kind="series") == gde.INVALID_ARG                            # no coefficients
+    assert v(kind="ppr", c=[0.5]) == gde.INVALID_ARG                      # c is for SERIES only
+    assert v(kind="series", c=[1.0] * 258) == gde.INVALID_ARG             # K > 256
     assert v(max_iters=0) == gde.INVALID_ARG
     assert v(seed=(1, 0)) == gde.INVALID_ARG            # unsorted
     assert v(seed=(1, 1)) == gde.INVALID_ARG            # duplicate

@@ -1,0 +1,169 @@
+"""The general truncated-series kind (GDE_SERIES: f_K = sum_k c_k (A D^-1)^k s
+with user coefficients) against the oracle's level push (oracle.series).
+
+Protocol as for the heat kernel: when the integer traces (T, sum vol, sum |S_k|,
+per-level sizes) equal the oracle's, x must match within 1e-12 (FP64) / 1e-6
+(FP32) of the mass m = ||s||_1 max(1, sum_k c_k) (A D^-1 keeps mass, so
+||f_K||_1 <= sum_k c_k ||s||_1); otherwise the oracle replays the GPU's recorded
+level sets and grades every decision.  Also: the deterministic mode equals the
+oracle bit for bit in FP64; the binned scatter; heat-kernel coefficients give
+the heat kernel's answer; the server's level-push workers; a full-size solve on
+the n = 10^6 graph.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import solvers as O  # noqa: E402
+from paper_2410_21634_amd import workloads as W  # noqa: E402
+
+from _parity import KAPPA, RTOL, TOL  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def gde():
+    from paper_2410_21634_amd import gde as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(gde):
+    c = gde.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1(gde, ctx):
+    G = W.chung_lu(10000, 50000, 2.5, seed=42)
+    return G, gde.Graph(ctx, G.row_ptr, G.col_idx)
+
+
+def coefficient_sets():
+    rng = np.random.default_rng(11)
+    return {
+        "ppr_trunc": 0.1 * 0.9 ** np.arange(41),
+        "random": rng.uniform(0.05, 1.0, size=21),
+        "heat": np.array([math.exp(-5.0) * 5.0**k / math.factorial(k) for k in range(31)]),
+    }
+
+
+def check_series(gde, ctx, g, G, c, eps, seeds, vt, flags=0, out=None):
+    seeds = np.atleast_1d(np.asarray(seeds, dtype=np.int32))
+    val = np.ones(len(seeds))
+    p = gde.make_params("series", c=c, eps=eps, value_type=vt, flags=gde.TRACE | flags)
+    res = gde.solve(ctx, g, p, seeds, val, trace_cap=1000, nodes_cap=4_000_000, out=out)
+    if out is not None:
+        import torch
+        torch.cuda.synchronize()
+    ref = O.series(G.row_ptr, G.col_idx, c, eps, seeds, val, trace_cap=1000)
+    m = len(seeds) * max(1.0, float(np.sum(c)))
+    x = res.dense(G.n)
+    same = ((res.iters, res.ops, res.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+            and np.array_equal(res.trace_size, ref["trace_size"]) and np.array_equal(res.trace_vol, ref["trace_vol"]))
+    assert res.status == gde.OK
+    if same:
+        err = float(np.abs(x - ref["x"]).sum()) / m
+        np.testing.assert_allclose(res.residual_l1, ref["residual_l1"], rtol=RTOL[vt], atol=1e-300)
+        np.testing.assert_allclose(res.residual_dinf, ref["residual_dinf"], rtol=RTOL[vt], atol=1e-300)
+    else:
+        assert vt == gde.F32, (res.iters, ref["iters"], res.ops, ref["ops"])
+        off = np.zeros(len(res.trace_size) + 1, np.int64)
+        off[1:] = np.cumsum(res.trace_size)
+        rp = O.series(G.row_ptr, G.col_idx, c, eps, seeds, val, replay=(off, res.trace_nodes), kappa=KAPPA[vt])
+        assert rp["violations"] == 0, rp
+        err = float(np.abs(x - rp["x"]).sum()) / m
+    assert err <= TOL[vt], err
+    return res, ref, err, same
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+def test_series_matches_oracle(gde, ctx, c1, vt):
+    G, g = c1
+    seeds = [int(s) for s in W.uniform_seeds(G, 2, seed=21)] + [int(np.argmax(G.degrees))]
+    for name, c in coefficient_sets().items():
+        for eps in (1e-4, 1e-6):
+            for s in seeds:
+                res, ref, err, same = check_series(gde, ctx, g, G, c, eps, [s], vt)
+                print("series", name, eps, s, vt, "iters", res.iters, "ops", res.ops, "l1", err,
+                      "free-run" if same else "replay", flush=True)
+    set8 = sorted(set(int(v) for v in W.uniform_seeds(G, 12, seed=22)))[:8]
+    check_series(gde, ctx, g, G, coefficient_sets()["random"], 1e-6, set8, vt)
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+def test_series_binned_scatter(gde, ctx, c1, vt):
+    G, g = c1
+    s = int(W.uniform_seeds(G, 1, seed=23)[0])
+    for c in coefficient_sets().values():
+        check_series(gde, ctx, g, G, c, 1e-6, [s], vt, flags=gde.SCATTER_BINNED)
+
+
+def test_series_deterministic_bit_exact(gde, ctx, c1):
+    G, g = c1
+    s = int(W.uniform_seeds(G, 1, seed=24)[0])
+    for c in coefficient_sets().values():
+        p = gde.make_params("series", c=c, eps=1e-6, value_type=gde.F64, flags=gde.DETERMINISTIC)
+        res = gde.solve(ctx, g, p, [s])
+        ref = O.series(G.row_ptr, G.col_idx, c, 1e-6, [s])
+        assert (res.iters, res.ops) == (ref["iters"], ref["ops"])
+        assert np.array_equal(res.dense(G.n), ref["x"])
+
+
+def test_series_heat_coefficients_equal_heat_kernel(gde, ctx, c1):
+    G, g = c1
+    s = int(W.uniform_seeds(G, 1, seed=25)[0])
+    c = coefficient_sets()["heat"]
+    a = gde.solve(ctx, g, gde.make_params("series", c=c, eps=1e-6, value_type=gde.F64), [s])
+    b = gde.solve(ctx, g, gde.make_params("hk", tau=5.0, K=30, eps=1e-6, value_type=gde.F64), [s])
+    assert (a.iters, a.ops) == (b.iters, b.ops)
+    assert np.abs(a.dense(G.n) - b.dense(G.n)).sum() <= 1e-12
+
+
+def test_series_in_server(gde, ctx, c1):
+    G, g = c1
+    seeds = [int(s) for s in W.uniform_seeds(G, 6, seed=26)]
+    c = coefficient_sets()["random"]
+    srv = gde.Server(ctx, g, lanes_per_group=8, max_groups=2, iters_per_step=3)
+    tickets = {}
+    for i, s in enumerate(seeds):
+        cc = c if i % 2 == 0 else coefficient_sets()["ppr_trunc"]
+        t = srv.submit(gde.make_params("series", c=cc, eps=1e-5), [s])
+        tickets[t] = (s, cc)
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < 60:
+        for comp in srv.poll():
+            got[comp["ticket"]] = comp
+        time.sleep(0.002)
+    srv.close()
+    assert len(got) == len(tickets)
+    for t, (s, cc) in tickets.items():
+        comp = got[t]
+        assert comp["status"] == gde.OK
+        x = np.zeros(G.n)
+        x[comp["idx"]] = comp["val"]
+        ref = O.series(G.row_ptr, G.col_idx, cc, 1e-5, [s])
+        err = np.abs(x - ref["x"]).sum() / max(1.0, cc.sum())
+        print("server series", s, "l1", err, flush=True)
+        assert err <= TOL[gde.F32]
+
+
+def test_series_full_size_c2(gde, ctx):
+    import torch
+    G = W.chung_lu(1_000_000, 10_000_000, 2.5, seed=42)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
+    s = int(W.uniform_seeds(G, 64, seed=42)[3])
+    out = (torch.empty(G.n, dtype=torch.int32, device=dev), torch.empty(G.n, dtype=torch.float32, device=dev))
+    for name in ("ppr_trunc", "random"):
+        res, ref, err, same = check_series(gde, ctx, g, G, coefficient_sets()[name], 1e-7, [s], gde.F32, out=out)
+        print("series c2", name, "iters", res.iters, "ops", res.ops, "max level vol", int(np.max(res.trace_vol)),
+              "l1", err, "free-run" if same else "replay", flush=True)
+    g.close()
