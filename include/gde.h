@@ -324,6 +324,52 @@ size_t gde_solve_noalloc_bytes(const gde_graph *g, const gde_params *p, const gd
 int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
                     gde_result *res, const char *schedule_json, hipStream_t stream);
 
+/* ------------------------------------------------ standing queries on a dynamic graph */
+/*
+ * Dynamic GDEs (Sec. 4): a private copy of a graph that changes by batches of
+ * edge insertions and deletions, and standing PPR / Katz LocalGD queries whose
+ * estimate x and residual r stay on the device between batches.  Each batch is
+ * applied to every query as the Insert / Delete corrections of
+ * LocalGS(Dynamic) and LocalSOR(Dynamic) (Algorithms 2-5) in the generic form
+ * r = b - Q x -- each undirected edge {a, c} as the directed events a -> c and
+ * c -> a, inserts before deletes; for PPR an event at a of current degree d
+ * moves D = x_a / d (insert: x_a += D, r_a -= D, r_c += (1-alpha) D; delete:
+ * the opposite signs; the first edge of a degree-0 node only adds (1-alpha) x_a
+ * to r_c); for Katz r_c +/-= beta x_a -- followed by a warm LocalGD re-solve
+ * from the corrected state: S_0 = {u : |r_u| >= theta_u, r_u != 0}, residuals
+ * may be negative.  The iterations run in the fixed order of GDE_DETERMINISTIC,
+ * so results do not depend on scheduling.  The first solve of a query starts
+ * from x = 0, r = b with S_0 = supp(s) forced (Definition 3.1).
+ *
+ * gde_dyn_create : copies g0 (device CSR) as version 0; value_type GDE_F32 or
+ *                  GDE_F64 for every query of this object.
+ * gde_dyn_graph  : the current version, usable with gde_solve / gde_solve_global
+ *                  (e.g. to compare with a solve from scratch); valid until the
+ *                  next gde_dyn_update or gde_dyn_destroy.
+ * gde_dyn_add    : a new standing query (PPR or Katz, LocalGD, p->value_type as
+ *                  the object's; GDE_KATZ_SUBTRACT_SEED unsupported), solved at
+ *                  once on the current version; *qid receives its id.
+ * gde_dyn_update : k_ins edges (iu[i], iv[i]) to insert -- each new, no
+ *                  self-loops -- and k_del existing edges (du[i], dv[i]) to
+ *                  delete; no edge twice in one batch.  All events are validated
+ *                  before anything changes (GDE_ERR_INVALID_ARG).  Then every
+ *                  query is corrected and re-solved.  Host arrays, borrowed.
+ * gde_dyn_read   : query qid's current x (sorted sparse, nonzero entries) into
+ *                  res (device buffers if flags has GDE_RESULT_DEVICE, else host),
+ *                  with iters / ops / pushes / residual norms of its last
+ *                  (re)solve.  GDE_ERR_CAPACITY as gde_solve.
+ * A gde_dyn is used by one host thread at a time; its work runs on its own
+ * stream and every call returns with it finished.
+ */
+typedef struct gde_dyn gde_dyn;
+int gde_dyn_create(gde_ctx *ctx, const gde_graph *g0, int32_t value_type, gde_dyn **out);
+const gde_graph *gde_dyn_graph(const gde_dyn *dy);
+int gde_dyn_add(gde_dyn *dy, const gde_params *p, const gde_seed *s, int32_t *qid);
+int gde_dyn_update(gde_dyn *dy, int32_t k_ins, const int32_t *iu, const int32_t *iv, int32_t k_del,
+                   const int32_t *du, const int32_t *dv);
+int gde_dyn_read(gde_dyn *dy, int32_t qid, gde_result *res, uint32_t flags);
+int gde_dyn_destroy(gde_dyn *dy);
+
 /* ---------------------------------------------------------------- serving */
 typedef struct gde_server_cfg {
     int32_t lanes_per_group;   /* queries per node-major residual tile (8, 16 or 32) */

@@ -489,6 +489,33 @@ int graph_replace_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const
     return GDE_OK;
 }
 
+// swap in a rebuilt CSR (owned) with the given current degrees, and drop every
+// context's workspaces of g (their tile tables, bins and degrees are stale)
+int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std::vector<int32_t> &deg) {
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        for (gde_ctx *c : g_ctxs) drop_workspaces_of(g, c);
+    }
+    if (g->owned) {
+        (void)hipFree(g->row_ptr);
+        (void)hipFree(g->col_idx);
+    }
+    g->row_ptr = rp;
+    g->col_idx = ci;
+    g->nnz = nnz;
+    g->owned = true;
+    int32_t dmax = 0;
+    for (int32_t v : deg) dmax = std::max(dmax, v);
+    g->d_max = dmax;
+    GraphHost *gh = graph_host(g);
+    if (gh) {
+        gh->deg = deg;
+        gh->row_ptr.assign(deg.size() + 1, 0);
+        for (size_t u = 0; u < deg.size(); u++) gh->row_ptr[u + 1] = gh->row_ptr[u] + deg[u];
+    }
+    return GDE_OK;
+}
+
 void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx) {
     for (size_t i = 0; i < ctx->ws.size();) {
         if (ctx->ws[i]->guid == g->uid) { ws_free(ctx->ws[i]); ctx->ws.erase(ctx->ws.begin() + i); }

@@ -14,6 +14,15 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
             long long *d_trs, long long *d_trv, int32_t *d_trn, long long tr_cap, long long tr_ncap, hipStream_t s,
             bool *converged);
 
+// LocalGD continued from the state in w (residual/degree plane, estimate, pushed
+// set, touched bitmap), the re-solve after edge events: S_0 = the active nodes
+// of the touched set, or the host list `forced` when given (a first solve's
+// supp(s)); signed residuals allowed; the state is left in place (residuals and
+// bitmaps are not cleared).  w->st holds the ops, pushes and residual norms.
+template <typename V>
+int det_warm(const gde_graph *g, const gde_params *p, Workspace *w, hipStream_t s, const int32_t *forced,
+             int32_t nforced, int32_t *T, bool *converged);
+
 void det_ws_free(DetWS *d);
 
 }  // namespace gde

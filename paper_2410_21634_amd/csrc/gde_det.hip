@@ -303,20 +303,20 @@ __global__ void __launch_bounds__(kDetBlock)
 // workgroup over the partials.  The residuals and the bitmap are cleared.
 template <typename V>
 __global__ void __launch_bounds__(kDetBlock) k_det_norm_part(uint32_t *bm, int64_t nwords, RD<V> *rd, double rscale,
-                                                             double *part, int64_t nblk) {
+                                                             double *part, int64_t nblk, int clear) {
     __shared__ double s_l1[kDetBlock], s_mx[kDetBlock];
     const int64_t i = blockIdx.x * (int64_t)kDetBlock + threadIdx.x;
     double l1 = 0.0, mx = 0.0;
     if (i < nwords) {
         uint32_t m = bm[i];
         if (m) {
-            bm[i] = 0u;
+            if (clear) bm[i] = 0u;
             while (m) {
                 const int b = __ffs((int)m) - 1;
                 m &= m - 1u;
                 const int64_t w = i * 32 + b;
                 const RD<V> e = rd[w];
-                rd[w].r = (V)0;
+                if (clear) rd[w].r = (V)0;
                 const double a = fabs((double)e.r) * rscale;
                 l1 = l1 + a;
                 const double dd = (double)e.d;
@@ -385,11 +385,16 @@ static void det_compact(DetWS *d, uint32_t *bm, int32_t *list, int slot, hipStre
 }
 
 template <typename V>
-static void det_norms(DetWS *d, uint32_t *bm, void *rd, double rscale, hipStream_t s) {
+static void det_norms(DetWS *d, uint32_t *bm, void *rd, double rscale, hipStream_t s, int clear = 1) {
     hipLaunchKernelGGL(k_det_norm_part<V>, dim3((unsigned)d->nblk), dim3(kDetBlock), 0, s, bm, d->nwords,
-                       (RD<V> *)rd, rscale, d->part, d->nblk);
+                       (RD<V> *)rd, rscale, d->part, d->nblk, clear);
     hipLaunchKernelGGL(k_det_norm_final, dim3(1), dim3(kDetBlock), 0, s, d->part, d->nblk, d->nrm);
 }
+
+template <typename V>
+static int det_gd_ch_loop(const gde_graph *g, const gde_params *p, Workspace *w, DetWS *d, long long ns,
+                          long long *d_trs, long long *d_trv, int32_t *d_trn, long long tr_cap, long long tr_ncap,
+                          hipStream_t s, int32_t *T_out, bool *converged);
 
 template <typename V>
 int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspace *w, const SeedInline *inl,
@@ -473,6 +478,33 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
 
     // PPR / Katz, LocalGD or LocalCH
     const bool ppr = p->kind == GDE_PPR;
+    launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, inl, sd->nnz, ppr ? p->alpha : 1.0, S, nullptr, nullptr, 0,
+                        w->tbm, w->st, s);
+    if ((rc = det_gd_ch_loop<V>(g, p, w, d, ns, d_trs, d_trv, d_trn, tr_cap, tr_ncap, s, &T, converged))) return rc;
+    det_norms<V>(d, w->tbm, w->rd, ppr ? 1.0 / p->alpha : 1.0, s);
+    hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1), 0, s, w->st, T, (const double *)d->nrm, 1, 0.0, 0.0);
+    if (p->kind == GDE_KATZ && (p->flags & GDE_KATZ_SUBTRACT_SEED))
+        launch_subtract_seed<V>(w->x, w->seed_idx, w->seed_val, sd->nnz, s);
+    GDE_HIP(hipGetLastError());
+    // a run that stopped at the iteration cap leaves its S_{t+1} bits cleared by
+    // the compaction; the S_t bitmaps are cleared at the next solve's start
+    return GDE_OK;
+}
+
+// The LocalGD / LocalCH iterations from the ns nodes in w->front[0] (S_0), on
+// w's residual/degree plane, estimate, pushed set and touched bitmap.
+template <typename V>
+static int det_gd_ch_loop(const gde_graph *g, const gde_params *p, Workspace *w, DetWS *d, long long ns,
+                          long long *d_trs, long long *d_trv, int32_t *d_trn, long long tr_cap, long long tr_ncap,
+                          hipStream_t s, int32_t *T_out, bool *converged) {
+    const size_t bmb = 4 * (size_t)d->nwords;
+    int32_t *S = w->front[0];
+    int32_t *U = w->front[1];
+    const unsigned pull_grid = kDetPullGrid;
+    long long base = 0;
+    int32_t T = 0;
+    *converged = false;
+    const bool ppr = p->kind == GDE_PPR;
     const bool ch = p->method == GDE_LOCAL_CH;
     const V wscale = (V)(ppr ? 1.0 - p->alpha : p->beta);
     const V eps_eff = (V)(ppr ? p->alpha * p->eps : p->eps);
@@ -484,8 +516,6 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
         sigma = (L + mu) / (L - mu);
         dlt = 1.0 / sigma;
     }
-    launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, inl, sd->nnz, ppr ? p->alpha : 1.0, S, nullptr, nullptr, 0,
-                        w->tbm, w->st, s);
     for (int t = 0;; t++) {
         if (ns == 0) { *converged = true; break; }
         if (t >= p->max_iters) break;
@@ -516,15 +546,64 @@ int det_run(const gde_graph *g, const gde_params *p, const gde_seed *sd, Workspa
         base += ns;
         ns = d->h_cnt[1];
     }
-    det_norms<V>(d, w->tbm, w->rd, ppr ? 1.0 / p->alpha : 1.0, s);
-    hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1), 0, s, w->st, T, (const double *)d->nrm, 1, 0.0, 0.0);
-    if (p->kind == GDE_KATZ && (p->flags & GDE_KATZ_SUBTRACT_SEED))
-        launch_subtract_seed<V>(w->x, w->seed_idx, w->seed_val, sd->nnz, s);
-    GDE_HIP(hipGetLastError());
-    // a run that stopped at the iteration cap leaves its S_{t+1} bits cleared by
-    // the compaction; the S_t bitmaps are cleared at the next solve's start
+    *T_out = T;
     return GDE_OK;
 }
+
+// S_0 of a warm start: the nodes of the touched bitmap whose residual is active
+template <typename V>
+__global__ void __launch_bounds__(kDetBlock) k_det_select(const uint32_t *__restrict__ tbm, int64_t nwords,
+                                                          const RD<V> *__restrict__ rd, V eps_eff, uint32_t *nbm) {
+    const int64_t i = blockIdx.x * (int64_t)kDetBlock + threadIdx.x;
+    if (i >= nwords) return;
+    uint32_t m = tbm[i], out = 0u;
+    while (m) {
+        const int b = __ffs((int)m) - 1;
+        m &= m - 1u;
+        const RD<V> e = rd[i * 32 + b];
+        if (e.r != (V)0 && fabs(e.r) >= eps_eff * e.d) out |= 1u << b;
+    }
+    nbm[i] = out;
+}
+
+template <typename V>
+int det_warm(const gde_graph *g, const gde_params *p, Workspace *w, hipStream_t s, const int32_t *forced,
+             int32_t nforced, int32_t *T, bool *converged) {
+    DetWS *d = nullptr;
+    int rc = det_ws_get(w, s, &d);
+    if (rc) return rc;
+    const bool ppr = p->kind == GDE_PPR;
+    const V eps_eff = (V)(ppr ? p->alpha * p->eps : p->eps);
+    const size_t bmb = 4 * (size_t)d->nwords;
+    GDE_HIP(hipMemsetAsync(d->sbm[0], 0, bmb, s));
+    GDE_HIP(hipMemsetAsync(d->sbm[1], 0, bmb, s));
+    GDE_HIP(hipMemsetAsync(w->st, 0, sizeof(DevState), s));
+    long long ns = 0;
+    if (forced) {  // a given S_0 (ascending ids), e.g. supp(s) of a first solve (Definition 3.1)
+        if (nforced > 0)
+            GDE_HIP(hipMemcpyAsync(w->front[0], forced, 4 * (size_t)nforced, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        ns = nforced;
+    } else {
+        hipLaunchKernelGGL(k_det_select<V>, dim3((unsigned)d->nblk), dim3(kDetBlock), 0, s, w->tbm, d->nwords,
+                           (const RD<V> *)w->rd, eps_eff, d->nbm);
+        det_compact(d, d->nbm, w->front[0], 1, s);
+        GDE_HIP(hipGetLastError());
+        GDE_HIP(hipMemcpyAsync(d->h_cnt, d->cnt, 16, hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        ns = d->h_cnt[1];
+    }
+    if ((rc = det_gd_ch_loop<V>(g, p, w, d, ns, nullptr, nullptr, nullptr, 0, 0, s, T, converged))) return rc;
+    det_norms<V>(d, w->tbm, w->rd, ppr ? 1.0 / p->alpha : 1.0, s, 0);
+    hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1), 0, s, w->st, *T, (const double *)d->nrm, 1, 0.0, 0.0);
+    GDE_HIP(hipGetLastError());
+    return GDE_OK;
+}
+
+template int det_warm<float>(const gde_graph *, const gde_params *, Workspace *, hipStream_t, const int32_t *,
+                             int32_t, int32_t *, bool *);
+template int det_warm<double>(const gde_graph *, const gde_params *, Workspace *, hipStream_t, const int32_t *,
+                              int32_t, int32_t *, bool *);
 
 template int det_run<float>(const gde_graph *, const gde_params *, const gde_seed *, Workspace *, const SeedInline *,
                             long long *, long long *, int32_t *, long long, long long, hipStream_t, bool *);

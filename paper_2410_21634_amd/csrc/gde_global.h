@@ -12,4 +12,13 @@ int solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gd
 
 void glob_ws_free(GlobWS *w);
 
+// Sparse form of a dense device vector (ascending ids of its nonzeros):
+// per-block counts into blk[dense_nblk(n) + 1], an exclusive scan with the total,
+// then the emission of (id, value) pairs at the scanned offsets.
+int64_t dense_nblk(int64_t n);
+template <typename V> void launch_dense_count(const V *x, int64_t n, int32_t *blk, hipStream_t s);
+void launch_dense_scan(int32_t *blk, int64_t nblk, long long *total, hipStream_t s);
+template <typename V>
+void launch_dense_emit(const V *x, int64_t n, const int32_t *blk, int32_t *idx, V *val, hipStream_t s);
+
 }  // namespace gde

@@ -249,13 +249,13 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_norm_final(const double *__
 }
 
 // sparse output: the nodes with x_u != 0 in ascending order
-// (x is read through inv: entry u of the output order is x[inv[u]])
+// (x is read through inv when given: entry u of the output order is x[inv[u]])
 template <typename V>
 __global__ void __launch_bounds__(kGlobBlock) k_glob_count(const V *__restrict__ x, const int32_t *__restrict__ inv,
                                                             int64_t n, int32_t *blk) {
     __shared__ int s[kGlobBlock / kWave];
     const int64_t u = blockIdx.x * (int64_t)kGlobBlock + threadIdx.x;
-    int c = (u < n && x[inv[u]] != (V)0) ? 1 : 0;
+    int c = (u < n && x[inv ? inv[u] : u] != (V)0) ? 1 : 0;
     for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if (lane() == 0) s[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_emit(const V *__restrict__ 
                                                            int32_t *out_idx, V *out_val) {
     __shared__ int s_w[kGlobBlock / kWave];
     const int64_t u = blockIdx.x * (int64_t)kGlobBlock + threadIdx.x;
-    const V v = u < n ? x[inv[u]] : (V)0;
+    const V v = u < n ? x[inv ? inv[u] : u] : (V)0;
     const bool nz = v != (V)0;
     const unsigned long long bal = __ballot(nz);
     const int before = __popcll(bal & lanemask_lt());
@@ -537,6 +537,29 @@ static int glob_run(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const
     if (!converged) return fail(GDE_ERR_NOT_CONVERGED, "max_iters reached before no node was active");
     return GDE_OK;
 }
+
+int64_t dense_nblk(int64_t n) { return (n + kGlobBlock - 1) / kGlobBlock; }
+
+template <typename V>
+void launch_dense_count(const V *x, int64_t n, int32_t *blk, hipStream_t s) {
+    hipLaunchKernelGGL(k_glob_count<V>, dim3((unsigned)dense_nblk(n)), dim3(kGlobBlock), 0, s, x,
+                       (const int32_t *)nullptr, n, blk);
+}
+
+void launch_dense_scan(int32_t *blk, int64_t nblk, long long *total, hipStream_t s) {
+    hipLaunchKernelGGL(k_glob_scan, dim3(1), dim3(1024), 0, s, blk, nblk, total);
+}
+
+template <typename V>
+void launch_dense_emit(const V *x, int64_t n, const int32_t *blk, int32_t *idx, V *val, hipStream_t s) {
+    hipLaunchKernelGGL(k_glob_emit<V>, dim3((unsigned)dense_nblk(n)), dim3(kGlobBlock), 0, s, x,
+                       (const int32_t *)nullptr, n, blk, idx, val);
+}
+
+template void launch_dense_count<float>(const float *, int64_t, int32_t *, hipStream_t);
+template void launch_dense_count<double>(const double *, int64_t, int32_t *, hipStream_t);
+template void launch_dense_emit<float>(const float *, int64_t, const int32_t *, int32_t *, float *, hipStream_t);
+template void launch_dense_emit<double>(const double *, int64_t, const int32_t *, int32_t *, double *, hipStream_t);
 
 int solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_seed *sd, gde_result *res,
                  hipStream_t s) {

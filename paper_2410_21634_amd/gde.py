@@ -96,6 +96,12 @@ _SIGS = {
     "gde_solve_global": ([_vp, _vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
     "gde_solve_noalloc": ([_vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), _vp], C.c_int),
     "gde_solve_noalloc_bytes": ([_vp, C.POINTER(Params), C.POINTER(Seed)], C.c_size_t),
+    "gde_dyn_create": ([_vp, _vp, _i32, C.POINTER(_vp)], C.c_int),
+    "gde_dyn_graph": ([_vp], _vp),
+    "gde_dyn_add": ([_vp, C.POINTER(Params), C.POINTER(Seed), C.POINTER(_i32)], C.c_int),
+    "gde_dyn_update": ([_vp, _i32, _vp, _vp, _i32, _vp, _vp], C.c_int),
+    "gde_dyn_read": ([_vp, _i32, C.POINTER(Result), C.c_uint32], C.c_int),
+    "gde_dyn_destroy": ([_vp], C.c_int),
     "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
                         C.c_int),
     "gde_server_create": ([_vp, _vp, C.POINTER(ServerCfg), C.POINTER(_vp)], C.c_int),
@@ -488,6 +494,68 @@ def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None
     res = BatchResults(rv, idx_of, val_of, traces)
     res._keep = (P, S, R, cat_idx, cat_val, host)
     return res
+
+
+class _GraphView:
+    """A graph handle owned by another object (the current version of a Dynamic)."""
+
+    def __init__(self, ctx, handle, n):
+        self.ctx, self.handle, self.n = ctx, handle, n
+
+
+class Dynamic:
+    """Standing PPR / Katz LocalGD queries on a graph changed by edge batches
+    (gde_dyn_*): the Insert / Delete corrections of Sec. 4 followed by a warm
+    re-solve, with x and r resident on the device."""
+
+    def __init__(self, ctx: Context, graph: Graph, value_type=F64):
+        self.ctx, self.n, self.value_type = ctx, graph.n, value_type
+        h = _vp()
+        _check(_lib.gde_dyn_create(ctx.handle, graph.handle, int(value_type), C.byref(h)))
+        self.handle = h
+
+    @property
+    def graph(self):
+        """The current version, for gde_solve / gde_solve_global comparisons."""
+        return _GraphView(self.ctx, _lib.gde_dyn_graph(self.handle), self.n)
+
+    def add(self, params: Params, seed_idx, seed_val=None) -> int:
+        sh = _SeedHolder(seed_idx, seed_val)
+        q = _i32()
+        _check(_lib.gde_dyn_add(self.handle, C.byref(params), C.byref(sh.seed), C.byref(q)))
+        return int(q.value)
+
+    def update(self, insert=(), delete=()):
+        iu = np.ascontiguousarray([e[0] for e in insert], dtype=np.int32)
+        iv = np.ascontiguousarray([e[1] for e in insert], dtype=np.int32)
+        du = np.ascontiguousarray([e[0] for e in delete], dtype=np.int32)
+        dv = np.ascontiguousarray([e[1] for e in delete], dtype=np.int32)
+        _check(_lib.gde_dyn_update(self.handle, len(iu), iu.ctypes.data_as(_vp), iv.ctypes.data_as(_vp), len(du),
+                                   du.ctypes.data_as(_vp), dv.ctypes.data_as(_vp)))
+
+    def read(self, qid: int) -> SolveResult:
+        vdt = np.float64 if self.value_type == F64 else np.float32
+        oi = np.zeros(max(self.n, 1), np.int32)
+        ov = np.zeros(max(self.n, 1), vdt)
+        r = Result()
+        r.capacity = self.n
+        r.idx = oi.ctypes.data
+        r.val = ov.ctypes.data
+        _check(_lib.gde_dyn_read(self.handle, int(qid), C.byref(r), 0), (OK, NOT_CONVERGED))
+        nnz = int(r.nnz)
+        return SolveResult(oi[:nnz].copy(), ov[:nnz].copy(), int(r.status), r.residual_l1, r.residual_dinf, r.iters,
+                           r.ops, r.pushes)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gde_dyn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     with open(os.path.join(ROOT, "include", "gde.h")) as fh:
         text = fh.read()
-    return sorted(set(re.findall(r"^(?:int|size_t|const char \*)\s*(gde_[a-z_]+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:int|size_t|const char \*|const gde_graph \*)\s*(gde_[a-z_]+)\s*\(", text,
+                                 re.M)))
 
 
 def test_header_symbols_exported():

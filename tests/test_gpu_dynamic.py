@@ -1,0 +1,198 @@
+"""Standing queries on a dynamic graph (gde_dyn_*) against the oracle's
+dynamic procedures: the first solve against oracle LocalGD (cold), then after
+every batch of insertions and deletions the oracle applies the same Insert /
+Delete corrections (oracle.edge_events, inserts before deletes) to its previous
+state and re-solves warm (oracle.localgd_warm) on the new graph.
+
+FP64: the first solve runs the deterministic iterations, so x equals the
+oracle's bit for bit; after a batch the corrections add into residuals with
+atomics (summation order differs), so the iteration counts and work must be
+equal and x within 1e-12 of the mass.  FP32: the state recomputed in FP64 on the
+new graph satisfies the stop rule within the FP32 residual bound.  A solve from
+scratch on the same version (through gde_dyn_graph) meets the same rule.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import exact as X  # noqa: E402
+from oracle import solvers as O  # noqa: E402
+from paper_2410_21634_amd import workloads as W  # noqa: E402
+
+from _parity import TOL, fp32_residual_bound, mass  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def gde():
+    from paper_2410_21634_amd import gde as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(gde):
+    c = gde.Context(0)
+    yield c
+    c.close()
+
+
+def edge_set(G):
+    s = set()
+    for a in range(G.n):
+        for b in G.col_idx[G.row_ptr[a]:G.row_ptr[a + 1]]:
+            if a < b:
+                s.add((a, int(b)))
+    return s
+
+
+def batches(G, rng):
+    """Three batches: inserts only, deletes only (isolating a leaf), both."""
+    E = edge_set(G)
+    d = np.diff(G.row_ptr)
+    out = []
+
+    def new_edges(k, E):
+        ins = set()
+        while len(ins) < k:
+            a, b = sorted(int(v) for v in rng.integers(0, G.n, 2))
+            if a != b and (a, b) not in E and (a, b) not in ins:
+                ins.add((a, b))
+        return sorted(ins)
+
+    ins = new_edges(300, E)
+    out.append((ins, []))
+    E = E | set(ins)
+    leaf = int(np.flatnonzero(d == 1)[0])
+    nb = int(G.col_idx[G.row_ptr[leaf]])
+    dels = [tuple(sorted((leaf, nb)))]
+    pool = sorted(E - set(dels))
+    dels += [pool[j] for j in rng.choice(len(pool), 199, replace=False)]
+    out.append(([], dels))
+    E = E - set(dels)
+    ins = new_edges(150, E)
+    pool = sorted(E)
+    dels = [pool[j] for j in rng.choice(len(pool), 150, replace=False)]
+    out.append((ins, dels))
+    return out
+
+
+def residual_of(row_ptr, col_idx, kind, param, seeds, x):
+    n = len(row_ptr) - 1
+    A = X.sparse_adjacency(row_ptr, col_idx)
+    d = np.diff(row_ptr).astype(float)
+    s = np.zeros(n)
+    s[np.asarray(seeds)] = 1.0
+    if kind == O.PPR:
+        inv = np.where(d > 0, 1.0 / np.maximum(d, 1), 0.0)
+        return param * s - (x - (1.0 - param) * (A @ (inv * x)))
+    return s - (x - param * (A @ x))
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+def test_dynamic_matches_oracle(gde, ctx, vt):
+    G = W.chung_lu(3000, 15000, 2.4, seed=17)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    lo, hi = X.lambda_bounds_power(G.row_ptr, G.col_idx, iters=300)
+    beta = 0.3 / hi
+    seeds = [int(s) for s in W.uniform_seeds(G, 3, seed=18)]
+    queries = [(O.PPR, "ppr", 0.1, 1e-6, [seeds[0]]), (O.PPR, "ppr", 0.15, 1e-5, sorted(seeds[1:3])),
+               (O.KATZ, "katz", beta, 1e-6, [seeds[2]])]
+    dyn = gde.Dynamic(ctx, g, value_type=vt)
+    qids, state, t_total = [], [], []
+    ev_total = 0  # the most events one node has seen so far (FP32 roundings of its x)
+    for kind, kname, param, eps, sd in queries:
+        prm = dict(alpha=param) if kind == O.PPR else dict(beta=param, lambda_bound=hi * 2.0)
+        qids.append(dyn.add(gde.make_params(kname, eps=eps, value_type=vt, **prm), sd))
+        ref = O.localgd(G.row_ptr, G.col_idx, kind, param, eps, sd)
+        state.append((ref["x"], ref["r"]))
+        got = dyn.read(qids[-1])
+        x = got.dense(G.n)
+        t_total.append(got.iters)
+        if vt == 1:
+            assert (got.iters, got.ops, got.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+            assert np.array_equal(x, ref["x"]), (kname, float(np.abs(x - ref["x"]).max()))
+        else:
+            assert np.abs(x - ref["x"]).sum() <= TOL[vt] * mass(kind, np.ones(len(sd)), ref["x"])
+    E = edge_set(G)
+    deg = np.diff(G.row_ptr).astype(np.int64)
+    rng = np.random.default_rng(19)
+    for b, (ins, dels) in enumerate(batches(G, rng)):
+        dyn.update(insert=ins, delete=dels)
+        ev_total += int(np.bincount(np.array([v for e in ins + dels for v in e], dtype=np.int64),
+                                    minlength=G.n).max())
+        E = (E | set(ins)) - set(dels)
+        G2 = W.from_edges(G.n, sorted(E))
+        d2 = np.diff(G2.row_ptr).astype(float)
+        for j, (kind, kname, param, eps, sd) in enumerate(queries):
+            x0, r0 = state[j]
+            x1, r1, _ = O.edge_events(kind, param, x0, r0, deg, [e[0] for e in ins], [e[1] for e in ins], +1)
+            deg_i = deg + np.bincount(np.array([v for e in ins for v in e], dtype=np.int64), minlength=G.n)
+            x1, r1, _ = O.edge_events(kind, param, x1, r1, deg_i, [e[0] for e in dels], [e[1] for e in dels], -1)
+            ref = O.localgd_warm(G2.row_ptr, G2.col_idx, kind, param, eps, x1, r1)
+            state[j] = (ref["x"], ref["r"])
+            got = dyn.read(qids[j])
+            x = got.dense(G.n)
+            t_total[j] += got.iters
+            err = float(np.abs(x - ref["x"]).sum()) / mass(kind, np.ones(len(sd)), ref["x"])
+            print("dyn batch", b, kname, vt, "iters", got.iters, ref["iters"], "ops", got.ops, ref["ops"], "l1", err,
+                  flush=True)
+            assert got.status == gde.OK
+            if vt == 1:
+                assert (got.iters, got.ops, got.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+                assert err <= TOL[vt]
+                np.testing.assert_allclose(got.residual_l1, ref["residual_l1"], rtol=1e-9, atol=1e-300)
+            else:
+                r = residual_of(G2.row_ptr, G2.col_idx, kind, param, sd, x)
+                sc = 1.0 / param if kind == O.PPR else 1.0
+                bound = fp32_residual_bound(G2.row_ptr, G2.col_idx, kind, param, eps, x, t_total[j],
+                                            events=ev_total)
+                # a node left with degree 0 has threshold 0: the device pushes whatever its
+                # residual holds, and in exact arithmetic the corrections cancel there, so
+                # what it holds (and x keeps) is the FP32 rounding of its correction terms,
+                # each at most max|x| (D = x_a / d_a, (1-alpha) D or beta x_a): at most
+                # 2 u per event, summed over the events the node has seen
+                iso = d2 == 0
+                bound[iso] = sc * 2.0 * 2.0**-24 * ev_total * float(np.abs(x).max() + np.abs(x0).max())
+                assert (np.abs(r) * sc <= bound).all(), (kname, b, int(np.argmax(np.abs(r) * sc - bound)))
+                assert err <= TOL[vt], err
+            # every node's recomputed residual meets the stop rule of the new graph
+            if vt == 1:
+                r = residual_of(G2.row_ptr, G2.col_idx, kind, param, sd, x)
+                sc = 1.0 / param if kind == O.PPR else 1.0
+                assert (np.abs(r[d2 > 0]) * sc < eps * d2[d2 > 0] * (1 + 1e-9) + 1e-15).all()
+        deg = np.diff(G2.row_ptr).astype(np.int64)
+        # the same version solved from scratch through gde_dyn_graph meets the rule too
+        kind, kname, param, eps, sd = queries[0]
+        cold = gde.solve(ctx, dyn.graph, gde.make_params(kname, alpha=param, eps=eps, value_type=vt), sd)
+        xc = cold.dense(G.n)
+        rc = residual_of(G2.row_ptr, G2.col_idx, kind, param, sd, xc) / param
+        lim = (fp32_residual_bound(G2.row_ptr, G2.col_idx, kind, param, eps, xc, cold.iters) if vt == 0
+               else eps * d2 * (1 + 1e-9) + 1e-15)
+        assert cold.status == gde.OK and (np.abs(rc) <= lim).all()
+    dyn.close()
+    g.close()
+
+
+def test_dynamic_rejects_bad_events(gde, ctx):
+    G = W.chung_lu(500, 2000, 2.5, seed=3)
+    g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    dyn = gde.Dynamic(ctx, g)
+    s = int(W.uniform_seeds(G, 1, seed=3)[0])
+    q = dyn.add(gde.make_params("ppr", eps=1e-4, value_type=gde.F64), [s])
+    before = dyn.read(q).dense(G.n)
+    a = int(G.col_idx[G.row_ptr[s]])
+    for ins, dels in (([(s, a)], []), ([], [(0, 0)]), ([(1, 1)], []), ([], [(s, s)])):
+        with pytest.raises(gde.GDEError):
+            dyn.update(insert=ins, delete=dels)
+    missing = next((u, v) for u in range(G.n) for v in range(u + 1, G.n) if (u, v) not in edge_set(G))
+    with pytest.raises(gde.GDEError):
+        dyn.update(delete=[missing])
+    with pytest.raises(gde.GDEError):
+        dyn.update(insert=[missing, missing[::-1]])
+    assert np.array_equal(dyn.read(q).dense(G.n), before)  # nothing changed
+    with pytest.raises(gde.GDEError):
+        dyn.add(gde.make_params("hk", value_type=gde.F64), [s])
+    with pytest.raises(gde.GDEError):
+        dyn.add(gde.make_params("ppr", value_type=gde.F32), [s])
+    dyn.close()
+    g.close()
