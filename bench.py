@@ -480,7 +480,7 @@ def run_c4(args):
     torch.cuda.empty_cache()
     if not args.no_sub:
         out["sub"] = dict(c2_plain=sub_c2(args), c1_latency=sub_c1(), c3_katz_hk=sub_c3(),
-                          global_vs_local=sub_global_vs_local())
+                          global_vs_local=sub_global_vs_local(), dynamic=sub_dynamic())
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline_c4(G, seeds, eps, budget_s=args.cpu_budget)
@@ -681,6 +681,71 @@ def sub_global_vs_local(budget_s=90.0):
     return out
 
 
+def sub_dynamic():
+    """Standing queries under graph snapshots (the analogue of the paper's dynamic
+    PPR experiment, Sec. 5): an ogbn-arxiv-sized Chung-Lu graph (n = 169,343,
+    1,166,243 edges, gamma 2.5), 17.9 % of its edges at the start and the rest
+    in 16 insertion batches (and a variant where every batch also deletes 10 % of
+    its size), 16 PPR queries (alpha 0.1, eps = 1e-2 / n, FP64).  Accumulated
+    operations (sum vol(S_t)) and time of the dynamic path (corrections and warm
+    re-solve, gde_dyn_update) against solving every query from scratch on each
+    snapshot (gde_solve)."""
+    import torch
+
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
+    G = W.chung_lu(169_343, 1_166_243, 2.5, seed=42)
+    n = G.n
+    eps = 1e-2 / n
+    out = dict(workload="Chung-Lu n=169,343, 1,166,243 edges, gamma 2.5, seed 42; 17.9% of the edges at start, "
+                        "16 batches; 16 uniform sources of graph 0 (deletions spare their edges); PPR alpha 0.1, eps 1e-2/n, FP64")
+    dev = torch.device("cuda:0")
+    for name, dfrac in (("insert", 0.0), ("insert_delete", 0.1)):
+        g0, _ = W.snapshots(G, 16, 0.179, 0.0, seed=42)
+        seeds = [int(s) for s in W.uniform_seeds(g0, 16, seed=42)]
+        g0, batches = W.snapshots(G, 16, 0.179, dfrac, seed=42, protect=seeds)
+        ctx = gde.Context(0)
+        rp = torch.from_numpy(g0.row_ptr).to(dev)
+        ci = torch.from_numpy(g0.col_idx).to(dev)
+        g = gde.Graph(ctx, rp, ci)
+        p = gde.make_params("ppr", alpha=0.1, eps=eps, value_type=gde.F64)
+        dyn = gde.Dynamic(ctx, g, value_type=gde.F64)
+        qids = [dyn.add(p, [s]) for s in seeds]
+        ops0 = sum(dyn.read(q).ops for q in qids)
+        dyn_ops, st_ops, dyn_ms, st_ms = [ops0], [ops0], [], []
+        oi = torch.empty(n, dtype=torch.int32, device=dev)
+        ov = torch.empty(n, dtype=torch.float64, device=dev)
+        for iu, iv, du, dv in batches:
+            t = time.perf_counter()
+            dyn.update(insert=list(zip(iu.tolist(), iv.tolist())), delete=list(zip(du.tolist(), dv.tolist())))
+            dyn_ms.append(1e3 * (time.perf_counter() - t))
+            dyn_ops.append(dyn_ops[-1] + sum(dyn.read(q).ops for q in qids))
+            gv = dyn.graph
+            gde.solve(ctx, gv, p, [seeds[0]], out=(oi, ov))  # the new version's workspace, untimed
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ops = 0
+            for s in seeds:
+                ops += gde.solve(ctx, gv, p, [s], out=(oi, ov)).ops
+            torch.cuda.synchronize()
+            st_ms.append(1e3 * (time.perf_counter() - t))
+            st_ops.append(st_ops[-1] + ops)
+        log(f"dynamic {name}: accumulated ops dynamic {dyn_ops[-1]} static {st_ops[-1]}")
+        out[name] = dict(accumulated_ops_dynamic=dyn_ops, accumulated_ops_static=st_ops,
+                         ops_ratio_static_over_dynamic=round(st_ops[-1] / max(dyn_ops[-1], 1), 2),
+                         ms_per_batch_dynamic=round(float(np.mean(dyn_ms)), 3),
+                         ms_per_batch_static=round(float(np.mean(st_ms)), 3),
+                         timing="dynamic: gde_dyn_update (host event checks, CSR rebuild and upload, corrections "
+                                "and fixed-order re-solve of all 16 queries); static: 16 gde_solve calls")
+        dyn.close()
+        g.close()
+        ctx.close()
+        del rp, ci
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_sweep(args, ctx, g, G, qps_list, warm_s, serve_s):
     """Open-loop Poisson arrivals of mixed PPR / Katz / HK queries (kind uniform,
     half single seeds, half 8-node seed sets, eps log-uniform [1e-7, 1e-4] for
@@ -823,8 +888,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve", "global"],
-                    help="global: only the local-vs-global comparison record")
+    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve", "global", "dynamic"],
+                    help="global / dynamic: only the local-vs-global or the snapshot record")
     ap.add_argument("--plain-sample", type=int, default=1024,
                     help="c4: plain solves timed for the comparison (1,024 = every query of the batch)")
     ap.add_argument("--no-sub", action="store_true", help="c4: skip the serving and other-config sub-records")
@@ -860,6 +925,8 @@ def main():
         sys.exit(2)
     if args.workload == "global":
         out = sub_global_vs_local(budget_s=1e9)
+    elif args.workload == "dynamic":
+        out = sub_dynamic()
     else:
         out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
     print(json.dumps(out), flush=True)

@@ -148,6 +148,59 @@ def from_edges(n: int, edges) -> Graph:
     return Graph(n, row_ptr, col_idx, 0.0, 0)
 
 
+def from_edge_arrays(n: int, u, v) -> Graph:
+    """Symmetric CSR (ascending neighbour lists) of the undirected edges
+    (u[i], v[i]); the edges must be distinct and free of self-loops."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    src = np.concatenate([u, v])
+    dst = np.concatenate([v, u])
+    order = np.lexsort((dst, src))
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(np.bincount(src, minlength=n))
+    return Graph(n, row_ptr, dst[order].astype(np.int32), 0.0, 0)
+
+
+def edge_arrays(graph: Graph):
+    """The undirected edges (u < v) of a symmetric CSR, in CSR order."""
+    src = np.repeat(np.arange(graph.n, dtype=np.int64), np.diff(graph.row_ptr))
+    keep = src < graph.col_idx
+    return src[keep].astype(np.int32), graph.col_idx[keep].astype(np.int32)
+
+
+def snapshots(graph: Graph, k: int = 16, initial: float = 0.179, delete_frac: float = 0.0, seed: int = 42,
+              protect=()):
+    """Dynamic-graph workload in the manner of the paper's snapshot experiment
+    (Sec. 5, 16 snapshots, 17.9% of the edges at the start): the edges in a
+    seeded random order, the first `initial` share as graph 0, the rest in k
+    equal insertion batches; with delete_frac > 0 every batch also deletes that
+    share of its size from the edges present before it, never an edge at a node
+    of `protect` (so that query seeds keep their edges).  Graph 0 does not
+    depend on delete_frac or protect.  Returns (graph 0,
+    [(insert_u, insert_v, delete_u, delete_v)] * k)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    u, v = edge_arrays(graph)
+    perm = rng.permutation(len(u))
+    u, v = u[perm], v[perm]
+    m0 = int(round(initial * len(u)))
+    present = np.zeros(len(u), dtype=bool)
+    present[:m0] = True
+    guard = np.zeros(graph.n, dtype=bool)
+    guard[np.asarray(list(protect), dtype=np.int64)] = True
+    deletable = ~(guard[u] | guard[v])
+    g0 = from_edge_arrays(graph.n, u[:m0], v[:m0])
+    bounds = np.linspace(m0, len(u), k + 1).round().astype(np.int64)
+    out = []
+    for b in range(k):
+        lo, hi = bounds[b], bounds[b + 1]
+        nd = int(round(delete_frac * (hi - lo)))
+        dels = rng.choice(np.flatnonzero(present & deletable), nd, replace=False) if nd else np.zeros(0, np.int64)
+        present[dels] = False
+        present[lo:hi] = True
+        out.append((u[lo:hi], v[lo:hi], u[dels], v[dels]))
+    return g0, out
+
+
 def grid_2d(rows: int, cols: int) -> Graph:
     """The rows x cols 4-neighbour grid graph (node (i, j) has id i * cols + j):
     1000 x 1000 gives 10^6 nodes and 1,998,000 edges, the grid of the paper's

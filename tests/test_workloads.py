@@ -54,3 +54,25 @@ def test_grid_2d_matches_edge_list():
     assert np.array_equal(G.row_ptr, H.row_ptr) and np.array_equal(G.col_idx, H.col_idx)
     big = W.grid_2d(1000, 1000)
     assert big.n == 10**6 and big.nnz == 2 * 1_998_000
+
+
+def test_snapshots_insert_then_delete_sequence():
+    from paper_2410_21634_amd import workloads as W
+    G = W.chung_lu(3000, 15000, 2.5, seed=5)
+    u, v = W.edge_arrays(G)
+    H = W.from_edge_arrays(G.n, u, v)
+    assert np.array_equal(G.row_ptr, H.row_ptr) and np.array_equal(G.col_idx, H.col_idx)
+    protect = [int(s) for s in W.uniform_seeds(G, 4, seed=1)]
+    g0, batches = W.snapshots(G, 8, 0.179, 0.1, seed=7, protect=protect)
+    g0b, _ = W.snapshots(G, 8, 0.179, 0.0, seed=7)
+    assert np.array_equal(g0.col_idx, g0b.col_idx)  # graph 0 does not depend on the deletions
+    E = set(zip(*W.edge_arrays(g0)))
+    assert len(E) == round(0.179 * len(u))
+    for iu, iv, du, dv in batches:
+        for a, b in zip(du.tolist(), dv.tolist()):
+            assert (a, b) in E and a not in protect and b not in protect
+            E.discard((a, b))
+        for a, b in zip(iu.tolist(), iv.tolist()):
+            assert (a, b) not in E
+            E.add((a, b))
+    assert len(E) == len(u) - sum(len(b[2]) for b in batches)
