@@ -64,7 +64,7 @@ typedef enum gde_status {
 } gde_status;
 
 typedef enum gde_kind { GDE_PPR = 0, GDE_KATZ = 1, GDE_HK = 2, GDE_SERIES = 3 } gde_kind;
-typedef enum gde_method { GDE_LOCAL_GD = 0, GDE_LOCAL_CH = 1 } gde_method;
+typedef enum gde_method { GDE_LOCAL_GD = 0, GDE_LOCAL_CH = 1, GDE_LOCAL_SOR = 2 } gde_method;
 typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
 
 /* gde_graph_create flags */
@@ -105,7 +105,15 @@ typedef struct gde_server gde_server;
 
 /*
  * One diffusion query.
- *   kind, method     : gde_kind, gde_method (LocalCH with HK or SERIES -> GDE_ERR_UNSUPPORTED)
+ *   kind, method     : gde_kind, gde_method (LocalCH or LocalSOR with HK or SERIES ->
+ *                      GDE_ERR_UNSUPPORTED).  GDE_LOCAL_SOR is the sequential push of
+ *                      Eq. (7) / Algorithm 1 (APPR and AKatz at omega = 1): a FIFO queue
+ *                      starting with supp(s) in index order; pop u, v = r_u,
+ *                      x_u += omega v, r_u -= omega v, r_w += omega w_u v on N(u), and
+ *                      every active node that is not queued joins the tail (the
+ *                      neighbours in CSR order, then u).  Each query runs in one
+ *                      wavefront; gde_solve_batch runs many at once.  Its "iterations"
+ *                      are the queue generations (the t of Eq. (7)), pushes the pops.
  *   value_type       : GDE_F32 or GDE_F64 -- the type of x and r on the device
  *   alpha            : PPR damping, 0 < alpha < 1
  *   beta             : Katz weight, beta > 0 and beta * lambda_bound < 1
@@ -140,6 +148,7 @@ typedef struct gde_params {
     const double *c;
     int32_t max_iters;
     uint32_t flags;
+    double omega;  /* GDE_LOCAL_SOR: relaxation, 0 < omega < 2; 0 means 1 (APPR / AKatz) */
 } gde_params;
 
 /* Sparse source vector s in host memory: idx strictly increasing node ids,

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgde.so")
 SOURCES = ["gde_kernels.hip", "gde_hk_small.hip", "gde_api.hip", "gde_det.hip", "gde_batch_kernels.hip",
-           "gde_batch.hip", "gde_server.hip", "gde_noalloc.hip", "gde_global.hip", "gde_dyn.hip"]
+           "gde_batch.hip", "gde_server.hip", "gde_noalloc.hip", "gde_global.hip", "gde_dyn.hip", "gde_fifo.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_FLAGS = [

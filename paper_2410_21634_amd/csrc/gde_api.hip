@@ -54,7 +54,14 @@ static int validate_csr_host(int32_t n, int64_t nnz, const int32_t *rp, const in
 static int validate_params(const gde_params *p) {
     if (!p) return fail(GDE_ERR_INVALID_ARG, "null params");
     if (p->kind < GDE_PPR || p->kind > GDE_SERIES) return fail(GDE_ERR_INVALID_ARG, "unknown kind");
-    if (p->method != GDE_LOCAL_GD && p->method != GDE_LOCAL_CH) return fail(GDE_ERR_INVALID_ARG, "unknown method");
+    if (p->method != GDE_LOCAL_GD && p->method != GDE_LOCAL_CH && p->method != GDE_LOCAL_SOR)
+        return fail(GDE_ERR_INVALID_ARG, "unknown method");
+    if (p->method == GDE_LOCAL_SOR) {
+        if (p->omega != 0.0 && !(p->omega > 0.0 && p->omega < 2.0))
+            return fail(GDE_ERR_INVALID_ARG, "LocalSOR needs 0 < omega < 2 (0 means 1)");
+        if (p->kind == GDE_HK || p->kind == GDE_SERIES)
+            return fail(GDE_ERR_UNSUPPORTED, "LocalSOR covers PPR and Katz");
+    }
     if (p->value_type != GDE_F32 && p->value_type != GDE_F64) return fail(GDE_ERR_INVALID_ARG, "unknown value_type");
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(GDE_ERR_INVALID_ARG, "eps must be finite and > 0");
     if (p->max_iters < 1) return fail(GDE_ERR_INVALID_ARG, "max_iters must be >= 1");
@@ -1273,6 +1280,7 @@ int gde_solve(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gde_s
     if (res->capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
     if (g->device != ctx->device) return fail(GDE_ERR_INVALID_ARG, "graph and context on different devices");
     GDE_HIP(hipSetDevice(ctx->device));
+    if (p->method == GDE_LOCAL_SOR) return solve_fifo(ctx, g, 1, p, s, res, stream);
     if (p->value_type == GDE_F64) return solve_plain<double>(ctx, g, p, s, res, stream);
     return solve_plain<float>(ctx, g, p, s, res, stream);
 }
@@ -1282,9 +1290,9 @@ int gde_solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, cons
     if (!ctx || !g || !res) return fail(GDE_ERR_INVALID_ARG, "null ctx, graph or result");
     int rc = validate_params(p);
     if (rc) { res->status = rc; return rc; }
-    if (p->kind == GDE_HK || p->kind == GDE_SERIES) {
+    if (p->kind == GDE_HK || p->kind == GDE_SERIES || p->method == GDE_LOCAL_SOR) {
         res->status = GDE_ERR_UNSUPPORTED;
-        return fail(GDE_ERR_UNSUPPORTED, "the global solvers cover PPR and Katz");
+        return fail(GDE_ERR_UNSUPPORTED, "the global solvers are GD and Chebyshev for PPR and Katz");
     }
     GraphHost *gh = graph_host(g);
     if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");

@@ -12,6 +12,7 @@
 
 #include "gde_batch.h"
 #include "gde_batch_kernels.h"
+#include "gde_global.h"
 #include "gde_internal.h"
 
 namespace gde {
@@ -586,6 +587,14 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
                 (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
     }
     GDE_HIP(hipSetDevice(ctx->device));
+    // LocalSOR / APPR: every query in one wavefront of the same launch
+    bool sor = true;
+    for (int32_t i = 0; i < B && sor; i++)
+        sor = p[i].method == GDE_LOCAL_SOR && p[i].value_type == p[0].value_type;
+    if (sor) {
+        for (int32_t i = 0; i < B; i++) res[i].status = GDE_OK;
+        return solve_fifo(ctx, g, B, p, s, res, stream);
+    }
     if (!fused) {
         int first = GDE_OK;
         for (int32_t i = 0; i < B; i++) {

@@ -12,6 +12,11 @@ int solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const gd
 
 void glob_ws_free(GlobWS *w);
 
+// LocalSOR / APPR (the FIFO push, gde_fifo.hip): B queries, one wavefront each;
+// every p[i] has method GDE_LOCAL_SOR and the same value type.
+int solve_fifo(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *sd, gde_result *res,
+               hipStream_t s);
+
 // Sparse form of a dense device vector (ascending ids of its nonzeros):
 // per-block counts into blk[dense_nblk(n) + 1], an exclusive scan with the total,
 // then the emission of (id, value) pairs at the scanned offsets.

@@ -138,6 +138,7 @@ extern "C" int gde_solve_noalloc(const gde_graph *g, const gde_params *p, const 
     if (res->capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
     if (!(p->flags & GDE_RESULT_DEVICE))
         return fail(GDE_ERR_INVALID_ARG, "gde_solve_noalloc writes device results only (set GDE_RESULT_DEVICE)");
+    if (p->method == GDE_LOCAL_SOR) return fail(GDE_ERR_UNSUPPORTED, "gde_solve_noalloc runs LocalGD and LocalCH");
     if (p->flags & (GDE_TRACE | GDE_DETERMINISTIC | GDE_SCATTER_BINNED))
         return fail(GDE_ERR_UNSUPPORTED, "gde_solve_noalloc provides no trace, deterministic mode or binned scatter");
     if (s->nnz > kNoallocSeedCap) return fail(GDE_ERR_INVALID_ARG, "gde_solve_noalloc takes at most 4096 seed entries");

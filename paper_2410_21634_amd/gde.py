@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgde.so")
 
 OK, INVALID_ARG, ISOLATED_SEED, CAPACITY, NOT_CONVERGED, OOM, BUSY, DEVICE, UNSUPPORTED = range(9)
 PPR, KATZ, HK, SERIES = 0, 1, 2, 3
-LOCAL_GD, LOCAL_CH = 0, 1
+LOCAL_GD, LOCAL_CH, LOCAL_SOR = 0, 1, 2
 F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
 KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
@@ -27,7 +27,8 @@ NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # GDE_NOALLOC_SCRATCH_BYTES of gde.h
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
 KINDS = {"ppr": PPR, "katz": KATZ, "hk": HK, "series": SERIES}
-METHODS = {"gd": LOCAL_GD, "localgd": LOCAL_GD, "ch": LOCAL_CH, "localch": LOCAL_CH}
+METHODS = {"gd": LOCAL_GD, "localgd": LOCAL_GD, "ch": LOCAL_CH, "localch": LOCAL_CH, "sor": LOCAL_SOR,
+           "localsor": LOCAL_SOR, "appr": LOCAL_SOR}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2410_21634_amd.build` (hipcc, gfx950)")
@@ -45,7 +46,7 @@ class Params(C.Structure):
     _fields_ = [("kind", C.c_int32), ("method", C.c_int32), ("value_type", C.c_int32), ("K", C.c_int32),
                 ("alpha", C.c_double), ("beta", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
                 ("lambda_bound", C.c_double), ("c", C.POINTER(C.c_double)), ("max_iters", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("omega", C.c_double)]
 
 
 class Seed(C.Structure):
@@ -152,7 +153,7 @@ def _stream_ptr(stream):
 
 
 def make_params(kind="ppr", method="gd", *, alpha=0.1, beta=0.0, tau=5.0, K=30, eps=1e-6, lambda_bound=0.0,
-                value_type=F32, max_iters=10000, flags=0, c=None) -> Params:
+                value_type=F32, max_iters=10000, flags=0, c=None, omega=0.0) -> Params:
     """Query parameters.  ``c``: the K + 1 coefficients of kind "series" (K is
     taken from their count); the returned struct keeps the array alive."""
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
@@ -163,7 +164,8 @@ def make_params(kind="ppr", method="gd", *, alpha=0.1, beta=0.0, tau=5.0, K=30, 
         coef = np.ascontiguousarray(c, dtype=np.float64)
         K = len(coef) - 1
     p = Params(k, m, vt, int(K), float(alpha), float(beta), float(tau), float(eps), float(lambda_bound),
-               coef.ctypes.data_as(C.POINTER(C.c_double)) if coef is not None else None, int(max_iters), int(flags))
+               coef.ctypes.data_as(C.POINTER(C.c_double)) if coef is not None else None, int(max_iters), int(flags),
+               float(omega))
     p._coef = coef
     return p
 

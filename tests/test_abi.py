@@ -62,6 +62,11 @@ def test_validation_errors(small):
     assert v(kind="series") == gde.INVALID_ARG                            # no coefficients
     assert v(kind="ppr", c=[0.5]) == gde.INVALID_ARG                      # c is for SERIES only
     assert v(kind="series", c=[1.0] * 258) == gde.INVALID_ARG             # K > 256
+    assert v(method="sor") == gde.OK and v(method="sor", omega=1.4) == gde.OK
+    assert v(method="sor", omega=2.0) == gde.INVALID_ARG
+    assert v(method="sor", omega=-0.5) == gde.INVALID_ARG
+    assert v(kind="hk", method="sor") == gde.UNSUPPORTED
+    assert v(method=3) == gde.INVALID_ARG
     assert v(max_iters=0) == gde.INVALID_ARG
     assert v(seed=(1, 0)) == gde.INVALID_ARG            # unsorted
     assert v(seed=(1, 1)) == gde.INVALID_ARG            # duplicate
