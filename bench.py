@@ -480,7 +480,7 @@ def run_c4(args):
     torch.cuda.empty_cache()
     if not args.no_sub:
         out["sub"] = dict(c2_plain=sub_c2(args), c1_latency=sub_c1(), c3_katz_hk=sub_c3(),
-                          global_vs_local=sub_global_vs_local(), dynamic=sub_dynamic())
+                          global_vs_local=sub_global_vs_local(), dynamic=sub_dynamic(), localsor=sub_sor())
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline_c4(G, seeds, eps, budget_s=args.cpu_budget)
@@ -678,6 +678,61 @@ def sub_global_vs_local(budget_s=90.0):
         ctx.close()
         del rp, ci
         torch.cuda.empty_cache()
+    return out
+
+
+def sub_sor(n_seeds=256):
+    """LocalSOR at omega* and APPR (the FIFO push, one query per wavefront)
+    against batched LocalGD as eps shrinks, on an ogbn-arxiv-sized Chung-Lu
+    graph (n = 169,343, 1,166,243 edges), PPR alpha 0.1: the comparison of
+    Fig. 5.  Solves/s of one gde_solve_batch call per method and eps, and the
+    mean operations (sum of d_u over the pushes) of its queries."""
+    import math
+
+    import torch
+
+    from paper_2410_21634_amd import gde
+    from paper_2410_21634_amd import workloads as W
+
+    G = W.chung_lu(169_343, 1_166_243, 2.5, seed=42)
+    seeds = [int(s) for s in W.uniform_seeds(G, n_seeds, seed=42)]
+    ctx = gde.Context(0)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(G.row_ptr).to(dev)
+    ci = torch.from_numpy(G.col_idx).to(dev)
+    g = gde.Graph(ctx, rp, ci)
+    om_star = 2.0 / (1.0 + math.sqrt(1.0 - 0.9 ** 2))
+    cap = G.n
+    bo = (torch.empty(n_seeds * cap, dtype=torch.int32, device=dev),
+          torch.empty(n_seeds * cap, dtype=torch.float32, device=dev))
+    methods = (("localgd", "gd", 0.0), ("appr", "sor", 1.0), ("localsor_omega_star", "sor", om_star))
+    out = dict(workload=f"Chung-Lu n=169,343, 1,166,243 edges, gamma 2.5, seed 42; {n_seeds} uniform seeds; "
+                        "PPR alpha 0.1; one gde_solve_batch call per method and eps (FP32 output; LocalSOR and "
+                        "APPR keep FP64 state)",
+               omega_star=round(om_star, 4), nnz=int(len(G.col_idx)), per_eps={})
+    for i, eps in enumerate((1e-6, 1e-7, 1e-8)):
+        rec = {}
+        for name, method, om in methods:
+            ps = [gde.make_params("ppr", method, alpha=0.1, eps=eps, omega=om, value_type=gde.F32) for _ in seeds]
+            if i == 0:  # first call per method sizes the workspaces
+                gde.solve_batch(ctx, g, ps, [([s], None) for s in seeds], out=bo)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = gde.solve_batch(ctx, g, ps, [([s], None) for s in seeds], out=bo)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            assert (np.asarray(res.status) == gde.OK).all(), name
+            rec[name] = dict(solves_per_s=round(n_seeds / dt, 1), mean_ops=round(float(res.ops.mean()), 1),
+                             mean_pushes=round(float(res.pushes.mean()), 1))
+        rec["mean_ops_over_nnz_appr"] = round(rec["appr"]["mean_ops"] / len(G.col_idx), 3)
+        rec["ops_sor_star_over_appr"] = round(rec["localsor_omega_star"]["mean_ops"] / rec["appr"]["mean_ops"], 3)
+        out["per_eps"][f"{eps:g}"] = rec
+        log(f"sor eps {eps:g}: " + ", ".join(f"{k} {v['solves_per_s']}/s ops {v['mean_ops']:.3g}"
+                                             for k, v in rec.items() if isinstance(v, dict)))
+    g.close()
+    ctx.close()
+    del rp, ci, bo
+    torch.cuda.empty_cache()
     return out
 
 
@@ -888,8 +943,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve", "global", "dynamic"],
-                    help="global / dynamic: only the local-vs-global or the snapshot record")
+    ap.add_argument("--workload", default="c4", choices=["c2", "c4", "serve", "global", "dynamic", "sor"],
+                    help="global / dynamic / sor: only the local-vs-global, snapshot or LocalSOR record")
     ap.add_argument("--plain-sample", type=int, default=1024,
                     help="c4: plain solves timed for the comparison (1,024 = every query of the batch)")
     ap.add_argument("--no-sub", action="store_true", help="c4: skip the serving and other-config sub-records")
@@ -927,6 +982,8 @@ def main():
         out = sub_global_vs_local(budget_s=1e9)
     elif args.workload == "dynamic":
         out = sub_dynamic()
+    elif args.workload == "sor":
+        out = sub_sor()
     else:
         out = {"c2": run_c2, "c4": run_c4, "serve": run_serve}[args.workload](args)
     print(json.dumps(out), flush=True)

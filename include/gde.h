@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define GDE_ABI_VERSION 1
+#define GDE_ABI_VERSION 2
 
 typedef enum gde_status {
     GDE_OK = 0,

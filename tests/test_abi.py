@@ -25,7 +25,7 @@ def test_header_symbols_exported():
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) == set(gde.EXPORTED)
-    assert gde.abi_version() == 1
+    assert gde.abi_version() == 2
 
 
 @pytest.fixture(scope="module")
