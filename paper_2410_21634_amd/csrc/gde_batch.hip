@@ -1,5 +1,6 @@
 // gde_batch.hip -- host side of gde_solve_batch: many LocalGD queries (PPR or
-// Katz) solved together by the node-major lane kernels of gde_batch_kernels.hip.
+// Katz), or many level-push queries (heat kernel, series), solved together by
+// the node-major lane kernels of gde_batch_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +15,7 @@
 #include "gde_batch_kernels.h"
 #include "gde_global.h"
 #include "gde_internal.h"
+#include "gde_kernels.h"
 
 namespace gde {
 
@@ -25,9 +27,9 @@ struct BatchWS {
     int vtype = 0, L = 0, Gcap = 0;
     int64_t n = 0, nwords = 0;
     size_t vs = 4;
-    void *R = nullptr, *X = nullptr, *deg = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
+    void *R = nullptr, *R2 = nullptr, *X = nullptr, *deg = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
     uint32_t *NM = nullptr, *TM = nullptr, *PB = nullptr, *group_unconv = nullptr;
-    uint64_t *act[2] = {nullptr, nullptr}, *touched = nullptr;
+    uint64_t *act[2] = {nullptr, nullptr}, *touched = nullptr, *touched2 = nullptr;
     int32_t act_cap = 0, touch_cap = 0, wl_cap = 0;
     int64_t tile_cap = 0;
     int32_t *wl_node = nullptr, *wl_group = nullptr, *wl_beg = nullptr, *wl_c = nullptr, *tile_start = nullptr;
@@ -50,8 +52,8 @@ struct BatchWS {
 };
 
 void batch_ws_free(BatchWS *w) {
-    void *p[] = {w->R, w->X, w->deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
-                 w->act[0], w->act[1], w->touched, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
+    void *p[] = {w->R, w->R2, w->X, w->deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
+                 w->act[0], w->act[1], w->touched, w->touched2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
                  w->lane_dst, w->row_stamp};
@@ -65,6 +67,16 @@ void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
         if (ctx->bws[i]->guid == g->uid) { batch_ws_free(ctx->bws[i]); ctx->bws.erase(ctx->bws.begin() + i); }
         else i++;
     }
+}
+
+int batch_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s) {
+    for (BatchWS *b : ctx->bws) {
+        if (b->guid != g->uid) continue;
+        const hipError_t e = b->vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)b->deg, g->n, s)
+                                                 : batch_init_deg<float>(g->row_ptr, (float *)b->deg, g->n, s);
+        if (e != hipSuccess) return hip_fail(e, "batch_init_deg");
+    }
+    return GDE_OK;
 }
 
 struct DevBuf {  // device scratch released on every return path
@@ -134,7 +146,8 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     w->act_cap = (int32_t)std::min<int64_t>(pairs, 32000000);
     // work-list entries are counted in the top 24 bits of the packed reservation
     w->wl_cap = std::min<int32_t>(w->act_cap, (1 << 24) - 1);
-    w->touch_cap = (int32_t)std::min<int64_t>(pairs, 128000000);
+    // touched entries: (lane, node) for batched solves, (group, node) for serving
+    w->touch_cap = (int32_t)std::min<int64_t>(pairs * L, 320000000);
     w->tile_cap = 32000000;
     w->nblk = (int)((w->nwords + kBlock - 1) / kBlock);
     BALLOC(w->R, (size_t)n * GL * w->vs);
@@ -244,6 +257,30 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     int rc = batch_ws_get(ctx, g, vt, L, G, s, &w);
     if (rc) return rc;
     const bool ppr = p[0].kind == GDE_PPR;
+    // level push (heat kernel, series): every lane runs the same levels, one per
+    // iteration, on two residual planes (levels t and t + 1)
+    const bool lvl = p[0].kind == GDE_HK || p[0].kind == GDE_SERIES;
+    const int K = p[0].K;
+    LevelSeries ls;
+    if (lvl) {
+        ls = level_series(&p[0]);
+        if (!w->R2) {
+            const size_t bytes = (size_t)g->n * (size_t)w->Gcap * L * w->vs;
+            if (hipMalloc(&w->R2, bytes) != hipSuccess) {
+                w->R2 = nullptr;
+                (void)hipGetLastError();
+                return fail(GDE_ERR_OOM, "no device memory for the second residual plane of the level push");
+            }
+            GDE_HIP(hipMemsetAsync(w->R2, 0, bytes, s));
+        }
+        if (!w->touched2) {
+            if (hipMalloc((void **)&w->touched2, (size_t)w->touch_cap * 8) != hipSuccess) {
+                w->touched2 = nullptr;
+                (void)hipGetLastError();
+                return fail(GDE_ERR_OOM, "no device memory for the odd levels' touched list");
+            }
+        }
+    }
 
     // lane assignment: query order[j] occupies lane j (group j / L)
     std::vector<int32_t> order(B);
@@ -271,7 +308,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
             h_node[k] = sd[q].idx[i];
             h_val[k] = sd[q].val[i];
         }
-        h_eps[j] = (V)(ppr ? p[q].alpha * p[q].eps : p[q].eps);
+        h_eps[j] = (V)(ppr ? p[q].alpha * p[q].eps : p[q].eps);  // level push: eps itself
         h_flag[j] = (!ppr && (p[q].flags & GDE_KATZ_SUBTRACT_SEED)) ? 1 : 0;
     }
     GDE_HIP(hipMemcpyAsync(w->s_lane, h_lane.data(), 4 * ns, hipMemcpyHostToDevice, s));
@@ -313,6 +350,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.act[1] = w->act[1];
     a.act_cap = w->act_cap;
     a.touched = w->touched;
+    a.touched2 = w->touched2;
     a.touch_cap = w->touch_cap;
     a.wl_node = w->wl_node;
     a.wl_group = w->wl_group;
@@ -325,8 +363,11 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.tile_start = w->tile_start;
     a.tile_cap = w->tile_cap;
     a.lane_eps = (const V *)w->lane_eps;
-    a.wscale = (V)(ppr ? 1.0 - p[0].alpha : p[0].beta);
-    a.w_div_deg = ppr ? 1 : 0;
+    a.wscale = (V)(ppr ? 1.0 - p[0].alpha : p[0].beta);  // level push: set per level below
+    a.w_div_deg = (ppr || lvl) ? 1 : 0;
+    a.R2 = lvl ? (V *)w->R2 : nullptr;
+    a.th_div = 0.0;
+    a.no_push = 0;
     a.lane_ops = w->lane_ops;
     a.lane_pushes = w->lane_pushes;
     a.lane_T = w->lane_T;
@@ -374,7 +415,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         GDE_HIP(hipMemcpyAsync(ncap, h_ncap.data(), 8 * GL, hipMemcpyHostToDevice, s));
     }
     a.st = w->st;
-    a.max_iters = p[0].max_iters;
+    a.max_iters = lvl ? K + 1 : p[0].max_iters;
     a.row_stamp = nullptr;
     if (ctx->prof_on) {  // measurement: count the distinct rows each round reads
         if (!w->row_stamp) {
@@ -385,7 +426,8 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         a.row_stamp = w->row_stamp;
     }
 
-    GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns, ppr ? p[0].alpha : 1.0, s));
+    GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns, lvl ? ls.c0 : ppr ? p[0].alpha : 1.0,
+                          s));
     int dev = 0;
     GDE_HIP(hipGetDevice(&dev));
     int cus = 0;
@@ -407,21 +449,34 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
                 w->round = 1u;
             }
             a.round_tag = w->round;
+            if (lvl) {  // level t: weight c_{t+1}/c_t, thresholds of level t + 1
+                a.no_push = t >= K;
+                a.wscale = (V)(t < K ? ls.ratio[t] : 0.0);
+                a.th_div = t < K ? (double)(K + 1) * ls.psi[t + 1] : 1.0;
+            }
             GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
             if ((rc = prof_mark_batch_push(ctx, s))) return rc;
             GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
             if ((rc = prof_mark_batch_push(ctx, s))) return rc;
+            // what level t kept (below its thresholds) leaves the plane, weighted psi_t
+            if (lvl) GDE_HIP(batch_harvest<V>(L, a, grid, t, ls.psi[t], (double)(K + 1) * ls.psi[t], s));
         }
         GDE_HIP(hipMemcpyAsync(&hst, w->st, sizeof(BatchDev), hipMemcpyDeviceToHost, s));
         GDE_HIP(hipStreamSynchronize(s));
         done = hst.acount[t & 1] == 0 || hst.ovf[0] || hst.ovf[1];
         chunk = std::min(chunk * 2, 32);
     }
+    if (lvl && t <= K && !hst.ovf[0] && !hst.ovf[1]) {
+        // no lane has an active node at level t, but push(t - 1) may have left
+        // residual there
+        GDE_HIP(batch_harvest<V>(L, a, grid, t, ls.psi[t], (double)(K + 1) * ls.psi[t], s));
+    }
     if ((rc = prof_mark_batch(ctx, s))) return rc;
     const int final_parity = t & 1;
     if (hst.ovf[0] || hst.ovf[1]) {
         // the kernels stopped on a capacity limit: restore the rest state by brute force
         GDE_HIP(hipMemsetAsync(w->R, 0, (size_t)g->n * GL * w->vs, s));
+        if (w->R2) GDE_HIP(hipMemsetAsync(w->R2, 0, (size_t)g->n * GL * w->vs, s));
         GDE_HIP(hipMemsetAsync(w->X, 0, (size_t)g->n * GL * w->vs, s));
         GDE_HIP(hipMemsetAsync(w->NM, 0, (size_t)g->n * G * 4, s));
         GDE_HIP(hipMemsetAsync(w->TM, 0, (size_t)g->n * G * 4, s));
@@ -430,9 +485,11 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         return fail(GDE_ERR_OOM, "batched work lists exceeded their capacity; split the batch");
     }
     // residual norms, unconverged lanes, Katz seed subtraction
+    // (the level push took its norms level by level and never hits a cap)
     const bool any_sub = std::any_of(h_flag.begin(), h_flag.end(), [](int32_t f) { return f != 0; });
-    GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, final_parity, w->s_lane, w->s_node,
-                            w->s_val, (int32_t)ns, any_sub ? w->sub_flag : nullptr, s));
+    if (!lvl)
+        GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, final_parity, w->s_lane, w->s_node,
+                                w->s_val, (int32_t)ns, any_sub ? w->sub_flag : nullptr, s));
     // extraction: counts per lane, then the sorted sparse outputs
     GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));
     std::vector<long long> nnz(GL), off(GL, -1);
@@ -575,14 +632,23 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
         }
         if (res[i].capacity < 0) return fail(GDE_ERR_INVALID_ARG, "negative capacity");
     }
-    // the fused kernels need one kind (PPR or Katz), LocalGD, one value type and
-    // shared kind parameters; anything else is solved query by query
-    // (deterministic queries are solved one by one in the fixed-order mode)
-    bool fused = (p[0].kind == GDE_PPR || p[0].kind == GDE_KATZ) && p[0].method == GDE_LOCAL_GD &&
-                 !(p[0].flags & GDE_DETERMINISTIC);
+    // the fused kernels need one kind, LocalGD, one value type and shared kind
+    // parameters (alpha, beta; tau and K; the series coefficients); anything
+    // else is solved query by query (deterministic queries are solved one by
+    // one in the fixed-order mode)
+    auto same_kind_params = [](const gde_params &x, const gde_params &y) {
+        if (x.kind != y.kind) return false;
+        if (x.kind == GDE_PPR || x.kind == GDE_KATZ)
+            return x.alpha == y.alpha && x.beta == y.beta && x.max_iters == y.max_iters;
+        if (x.K != y.K) return false;
+        if (x.kind == GDE_HK) return x.tau == y.tau;
+        for (int32_t k = 0; k <= x.K; k++)
+            if (x.c[k] != y.c[k]) return false;
+        return true;
+    };
+    bool fused = p[0].method == GDE_LOCAL_GD && !(p[0].flags & GDE_DETERMINISTIC);
     for (int32_t i = 1; i < B && fused; i++) {
-        fused = p[i].kind == p[0].kind && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
-                p[i].alpha == p[0].alpha && p[i].beta == p[0].beta && p[i].max_iters == p[0].max_iters &&
+        fused = same_kind_params(p[i], p[0]) && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
                 !(p[i].flags & GDE_DETERMINISTIC) &&
                 (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
     }

@@ -27,6 +27,7 @@ struct BatchDev {
     unsigned long long rowpack[2];
     long long rows;
     long long row_vol;
+    int32_t tcount2;  // level push: entries of the odd levels' touched list (touched2)
 };
 
 // Everything a batch kernel needs.  Node-major layout: the L lanes of group g
@@ -51,6 +52,7 @@ struct BatchArgs {
     uint64_t *act[2];
     int32_t act_cap;
     uint64_t *touched;
+    uint64_t *touched2;  // level push: touched entries of odd levels (even levels use touched)
     int32_t touch_cap;
     int32_t *wl_node, *wl_group, *wl_beg, *wl_c;
     long long *wl_off;
@@ -79,6 +81,12 @@ struct BatchArgs {
     unsigned long long *tr_ncount;      // [G*L] entries recorded (may exceed the capacity)
     BatchDev *st;
     int32_t max_iters;
+    // level push (heat kernel, series; null R2 = LocalGD): R holds the residual
+    // of even levels, R2 of odd ones; snap(t) takes level t, push(t) adds into
+    // level t + 1, whose threshold is (eps_lane / th_div) * d_u
+    V *R2;
+    double th_div;
+    int32_t no_push;  // snap of the last level: x only, nothing pushed
     // measurement only: row_stamp[u] == round_tag once row u was counted in this
     // iteration (distinct CSR rows read per round, whatever the groups); null = off
     uint32_t *row_stamp;
@@ -91,6 +99,11 @@ template <typename V> hipError_t batch_occupancy(int L, int *blocks_per_cu);
 template <typename V>
 hipError_t batch_seed(int L, const BatchArgs<V> &a, const int32_t *s_lane, const int32_t *s_node, const double *s_val,
                       int32_t ns, double bscale, hipStream_t s);
+// level push: residual norms of level t over its touched entries (read, reset),
+// weighted w_l1 = psi_t in the 1-norm and w_dinf = (K + 1) psi_t in the
+// degree-scaled max norm
+template <typename V>
+hipError_t batch_harvest(int L, const BatchArgs<V> &a, int grid, int t, double w_l1, double w_dinf, hipStream_t s);
 template <typename V>
 hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, int last, const int32_t *s_lane,
                         const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,

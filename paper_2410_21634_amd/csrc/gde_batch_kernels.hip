@@ -15,6 +15,12 @@
 //          active list.  A returned zero marks the pair as touched (the
 //          residual clean-up at the end reads only touched pairs).  List
 //          appends are aggregated per workgroup and tile (one counter atomic).
+// Touched lists.  Batched solves (LT = true) record touched (lane, node)
+// entries with no extra memory access: a snapshot leaves -0.0 where it took a
+// residual, so a returned old value of +0.0 (bit pattern 0) means the lane has
+// never held a residual in this solve, and each (lane, node) is listed exactly
+// once (the seeds by the seed kernel).  The serving engine (LT = false) keeps
+// per-group tags TM, because its groups change occupants between steps.
 #include <hip/hip_runtime.h>
 
 #include "gde_batch_kernels.h"
@@ -53,15 +59,26 @@ __device__ __forceinline__ double batomic_take<double>(double *p) {
 constexpr unsigned long long kLaneEdgeMask = (1ull << 40) - 1ull;
 
 // ------------------------------------------------------------------ phase S
-template <typename V, int L>
+template <typename V>
+__device__ __forceinline__ bool pos_zero(V v);
+template <>
+__device__ __forceinline__ bool pos_zero<float>(float v) { return __float_as_uint(v) == 0u; }
+template <>
+__device__ __forceinline__ bool pos_zero<double>(double v) { return __double_as_longlong(v) == 0ll; }
+
+template <typename V, int L, bool LT>
 __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     BatchDev *st = a.st;
     const int cur = t & 1, nxt = cur ^ 1;
     const int nact = min(st->acount[cur], a.act_cap);
+    V *Rs = (a.R2 && (t & 1)) ? a.R2 : a.R;  // the residual plane of this level
     if (bid == 0 && threadIdx.x == 0) {
         st->packed[nxt] = 0ull;
         st->acount[nxt] = 0;
         st->rowpack[nxt] = 0ull;
+        // level push: push(t) lists the entries of level t + 1; that list last
+        // held level t - 1, whose harvest has run
+        if (a.R2) *(nxt ? &st->tcount2 : &st->tcount) = 0;
     }
     int32_t *ovf = &st->ovf[cur];
     if (nact > a.wl_cap) {  // one work-list entry per active pair: refuse rather than wrap
@@ -92,12 +109,12 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             ri = ((size_t)u * a.G + g) * L + l;
             mine = (m >> l) & 1u;
             if (mine && (mode & 2)) {  // candidate mode: the threshold decides
-                const V r = a.R[ri];
+                const V r = Rs[ri];
                 mine = r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg;
             }
             if (mine) {
-                v = a.R[ri];
-                a.R[ri] = (V)0;
+                v = Rs[ri];
+                Rs[ri] = LT ? (V)-0.0 : (V)0;  // -0.0: taken, already on the touched list
                 a.X[ri] += v;
             }
         }
@@ -116,7 +133,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             if (leader) fresh_row = atomicExch(&a.row_stamp[u], a.round_tag) != a.round_tag;
             block_reserve64(fresh_row ? ((1ull << 40) | (unsigned long long)deg) : 0ull, &st->rowpack[cur]);
         }
-        const long long le = leader ? (long long)deg * c : 0ll;
+        const long long le = (leader && !a.no_push) ? (long long)deg * c : 0ll;
         const unsigned long long res =
             block_reserve64(leader ? ((1ull << 40) | (unsigned long long)le) : 0ull, &st->packed[cur]);
         int slot = (int)(res >> 40);
@@ -143,7 +160,8 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                     const V ws = a.g_wscale ? a.g_wscale[g] : a.wscale;
                     const V w = (mode & 1) ? ws / (V)deg : ws;
                     a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
-                    a.wl_sv[(size_t)slot * L + k] = w * v;
+                    // level push: (c_{t+1} / c_t) v / d_u, in the order of the series' definition
+                    a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)deg : w * v;
                     const int lane_id = g * L + l;
                     const int shard = bid & (kStatShards - 1);
                     atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
@@ -165,7 +183,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
 }
 
 // ------------------------------------------------------------------ phase P
-template <typename V, int L>
+template <typename V, int L, bool LT>
 __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     __shared__ long long s_off[kTile + 1];
     __shared__ int32_t s_beg[kTile + 1];
@@ -173,6 +191,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
     __shared__ int32_t s_g[kTile + 1];
     BatchDev *st = a.st;
     const int cur = t & 1, nxt = cur ^ 1;
+    V *Rp = (a.R2 && !(t & 1)) ? a.R2 : a.R;  // the plane receiving the pushes
     const unsigned long long pk = st->packed[cur];
     const int count = min((int)(pk >> 40), a.wl_cap);
     const long long total = (long long)(pk & kLaneEdgeMask);
@@ -244,11 +263,16 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         }
         V old[kPer], th[kPer];
 #pragma unroll
-        for (int q = 0; q < kPer; q++)
-            th[q] = wq[q] >= 0 ? a.lane_eps[gq[q] * L + lq[q]] * a.deg[wq[q]] : (V)0;
+        for (int q = 0; q < kPer; q++) {
+            th[q] = (V)0;
+            if (wq[q] >= 0) {
+                const V e = a.lane_eps[gq[q] * L + lq[q]];
+                th[q] = (a.R2 ? (V)((double)e / a.th_div) : e) * a.deg[wq[q]];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < kPer; q++)
-            old[q] = wq[q] >= 0 ? unsafeAtomicAdd(&a.R[((size_t)wq[q] * a.G + gq[q]) * L + lq[q]], dv[q]) : (V)0;
+            old[q] = wq[q] >= 0 ? unsafeAtomicAdd(&Rp[((size_t)wq[q] * a.G + gq[q]) * L + lq[q]], dv[q]) : (V)0;
         int n_act = 0, n_touch = 0;
         bool new_act[kPer], new_touch[kPer];
 #pragma unroll
@@ -257,9 +281,11 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             if (wq[q] >= 0) {
                 const bool cand = a.g_mode && (a.g_mode[gq[q]] & 2);
                 hit[q] = cand || ((old[q] < th[q]) && (old[q] + dv[q] >= th[q]));
-                first[q] = old[q] == (V)0;
+                first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) new_act[q] = atomicOr(&a.NM[(size_t)wq[q] * a.G + gq[q]], 1u << lq[q]) == 0u;
-                if (first[q]) {
+                if (LT) {
+                    new_touch[q] = first[q];
+                } else if (first[q]) {
                     uint32_t *tm = &a.TM[(size_t)wq[q] * a.G + gq[q]];
                     const uint32_t ep = a.g_epoch ? a.g_epoch[gq[q]] : a.epoch;
                     if (*tm != ep) new_touch[q] = atomicExch(tm, ep) != ep;
@@ -269,7 +295,9 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             n_touch += new_touch[q] ? 1 : 0;
         }
         int sa = block_reserve(n_act, &st->acount[nxt]);
-        int stt = block_reserve(n_touch, &st->tcount);
+        const bool odd = a.R2 && !(t & 1);  // level push: entries of level t + 1 go to its parity's list
+        uint64_t *tlist = odd ? a.touched2 : a.touched;
+        int stt = block_reserve(n_touch, odd ? &st->tcount2 : &st->tcount);
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const uint64_t pair = ((uint64_t)(uint32_t)gq[q] << 32) | (uint32_t)wq[q];
@@ -279,7 +307,9 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                 sa++;
             }
             if (new_touch[q]) {
-                if (stt < a.touch_cap) a.touched[stt] = pair;
+                // LT: the entry names the lane, (g * L + l) << 32 | node
+                const uint64_t te = LT ? ((uint64_t)(uint32_t)(gq[q] * L + lq[q]) << 32) | (uint32_t)wq[q] : pair;
+                if (stt < a.touch_cap) tlist[stt] = te;
                 else *ovf = 1;
                 stt++;
             }
@@ -288,17 +318,18 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
 }
 
 // ------------------------------------------------------------------ launches
-template <typename V, int L>
+template <typename V, int L, bool LT>
 __global__ void __launch_bounds__(kBatchSnapBlock) k_batch_snap(BatchArgs<V> a, int t) {
-    batch_snap<V, L>(a, t, blockIdx.x, gridDim.x);
+    batch_snap<V, L, LT>(a, t, blockIdx.x, gridDim.x);
 }
-template <typename V, int L>
+template <typename V, int L, bool LT>
 __global__ void __launch_bounds__(kBlock) k_batch_push(BatchArgs<V> a, int t) {
-    batch_push<V, L>(a, t, blockIdx.x, gridDim.x);
+    batch_push<V, L, LT>(a, t, blockIdx.x, gridDim.x);
 }
 
 // r <- b for every lane's seeds; the (group, node) pairs of the seeds form S_0
-// (forced, Definition 3.1) with their lanes' bits in the next-mask.
+// (forced, Definition 3.1) with their lanes' bits in the next-mask.  Each seed
+// (lane, node) goes on the touched list (batched solves list lanes, see above).
 template <typename V, int L>
 __global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane, const int32_t *__restrict__ s_node,
                              const double *__restrict__ s_val, int32_t ns, double bscale) {
@@ -314,57 +345,67 @@ __global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane,
         pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
     }
     bwave_append64(fresh, &a.st->acount[0], pair, a.act[0], a.act_cap, &a.st->ovf[0]);
+    const uint64_t te = i < ns ? ((uint64_t)(uint32_t)s_lane[i] << 32) | (uint32_t)s_node[i] : 0ull;
+    bwave_append64(i < ns, &a.st->tcount, te, a.touched, a.touch_cap, &a.st->ovf[0]);
 }
 
-// Residual norms per lane over the touched pairs (each pair read and zeroed
-// once, L threads per pair), plus the lanes still active at the iteration cap.
-// With lds_lanes (G*L lanes fit in the dynamic LDS) a workgroup first sums its
-// share per lane in LDS and adds each lane's total once at the end, instead of
-// one global atomic per nonzero (pair, lane).
+// Residual norms per lane over the touched (lane, node) entries (each listed
+// once: read, reset to +0.0, one thread per entry), plus the lanes still active
+// at the iteration cap.  With lds_lanes (G*L lanes fit in the dynamic LDS) a
+// workgroup first sums its share per lane in LDS and adds each lane's total
+// once at the end, instead of one global atomic per nonzero entry.
+// Level push (lvl >= 0): the entries of level lvl only (its parity's list), on
+// its plane, each |r| weighted rscale in the 1-norm and w_dinf * (|r| / d) in
+// the max norm.
 template <typename V, int L>
-__global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, double rscale, int last, int lds_lanes) {
+__global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, double rscale, int last, int lds_lanes,
+                                                           int lvl, double w_dinf) {
     extern __shared__ __attribute__((aligned(16))) unsigned char s_res[];
     double *s_l1 = (double *)s_res;
     unsigned long long *s_dm = (unsigned long long *)(s_l1 + lds_lanes);
     BatchDev *st = a.st;
-    constexpr int PPW = kWave / L;
-    const int sub = blane() / L, l = blane() % L;
-    const int wave_id = blockIdx.x * (kBlock / kWave) + (int)threadIdx.x / kWave;
-    const int nwaves = gridDim.x * (kBlock / kWave);
-    const int nt = min(st->tcount, a.touch_cap);
+    int nt = min(st->tcount, a.touch_cap);
+    V *R = a.R;
+    const uint64_t *list = a.touched;
+    if (lvl >= 0 && (lvl & 1)) {
+        nt = min(st->tcount2, a.touch_cap);
+        R = a.R2;
+        list = a.touched2;
+    }
     for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
         s_l1[j] = 0.0;
         s_dm[j] = 0ull;
     }
     __syncthreads();
-    // kU pairs per lane group and step: their list entries, then their residual
-    // lines, are loaded before any is used (the loop is latency-bound otherwise)
+    // kU entries per thread and step: their list words, then their residuals,
+    // are loaded before any is used (the loop is latency-bound otherwise)
     constexpr int kU = 4;
-    for (int base = wave_id * PPW * kU; base < nt; base += nwaves * PPW * kU) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x * kU + threadIdx.x; base < nt; base += stride * kU) {
         uint64_t pr[kU];
         V val[kU];
 #pragma unroll
         for (int q = 0; q < kU; q++) {
-            const int i = base + q * PPW + sub;
-            pr[q] = i < nt ? a.touched[i] : ~0ull;
+            const int i = base + q * (int)blockDim.x;
+            pr[q] = i < nt ? list[i] : ~0ull;
         }
 #pragma unroll
         for (int q = 0; q < kU; q++) {
             val[q] = (V)0;
             if (pr[q] != ~0ull) {
-                const int32_t g = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
-                val[q] = a.R[((size_t)w * a.G + g) * L + l];
+                const int32_t lane_id = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
+                val[q] = R[((size_t)w * a.G + lane_id / L) * L + lane_id % L];
             }
         }
 #pragma unroll
         for (int q = 0; q < kU; q++) {
             if (pr[q] == ~0ull) continue;
-            const int32_t g = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
-            a.R[((size_t)w * a.G + g) * L + l] = (V)0;
+            const int32_t lane_id = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
+            R[((size_t)w * a.G + lane_id / L) * L + lane_id % L] = (V)0;
             const double av = fabs((double)val[q]) * rscale;
             if (av > 0.0) {
-                const int lane_id = g * L + l;
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(av / (double)a.deg[w]);
+                const double dm = lvl >= 0 ? w_dinf * (fabs((double)val[q]) / (double)a.deg[w]) : av / (double)a.deg[w];
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(dm);
                 if (lds_lanes) {
                     atomicAdd(&s_l1[lane_id], av);
                     if (s_dm[lane_id] < bits) atomicMax(&s_dm[lane_id], bits);
@@ -382,7 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
         if (s_dm[j] != 0ull && a.lane_dinf[j] < s_dm[j]) atomicMax(&a.lane_dinf[j], s_dm[j]);
     }
     // pairs left in the active list at the iteration cap: their lanes did not converge
-    const int na = min(st->acount[last], a.act_cap);
+    const int na = last >= 0 ? min(st->acount[last], a.act_cap) : 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < na; j += gridDim.x * blockDim.x) {
         const uint64_t p = a.act[last][j];
         const int32_t g = (int32_t)(p >> 32), u = (int32_t)(p & 0xffffffffull);
@@ -541,12 +582,17 @@ __global__ void k_batch_init_deg(const int32_t *__restrict__ row_ptr, V *deg, in
 // ------------------------------------------------------------------ host-side launchers
 template <typename V>
 hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t, hipStream_t s) {
+    // per-group tags (serving) or lane entries (batched solves), see the touched lists above
+    const bool lt = a.g_epoch == nullptr;
+    const int sgrid = (grid * kBlock + kBatchSnapBlock - 1) / kBatchSnapBlock;
 #define GDE_BL(LL)                                                                                       \
     case LL:                                                                                             \
-        if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL>),                                         \
-                                           dim3((grid * kBlock + kBatchSnapBlock - 1) / kBatchSnapBlock),   \
-                                           dim3(kBatchSnapBlock), 0, s, a, t);                            \
-        else hipLaunchKernelGGL((k_batch_push<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, t);             \
+        if (which == 1 && lt) hipLaunchKernelGGL((k_batch_snap<V, LL, true>), dim3(sgrid),                \
+                                                 dim3(kBatchSnapBlock), 0, s, a, t);                      \
+        else if (which == 1) hipLaunchKernelGGL((k_batch_snap<V, LL, false>), dim3(sgrid),                \
+                                                dim3(kBatchSnapBlock), 0, s, a, t);                       \
+        else if (lt) hipLaunchKernelGGL((k_batch_push<V, LL, true>), dim3(grid), dim3(kBlock), 0, s, a, t); \
+        else hipLaunchKernelGGL((k_batch_push<V, LL, false>), dim3(grid), dim3(kBlock), 0, s, a, t);      \
         return hipGetLastError();
     switch (L) {
         GDE_BL(8)
@@ -561,9 +607,9 @@ hipError_t batch_launch(int which, int L, const BatchArgs<V> &a, int grid, int t
 template <typename V>
 hipError_t batch_occupancy(int L, int *blocks_per_cu) {
     switch (L) {
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 8>, kBlock, 0);
-    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 16>, kBlock, 0);
-    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 32>, kBlock, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 8, true>, kBlock, 0);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 16, true>, kBlock, 0);
+    case 32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_push<V, 32, true>, kBlock, 0);
     default: return hipErrorInvalidValue;
     }
 }
@@ -582,6 +628,18 @@ hipError_t batch_seed(int L, const BatchArgs<V> &a, const int32_t *s_lane, const
 }
 
 template <typename V>
+hipError_t batch_harvest(int L, const BatchArgs<V> &a, int grid, int t, double w_l1, double w_dinf, hipStream_t s) {
+    const int lds_lanes = (int64_t)a.G * L <= kResLdsLanes ? a.G * L : 0;
+    switch (L) {
+    case 8: hipLaunchKernelGGL((k_batch_residual<V, 8>), dim3(grid), dim3(kBlock), 16 * (size_t)lds_lanes, s, a, w_l1, -1, lds_lanes, t, w_dinf); break;
+    case 16: hipLaunchKernelGGL((k_batch_residual<V, 16>), dim3(grid), dim3(kBlock), 16 * (size_t)lds_lanes, s, a, w_l1, -1, lds_lanes, t, w_dinf); break;
+    case 32: hipLaunchKernelGGL((k_batch_residual<V, 32>), dim3(grid), dim3(kBlock), 16 * (size_t)lds_lanes, s, a, w_l1, -1, lds_lanes, t, w_dinf); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
 hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, int last, const int32_t *s_lane,
                         const int32_t *s_node, const double *s_val, int32_t ns, const int32_t *sub_flag,
                         hipStream_t s) {
@@ -591,7 +649,7 @@ hipError_t batch_finish(int L, const BatchArgs<V> &a, int grid, double rscale, i
 #define GDE_BF(LL)                                                                                             \
     case LL:                                                                                                   \
         hipLaunchKernelGGL((k_batch_residual<V, LL>), dim3(grid), dim3(kBlock), 16 * (size_t)lds_lanes, s, a,   \
-                           rscale, last, lds_lanes);                                                           \
+                           rscale, last, lds_lanes, -1, 0.0);                                                  \
         if (sub_flag) hipLaunchKernelGGL((k_batch_subtract_seed<V, LL>), dim3(sg), dim3(256), 0, s, a, s_lane, \
                                          s_node, s_val, ns, sub_flag);                                         \
         break;
@@ -643,6 +701,7 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
 #define GDE_BINST(V)                                                                                               \
     template hipError_t batch_launch<V>(int, int, const BatchArgs<V> &, int, int, hipStream_t);                    \
     template hipError_t batch_occupancy<V>(int, int *);                                                            \
+    template hipError_t batch_harvest<V>(int, const BatchArgs<V> &, int, int, double, double, hipStream_t);        \
     template hipError_t batch_seed<V>(int, const BatchArgs<V> &, const int32_t *, const int32_t *, const double *, \
                                       int32_t, double, hipStream_t);                                               \
     template hipError_t batch_finish<V>(int, const BatchArgs<V> &, int, double, int, const int32_t *,              \

@@ -164,3 +164,68 @@ def test_batch_status_paths(gde, ctx, c1):
     hk = gde.make_params("hk", tau=5.0, K=30, eps=1e-5, value_type=gde.F64)
     out = gde.solve_batch(ctx, g, [params[0], hk], [(queries[0][0], queries[0][1]), (queries[1][0], queries[1][1])])
     assert out[0].status == gde.OK and out[1].status == gde.OK
+
+
+def run_levels(gde, ctx, g, G, queries, vt, kind, prm):
+    """Batched level push (heat kernel or series) against the oracle's level push,
+    query by query: P1 when the lane's level trace equals the oracle's, else P2
+    (replay of the lane's recorded S_k, heat kernel in FP32)."""
+    params = [gde.make_params(kind, eps=eps, value_type=vt, flags=gde.TRACE, **prm) for _, _, eps in queries]
+    out = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries], trace_cap=512, nodes_cap=60 * G.n)
+    worst, replays = 0.0, 0
+    for (idx, val, eps), r in zip(queries, out):
+        if kind == "hk":
+            ref = O.hk(G.row_ptr, G.col_idx, prm["tau"], prm["K"], eps, idx, val, trace_cap=512)
+        else:
+            ref = O.series(G.row_ptr, G.col_idx, prm["c"], eps, idx, val, trace_cap=512)
+        assert r.status == gde.OK
+        assert np.all(np.diff(r.idx) > 0)
+        assert len(r.trace_nodes) == r.pushes
+        same = ((r.iters, r.ops, r.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+                and np.array_equal(r.trace_size, ref["trace_size"]) and np.array_equal(r.trace_vol, ref["trace_vol"]))
+        if vt == 1:
+            assert same, (eps, r.iters, ref["iters"], r.ops, ref["ops"])
+        s1 = float(np.abs(val).sum())
+        if same:
+            err = np.abs(r.dense(G.n) - ref["x"]).sum() / s1
+            np.testing.assert_allclose(r.residual_l1, ref["residual_l1"], rtol=1e-5 if vt == 0 else 1e-10)
+            np.testing.assert_allclose(r.residual_dinf, ref["residual_dinf"], rtol=1e-5 if vt == 0 else 1e-10)
+        else:
+            assert kind == "hk"
+            rp = oracle_replay(G, gde.HK, gde.LOCAL_GD, dict(prm, eps=eps), idx, val, r.trace_size, r.trace_nodes,
+                               KAPPA[vt])
+            assert rp["violations"] == 0, rp
+            err = np.abs(r.dense(G.n) - rp["x"]).sum() / s1
+            replays += 1
+        assert err <= TOL[vt], (eps, err, same)
+        worst = max(worst, err)
+    print("replays", replays, flush=True)
+    return worst
+
+
+@pytest.mark.parametrize("vt", [1, 0])
+def test_batch_hk_matches_oracle(gde, ctx, c1, vt):
+    # every lane runs levels 0..K in the same launches, on two residual planes
+    G, g = c1
+    rng = np.random.default_rng(6)
+    queries = [(q[0], q[1], float(10.0 ** rng.uniform(-5, -2))) for q in make_queries(G, 40, seed=6)]
+    worst = run_levels(gde, ctx, g, G, queries, vt, "hk", dict(tau=5.0, K=30))
+    print("batch hk", vt, "worst l1", worst, flush=True)
+    # the planes are clean afterwards: a repeat in FP64 gives identical output
+    if vt == 1:
+        params = [gde.make_params("hk", tau=5.0, K=30, eps=q[2], value_type=vt) for q in queries[:8]]
+        a = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries[:8]])
+        b = gde.solve_batch(ctx, g, params, [(q[0], q[1]) for q in queries[:8]])
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x.idx, y.idx)
+            assert np.abs(x.val - y.val).sum() <= 1e-12
+
+
+def test_batch_series_matches_oracle(gde, ctx, c1):
+    # the truncated PPR series (c_k = alpha (1 - alpha)^k) and a short K, FP64
+    G, g = c1
+    rng = np.random.default_rng(7)
+    queries = [(q[0], q[1], float(10.0 ** rng.uniform(-6, -3))) for q in make_queries(G, 24, seed=7)]
+    for c in (0.15 * 0.85 ** np.arange(41), np.array([0.5, 0.3, 0.2])):
+        worst = run_levels(gde, ctx, g, G, queries, 1, "series", dict(c=c))
+        print("batch series K", len(c) - 1, "worst l1", worst, flush=True)
