@@ -64,9 +64,10 @@ def kernel_source_hash(source="gde_kernels.hip"):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(fname, source, entry_name):
+def traffic_from_profile(fname, source, entry_name, kernel_names=None):
     """HBM traffic per launch from a committed rocprofv3 --pmc summary
-    (profiles/<fname>), if it was taken on the current kernel source."""
+    (profiles/<fname>), if it was taken on the current kernel source (and, when
+    kernel_names is given, on exactly those kernel instantiations)."""
     path = os.path.join(ROOT, "profiles", fname)
     try:
         with open(path) as fh:
@@ -74,6 +75,8 @@ def traffic_from_profile(fname, source, entry_name):
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha") != kernel_source_hash(source):
+        return None
+    if kernel_names is not None and sorted(d.get("kernel_names", [])) != sorted(kernel_names):
         return None
     return d.get(entry_name)
 
@@ -85,9 +88,10 @@ PMC_TARGETS = {
                   kernel="k_push<float,0|2> + k_reduce + k_small (scatter step)",
                   workload="ppr-plain-n1M (bench.py --workload c2 --phase plain)",
                   step=("k_push<", "k_small<"), extra=("k_reduce<",)),
-    "batch": dict(source="gde_batch_kernels.hip", out="batch_push_traffic_c4.json",
-                  kernel="k_batch_push<float,16> (batched residual scatter)",
-                  workload="ppr-batched-n10M (bench.py --workload c4 --no-sub)",
+    "batch": dict(source="gde_batch_kernels.hip", out="batch_push_traffic_c4_L{lanes}.json",
+                  kernel="k_batch_push<float,L,true> (batched residual scatter)",
+                  workload="ppr-batched-n10M (bench.py --workload c4 --no-sub --no-cpu-baseline --steps 2 "
+                           "--warmup 1 --schedule <the chosen lanes> --copy-calib)",
                   step=("k_batch_push<",), extra=()),
 }
 
@@ -115,16 +119,27 @@ def pmc_summary(target, fetch_dir, write_dir):
         rows = load(d, counter)
         calib = [v for k, v in rows if "MulFunctor" in k]
         step = [v for k, v in rows if any(m in k for m in tg["step"])]
+        names = sorted({k.split("(")[0].replace("void ", "").strip() for k, _ in rows
+                        if any(m in k for m in tg["step"])})
         extra = [v for k, v in rows if any(m in k for m in tg["extra"])]
         if not calib or not step:
             raise SystemExit(f"{d}: no calibration or timed dispatches with {counter}")
         factor = CALIB_BYTES / max(calib)
         res[key] = dict(counter=counter, calib_counted_bytes=max(calib), factor=factor, launches=len(step),
-                        extra_dispatches=len(extra), bytes_per_launch=factor * (sum(step) + sum(extra)) / len(step))
+                        extra_dispatches=len(extra), bytes_per_launch=factor * (sum(step) + sum(extra)) / len(step),
+                        kernel_names=names)
     out = dict(kernel=tg["kernel"], workload=tg["workload"], kernel_source_sha=kernel_source_hash(tg["source"]),
+               kernel_names=res["fetch"]["kernel_names"],
                bytes_per_launch=round(res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"], 1),
                fetch=res["fetch"], write=res["write"])
-    with open(os.path.join(ROOT, "profiles", tg["out"]), "w") as fh:
+    lanes = ""
+    if "{lanes}" in tg["out"]:  # one summary per lane width: the name carries it
+        import re
+        m = {re.search(r"<float, (\d+),", k).group(1) for k in out["kernel_names"]}
+        if len(m) != 1:
+            raise SystemExit(f"expected one lane width among {out['kernel_names']}")
+        lanes = m.pop()
+    with open(os.path.join(ROOT, "profiles", tg["out"].format(lanes=lanes)), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
@@ -419,6 +434,8 @@ def run_c4(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = ctx.profile(False, reset=True)
+    tuned = ctx.batch_tuned(g, "ppr", gde.F32, B)
+    lanes = tuned[0] if tuned else 16
     ops = int(res.ops.sum())
     pushes = int(res.pushes.sum())
     value = B * args.steps / el
@@ -429,10 +446,12 @@ def run_c4(args):
     push_ms = prof["batch_push_ms"] / pl
     push_bytes = batch_push_bytes(prof) / pl
     achieved = push_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
-    traffic = traffic_from_profile("batch_push_traffic_c4.json", "gde_batch_kernels.hip", "bytes_per_launch")
+    # counters count only if they were taken on this lane width's push kernel
+    traffic = traffic_from_profile(f"batch_push_traffic_c4_L{lanes}.json", "gde_batch_kernels.hip", "bytes_per_launch",
+                                   kernel_names=[f"gde::k_batch_push<float, {lanes}, true>"])
     roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic,
-                kernel="k_batch_push<float,16> (batched residual scatter)", launches=prof["batch_push_launches"],
+                kernel=f"k_batch_push<float,{lanes},true> (batched residual scatter)", launches=prof["batch_push_launches"],
                 avg_launch_us=round(push_ms * 1e3, 3), alg_bytes_per_launch=round(push_bytes, 1),
                 timed_launches="every push launch of the timed batches, HIP events on the solve stream",
                 byte_rule="4 B per column index of each distinct row pushed in a round + 8 B per (edge, query) "
@@ -460,7 +479,8 @@ def run_c4(args):
                                     "degree-stratified seeds (16 log2 degree bins), eps log-uniform [1e-7,1e-4] "
                                     "(seed 42), PPR alpha 0.1, LocalGD, FP32; one gde_solve_batch call per step",
                            n=G.n, edges=G.nnz // 2, d_max=int(G.degrees.max()), queries=B, path="batched",
-                           schedule=args.schedule or "default"),
+                           schedule=args.schedule or "default",
+                           schedule_chosen=dict(lanes=tuned[0], blocks_per_cu=tuned[1]) if tuned else None),
                hbm_gbs_alg=round(gbs, 2), hbm_frac_alg=round(gbs / PEAK_HBM_GBS, 5),
                roofline=roof,
                batch=dict(ms_per_batch=round(1e3 * el / args.steps, 3), solve_span_ms=round(kms, 3),
@@ -552,7 +572,9 @@ def sub_c3():
     beta = 0.5 / lo
     oi = torch.empty(G.n, dtype=torch.int32, device=dev)
     ov = torch.empty(G.n, dtype=torch.float32, device=dev)
-    out = dict(workload="Chung-Lu n=2.4e6, 6.2e7 edges, gamma 2.3, seed 42; 32 uniform seeds, eps 1e-6, FP32",
+    cap_b = G.n  # result entries per batched query
+    out = dict(workload="Chung-Lu n=2.4e6, 6.2e7 edges, gamma 2.3, seed 42; 32 uniform seeds one by one, and 256 "
+                        "uniform seeds in one batch; eps 1e-6, FP32",
                lambda_bounds=[round(lo, 4), round(hi, 4)], beta=beta)
     for name, p in (("katz", gde.make_params("katz", beta=beta, eps=1e-6, lambda_bound=hi, value_type=gde.F32)),
                     ("hk", gde.make_params("hk", tau=5.0, K=30, eps=1e-6, value_type=gde.F32))):
@@ -566,8 +588,23 @@ def sub_c3():
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         out[name] = dict(solves_per_s=round(len(seeds) / t, 2), mean_ops=round(ops / len(seeds), 1))
+        # the same query kind for 256 uniform seeds in one gde_solve_batch call
+        # (Katz: batched LocalGD; heat kernel: the batched level push)
+        bseeds = [([int(s)], None) for s in W.uniform_seeds(G, 256, seed=43)]
+        bo = (torch.empty(256 * cap_b, dtype=torch.int32, device=dev),
+              torch.empty(256 * cap_b, dtype=torch.float32, device=dev))
+        gde.solve_batch(ctx, g, [p] * 256, bseeds, out=bo)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = gde.solve_batch(ctx, g, [p] * 256, bseeds, out=bo)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        out[name].update(batched_256_solves_per_s=round(256 / t, 1), batched_mean_ops=round(float(res.ops.mean()), 1))
+        log(f"c3 {name}: {out[name]}")
+        del bo
     g.close()
     ctx.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -962,7 +999,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--phase", default="all", choices=["all", "plain", "batch"],
                     help="profiling aid: run only one path (the JSON line then covers that path only)")
-    ap.add_argument("--schedule", default=None, help='batched schedule JSON, e.g. {"lanes":16}')
+    ap.add_argument("--schedule", default='{"auto":1}',
+                    help='batched schedule JSON, e.g. {"lanes":16}; default: chosen by the library\'s autotuner')
     ap.add_argument("--pmc-summary", nargs=3, metavar=("TARGET", "FETCH_DIR", "WRITE_DIR"),
                     help="TARGET plain|batch: write profiles/<target summary>.json, the per-launch traffic from "
                          "two rocprofv3 --pmc runs, and exit")

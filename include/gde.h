@@ -98,6 +98,16 @@ typedef enum gde_value_type { GDE_F32 = 0, GDE_F64 = 1 } gde_value_type;
  * scatter flags.  gde_solve_batch honours it by solving each query in this mode;
  * the server rejects it (GDE_ERR_UNSUPPORTED). */
 #define GDE_DETERMINISTIC 0x20u
+/* PPR, HK and GDE_SERIES: propagation matrix M = D^-1/2 A D^-1/2 (APPNP in
+ * Table 1) in place of A D^-1.  Since (D^-1/2 A D^-1/2)^k = D^-1/2 (A D^-1)^k
+ * D^1/2, the call solves the A D^-1 form from the source D^1/2 s and returns
+ * x_u / sqrt(d_u) (the symmetrisation of Sec. 3.3).  The stop rule, T, the
+ * operation counts and the residual norms are those of the A D^-1 form with
+ * source D^1/2 s, so |f_u - x_u| <= eps sqrt(d_u) (PPR LocalGD).  gde_solve and
+ * gde_solve_batch; Katz gives GDE_ERR_INVALID_ARG, LocalSOR, the deterministic
+ * mode, gde_solve_global, gde_solve_noalloc, the server and standing queries
+ * give GDE_ERR_UNSUPPORTED. */
+#define GDE_SYM_NORM 0x40u
 
 typedef struct gde_ctx gde_ctx;
 typedef struct gde_graph gde_graph;
@@ -322,16 +332,32 @@ size_t gde_solve_noalloc_bytes(const gde_graph *g, const gde_params *p, const gd
  * of them in the same launches: seeds are packed into lanes of node-major
  * residual tiles, so a CSR row that several queries push in the same round is
  * read once.  Queries may differ in eps; they must share kind, method
- * (LocalGD), value type and kind parameters.  schedule_json: NULL = the
- * default schedule (16 lanes, full occupancy), else a JSON object
- * {"lanes":L,"blocks_per_cu":G,"sort":0|1}.  Every iteration is one snapshot
- * and one push launch; "persistent":1 (a single launch for all iterations) is
- * not provided and gives GDE_ERR_UNSUPPORTED.
+ * (LocalGD), value type and kind parameters (alpha, beta; tau and K; the
+ * series coefficients).  PPR and Katz run the LocalGD iterations (Eq. (9));
+ * the heat kernel and GDE_SERIES run the level push, level t of every lane in
+ * iteration t.  A batch of GDE_LOCAL_SOR queries runs one query per wavefront
+ * (the sequential push of Eq. (7)); any other mix is solved query by query.
+ * schedule_json: NULL = the default schedule (16 lanes, full occupancy), else
+ * a JSON object {"lanes":L,"blocks_per_cu":G,"sort":0|1,"auto":0|1}.  With
+ * "auto":1 the first batch of a (graph, kind, value type, power-of-two size
+ * class) is solved once per candidate schedule (8, 32 and 16 lanes, two
+ * blocks per CU) and timed; the fastest is kept in the context for later
+ * calls, and the results of the last run (a complete solve) are returned.
+ * Every iteration is one snapshot and one push launch; "persistent":1 (a
+ * single launch for all iterations) is not provided and gives
+ * GDE_ERR_UNSUPPORTED.
  * res[i].status holds each query's own status; the call returns the first
  * non-OK status, or GDE_OK.
  */
 int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
                     gde_result *res, const char *schedule_json, hipStream_t stream);
+
+/* The schedule the "auto" mode of gde_solve_batch chose in ctx for batches of
+ * B queries of this kind and value type on g: *lanes and *blocks_per_cu (0 =
+ * the occupancy limit).  GDE_ERR_INVALID_ARG when none was chosen yet or an
+ * argument is null.  Host only. */
+int gde_batch_tuned(const gde_ctx *ctx, const gde_graph *g, int32_t kind, int32_t value_type, int32_t B,
+                    int32_t *lanes, int32_t *blocks_per_cu);
 
 /* ------------------------------------------------ standing queries on a dynamic graph */
 /*

@@ -232,6 +232,23 @@ def series(row_ptr, col_idx, c, eps, seed_idx, seed_val=None, trace_cap=64, repl
     return out
 
 
+def symmetric(fn, row_ptr, col_idx, *args, seed_idx, seed_val=None, **kw):
+    """``fn`` (localgd, localch, hk or series) with the propagation matrix
+    D^-1/2 A D^-1/2 of Table 1 (APPNP) in place of A D^-1.  Since
+    (D^-1/2 A D^-1/2)^k = D^-1/2 (A D^-1)^k D^1/2, the series equals
+    D^-1/2 f(D^1/2 s) with f the A D^-1 form (the symmetrisation of Sec. 3.3):
+    ``fn`` runs on the source D^1/2 s, then x is scaled by D^-1/2.  ``args`` are
+    fn's arguments before the seed; the stop rule, counts and residuals stay
+    those of the A D^-1 form."""
+    d = np.diff(np.asarray(row_ptr, dtype=np.int64)).astype(np.float64)
+    idx = np.atleast_1d(np.asarray(seed_idx, dtype=np.int32))
+    val = np.ones(len(idx)) if seed_val is None else np.asarray(seed_val, dtype=np.float64)
+    out = fn(row_ptr, col_idx, *args, idx, val * np.sqrt(d[idx]), **kw)
+    x = out["x"]
+    out["x"] = np.where(d > 0, x / np.sqrt(np.where(d > 0, d, 1.0)), 0.0)
+    return out
+
+
 def replay_gd_ch(row_ptr, col_idx, method, kind, param, eps, seed_idx, seed_val, offsets, nodes, kappa, lam=0.0):
     """Re-run LocalGD (method 0) / LocalCH (method 1) in FP64 on recorded active sets.
 

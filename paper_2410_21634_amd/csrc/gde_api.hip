@@ -70,8 +70,13 @@ static int validate_params(const gde_params *p) {
     if ((p->flags & GDE_SCATTER_BINNED) && (p->flags & GDE_SCATTER_ATOMIC))
         return fail(GDE_ERR_INVALID_ARG, "GDE_SCATTER_BINNED and GDE_SCATTER_ATOMIC exclude each other");
     if (p->flags & ~(GDE_KATZ_SUBTRACT_SEED | GDE_TRACE | GDE_RESULT_DEVICE | GDE_SCATTER_BINNED | GDE_SCATTER_ATOMIC |
-                     GDE_DETERMINISTIC))
+                     GDE_DETERMINISTIC | GDE_SYM_NORM))
         return fail(GDE_ERR_INVALID_ARG, "unknown flag bits");
+    if (p->flags & GDE_SYM_NORM) {
+        if (p->kind == GDE_KATZ) return fail(GDE_ERR_INVALID_ARG, "GDE_SYM_NORM applies to the kinds with M = A D^-1");
+        if (p->method == GDE_LOCAL_SOR || (p->flags & GDE_DETERMINISTIC))
+            return fail(GDE_ERR_UNSUPPORTED, "GDE_SYM_NORM is provided for LocalGD, LocalCH and the level push");
+    }
     switch (p->kind) {
     case GDE_PPR:
         if (!(p->alpha > 0.0 && p->alpha < 1.0)) return fail(GDE_ERR_INVALID_ARG, "PPR needs 0 < alpha < 1");
@@ -589,6 +594,8 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
     int rc = GDE_OK;
     const bool hk = p->kind == GDE_HK || p->kind == GDE_SERIES;  // the level push
     const bool ch = p->method == GDE_LOCAL_CH;
+    // D^-1/2 A D^-1/2: seed scaled by sqrt(d), output by 1/sqrt(d) (the kernels read the degrees)
+    const int32_t *sym_rp = (p->flags & GDE_SYM_NORM) ? g->row_ptr : nullptr;
     if (hk && (rc = ws_ensure_hk(w, g, s))) return rc;
     if (ch && (rc = ws_ensure_ch(w, s))) return rc;
     if ((rc = ws_ensure_seed(w, sd->nnz))) return rc;
@@ -681,7 +688,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
         GDE_HIP(hipMemcpyAsync(w->lvl_tab, w->h_lvl.data(), 8 * w->h_lvl.size(), hipMemcpyHostToDevice, s));
         void *plane[2] = {w->rd, w->rd2};
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, ls.c0, w->front[0], w->touched[0],
-                            nullptr, 0, nullptr, w->st, s);
+                            nullptr, 0, nullptr, w->st, s, sym_rp);
         auto eps_at = [&](int k) { return k >= K ? 0.0 : p->eps / ((double)(K + 1) * psi[k + 1]); };
         // level k on the grid-wide kernels: clean-up of k-1 and snapshot of k, then the push into k+1
         auto grid_level = [&](int k) -> int {
@@ -797,7 +804,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
             base = w->stamp_base;
         }
         launch_seed_init<V>(w->rd, w->seed_idx, w->seed_val, pinl, sd->nnz, bscale, w->front[0], nullptr,
-                            ch ? w->cstamp : nullptr, base, w->tbm, w->st, s);
+                            ch ? w->cstamp : nullptr, base, w->tbm, w->st, s, sym_rp);
         a.rd = w->rd;
         // LocalCH scalars (c_t, m_t) of iteration t: delta_{t+1} = 1 / (2 sigma - delta_t),
         // c_t = 2 sigma delta_{t+1}, m_t = delta_t delta_{t+1}; t = 0 is the forced first step
@@ -982,7 +989,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
         launch_ex_count(w->bitmap, nwords, w->blk, w->nblk, s);
         launch_ex_scan(w->blk, w->nblk, w->st, s);
         launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, bufs ? res->idx : nullptr,
-                          bufs ? res->val : nullptr, bufs ? res->capacity : 0, w->st, s);
+                          bufs ? res->val : nullptr, bufs ? res->capacity : 0, w->st, s, sym_rp);
         GDE_HIP(hipGetLastError());
         if ((rc = sync_state(w, s))) return rc;
         nnz = w->hst->out_count;
@@ -1002,7 +1009,7 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
             o_idx = w->out_idx;
             o_val = w->out_val;
         }
-        launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, nullptr, s);
+        launch_ex_emit<V>(w->bitmap, nwords, w->blk, w->nblk, w->x, o_idx, o_val, fits ? nnz : 0, nullptr, s, sym_rp);
         GDE_HIP(hipGetLastError());
         if (fits && nnz > 0) {
             GDE_HIP(hipMemcpyAsync(res->idx, w->out_idx, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
@@ -1290,9 +1297,9 @@ int gde_solve_global(gde_ctx *ctx, const gde_graph *g, const gde_params *p, cons
     if (!ctx || !g || !res) return fail(GDE_ERR_INVALID_ARG, "null ctx, graph or result");
     int rc = validate_params(p);
     if (rc) { res->status = rc; return rc; }
-    if (p->kind == GDE_HK || p->kind == GDE_SERIES || p->method == GDE_LOCAL_SOR) {
+    if (p->kind == GDE_HK || p->kind == GDE_SERIES || p->method == GDE_LOCAL_SOR || (p->flags & GDE_SYM_NORM)) {
         res->status = GDE_ERR_UNSUPPORTED;
-        return fail(GDE_ERR_UNSUPPORTED, "the global solvers are GD and Chebyshev for PPR and Katz");
+        return fail(GDE_ERR_UNSUPPORTED, "the global solvers are GD and Chebyshev for PPR and Katz (M = A D^-1)");
     }
     GraphHost *gh = graph_host(g);
     if (!gh) return fail(GDE_ERR_INVALID_ARG, "unknown graph handle");

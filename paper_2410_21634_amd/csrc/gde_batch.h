@@ -7,8 +7,6 @@ namespace gde {
 int get_workspace(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out);
 void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx);
 void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx);
-// after g's CSR gained edges (same n): recompute the degrees the batch workspaces of ctx hold
-int batch_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s);
 // push-kernel timing helpers (no-ops unless profiling is enabled on ctx)
 int prof_mark(gde_ctx *ctx, hipStream_t s);
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries);

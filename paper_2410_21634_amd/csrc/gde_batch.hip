@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -69,16 +70,6 @@ void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
     }
 }
 
-int batch_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s) {
-    for (BatchWS *b : ctx->bws) {
-        if (b->guid != g->uid) continue;
-        const hipError_t e = b->vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)b->deg, g->n, s)
-                                                 : batch_init_deg<float>(g->row_ptr, (float *)b->deg, g->n, s);
-        if (e != hipSuccess) return hip_fail(e, "batch_init_deg");
-    }
-    return GDE_OK;
-}
-
 struct DevBuf {  // device scratch released on every return path
     void *p = nullptr;
     ~DevBuf() {
@@ -90,6 +81,7 @@ struct Schedule {
     int lanes = 16;
     int blocks_per_cu = 0;  // 0: the occupancy limit
     int sort = 1;           // order queries by eps, then seed degree, before packing lanes
+    int autotune = 0;       // choose lanes and blocks_per_cu by timing candidates (cached per context)
 };
 
 static int json_int(const char *js, const char *key, int dflt) {
@@ -106,6 +98,7 @@ static int parse_schedule(const char *js, Schedule *sc) {
     sc->lanes = json_int(js, "lanes", 16);
     sc->blocks_per_cu = json_int(js, "blocks_per_cu", 0);
     sc->sort = json_int(js, "sort", 1);
+    sc->autotune = json_int(js, "auto", 0);
     if (sc->lanes != 8 && sc->lanes != 16 && sc->lanes != 32)
         return fail(GDE_ERR_INVALID_ARG, "schedule.lanes must be 8, 16 or 32");
     if (sc->blocks_per_cu < 0 || sc->blocks_per_cu > 64) return fail(GDE_ERR_INVALID_ARG, "bad schedule.blocks_per_cu");
@@ -368,6 +361,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.R2 = lvl ? (V *)w->R2 : nullptr;
     a.th_div = 0.0;
     a.no_push = 0;
+    a.sym = (p[0].flags & GDE_SYM_NORM) ? 1 : 0;
     a.lane_ops = w->lane_ops;
     a.lane_pushes = w->lane_pushes;
     a.lane_T = w->lane_T;
@@ -613,7 +607,64 @@ static int solve_batch_split(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     return r1 ? r1 : r2;
 }
 
+// "auto" schedule: the first batch of a (graph, kind, value type, size class)
+// is solved once with each candidate schedule, timed on the host around the
+// whole call (workspace taken beforehand, so no candidate pays for an
+// allocation); the fastest is kept in the context and used from then on.  The
+// last candidate's results are returned (every run is a complete solve).
+static int solve_batch_tuned(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
+                             gde_result *res, const Schedule &sc, hipStream_t stream) {
+    int bclass = 0;
+    while ((1 << bclass) < B) bclass++;
+    for (const gde_ctx::Tuned &t : ctx->tuned) {
+        if (t.guid == g->uid && t.kind == p[0].kind && t.vtype == p[0].value_type && t.bclass == bclass) {
+            Schedule c = sc;
+            c.lanes = t.lanes;
+            c.blocks_per_cu = t.bpc;
+            return solve_batch_split(ctx, g, B, p, s, res, c, stream);
+        }
+    }
+    static const int cand[][2] = {{8, 0}, {32, 0}, {16, 2}, {16, 0}};
+    double best = 1e300;
+    Schedule pick = sc;
+    int rc = GDE_OK;
+    for (const auto &cd : cand) {
+        Schedule c = sc;
+        c.lanes = cd[0];
+        c.blocks_per_cu = cd[1];
+        BatchWS *w = nullptr;
+        if ((rc = batch_ws_get(ctx, g, p[0].value_type, c.lanes, (B + c.lanes - 1) / c.lanes, stream, &w))) return rc;
+        GDE_HIP(hipStreamSynchronize(stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = solve_batch_split(ctx, g, B, p, s, res, c, stream);
+        GDE_HIP(hipStreamSynchronize(stream));
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc != GDE_OK && rc != GDE_ERR_NOT_CONVERGED && rc != GDE_ERR_CAPACITY) return rc;
+        if (dt < best) {
+            best = dt;
+            pick = c;
+        }
+    }
+    ctx->tuned.push_back(gde_ctx::Tuned{g->uid, p[0].kind, p[0].value_type, bclass, pick.lanes, pick.blocks_per_cu});
+    return rc;
+}
+
 extern "C" {
+
+int gde_batch_tuned(const gde_ctx *ctx, const gde_graph *g, int32_t kind, int32_t value_type, int32_t B,
+                    int32_t *lanes, int32_t *blocks_per_cu) {
+    if (!ctx || !g || !lanes || !blocks_per_cu || B < 1) return fail(GDE_ERR_INVALID_ARG, "null argument or B < 1");
+    int bclass = 0;
+    while ((1 << bclass) < B) bclass++;
+    for (const gde_ctx::Tuned &t : ctx->tuned) {
+        if (t.guid == g->uid && t.kind == kind && t.vtype == value_type && t.bclass == bclass) {
+            *lanes = t.lanes;
+            *blocks_per_cu = t.bpc;
+            return GDE_OK;
+        }
+    }
+    return fail(GDE_ERR_INVALID_ARG, "no schedule was chosen for this graph, kind, value type and batch size");
+}
 
 int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *s,
                     gde_result *res, const char *schedule_json, hipStream_t stream) {
@@ -650,7 +701,7 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
     for (int32_t i = 1; i < B && fused; i++) {
         fused = same_kind_params(p[i], p[0]) && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
                 !(p[i].flags & GDE_DETERMINISTIC) &&
-                (p[i].flags & GDE_RESULT_DEVICE) == (p[0].flags & GDE_RESULT_DEVICE);
+                (p[i].flags & (GDE_RESULT_DEVICE | GDE_SYM_NORM)) == (p[0].flags & (GDE_RESULT_DEVICE | GDE_SYM_NORM));
     }
     GDE_HIP(hipSetDevice(ctx->device));
     // LocalSOR / APPR: every query in one wavefront of the same launch
@@ -670,6 +721,7 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
         }
         return first;
     }
+    if (sc.autotune) return solve_batch_tuned(ctx, g, B, p, s, res, sc, stream);
     return solve_batch_split(ctx, g, B, p, s, res, sc, stream);
 }
 

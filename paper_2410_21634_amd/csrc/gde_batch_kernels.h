@@ -87,6 +87,7 @@ struct BatchArgs {
     V *R2;
     double th_div;
     int32_t no_push;  // snap of the last level: x only, nothing pushed
+    int32_t sym;      // M = D^-1/2 A D^-1/2: seeds scaled by sqrt(d), outputs by 1/sqrt(d)
     // measurement only: row_stamp[u] == round_tag once row u was counted in this
     // iteration (distinct CSR rows read per round, whatever the groups); null = off
     uint32_t *row_stamp;

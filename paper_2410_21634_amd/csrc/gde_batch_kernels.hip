@@ -340,7 +340,9 @@ __global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane,
         const int lane_id = s_lane[i];
         const int g = lane_id / L, l = lane_id % L;
         const int32_t u = s_node[i];
-        a.R[((size_t)u * a.G + g) * L + l] = (V)(bscale * s_val[i]);
+        double sv = s_val[i];
+        if (a.sym) sv = sv * sqrt((double)(a.row_ptr[u + 1] - a.row_ptr[u]));
+        a.R[((size_t)u * a.G + g) * L + l] = (V)(bscale * sv);
         fresh = atomicOr(&a.NM[(size_t)u * a.G + g], 1u << l) == 0u;
         pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
     }
@@ -552,9 +554,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const 
             V *xr = a.X + ((size_t)u * a.G + g) * L;
 #pragma unroll
             for (int l = 0; l < L; l++) {
-                const V xv = xr[l];
-                if (xv != (V)0) {
+                const V xv0 = xr[l];
+                if (xv0 != (V)0) {
                     const long long lo = lane_out_off[g * L + l];
+                    const V xv = a.sym ? (V)((double)xv0 / sqrt((double)(a.row_ptr[u + 1] - a.row_ptr[u]))) : xv0;
                     if (write && lo >= 0) {
                         if (lane_idx) {  // straight into the query's own buffers
                             lane_idx[g * L + l][pos[l] - lo] = u;

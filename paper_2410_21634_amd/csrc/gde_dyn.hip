@@ -231,6 +231,7 @@ int gde_dyn_add(gde_dyn *dy, const gde_params *p, const gde_seed *s, int32_t *qi
         return fail(GDE_ERR_UNSUPPORTED, "standing queries are PPR or Katz with LocalGD");
     if (p->value_type != dy->vtype) return fail(GDE_ERR_INVALID_ARG, "value_type differs from the dynamic graph's");
     if (p->flags & GDE_KATZ_SUBTRACT_SEED) return fail(GDE_ERR_UNSUPPORTED, "standing Katz queries keep x, not x - s");
+    if (p->flags & GDE_SYM_NORM) return fail(GDE_ERR_UNSUPPORTED, "standing queries use M = A D^-1");
     GDE_HIP(hipSetDevice(dy->ctx->device));
     const int64_t n = dy->n;
     gde_dyn_query *q = new gde_dyn_query();

@@ -184,6 +184,13 @@ struct gde_ctx {
     int64_t prof_b_launches = 0, prof_b_lane_edges = 0, prof_b_entries = 0;
     double prof_b_ms = 0.0;
     std::vector<gde::BatchWS *> bws;  // batched-solver workspaces
+    // schedules chosen by gde_solve_batch's "auto" mode, per (graph, kind, value
+    // type, batch size class): lanes and blocks per CU
+    struct Tuned {
+        uint64_t guid;
+        int32_t kind, vtype, bclass, lanes, bpc;
+    };
+    std::vector<Tuned> tuned;
     hipEvent_t ev_b[2] = {nullptr, nullptr};
     int ev_b_used = 0;
     // batched push launches: event pairs of the current solve, and their totals

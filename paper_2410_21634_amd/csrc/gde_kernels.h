@@ -154,7 +154,8 @@ struct SeedInline {
 template <typename V>
 void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, const SeedInline *inl, int32_t nnz,
                       double bscale, int32_t *f0,
-                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s);
+                      int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm, DevState *st, hipStream_t s,
+                      const int32_t *sym_rp = nullptr);
 template <typename V> void launch_snap_gd(const SnapArgs &a, V wscale, int w_div_deg, hipStream_t s);
 template <typename V>
 void launch_snap_hk(const SnapArgs &a, void *prev, V wmul, int last_level, int frontier_on, const int32_t *prev_touched,
@@ -179,7 +180,7 @@ void launch_ex_count(const uint32_t *bm, int64_t nwords, int32_t *blk, int64_t n
 void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s);
 template <typename V>
 void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
-                    void *out_val, int64_t cap, const DevState *st, hipStream_t s);
+                    void *out_val, int64_t cap, const DevState *st, hipStream_t s, const int32_t *sym_rp = nullptr);
 void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
                       int32_t *dmax, hipStream_t s);
 void launch_lam_step(const int32_t *row_ptr, const int32_t *col_idx, const double *v, double *y, int32_t n,

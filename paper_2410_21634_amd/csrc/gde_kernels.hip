@@ -85,14 +85,19 @@ __global__ void k_init_rd(const int32_t *__restrict__ row_ptr, RD<V> *rd, int32_
 // r <- b on supp(s); S_0 = supp(s) (forced, Definition 3.1); counters reset.
 // A seed of at most kSeedInline entries arrives in the kernel arguments (inl.n
 // > 0) instead of device buffers, which saves two host-to-device copies.
+// sym_rp (row pointers, or null): the propagation matrix D^-1/2 A D^-1/2, solved
+// in the A D^-1 form from the source D^1/2 s (Sec. 3.3), so s_u is scaled by
+// sqrt(d_u) here and x_u by 1/sqrt(d_u) on output.
 template <typename V>
 __global__ void k_seed_init(RD<V> *rd, const int32_t *__restrict__ sidx, const double *__restrict__ sval, int32_t nnz,
                             SeedInline inl, double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp,
-                            int32_t stamp0, uint32_t *tbm, DevState *st) {
+                            int32_t stamp0, uint32_t *tbm, DevState *st, const int32_t *__restrict__ sym_rp) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nnz) {
         const int32_t u = inl.n ? inl.idx[i] : sidx[i];
-        rd[u].r = (V)(bscale * (inl.n ? inl.val[i] : sval[i]));
+        double sv = inl.n ? inl.val[i] : sval[i];
+        if (sym_rp) sv = sv * sqrt((double)(sym_rp[u + 1] - sym_rp[u]));
+        rd[u].r = (V)(bscale * sv);
         f0[i] = u;
         if (touched0) touched0[i] = u;
         if (cstamp) cstamp[u] = stamp0;
@@ -1234,7 +1239,7 @@ __global__ void __launch_bounds__(1024) k_ex_scan(int32_t *blk, int64_t nblk, De
 template <typename V>
 __global__ void __launch_bounds__(kBlock) k_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *__restrict__ blk,
                                                      V *x, int32_t *out_idx, V *out_val, int64_t cap,
-                                                     const DevState *st) {
+                                                     const DevState *st, const int32_t *__restrict__ sym_rp) {
     __shared__ int s[kBlock];
     // with st: write only if the whole support fits (else nothing is written)
     if (st && (int64_t)st->out_count > cap) cap = 0;
@@ -1257,7 +1262,8 @@ __global__ void __launch_bounds__(kBlock) k_ex_emit(uint32_t *bm, int64_t nwords
             int32_t u = (int32_t)(i * 32 + b);
             if (out_idx && pos < cap) {
                 out_idx[pos] = u;
-                out_val[pos] = x[u];
+                // D^-1/2 A D^-1/2: the A D^-1 solution scaled back (see k_seed_init)
+                out_val[pos] = sym_rp ? (V)((double)x[u] / sqrt((double)(sym_rp[u + 1] - sym_rp[u]))) : x[u];
             }
             x[u] = (V)0;
             pos++;
@@ -1362,10 +1368,10 @@ void launch_init_rd(const int32_t *row_ptr, void *rd, int32_t n, hipStream_t s) 
 template <typename V>
 void launch_seed_init(void *rd, const int32_t *sidx, const double *sval, const SeedInline *inl, int32_t nnz,
                       double bscale, int32_t *f0, int32_t *touched0, int32_t *cstamp, int32_t stamp0, uint32_t *tbm,
-                      DevState *st, hipStream_t s) {
+                      DevState *st, hipStream_t s, const int32_t *sym_rp) {
     SeedInline none{};
     hipLaunchKernelGGL(k_seed_init<V>, dim3(grid_for(nnz, 256, 65535)), dim3(256), 0, s, (RD<V> *)rd, sidx, sval, nnz,
-                       inl ? *inl : none, bscale, f0, touched0, cstamp, stamp0, tbm, st);
+                       inl ? *inl : none, bscale, f0, touched0, cstamp, stamp0, tbm, st, sym_rp);
 }
 
 template <typename V>
@@ -1444,9 +1450,9 @@ void launch_ex_scan(int32_t *blk, int64_t nblk, DevState *st, hipStream_t s) {
 }
 template <typename V>
 void launch_ex_emit(uint32_t *bm, int64_t nwords, const int32_t *blk, int64_t nblk, void *x, int32_t *out_idx,
-                    void *out_val, int64_t cap, const DevState *st, hipStream_t s) {
+                    void *out_val, int64_t cap, const DevState *st, hipStream_t s, const int32_t *sym_rp) {
     hipLaunchKernelGGL(k_ex_emit<V>, dim3((unsigned)nblk), dim3(kBlock), 0, s, bm, nwords, blk, (V *)x, out_idx,
-                       (V *)out_val, cap, st);
+                       (V *)out_val, cap, st, sym_rp);
 }
 
 void launch_check_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz, int32_t *bad,
@@ -1470,7 +1476,8 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
     template void launch_small<V>(const SmallArgs<V> &, bool, hipStream_t);                                       \
     template void launch_init_rd<V>(const int32_t *, void *, int32_t, hipStream_t);                               \
     template void launch_seed_init<V>(void *, const int32_t *, const double *, const SeedInline *, int32_t, double, int32_t *,        \
-                                      int32_t *, int32_t *, int32_t, uint32_t *, DevState *, hipStream_t);        \
+                                      int32_t *, int32_t *, int32_t, uint32_t *, DevState *, hipStream_t,         \
+                                      const int32_t *);        \
     template void launch_snap_gd<V>(const SnapArgs &, V, int, hipStream_t);                                       \
     template void launch_snap_hk<V>(const SnapArgs &, void *, V, int, int, const int32_t *, int, int, double,    \
                                     double, hipStream_t);                                                         \
@@ -1484,7 +1491,7 @@ void launch_fill_f64(double *v, int64_t n, double val, hipStream_t s) {
     template void launch_subtract_seed<V>(void *, const int32_t *, const double *, int, hipStream_t);             \
     template void launch_ch_probe<V>(const void *, const int32_t *, DevState *, int, V, int32_t, hipStream_t);     \
     template void launch_ex_emit<V>(uint32_t *, int64_t, const int32_t *, int64_t, void *, int32_t *, void *,   \
-                                    int64_t, const DevState *, hipStream_t);
+                                    int64_t, const DevState *, hipStream_t, const int32_t *);
 
 GDE_INST(float)
 GDE_INST(double)

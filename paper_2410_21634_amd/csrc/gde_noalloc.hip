@@ -139,8 +139,9 @@ extern "C" int gde_solve_noalloc(const gde_graph *g, const gde_params *p, const 
     if (!(p->flags & GDE_RESULT_DEVICE))
         return fail(GDE_ERR_INVALID_ARG, "gde_solve_noalloc writes device results only (set GDE_RESULT_DEVICE)");
     if (p->method == GDE_LOCAL_SOR) return fail(GDE_ERR_UNSUPPORTED, "gde_solve_noalloc runs LocalGD and LocalCH");
-    if (p->flags & (GDE_TRACE | GDE_DETERMINISTIC | GDE_SCATTER_BINNED))
-        return fail(GDE_ERR_UNSUPPORTED, "gde_solve_noalloc provides no trace, deterministic mode or binned scatter");
+    if (p->flags & (GDE_TRACE | GDE_DETERMINISTIC | GDE_SCATTER_BINNED | GDE_SYM_NORM))
+        return fail(GDE_ERR_UNSUPPORTED,
+                    "gde_solve_noalloc provides no trace, deterministic mode, binned scatter or GDE_SYM_NORM");
     if (s->nnz > kNoallocSeedCap) return fail(GDE_ERR_INVALID_ARG, "gde_solve_noalloc takes at most 4096 seed entries");
     const size_t need = gde_solve_noalloc_bytes(g, p, s);
     if (need > (size_t)GDE_NOALLOC_SCRATCH_BYTES)

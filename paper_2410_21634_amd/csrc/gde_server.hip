@@ -1013,8 +1013,9 @@ int gde_server_submit(gde_server *sv, const gde_params *p, const gde_seed *s, ui
     int rc = gde_validate_query(sv->g, p, s);
     if (rc) return rc;
     if (p->method != GDE_LOCAL_GD) return fail(GDE_ERR_UNSUPPORTED, "the server runs LocalGD");
-    if (p->flags & GDE_DETERMINISTIC)
-        return fail(GDE_ERR_UNSUPPORTED, "the deterministic mode is provided by gde_solve, not by the server");
+    if (p->flags & (GDE_DETERMINISTIC | GDE_SYM_NORM))
+        return fail(GDE_ERR_UNSUPPORTED, "the deterministic mode and GDE_SYM_NORM are provided by gde_solve, not by "
+                                         "the server");
     std::unique_lock<std::mutex> lk(sv->hk_mu);
     if (sv->n_pending + (int64_t)sv->hk_queue.size() >= sv->cfg.queue_capacity)
         return fail(GDE_ERR_BUSY, "server queue is full");

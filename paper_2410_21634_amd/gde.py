@@ -23,6 +23,7 @@ F32, F64 = 0, 1
 HOST_PTRS, DEVICE_PTRS, COPY, BORROW = 0x1, 0x2, 0x4, 0x8
 KATZ_SUBTRACT_SEED, TRACE, RESULT_DEVICE = 0x1, 0x2, 0x4
 SCATTER_BINNED, SCATTER_ATOMIC, DETERMINISTIC = 0x8, 0x10, 0x20
+SYM_NORM = 0x40  # M = D^-1/2 A D^-1/2 (APPNP) for PPR, HK and series
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # GDE_NOALLOC_SCRATCH_BYTES of gde.h
 STATUS_NAMES = ["OK", "INVALID_ARG", "ISOLATED_SEED", "CAPACITY", "NOT_CONVERGED", "OOM", "BUSY", "DEVICE",
                 "UNSUPPORTED"]
@@ -103,6 +104,7 @@ _SIGS = {
     "gde_dyn_update": ([_vp, _i32, _vp, _vp, _i32, _vp, _vp], C.c_int),
     "gde_dyn_read": ([_vp, _i32, C.POINTER(Result), C.c_uint32], C.c_int),
     "gde_dyn_destroy": ([_vp], C.c_int),
+    "gde_batch_tuned": ([_vp, _vp, _i32, _i32, _i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "gde_solve_batch": ([_vp, _vp, _i32, C.POINTER(Params), C.POINTER(Seed), C.POINTER(Result), C.c_char_p, _vp],
                         C.c_int),
     "gde_server_create": ([_vp, _vp, C.POINTER(ServerCfg), C.POINTER(_vp)], C.c_int),
@@ -197,6 +199,13 @@ class Context:
         _check(_lib.gde_ctx_create(int(device), C.byref(h)))
         self.handle = h
         self.device = device
+
+    def batch_tuned(self, graph, kind, value_type, B):
+        """(lanes, blocks_per_cu) chosen by the "auto" schedule for such batches, or None."""
+        ln, bp = C.c_int32(0), C.c_int32(0)
+        k = KINDS[kind] if isinstance(kind, str) else int(kind)
+        rc = _lib.gde_batch_tuned(self.handle, graph.handle, k, int(value_type), int(B), C.byref(ln), C.byref(bp))
+        return (ln.value, bp.value) if rc == OK else None
 
     def profile(self, enable: bool = True, reset: bool = True) -> dict:
         """Push-kernel event timing: returns the totals so far, then sets the mode."""

@@ -81,8 +81,15 @@ def test_validation_errors(small):
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
     for f in (gde.SCATTER_BINNED, gde.SCATTER_ATOMIC, gde.DETERMINISTIC, gde.DETERMINISTIC | gde.TRACE):
         assert gde.validate(rp, ci, gde.make_params(flags=f), [0]) == gde.OK
-    p = gde.make_params(flags=gde.DETERMINISTIC << 1)  # the first undefined flag bit
+    p = gde.make_params(flags=gde.SYM_NORM << 1)  # the first undefined flag bit
     assert gde.validate(rp, ci, p, [0]) == gde.INVALID_ARG
+    # D^-1/2 A D^-1/2: PPR, HK and series with LocalGD / LocalCH / the level push
+    for kw in (dict(), dict(method="ch"), dict(kind="hk", tau=5.0, K=30), dict(kind="series", c=[0.5, 0.25])):
+        assert gde.validate(rp, ci, gde.make_params(flags=gde.SYM_NORM, **kw), [0]) == gde.OK
+    assert gde.validate(rp, ci, gde.make_params(kind="katz", beta=0.1, lambda_bound=2.0, flags=gde.SYM_NORM),
+                        [0]) == gde.INVALID_ARG
+    for kw in (dict(method="sor", flags=gde.SYM_NORM), dict(flags=gde.SYM_NORM | gde.DETERMINISTIC)):
+        assert gde.validate(rp, ci, gde.make_params(**kw), [0]) == gde.UNSUPPORTED
     # malformed CSR
     bad = rp.copy()
     bad[-1] += 1

@@ -93,7 +93,8 @@ def run_and_check(gde, ctx, g, G, queries, kind, vt, schedule, param, lam=0.0):
 
 
 @pytest.mark.parametrize("vt", [1, 0])
-@pytest.mark.parametrize("schedule", ['{"lanes":16}', '{"lanes":8,"persistent":0}', '{"lanes":32,"blocks_per_cu":2}'])
+@pytest.mark.parametrize("schedule", ['{"lanes":16}', '{"lanes":8,"persistent":0}', '{"lanes":32,"blocks_per_cu":2}',
+                                      '{"auto":1}'])
 def test_batch_ppr_matches_oracle(gde, ctx, c1, vt, schedule):
     G, g = c1
     queries = make_queries(G, 40, seed=1)

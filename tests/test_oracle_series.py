@@ -90,3 +90,57 @@ def test_series_truncated_ppr_approaches_ppr(g300):
 def test_series_rejects_bad_coefficients(g300, bad):
     with pytest.raises(ValueError):
         O.series(g300.row_ptr, g300.col_idx, np.array(bad), 1e-4, [0])
+
+
+def sym_matrix(A):
+    d = A.sum(axis=0)
+    inv = np.where(d > 0, 1.0 / np.sqrt(np.where(d > 0, d, 1.0)), 0.0)
+    return inv[:, None] * A * inv[None, :]
+
+
+def test_symmetric_series_is_the_appnp_series(g300):
+    # M = D^-1/2 A D^-1/2 (Table 1, APPNP): at eps -> 0 the transformed level push
+    # equals sum_k c_k M^k s computed densely from M itself; at finite eps the
+    # A D^-1 guarantee, scaled by D^-1/2, gives 0 <= f - x <= eps sqrt(d)
+    G = g300
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    Ms = sym_matrix(A)
+    d = np.diff(G.row_ptr).astype(float)
+    c = 0.1 * 0.9 ** np.arange(21)
+    seeds = [int(v) for v in W.uniform_seeds(G, 3, seed=8)]
+    vals = [0.2, 0.7, 0.1]
+    s = np.zeros(G.n)
+    s[seeds] = vals
+    f = np.zeros(G.n)
+    v = s.copy()
+    for ck in c:
+        f += ck * v
+        v = Ms @ v
+    res = O.symmetric(O.series, G.row_ptr, G.col_idx, c, TINY, seed_idx=seeds, seed_val=vals)
+    np.testing.assert_allclose(res["x"], f, rtol=1e-12, atol=1e-16)
+    for eps in (1e-3, 1e-5):
+        res = O.symmetric(O.series, G.row_ptr, G.col_idx, c, eps, seed_idx=seeds, seed_val=vals)
+        gap = f - res["x"]
+        assert (gap >= -1e-15).all() and (gap <= eps * np.sqrt(d) + 1e-15).all()
+        if eps == 1e-3:
+            assert (gap > eps * np.sqrt(d) * 1e-2).any()  # the stop rule left something behind
+
+
+def test_symmetric_ppr_localgd(g300):
+    # PPR with M = D^-1/2 A D^-1/2: f = alpha (I - (1 - alpha) M)^-1 s; LocalGD
+    # through the transform stops with |f - x| <= eps sqrt(d) componentwise
+    G = g300
+    A = X.dense_adjacency(G.row_ptr, G.col_idx)
+    Ms = sym_matrix(A)
+    d = np.diff(G.row_ptr).astype(float)
+    a = 0.15
+    for s_node in W.uniform_seeds(G, 3, seed=9):
+        s = np.zeros(G.n)
+        s[int(s_node)] = 1.0
+        f = a * np.linalg.solve(np.eye(G.n) - (1 - a) * Ms, s)
+        for eps in (1e-4, 1e-7):
+            res = O.symmetric(O.localgd, G.row_ptr, G.col_idx, O.PPR, a, eps, seed_idx=[int(s_node)])
+            gap = f - res["x"]
+            assert (gap >= -1e-14).all() and (gap <= eps * np.sqrt(d) + 1e-14).all()
+        res = O.symmetric(O.localgd, G.row_ptr, G.col_idx, O.PPR, a, 1e-15, seed_idx=[int(s_node)])
+        np.testing.assert_allclose(res["x"], f, rtol=1e-9, atol=1e-13)
