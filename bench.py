@@ -428,14 +428,17 @@ def run_c4(args):
     torch.cuda.synchronize()
     ctx.profile(True, reset=True)
     t0 = time.perf_counter()
+    per_batch = []
     for i in range(args.steps):
-        res = gde.solve_batch(ctx, g, params, bseeds, schedule=args.schedule, out=bout)
+        tb = time.perf_counter()
+        res = gde.solve_batch(ctx, g, params, bseeds, schedule=args.schedule, out=bout)  # returns when done
+        per_batch.append(time.perf_counter() - tb)
         log(f"timed batch {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = ctx.profile(False, reset=True)
     tuned = ctx.batch_tuned(g, "ppr", gde.F32, B)
-    lanes = tuned[0] if tuned else 16
+    lanes = tuned[0] if tuned else json.loads(args.schedule or "{}").get("lanes", 16)
     ops = int(res.ops.sum())
     pushes = int(res.pushes.sum())
     value = B * args.steps / el
@@ -483,7 +486,9 @@ def run_c4(args):
                            schedule_chosen=dict(lanes=tuned[0], blocks_per_cu=tuned[1]) if tuned else None),
                hbm_gbs_alg=round(gbs, 2), hbm_frac_alg=round(gbs / PEAK_HBM_GBS, 5),
                roofline=roof,
-               batch=dict(ms_per_batch=round(1e3 * el / args.steps, 3), solve_span_ms=round(kms, 3),
+               batch=dict(ms_per_batch=round(1e3 * el / args.steps, 3),
+                          ms_per_batch_median=round(1e3 * float(np.median(per_batch)), 3),
+                          ms_per_batch_min=round(1e3 * min(per_batch), 3), solve_span_ms=round(kms, 3),
                           push_ms_per_batch=round(prof["batch_push_ms"] / K, 3),
                           lane_edges=int(prof["batch_lane_edges"] // K), entries=int(prof["batch_entries"] // K),
                           distinct_rows=int(prof["batch_rows"] // K), distinct_row_vol=int(prof["batch_row_vol"] // K),

@@ -340,9 +340,10 @@ size_t gde_solve_noalloc_bytes(const gde_graph *g, const gde_params *p, const gd
  * schedule_json: NULL = the default schedule (16 lanes, full occupancy), else
  * a JSON object {"lanes":L,"blocks_per_cu":G,"sort":0|1,"auto":0|1}.  With
  * "auto":1 the first batch of a (graph, kind, value type, power-of-two size
- * class) is solved once per candidate schedule (8, 32 and 16 lanes, two
- * blocks per CU) and timed; the fastest is kept in the context for later
- * calls, and the results of the last run (a complete solve) are returned.
+ * class) is solved twice per candidate schedule (8, 32 and 16 lanes, 16 lanes
+ * at two blocks per CU) and timed; the candidate of the fastest run is kept in
+ * the context for later calls, and the results of the last run (a complete
+ * solve) are returned.
  * Every iteration is one snapshot and one push launch; "persistent":1 (a
  * single launch for all iterations) is not provided and gives
  * GDE_ERR_UNSUPPORTED.

@@ -42,6 +42,7 @@ struct BatchArgs {
     const int32_t *row_ptr;
     const int32_t *col_idx;
     const V *deg;
+    const V *col_deg;  // optional [nnz]: deg[col_idx[e]], streamed beside col_idx instead of gathered
     V *R;
     V *X;
     uint32_t *NM;  // [n][G] lanes crossing their threshold this iteration
@@ -116,5 +117,7 @@ hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, 
                          const int32_t *gmap = nullptr, int ngroups = 0, int32_t *const *lane_idx = nullptr,
                          V *const *lane_val = nullptr);
 template <typename V> hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s);
+template <typename V>
+hipError_t batch_init_col_deg(const int32_t *col_idx, const V *deg, V *col_deg, int64_t nnz, hipStream_t s);
 
 }  // namespace gde

@@ -226,7 +226,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         // and atomics are issued before any result is waited on
         constexpr int kPer = kTile / kBlock;
         int32_t gq[kPer], wq[kPer], lq[kPer];
-        V dv[kPer];
+        V dv[kPer], dq[kPer];
         bool hit[kPer], first[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
@@ -236,6 +236,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             wq[q] = -1;
             lq[q] = 0;
             dv[q] = (V)0;
+            dq[q] = (V)0;
             if (e < e1) {
                 int lo = 0, hi = m - 1;
                 while (lo < hi) {
@@ -253,6 +254,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                     if (ci >= 0 && ci < a.nnz && l < L) {
                         gq[q] = s_g[lo];
                         wq[q] = a.col_idx[ci];
+                        if (a.col_deg) dq[q] = a.col_deg[ci];
                         lq[q] = l;
                         dv[q] = a.wl_sv[slot * L + k];
                     } else {
@@ -267,7 +269,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             th[q] = (V)0;
             if (wq[q] >= 0) {
                 const V e = a.lane_eps[gq[q] * L + lq[q]];
-                th[q] = (a.R2 ? (V)((double)e / a.th_div) : e) * a.deg[wq[q]];
+                th[q] = (a.R2 ? (V)((double)e / a.th_div) : e) * (a.col_deg ? dq[q] : a.deg[wq[q]]);
             }
         }
 #pragma unroll
@@ -696,6 +698,19 @@ hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, 
 }
 
 template <typename V>
+__global__ void k_batch_col_deg(const int32_t *__restrict__ col_idx, const V *__restrict__ deg, V *col_deg,
+                                int64_t nnz) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        col_deg[e] = deg[col_idx[e]];
+}
+
+template <typename V>
+hipError_t batch_init_col_deg(const int32_t *col_idx, const V *deg, V *col_deg, int64_t nnz, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_col_deg<V>, dim3(8192), dim3(256), 0, s, col_idx, deg, col_deg, nnz);
+    return hipGetLastError();
+}
+
+template <typename V>
 hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_init_deg<V>, dim3(4096), dim3(256), 0, s, row_ptr, deg, n);
     return hipGetLastError();
@@ -712,7 +727,8 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
     template hipError_t batch_extract<V>(int, const BatchArgs<V> &, int, int32_t *, int, long long *,              \
                                          const long long *, int32_t *, V *, int, hipStream_t, const int32_t *,     \
                                          int, int32_t *const *, V *const *);                                       \
-    template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);
+    template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);                            \
+    template hipError_t batch_init_col_deg<V>(const int32_t *, const V *, V *, int64_t, hipStream_t);
 
 GDE_BINST(float)
 GDE_BINST(double)
