@@ -103,6 +103,12 @@ __global__ void __launch_bounds__(kFifoBlock) k_fifo(FifoArgs a) {
     long long pops = 0, ops = 0, epochs = 0, epoch_left = count;
     int status = GDE_OK;
     const double om = P.omega;
+    // The next pop's node, row bounds and first 64 column ids are read while the
+    // current pop runs: the queue entry is fixed once appended (appends go to
+    // the tail of a ring of capacity n) and the CSR never changes, so only the
+    // residuals and flags have to be read in order.
+    bool have = false;
+    int32_t nu = 0, nbeg = 0, nend = 0, nw = 0;
     while (count > 0) {
         if (pops >= P.max_pops) {
             status = GDE_ERR_NOT_CONVERGED;
@@ -112,19 +118,36 @@ __global__ void __launch_bounds__(kFifoBlock) k_fifo(FifoArgs a) {
             epochs++;
             epoch_left = count;
         }
-        const int32_t u = q[head];
+        const bool pre = have;
+        int32_t u, beg, end;
+        if (pre) {
+            u = nu;
+            beg = nbeg;
+            end = nend;
+        } else {
+            u = q[head];
+            beg = a.row_ptr[u];
+            end = a.row_ptr[u + 1];
+        }
+        const int32_t w_first = nw;
         head = head + 1 == n ? 0 : head + 1;
         count--;
         epoch_left--;
-        const int32_t beg = a.row_ptr[u], end = a.row_ptr[u + 1];
+        have = count > 0;  // the following pop is already in the queue
+        if (have) nu = q[head];
         const int32_t du = end - beg;
         const double v = r[u];
         const double wu = P.ppr ? P.w / (double)du : P.w;
         const double coef = om * wu;
+        double ru = 0.0;
         if (ln == 0) {
             x[u] = x[u] + om * v;
-            r[u] = r[u] - om * v;
-            fl[u] = (uint8_t)(fl[u] & ~kQueued);
+            ru = v - om * v;  // r[u] holds v: it is the residual just read
+            r[u] = ru;
+        }
+        if (have) {
+            nbeg = a.row_ptr[nu];
+            nend = a.row_ptr[nu + 1];
         }
         for (int32_t base = beg; base < end; base += kWave) {
             const int32_t e = base + ln;
@@ -132,7 +155,7 @@ __global__ void __launch_bounds__(kFifoBlock) k_fifo(FifoArgs a) {
             int32_t w = 0;
             bool act = false, fresh = false;
             if (valid) {
-                w = a.col_idx[e];
+                w = (pre && base == beg) ? w_first : a.col_idx[e];
                 const double rw = r[w] + coef * v;
                 r[w] = rw;
                 const uint8_t f = fl[w];
@@ -152,18 +175,19 @@ __global__ void __launch_bounds__(kFifoBlock) k_fifo(FifoArgs a) {
             count += __popcll(ma);
             nt += __popcll(mt);
         }
-        __threadfence_block();
-        // u itself, after its row (lane 0 wrote r[u] and fl[u])
+        if (have) nw = nbeg + ln < nend ? a.col_idx[nbeg + ln] : 0;
+        // u itself, after its row: no neighbour is u (simple graph), so its
+        // residual is the ru lane 0 wrote and it is not queued (it was popped)
         int back = 0;
         if (ln == 0) {
-            const uint8_t f = fl[u];
-            const double ru = r[u];
-            if (!(f & kQueued) && ru != 0.0 && fabs(ru) >= P.eps_eff * (double)du) {
+            if (ru != 0.0 && fabs(ru) >= P.eps_eff * (double)du) {
                 long long pos = head + count;
                 if (pos >= n) pos -= n;
                 q[pos] = u;
-                fl[u] = (uint8_t)(f | kQueued);
+                fl[u] = (uint8_t)(kTouched | kQueued);
                 back = 1;
+            } else {
+                fl[u] = kTouched;
             }
         }
         back = __shfl(back, 0);
