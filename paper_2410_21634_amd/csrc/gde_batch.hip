@@ -31,6 +31,7 @@ struct BatchWS {
     void *R = nullptr, *R2 = nullptr, *X = nullptr, *deg = nullptr, *col_deg = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
     uint32_t *NM = nullptr, *TM = nullptr, *PB = nullptr, *group_unconv = nullptr;
     uint64_t *act[2] = {nullptr, nullptr}, *touched = nullptr, *touched2 = nullptr;
+    int32_t *tdeg = nullptr, *tdeg2 = nullptr;  // batched solves: degrees beside the touched entries
     int32_t act_cap = 0, touch_cap = 0, wl_cap = 0;
     int64_t tile_cap = 0;
     int32_t *wl_node = nullptr, *wl_group = nullptr, *wl_beg = nullptr, *wl_c = nullptr, *tile_start = nullptr;
@@ -56,7 +57,7 @@ struct BatchWS {
 
 void batch_ws_free(BatchWS *w) {
     void *p[] = {w->R, w->R2, w->X, w->deg, w->col_deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
-                 w->act[0], w->act[1], w->touched, w->touched2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
+                 w->act[0], w->act[1], w->touched, w->touched2, w->tdeg, w->tdeg2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
                  w->lane_dst, w->row_stamp};
@@ -269,9 +270,12 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
             GDE_HIP(hipMemsetAsync(w->R2, 0, bytes, s));
         }
         if (!w->touched2) {
-            if (hipMalloc((void **)&w->touched2, (size_t)w->touch_cap * 8) != hipSuccess) {
-                w->touched2 = nullptr;
+            if (hipMalloc((void **)&w->touched2, (size_t)w->touch_cap * 8) != hipSuccess ||
+                hipMalloc((void **)&w->tdeg2, (size_t)w->touch_cap * 4) != hipSuccess) {
                 (void)hipGetLastError();
+                if (w->touched2) (void)hipFree(w->touched2);
+                w->touched2 = nullptr;
+                w->tdeg2 = nullptr;
                 return fail(GDE_ERR_OOM, "no device memory for the odd levels' touched list");
             }
         }
@@ -292,6 +296,12 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         GDE_HIP(batch_init_col_deg<V>(g->col_idx, (const V *)w->deg, (V *)w->col_deg, g->nnz, s));
         w->col_deg_of = g->col_idx;
         w->col_deg_nnz = g->nnz;
+    }
+
+    if (!w->tdeg && hipMalloc((void **)&w->tdeg, (size_t)w->touch_cap * 4) != hipSuccess) {
+        w->tdeg = nullptr;
+        (void)hipGetLastError();
+        return fail(GDE_ERR_OOM, "no device memory for the touched entries' degrees");
     }
 
     // lane assignment: query order[j] occupies lane j (group j / L)
@@ -364,6 +374,8 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.act_cap = w->act_cap;
     a.touched = w->touched;
     a.touched2 = w->touched2;
+    a.tdeg = w->tdeg;
+    a.tdeg2 = w->tdeg2;
     a.touch_cap = w->touch_cap;
     a.wl_node = w->wl_node;
     a.wl_group = w->wl_group;

@@ -54,6 +54,7 @@ struct BatchArgs {
     int32_t act_cap;
     uint64_t *touched;
     uint64_t *touched2;  // level push: touched entries of odd levels (even levels use touched)
+    int32_t *tdeg, *tdeg2;  // optional, parallel to touched / touched2: the entry node's degree
     int32_t touch_cap;
     int32_t *wl_node, *wl_group, *wl_beg, *wl_c;
     long long *wl_off;

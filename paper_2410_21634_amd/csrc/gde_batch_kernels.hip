@@ -299,6 +299,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         int sa = block_reserve(n_act, &st->acount[nxt]);
         const bool odd = a.R2 && !(t & 1);  // level push: entries of level t + 1 go to its parity's list
         uint64_t *tlist = odd ? a.touched2 : a.touched;
+        int32_t *tdl = odd ? a.tdeg2 : a.tdeg;
         int stt = block_reserve(n_touch, odd ? &st->tcount2 : &st->tcount);
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
@@ -311,7 +312,11 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             if (new_touch[q]) {
                 // LT: the entry names the lane, (g * L + l) << 32 | node
                 const uint64_t te = LT ? ((uint64_t)(uint32_t)(gq[q] * L + lq[q]) << 32) | (uint32_t)wq[q] : pair;
-                if (stt < a.touch_cap) tlist[stt] = te;
+                if (stt < a.touch_cap) {
+                    tlist[stt] = te;
+                    // the node's degree beside the entry, for the norms at the end
+                    if (LT && tdl) tdl[stt] = (int32_t)(a.col_deg ? dq[q] : a.deg[wq[q]]);
+                }
                 else *ovf = 1;
                 stt++;
             }
@@ -350,7 +355,8 @@ __global__ void k_batch_seed(BatchArgs<V> a, const int32_t *__restrict__ s_lane,
     }
     bwave_append64(fresh, &a.st->acount[0], pair, a.act[0], a.act_cap, &a.st->ovf[0]);
     const uint64_t te = i < ns ? ((uint64_t)(uint32_t)s_lane[i] << 32) | (uint32_t)s_node[i] : 0ull;
-    bwave_append64(i < ns, &a.st->tcount, te, a.touched, a.touch_cap, &a.st->ovf[0]);
+    const int sl = bwave_append64(i < ns, &a.st->tcount, te, a.touched, a.touch_cap, &a.st->ovf[0]);
+    if (sl >= 0 && sl < a.touch_cap && a.tdeg) a.tdeg[sl] = a.row_ptr[s_node[i] + 1] - a.row_ptr[s_node[i]];
 }
 
 // Residual norms per lane over the touched (lane, node) entries (each listed
@@ -371,10 +377,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
     int nt = min(st->tcount, a.touch_cap);
     V *R = a.R;
     const uint64_t *list = a.touched;
+    const int32_t *dl = a.tdeg;
     if (lvl >= 0 && (lvl & 1)) {
         nt = min(st->tcount2, a.touch_cap);
         R = a.R2;
         list = a.touched2;
+        dl = a.tdeg2;
     }
     for (int j = threadIdx.x; j < lds_lanes; j += blockDim.x) {
         s_l1[j] = 0.0;
@@ -388,10 +396,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
     for (int base = blockIdx.x * blockDim.x * kU + threadIdx.x; base < nt; base += stride * kU) {
         uint64_t pr[kU];
         V val[kU];
+        int32_t dd[kU];
 #pragma unroll
         for (int q = 0; q < kU; q++) {
             const int i = base + q * (int)blockDim.x;
             pr[q] = i < nt ? list[i] : ~0ull;
+            dd[q] = (i < nt && dl) ? dl[i] : 0;
         }
 #pragma unroll
         for (int q = 0; q < kU; q++) {
@@ -408,7 +418,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
             R[((size_t)w * a.G + lane_id / L) * L + lane_id % L] = (V)0;
             const double av = fabs((double)val[q]) * rscale;
             if (av > 0.0) {
-                const double dm = lvl >= 0 ? w_dinf * (fabs((double)val[q]) / (double)a.deg[w]) : av / (double)a.deg[w];
+                const double dw = dl ? (double)dd[q] : (double)a.deg[w];
+                const double dm = lvl >= 0 ? w_dinf * (fabs((double)val[q]) / dw) : av / dw;
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(dm);
                 if (lds_lanes) {
                     atomicAdd(&s_l1[lane_id], av);
