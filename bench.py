@@ -275,6 +275,24 @@ def run_c2(args):
                        lane_edges_per_batch=int(bprof["batch_lane_edges"] // max(args.steps, 1)),
                        entries_per_batch=int(bprof["batch_entries"] // max(args.steps, 1)),
                        schedule=sched or "default", not_converged=int((bres.status != 0).sum()))
+        # the LocalCH queries of the step as one batch as well (batched LocalCH)
+        ch_q = [(eps, s) for m, eps, s in queries if m == "ch"]
+        if ch_q:
+            cparams = [params[("ch", eps)] for eps, _ in ch_q]
+            cseeds = [([s], None) for _, s in ch_q]
+            gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=bout)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            for _ in range(args.steps):
+                cres = gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=bout)
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - tc
+            plain_ch = [r for r in recs if r[0] == "ch"]
+            plain_ch_rate = len(plain_ch) / sum(r[3] for r in plain_ch)
+            batched["localch"] = dict(queries=len(ch_q), solves_per_s=round(len(ch_q) * args.steps / tc, 2),
+                                      plain_solves_per_s_same_queries=round(plain_ch_rate, 2),
+                                      speedup_vs_plain=round(len(ch_q) * args.steps / tc / plain_ch_rate, 2),
+                                      not_converged=int((cres.status != 0).sum()))
         log(f"batched: {batched}")
 
     nq = len(queries)

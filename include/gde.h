@@ -332,9 +332,11 @@ size_t gde_solve_noalloc_bytes(const gde_graph *g, const gde_params *p, const gd
  * of them in the same launches: seeds are packed into lanes of node-major
  * residual tiles, so a CSR row that several queries push in the same round is
  * read once.  Queries may differ in eps; they must share kind, method
- * (LocalGD), value type and kind parameters (alpha, beta; tau and K; the
- * series coefficients).  PPR and Katz run the LocalGD iterations (Eq. (9));
- * the heat kernel and GDE_SERIES run the level push, level t of every lane in
+ * (LocalGD or LocalCH), value type and kind parameters (alpha, beta, and
+ * lambda_bound for Katz LocalCH; tau and K; the series coefficients).  PPR and
+ * Katz run the LocalGD (Eq. (9)) or LocalCH (Sec. 3.3) iterations, every lane
+ * with its own residuals and, for LocalCH, its own momentum term; the heat
+ * kernel and GDE_SERIES run the level push, level t of every lane in
  * iteration t.  A batch of GDE_LOCAL_SOR queries runs one query per wavefront
  * (the sequential push of Eq. (7)); any other mix is solved query by query.
  * schedule_json: NULL = the default schedule (16 lanes, full occupancy), else

@@ -28,8 +28,8 @@ struct BatchWS {
     int vtype = 0, L = 0, Gcap = 0;
     int64_t n = 0, nwords = 0;
     size_t vs = 4;
-    void *R = nullptr, *R2 = nullptr, *X = nullptr, *deg = nullptr, *col_deg = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
-    uint32_t *NM = nullptr, *TM = nullptr, *PB = nullptr, *group_unconv = nullptr;
+    void *R = nullptr, *R2 = nullptr, *X = nullptr, *deg = nullptr, *col_deg = nullptr, *D = nullptr, *lane_eps = nullptr, *wl_sv = nullptr, *out_val = nullptr;
+    uint32_t *NM = nullptr, *TM = nullptr, *PB = nullptr, *group_unconv = nullptr, *PM = nullptr;
     uint64_t *act[2] = {nullptr, nullptr}, *touched = nullptr, *touched2 = nullptr;
     int32_t *tdeg = nullptr, *tdeg2 = nullptr;  // batched solves: degrees beside the touched entries
     int32_t act_cap = 0, touch_cap = 0, wl_cap = 0;
@@ -56,7 +56,7 @@ struct BatchWS {
 };
 
 void batch_ws_free(BatchWS *w) {
-    void *p[] = {w->R, w->R2, w->X, w->deg, w->col_deg, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
+    void *p[] = {w->R, w->R2, w->X, w->deg, w->col_deg, w->D, w->PM, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
                  w->act[0], w->act[1], w->touched, w->touched2, w->tdeg, w->tdeg2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
@@ -298,6 +298,20 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         w->col_deg_nnz = g->nnz;
     }
 
+    // LocalCH: the Delta plane and the previous-active masks, zero at rest
+    const bool ch = p[0].method == GDE_LOCAL_CH;
+    if (ch && !w->D) {
+        const size_t dbytes = (size_t)g->n * (size_t)w->Gcap * L * w->vs, mbytes = (size_t)g->n * (size_t)w->Gcap * 4;
+        if (hipMalloc(&w->D, dbytes) != hipSuccess || hipMalloc((void **)&w->PM, mbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (w->D) (void)hipFree(w->D);
+            w->D = nullptr;
+            w->PM = nullptr;
+            return fail(GDE_ERR_OOM, "no device memory for the LocalCH planes of the batch");
+        }
+        GDE_HIP(hipMemsetAsync(w->D, 0, dbytes, s));
+        GDE_HIP(hipMemsetAsync(w->PM, 0, mbytes, s));
+    }
     if (!w->tdeg && hipMalloc((void **)&w->tdeg, (size_t)w->touch_cap * 4) != hipSuccess) {
         w->tdeg = nullptr;
         (void)hipGetLastError();
@@ -394,6 +408,22 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.th_div = 0.0;
     a.no_push = 0;
     a.sym = (p[0].flags & GDE_SYM_NORM) ? 1 : 0;
+    a.ch = ch ? 1 : 0;
+    a.force = 0;
+    a.probe = 0;
+    a.D = ch ? (V *)w->D : nullptr;
+    a.PM = ch ? w->PM : nullptr;
+    // LocalCH scalars (the plain solver's recurrence): t = 0 is the forced first
+    // step h = r; then delta_{t+1} = 1 / (2 sigma - delta_t), c_t = 2 sigma delta_{t+1},
+    // m_t = delta_t delta_{t+1}, with sigma = (L + mu) / (L - mu) from the kind's bounds
+    double ch_sigma = 1.0, ch_dlt = 1.0;
+    if (ch) {
+        double mu, Lb;
+        if (ppr) { mu = p[0].alpha; Lb = 2.0 - p[0].alpha; }
+        else { mu = 1.0 - p[0].beta * p[0].lambda_bound; Lb = 1.0 + p[0].beta * p[0].lambda_bound; }
+        ch_sigma = (Lb + mu) / (Lb - mu);
+        ch_dlt = 1.0 / ch_sigma;
+    }
     a.lane_ops = w->lane_ops;
     a.lane_pushes = w->lane_pushes;
     a.lane_T = w->lane_T;
@@ -480,6 +510,18 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
                 a.wscale = (V)(t < K ? ls.ratio[t] : 0.0);
                 a.th_div = t < K ? (double)(K + 1) * ls.psi[t + 1] : 1.0;
             }
+            if (ch) {
+                a.force = t == 0;
+                if (t == 0) {
+                    a.c_t = (V)1;
+                    a.m_t = (V)0;
+                } else {
+                    const double dnext = 1.0 / (2.0 * ch_sigma - ch_dlt);
+                    a.c_t = (V)(2.0 * ch_sigma * dnext);
+                    a.m_t = (V)(ch_dlt * dnext);
+                    ch_dlt = dnext;
+                }
+            }
             GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
             if ((rc = prof_mark_batch_push(ctx, s))) return rc;
             GDE_HIP(batch_launch<V>(2, L, a, grid, t, s));
@@ -497,8 +539,15 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         // residual there
         GDE_HIP(batch_harvest<V>(L, a, grid, t, ls.psi[t], (double)(K + 1) * ls.psi[t], s));
     }
+    if (ch && t >= a.max_iters && hst.acount[t & 1] > 0 && !hst.ovf[0] && !hst.ovf[1]) {
+        // LocalCH at the iteration cap: the list holds candidates; a snapshot that
+        // changes nothing marks the lanes still active and clears the masks
+        a.probe = 1;
+        GDE_HIP(batch_launch<V>(1, L, a, grid, t, s));
+        a.probe = 0;
+    }
     if ((rc = prof_mark_batch(ctx, s))) return rc;
-    const int final_parity = t & 1;
+    const int final_parity = ch ? -1 : (t & 1);
     if (hst.ovf[0] || hst.ovf[1]) {
         // the kernels stopped on a capacity limit: restore the rest state by brute force
         GDE_HIP(hipMemsetAsync(w->R, 0, (size_t)g->n * GL * w->vs, s));
@@ -507,6 +556,8 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         GDE_HIP(hipMemsetAsync(w->NM, 0, (size_t)g->n * G * 4, s));
         GDE_HIP(hipMemsetAsync(w->TM, 0, (size_t)g->n * G * 4, s));
         GDE_HIP(hipMemsetAsync(w->PB, 0, (size_t)G * w->nwords * 4, s));
+        if (w->D) GDE_HIP(hipMemsetAsync(w->D, 0, (size_t)g->n * GL * w->vs, s));
+        if (w->PM) GDE_HIP(hipMemsetAsync(w->PM, 0, (size_t)g->n * G * 4, s));
         GDE_HIP(hipStreamSynchronize(s));
         return fail(GDE_ERR_OOM, "batched work lists exceeded their capacity; split the batch");
     }
@@ -725,16 +776,17 @@ int gde_solve_batch(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_param
     auto same_kind_params = [](const gde_params &x, const gde_params &y) {
         if (x.kind != y.kind) return false;
         if (x.kind == GDE_PPR || x.kind == GDE_KATZ)
-            return x.alpha == y.alpha && x.beta == y.beta && x.max_iters == y.max_iters;
+            return x.alpha == y.alpha && x.beta == y.beta && x.max_iters == y.max_iters &&
+                   (x.method != GDE_LOCAL_CH || x.lambda_bound == y.lambda_bound);
         if (x.K != y.K) return false;
         if (x.kind == GDE_HK) return x.tau == y.tau;
         for (int32_t k = 0; k <= x.K; k++)
             if (x.c[k] != y.c[k]) return false;
         return true;
     };
-    bool fused = p[0].method == GDE_LOCAL_GD && !(p[0].flags & GDE_DETERMINISTIC);
+    bool fused = (p[0].method == GDE_LOCAL_GD || p[0].method == GDE_LOCAL_CH) && !(p[0].flags & GDE_DETERMINISTIC);
     for (int32_t i = 1; i < B && fused; i++) {
-        fused = same_kind_params(p[i], p[0]) && p[i].method == GDE_LOCAL_GD && p[i].value_type == p[0].value_type &&
+        fused = same_kind_params(p[i], p[0]) && p[i].method == p[0].method && p[i].value_type == p[0].value_type &&
                 !(p[i].flags & GDE_DETERMINISTIC) &&
                 (p[i].flags & (GDE_RESULT_DEVICE | GDE_SYM_NORM)) == (p[0].flags & (GDE_RESULT_DEVICE | GDE_SYM_NORM));
     }

@@ -90,6 +90,14 @@ struct BatchArgs {
     double th_div;
     int32_t no_push;  // snap of the last level: x only, nothing pushed
     int32_t sym;      // M = D^-1/2 A D^-1/2: seeds scaled by sqrt(d), outputs by 1/sqrt(d)
+    // LocalCH (ch != 0): every lane in iteration t applies h = c_t r + m_t Delta
+    // (Delta kept only for lanes active in t - 1, PM), or h = r when force (t =
+    // 0); residuals are signed, so every touched lane is a candidate (NM) and a
+    // pushed pair is a candidate of t + 1 itself
+    int32_t ch, force, probe;
+    V c_t, m_t;
+    V *D;          // [n][G][L] Delta, the last update of each lane
+    uint32_t *PM;  // [n][G] lanes active when the pair was last snapshot
     // measurement only: row_stamp[u] == round_tag once row u was counted in this
     // iteration (distinct CSR rows read per round, whatever the groups); null = off
     uint32_t *row_stamp;

@@ -103,7 +103,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
             m = a.NM[(size_t)u * a.G + g];
-            mode = a.g_mode ? a.g_mode[g] : (a.w_div_deg ? 1 : 0);
+            mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | (a.ch && !a.force ? 2 : 0));
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
             ri = ((size_t)u * a.G + g) * L + l;
@@ -112,7 +112,20 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                 const V r = Rs[ri];
                 mine = r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg;
             }
-            if (mine) {
+            if (a.probe) {  // LocalCH at the iteration cap: record active lanes, change nothing
+                if (mine) atomicOr(&a.group_unconv[g], 1u << l);
+                mine = false;
+            }
+            if (mine && a.ch) {  // LocalCH: h = c_t r + m_t Delta (Delta of lanes active in t - 1)
+                const uint32_t prev = a.PM[(size_t)u * a.G + g];
+                const V r = Rs[ri];
+                const V h = a.force ? r : a.c_t * r + a.m_t * (((prev >> l) & 1u) ? a.D[ri] : (V)0);
+                const V rn = r - h;
+                Rs[ri] = rn == (V)0 ? (V)-0.0 : rn;  // a zero keeps the touched mark
+                a.X[ri] += h;
+                a.D[ri] = h;
+                v = h;
+            } else if (mine) {
                 v = Rs[ri];
                 Rs[ri] = LT ? (V)-0.0 : (V)0;  // -0.0: taken, already on the touched list
                 a.X[ri] += v;
@@ -122,9 +135,11 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         const unsigned long long bal = __ballot(mine);
         const uint32_t pm = (uint32_t)((bal >> (sub * L)) & ((L == 32) ? 0xffffffffull : ((1ull << L) - 1ull)));
         const int c = __popc(pm);
-        // the whole wave has read its masks: the pair leaders clear them
+        // the whole wave has read its masks: the pair leaders clear them (LocalCH:
+        // and record which lanes were active, for the next iteration's Delta)
         if (valid && l == 0) {
             a.NM[(size_t)u * a.G + g] = 0u;
+            if (a.ch) a.PM[(size_t)u * a.G + g] = pm;
             if (c > 0) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
         }
         const bool leader = valid && l == 0 && c > 0;
@@ -202,6 +217,28 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         const unsigned long long rp = st->rowpack[cur];
         st->rows += (long long)(rp >> 40);
         st->row_vol += (long long)(rp & kLaneEdgeMask);
+    }
+    if (a.ch && count > 0) {
+        // LocalCH: each pushed pair's residual changed, so its pushed lanes are
+        // candidates of t + 1 (the snapshot cleared their masks)
+        for (int b0 = bid * (int)blockDim.x; b0 < count; b0 += nblocks * (int)blockDim.x) {
+            const int slot = b0 + (int)threadIdx.x;
+            bool fresh = false;
+            uint64_t pair = 0;
+            if (slot < count) {
+                const int c = a.wl_c[slot];
+                uint32_t m = 0u;
+                for (int k = 0; k < c; k++) m |= 1u << a.wl_lanes[(size_t)slot * L + k];
+                const int32_t u = a.wl_node[slot], g = a.wl_group[slot];
+                fresh = m && atomicOr(&a.NM[(size_t)u * a.G + g], m) == 0u;
+                pair = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
+            }
+            int sa = block_reserve(fresh ? 1 : 0, &st->acount[nxt]);
+            if (fresh) {
+                if (sa < a.act_cap) a.act[nxt][sa] = pair;
+                else *ovf = 1;
+            }
+        }
     }
     const long long ntiles = min((total + kTile - 1) / kTile, (long long)a.tile_cap - 1);
     for (long long tile = bid; tile < ntiles; tile += nblocks) {
@@ -281,10 +318,15 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         for (int q = 0; q < kPer; q++) {
             new_act[q] = new_touch[q] = false;
             if (wq[q] >= 0) {
-                const bool cand = a.g_mode && (a.g_mode[gq[q]] & 2);
+                const bool cand = a.ch || (a.g_mode && (a.g_mode[gq[q]] & 2));
                 hit[q] = cand || ((old[q] < th[q]) && (old[q] + dv[q] >= th[q]));
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
-                if (hit[q]) new_act[q] = atomicOr(&a.NM[(size_t)wq[q] * a.G + gq[q]], 1u << lq[q]) == 0u;
+                if (hit[q]) {
+                    // (a candidate lane is often marked already: read before the atomic)
+                    uint32_t *nm = &a.NM[(size_t)wq[q] * a.G + gq[q]];
+                    const uint32_t bit = 1u << lq[q];
+                    new_act[q] = !(cand && (*nm & bit)) && atomicOr(nm, bit) == 0u;
+                }
                 if (LT) {
                     new_touch[q] = first[q];
                 } else if (first[q]) {
@@ -408,7 +450,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
             val[q] = (V)0;
             if (pr[q] != ~0ull) {
                 const int32_t lane_id = (int32_t)(pr[q] >> 32), w = (int32_t)(pr[q] & 0xffffffffull);
-                val[q] = R[((size_t)w * a.G + lane_id / L) * L + lane_id % L];
+                V *rp = &R[((size_t)w * a.G + lane_id / L) * L + lane_id % L];
+                // LocalCH: a signed residual that cancelled to +0.0 is listed again when it
+                // is touched next, so the value is taken by exchange (once) there
+                val[q] = a.ch ? batomic_take<V>(rp) : *rp;
             }
         }
 #pragma unroll
