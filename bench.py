@@ -280,11 +280,15 @@ def run_c2(args):
         if ch_q:
             cparams = [params[("ch", eps)] for eps, _ in ch_q]
             cseeds = [([s], None) for _, s in ch_q]
-            gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=bout)
+            del bout
+            # LocalCH's support can exceed n/4 at small eps: a full-length buffer per query
+            cout = (torch.empty(len(ch_q) * G.n, dtype=torch.int32, device=dev),
+                    torch.empty(len(ch_q) * G.n, dtype=torch.float32, device=dev))
+            gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=cout)
             torch.cuda.synchronize()
             tc = time.perf_counter()
             for _ in range(args.steps):
-                cres = gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=bout)
+                cres = gde.solve_batch(ctx, g, cparams, cseeds, schedule=sched, out=cout)
             torch.cuda.synchronize()
             tc = time.perf_counter() - tc
             plain_ch = [r for r in recs if r[0] == "ch"]
@@ -293,6 +297,7 @@ def run_c2(args):
                                       plain_solves_per_s_same_queries=round(plain_ch_rate, 2),
                                       speedup_vs_plain=round(len(ch_q) * args.steps / tc / plain_ch_rate, 2),
                                       not_converged=int((cres.status != 0).sum()))
+            del cout
         log(f"batched: {batched}")
 
     nq = len(queries)
