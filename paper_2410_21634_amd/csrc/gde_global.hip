@@ -100,26 +100,6 @@ struct GlobArgs {
     int32_t *iters;
 };
 
-// sum of z over the entries e0, e0 + step, e0 + 2 step, ... below e1, added in
-// that order; four column ids, then their four values, are loaded before any is
-// added (the order of the additions, so the result, is that of the plain loop)
-template <typename V>
-__device__ __forceinline__ V glob_gather(const int32_t *__restrict__ col_idx, const V *__restrict__ z, int32_t e0,
-                                         int32_t e1, int32_t step) {
-    V sum = (V)0;
-    int32_t e = e0;
-    for (; e + 3 * step < e1; e += 4 * step) {
-        const int32_t c0 = col_idx[e], c1 = col_idx[e + step], c2 = col_idx[e + 2 * step], c3 = col_idx[e + 3 * step];
-        const V z0 = z[c0], z1 = z[c1], z2 = z[c2], z3 = z[c3];
-        sum += z0;
-        sum += z1;
-        sum += z2;
-        sum += z3;
-    }
-    for (; e < e1; e += step) sum += z[col_idx[e]];
-    return sum;
-}
-
 // the per-node epilogue: apply h_t, new residual, next update and its scatter value
 template <typename V>
 __device__ __forceinline__ unsigned glob_node(const GlobArgs<V> &a, int32_t w, int32_t dw, V sum, int ch, V c, V m) {
@@ -152,7 +132,8 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_step(GlobArgs<V> a, int t, 
         // one long row per workgroup
         const int32_t w = (int32_t)blockIdx.x;
         const int32_t beg = a.row_ptr[w], end = a.row_ptr[w + 1];
-        const V sum = glob_gather(a.col_idx, a.z_cur, beg + (int32_t)threadIdx.x, end, kGlobBlock);
+        V sum = (V)0;
+        for (int32_t e = beg + (int32_t)threadIdx.x; e < end; e += kGlobBlock) sum += a.z_cur[a.col_idx[e]];
         s_sum[threadIdx.x] = sum;
         __syncthreads();
         for (int off = kGlobBlock / 2; off > 0; off >>= 1) {
@@ -166,7 +147,8 @@ __global__ void __launch_bounds__(kGlobBlock) k_glob_step(GlobArgs<V> a, int t, 
         if (w64 < a.n) {
             const int32_t w = (int32_t)w64;
             const int32_t beg = a.row_ptr[w], end = a.row_ptr[w + 1];
-            V sum = glob_gather(a.col_idx, a.z_cur, beg + sl, end, kLanesPerRow);
+            V sum = (V)0;
+            for (int32_t e = beg + sl; e < end; e += kLanesPerRow) sum += a.z_cur[a.col_idx[e]];
 #pragma unroll
             for (int off = kLanesPerRow / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kLanesPerRow);
             if (sl == 0) act = glob_node(a, w, end - beg, sum, ch, c, m);
