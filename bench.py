@@ -838,7 +838,7 @@ def sub_dynamic():
         ov = torch.empty(n, dtype=torch.float64, device=dev)
         for iu, iv, du, dv in batches:
             t = time.perf_counter()
-            dyn.update(insert=list(zip(iu.tolist(), iv.tolist())), delete=list(zip(du.tolist(), dv.tolist())))
+            dyn.update(insert=np.stack([iu, iv], axis=1), delete=np.stack([du, dv], axis=1))
             dyn_ms.append(1e3 * (time.perf_counter() - t))
             dyn_ops.append(dyn_ops[-1] + sum(dyn.read(q).ops for q in qids))
             gv = dyn.graph
@@ -857,7 +857,7 @@ def sub_dynamic():
                          ms_per_batch_dynamic=round(float(np.mean(dyn_ms)), 3),
                          ms_per_batch_static=round(float(np.mean(st_ms)), 3),
                          timing="dynamic: gde_dyn_update (host event checks, CSR rebuild and upload, corrections "
-                                "and fixed-order re-solve of all 16 queries); static: 16 gde_solve calls")
+                                "and one batched warm re-solve of all 16 queries); static: 16 gde_solve calls")
         dyn.close()
         g.close()
         ctx.close()

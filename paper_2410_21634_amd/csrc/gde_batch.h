@@ -7,6 +7,14 @@ namespace gde {
 int get_workspace(gde_ctx *ctx, const gde_graph *g, int vtype, hipStream_t s, Workspace **out);
 void drop_workspaces_of(const gde_graph *g, gde_ctx *ctx);
 void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx);
+// after g's CSR was replaced (same n): recompute the degrees the batch workspaces of ctx hold
+int batch_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s);
+// warm LocalGD re-solve of B standing queries (PPR or Katz, one kind and
+// parameter) from their device state (per query: RD<V> array, x, pushed and
+// touched bitmaps), as one batch; res[i]: iters, ops, pushes, norms, status
+int batch_warm_resolve(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, void *const *rd,
+                       void *const *x, uint32_t *const *pushed, uint32_t *const *tbm, gde_result *res,
+                       hipStream_t s);
 // push-kernel timing helpers (no-ops unless profiling is enabled on ctx)
 int prof_mark(gde_ctx *ctx, hipStream_t s);
 int prof_collect(gde_ctx *ctx, int64_t edges, int64_t entries);

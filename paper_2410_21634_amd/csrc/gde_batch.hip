@@ -49,6 +49,8 @@ struct BatchWS {
     int64_t out_cap = 0;
     int nblk = 0;
     void **lane_dst = nullptr;  // [2 * Gcap * L]: per-lane output pointers (idx, then val) for device results
+                                // (warm starts: the queries' rd, then x)
+    void **warm_ptr = nullptr;  // [2 * Gcap * L]: warm starts: the queries' pushed, then touched bitmaps
     uint32_t *row_stamp = nullptr;  // [n], measurement only: distinct rows per round
     const int32_t *col_deg_of = nullptr;  // the col_idx that col_deg was built from
     int64_t col_deg_nnz = 0;
@@ -60,7 +62,7 @@ void batch_ws_free(BatchWS *w) {
                  w->act[0], w->act[1], w->touched, w->touched2, w->tdeg, w->tdeg2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
                  w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
-                 w->lane_dst, w->row_stamp};
+                 w->lane_dst, w->warm_ptr, w->row_stamp};
     for (void *q : p)
         if (q) (void)hipFree(q);
     delete w;
@@ -71,6 +73,17 @@ void drop_batch_workspaces_of(const gde_graph *g, gde_ctx *ctx) {
         if (ctx->bws[i]->guid == g->uid) { batch_ws_free(ctx->bws[i]); ctx->bws.erase(ctx->bws.begin() + i); }
         else i++;
     }
+}
+
+int batch_workspaces_refresh(const gde_graph *g, gde_ctx *ctx, hipStream_t s) {
+    for (BatchWS *b : ctx->bws) {
+        if (b->guid != g->uid) continue;
+        const hipError_t e = b->vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)b->deg, g->n, s)
+                                                 : batch_init_deg<float>(g->row_ptr, (float *)b->deg, g->n, s);
+        if (e != hipSuccess) return hip_fail(e, "batch_init_deg");
+        b->col_deg_of = nullptr;  // rebuilt from the new column array on the next solve
+    }
+    return GDE_OK;
 }
 
 struct DevBuf {  // device scratch released on every return path
@@ -176,6 +189,7 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     BALLOC(w->cnt, (size_t)GL * w->nblk * 4);
     BALLOC(w->st, sizeof(BatchDev));
     BALLOC(w->lane_dst, 2 * (size_t)GL * sizeof(void *));
+    BALLOC(w->warm_ptr, 2 * (size_t)GL * sizeof(void *));
     hipError_t e = vtype == GDE_F64 ? batch_init_deg<double>(g->row_ptr, (double *)w->deg, g->n, s)
                                     : batch_init_deg<float>(g->row_ptr, (float *)w->deg, g->n, s);
     if (e != hipSuccess) { batch_ws_free(w); return hip_fail(e, "batch_init_deg"); }
@@ -243,9 +257,18 @@ void batch_ws_swap_list(BatchWS *w, int which, uint64_t **spare) {
     std::swap(*slot, *spare);
 }
 
+// Standing queries' state for a warm start (per query, device pointers): the
+// residual-and-degree array, x, the pushed and touched bitmaps.
+struct WarmState {
+    void *const *rd;
+    void *const *x;
+    uint32_t *const *pushed;
+    uint32_t *const *tbm;
+};
+
 template <typename V>
 static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, const gde_seed *sd,
-                             gde_result *res, const Schedule &sc, hipStream_t s) {
+                             gde_result *res, const Schedule &sc, hipStream_t s, const WarmState *warm = nullptr) {
     const int L = sc.lanes;
     const int G = (B + L - 1) / L;
     const int vt = p[0].value_type;
@@ -347,9 +370,25 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         h_eps[j] = (V)(ppr ? p[q].alpha * p[q].eps : p[q].eps);  // level push: eps itself
         h_flag[j] = (!ppr && (p[q].flags & GDE_KATZ_SUBTRACT_SEED)) ? 1 : 0;
     }
-    GDE_HIP(hipMemcpyAsync(w->s_lane, h_lane.data(), 4 * ns, hipMemcpyHostToDevice, s));
-    GDE_HIP(hipMemcpyAsync(w->s_node, h_node.data(), 4 * ns, hipMemcpyHostToDevice, s));
-    GDE_HIP(hipMemcpyAsync(w->s_val, h_val.data(), 8 * ns, hipMemcpyHostToDevice, s));
+    if (ns > 0) {
+        GDE_HIP(hipMemcpyAsync(w->s_lane, h_lane.data(), 4 * ns, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->s_node, h_node.data(), 4 * ns, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->s_val, h_val.data(), 8 * ns, hipMemcpyHostToDevice, s));
+    }
+    // warm start: the queries' state pointers in lane order (rd, x, pushed, tbm)
+    if (warm) {
+        const size_t GLw = (size_t)G * L;
+        std::vector<void *> qp(4 * GLw, nullptr);
+        for (int j = 0; j < B; j++) {
+            const int q = order[j];
+            qp[j] = warm->rd[q];
+            qp[GLw + j] = warm->x[q];
+            qp[2 * GLw + j] = warm->pushed[q];
+            qp[3 * GLw + j] = warm->tbm[q];
+        }
+        GDE_HIP(hipMemcpyAsync(w->lane_dst, qp.data(), sizeof(void *) * 2 * GLw, hipMemcpyHostToDevice, s));
+        GDE_HIP(hipMemcpyAsync(w->warm_ptr, qp.data() + 2 * GLw, sizeof(void *) * 2 * GLw, hipMemcpyHostToDevice, s));
+    }
     GDE_HIP(hipMemcpyAsync(w->lane_eps, h_eps.data(), sizeof(V) * h_eps.size(), hipMemcpyHostToDevice, s));
     GDE_HIP(hipMemcpyAsync(w->sub_flag, h_flag.data(), 4 * h_flag.size(), hipMemcpyHostToDevice, s));
     const size_t GL = (size_t)G * L;
@@ -411,6 +450,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.ch = ch ? 1 : 0;
     a.force = 0;
     a.probe = 0;
+    a.cand_all = warm ? 1 : 0;  // warm start: signed residuals, no forced S_0
     a.D = ch ? (V *)w->D : nullptr;
     a.PM = ch ? w->PM : nullptr;
     // LocalCH scalars (the plain solver's recurrence): t = 0 is the forced first
@@ -482,8 +522,12 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         a.row_stamp = w->row_stamp;
     }
 
-    GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns, lvl ? ls.c0 : ppr ? p[0].alpha : 1.0,
-                          s));
+    if (warm)
+        GDE_HIP(batch_warm_load<V>(L, a, (const void *const *)w->lane_dst,
+                                   (const uint32_t *const *)(w->warm_ptr + GL), B, s));
+    else
+        GDE_HIP(batch_seed<V>(L, a, w->s_lane, w->s_node, w->s_val, (int32_t)ns,
+                              lvl ? ls.c0 : ppr ? p[0].alpha : 1.0, s));
     int dev = 0;
     GDE_HIP(hipGetDevice(&dev));
     int cus = 0;
@@ -539,7 +583,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         // residual there
         GDE_HIP(batch_harvest<V>(L, a, grid, t, ls.psi[t], (double)(K + 1) * ls.psi[t], s));
     }
-    if (ch && t >= a.max_iters && hst.acount[t & 1] > 0 && !hst.ovf[0] && !hst.ovf[1]) {
+    if ((ch || warm) && t >= a.max_iters && hst.acount[t & 1] > 0 && !hst.ovf[0] && !hst.ovf[1]) {
         // LocalCH at the iteration cap: the list holds candidates; a snapshot that
         // changes nothing marks the lanes still active and clears the masks
         a.probe = 1;
@@ -547,7 +591,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         a.probe = 0;
     }
     if ((rc = prof_mark_batch(ctx, s))) return rc;
-    const int final_parity = ch ? -1 : (t & 1);
+    const int final_parity = (ch || warm) ? -1 : (t & 1);
     if (hst.ovf[0] || hst.ovf[1]) {
         // the kernels stopped on a capacity limit: restore the rest state by brute force
         GDE_HIP(hipMemsetAsync(w->R, 0, (size_t)g->n * GL * w->vs, s));
@@ -562,56 +606,67 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         return fail(GDE_ERR_OOM, "batched work lists exceeded their capacity; split the batch");
     }
     // residual norms, unconverged lanes, Katz seed subtraction
+    // warm start: the residuals go back to the queries before the pass clears them
+    if (warm)
+        GDE_HIP(batch_warm_store<V>(L, a, 0, w->lane_dst, (uint32_t *const *)(w->warm_ptr + GL), nullptr, nullptr, B,
+                                    w->nblk, grid, s));
     // (the level push took its norms level by level and never hits a cap)
     const bool any_sub = std::any_of(h_flag.begin(), h_flag.end(), [](int32_t f) { return f != 0; });
     if (!lvl)
         GDE_HIP(batch_finish<V>(L, a, grid, ppr ? 1.0 / p[0].alpha : 1.0, final_parity, w->s_lane, w->s_node,
                                 w->s_val, (int32_t)ns, any_sub ? w->sub_flag : nullptr, s));
-    // extraction: counts per lane, then the sorted sparse outputs
-    GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));
-    std::vector<long long> nnz(GL), off(GL, -1);
-    GDE_HIP(hipMemcpyAsync(nnz.data(), w->lane_nnz, 8 * GL, hipMemcpyDeviceToHost, s));
-    GDE_HIP(hipStreamSynchronize(s));
-    long long total = 0;
-    for (int j = 0; j < B; j++) {
-        const int q = order[j];
-        if (nnz[j] <= res[q].capacity && res[q].idx && res[q].val) {
-            off[j] = total;
-            total += nnz[j];
-        }
-    }
-    const bool dev_out = (p[0].flags & GDE_RESULT_DEVICE) != 0;
-    if (dev_out) {
-        // every lane's entries go straight to its query's device buffers
-        std::vector<void *> dst(2 * (size_t)GL, nullptr);
-        for (int j = 0; j < B; j++) {
-            if (off[j] < 0) continue;
-            dst[j] = res[order[j]].idx;
-            dst[GL + j] = res[order[j]].val;
-        }
-        GDE_HIP(hipMemcpyAsync(w->lane_dst, dst.data(), sizeof(void *) * dst.size(), hipMemcpyHostToDevice, s));
-        GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
-        GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, nullptr, nullptr, 1, s,
-                                 nullptr, 0, (int32_t *const *)w->lane_dst, (V *const *)(w->lane_dst + GL)));
+    // extraction: counts per lane, then the sorted sparse outputs (warm start:
+    // the lanes' x increments go into the queries' x instead)
+    std::vector<long long> nnz(GL, 0), off(GL, 0);
+    if (warm) {
+        GDE_HIP(batch_warm_store<V>(L, a, 1, nullptr, nullptr, w->lane_dst + GL, (uint32_t *const *)w->warm_ptr, B,
+                                    w->nblk, grid, s));
     } else {
-        if (total > w->out_cap) {
-            if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
-            w->out_idx = nullptr;
-            w->out_val = nullptr;
-            w->out_cap = 0;
-            GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)total));
-            GDE_HIP(hipMalloc(&w->out_val, sizeof(V) * (size_t)total));
-            w->out_cap = total;
-        }
-        GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
-        GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, w->out_idx,
-                                 (V *)w->out_val, 1, s));
+        GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));
+        std::fill(off.begin(), off.end(), -1);
+        GDE_HIP(hipMemcpyAsync(nnz.data(), w->lane_nnz, 8 * GL, hipMemcpyDeviceToHost, s));
+        GDE_HIP(hipStreamSynchronize(s));
+        long long total = 0;
         for (int j = 0; j < B; j++) {
             const int q = order[j];
-            if (off[j] < 0 || nnz[j] == 0) continue;
-            GDE_HIP(hipMemcpyAsync(res[q].idx, w->out_idx + off[j], 4 * (size_t)nnz[j], hipMemcpyDeviceToHost, s));
-            GDE_HIP(hipMemcpyAsync(res[q].val, (V *)w->out_val + off[j], sizeof(V) * (size_t)nnz[j],
-                                   hipMemcpyDeviceToHost, s));
+            if (nnz[j] <= res[q].capacity && res[q].idx && res[q].val) {
+                off[j] = total;
+                total += nnz[j];
+            }
+        }
+        const bool dev_out = (p[0].flags & GDE_RESULT_DEVICE) != 0;
+        if (dev_out) {
+            // every lane's entries go straight to its query's device buffers
+            std::vector<void *> dst(2 * (size_t)GL, nullptr);
+            for (int j = 0; j < B; j++) {
+                if (off[j] < 0) continue;
+                dst[j] = res[order[j]].idx;
+                dst[GL + j] = res[order[j]].val;
+            }
+            GDE_HIP(hipMemcpyAsync(w->lane_dst, dst.data(), sizeof(void *) * dst.size(), hipMemcpyHostToDevice, s));
+            GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
+            GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, nullptr, nullptr, 1, s,
+                                     nullptr, 0, (int32_t *const *)w->lane_dst, (V *const *)(w->lane_dst + GL)));
+        } else {
+            if (total > w->out_cap) {
+                if (w->out_idx) { (void)hipFree(w->out_idx); (void)hipFree(w->out_val); }
+                w->out_idx = nullptr;
+                w->out_val = nullptr;
+                w->out_cap = 0;
+                GDE_HIP(hipMalloc((void **)&w->out_idx, 4 * (size_t)total));
+                GDE_HIP(hipMalloc(&w->out_val, sizeof(V) * (size_t)total));
+                w->out_cap = total;
+            }
+            GDE_HIP(hipMemcpyAsync(w->lane_out_off, off.data(), 8 * GL, hipMemcpyHostToDevice, s));
+            GDE_HIP(batch_extract<V>(L, a, 1, w->cnt, w->nblk, w->lane_nnz, w->lane_out_off, w->out_idx,
+                                     (V *)w->out_val, 1, s));
+            for (int j = 0; j < B; j++) {
+                const int q = order[j];
+                if (off[j] < 0 || nnz[j] == 0) continue;
+                GDE_HIP(hipMemcpyAsync(res[q].idx, w->out_idx + off[j], 4 * (size_t)nnz[j], hipMemcpyDeviceToHost, s));
+                GDE_HIP(hipMemcpyAsync(res[q].val, (V *)w->out_val + off[j], sizeof(V) * (size_t)nnz[j],
+                                       hipMemcpyDeviceToHost, s));
+            }
         }
     }
     std::vector<long long> ops(GL * kStatShards), pushes(GL * kStatShards);
@@ -676,6 +731,25 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
 }  // namespace gde
 
 using namespace gde;
+
+// Warm LocalGD re-solve of B standing queries (one kind and parameter) from
+// their current state, all in one batch: see WarmState and the warm-start
+// kernels.  res[i] receives iterations, work, residual norms and status.
+int gde::batch_warm_resolve(gde_ctx *ctx, const gde_graph *g, int32_t B, const gde_params *p, void *const *rd,
+                            void *const *x, uint32_t *const *pushed, uint32_t *const *tbm, gde_result *res,
+                            hipStream_t s) {
+    std::vector<gde_seed> sd((size_t)B, gde_seed{0, nullptr, nullptr});
+    for (int32_t i = 0; i < B; i++) {
+        res[i] = gde_result{};
+        res[i].status = GDE_OK;
+    }
+    Schedule sc;
+    sc.lanes = 16;
+    sc.sort = 0;
+    const WarmState ws{rd, x, pushed, tbm};
+    return p[0].value_type == GDE_F64 ? solve_batch_fused<double>(ctx, g, B, p, sd.data(), res, sc, s, &ws)
+                                      : solve_batch_fused<float>(ctx, g, B, p, sd.data(), res, sc, s, &ws);
+}
 
 // A batch whose work lists outgrow the workspace (GDE_ERR_OOM, state already
 // restored) is solved as two halves, recursively, down to one lane group.

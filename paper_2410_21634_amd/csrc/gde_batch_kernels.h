@@ -95,6 +95,9 @@ struct BatchArgs {
     // 0); residuals are signed, so every touched lane is a candidate (NM) and a
     // pushed pair is a candidate of t + 1 itself
     int32_t ch, force, probe;
+    // warm start (standing queries): LocalGD steps with signed residuals, every
+    // touched lane a candidate, as for LocalCH but h = r
+    int32_t cand_all;
     V c_t, m_t;
     V *D;          // [n][G][L] Delta, the last update of each lane
     uint32_t *PM;  // [n][G] lanes active when the pair was last snapshot
@@ -126,6 +129,15 @@ hipError_t batch_extract(int L, const BatchArgs<V> &a, int stage, int32_t *cnt, 
                          const int32_t *gmap = nullptr, int ngroups = 0, int32_t *const *lane_idx = nullptr,
                          V *const *lane_val = nullptr);
 template <typename V> hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t s);
+// warm start of B standing queries (lane j = query of lane j): load their residuals
+// at the nodes of their touched bitmaps; afterwards store the residuals back
+// (before the residual pass) and add the lanes' x into theirs (the extraction)
+template <typename V>
+hipError_t batch_warm_load(int L, const BatchArgs<V> &a, const void *const *q_rd, const uint32_t *const *q_tbm, int B,
+                           hipStream_t s);
+template <typename V>
+hipError_t batch_warm_store(int L, const BatchArgs<V> &a, int stage, void *const *q_rd, uint32_t *const *q_tbm,
+                            void *const *q_x, uint32_t *const *q_pushed, int B, int nblk, int grid, hipStream_t s);
 template <typename V>
 hipError_t batch_init_col_deg(const int32_t *col_idx, const V *deg, V *col_deg, int64_t nnz, hipStream_t s);
 

@@ -103,7 +103,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
             m = a.NM[(size_t)u * a.G + g];
-            mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | (a.ch && !a.force ? 2 : 0));
+            mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | ((a.ch && !a.force) || a.cand_all ? 2 : 0));
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
             ri = ((size_t)u * a.G + g) * L + l;
@@ -318,7 +318,7 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         for (int q = 0; q < kPer; q++) {
             new_act[q] = new_touch[q] = false;
             if (wq[q] >= 0) {
-                const bool cand = a.ch || (a.g_mode && (a.g_mode[gq[q]] & 2));
+                const bool cand = a.ch || a.cand_all || (a.g_mode && (a.g_mode[gq[q]] & 2));
                 hit[q] = cand || ((old[q] < th[q]) && (old[q] + dv[q] >= th[q]));
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) {
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
                 V *rp = &R[((size_t)w * a.G + lane_id / L) * L + lane_id % L];
                 // LocalCH: a signed residual that cancelled to +0.0 is listed again when it
                 // is touched next, so the value is taken by exchange (once) there
-                val[q] = a.ch ? batomic_take<V>(rp) : *rp;
+                val[q] = (a.ch || a.cand_all) ? batomic_take<V>(rp) : *rp;
             }
         }
 #pragma unroll
@@ -634,6 +634,81 @@ __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const 
     }
 }
 
+// Warm start: lane j (grid.y) takes its query's residual at every node of the
+// query's touched bitmap (the only nodes where it can be nonzero); a nonzero one
+// becomes a touched entry (its degree beside it) and a candidate of iteration 0.
+// Few entries per query, so the lists are appended to one atomic at a time.
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_warm_load(BatchArgs<V> a, const RD<V> *const *__restrict__ q_rd,
+                                                            const uint32_t *const *__restrict__ q_tbm) {
+    const int j = (int)blockIdx.y, g = j / L, l = j % L;
+    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t m = wi < a.nwords ? q_tbm[j][wi] : 0u;
+    const RD<V> *rd = q_rd[j];
+    while (m) {
+        const int b = __ffs((int)m) - 1;
+        m &= m - 1u;
+        const int32_t u = (int32_t)(wi * 32 + b);
+        const V r = rd[u].r;
+        if (r == (V)0) continue;
+        a.R[((size_t)u * a.G + g) * L + l] = r;
+        const int te = atomicAdd(&a.st->tcount, 1);
+        if (te < a.touch_cap) {
+            a.touched[te] = ((uint64_t)(uint32_t)j << 32) | (uint32_t)u;
+            if (a.tdeg) a.tdeg[te] = a.row_ptr[u + 1] - a.row_ptr[u];
+        } else {
+            a.st->ovf[0] = 1;
+        }
+        if (atomicOr(&a.NM[(size_t)u * a.G + g], 1u << l) == 0u) {
+            const int sa = atomicAdd(&a.st->acount[0], 1);
+            if (sa < a.act_cap) a.act[0][sa] = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
+            else a.st->ovf[0] = 1;
+        }
+    }
+}
+
+// stage 0 (before the residual pass): each touched entry's residual back into
+// its query (and the node into the query's touched bitmap); the pass then reads
+// and clears R as usual.  Stage 1 (the extraction): per group, every pushed
+// node's lane increments added into the queries' x, which marks the node pushed.
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_warm_store_r(BatchArgs<V> a, RD<V> *const *__restrict__ q_rd,
+                                                               uint32_t *const *__restrict__ q_tbm) {
+    const int nt = min(a.st->tcount, a.touch_cap);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nt; i += gridDim.x * kBlock) {
+        const uint64_t e = a.touched[i];
+        const int32_t j = (int32_t)(e >> 32), u = (int32_t)(e & 0xffffffffull);
+        const V v = a.R[((size_t)u * a.G + j / L) * L + j % L];
+        q_rd[j][u].r = v == (V)0 ? (V)0 : v;  // -0.0 (taken) is stored as 0
+        atomicOr(&q_tbm[j][u >> 5], 1u << (u & 31));
+    }
+}
+
+template <typename V, int L>
+__global__ void __launch_bounds__(kBlock) k_batch_warm_store_x(BatchArgs<V> a, V *const *__restrict__ q_x,
+                                                               uint32_t *const *__restrict__ q_pushed, int B) {
+    const int g = (int)blockIdx.y;
+    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (wi >= a.nwords) return;
+    uint32_t word = a.PB[(size_t)g * a.nwords + wi];
+    if (!word) return;
+    a.PB[(size_t)g * a.nwords + wi] = 0u;
+    while (word) {
+        const int b = __ffs((int)word) - 1;
+        word &= word - 1u;
+        const int32_t u = (int32_t)(wi * 32 + b);
+        V *xr = a.X + ((size_t)u * a.G + g) * L;
+        for (int l = 0; l < L; l++) {
+            const int j = g * L + l;
+            const V xv = xr[l];
+            if (xv == (V)0 || j >= B) continue;
+            q_x[j][u] = q_x[j][u] + xv;
+            atomicOr(&q_pushed[j][u >> 5], 1u << (u & 31));
+            xr[l] = (V)0;
+        }
+    }
+}
+
 template <typename V>
 __global__ void k_batch_init_deg(const int32_t *__restrict__ row_ptr, V *deg, int32_t n) {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
@@ -761,6 +836,42 @@ __global__ void k_batch_col_deg(const int32_t *__restrict__ col_idx, const V *__
 }
 
 template <typename V>
+hipError_t batch_warm_load(int L, const BatchArgs<V> &a, const void *const *q_rd, const uint32_t *const *q_tbm, int B,
+                           hipStream_t s) {
+    const dim3 grid((unsigned)((a.nwords + kBlock - 1) / kBlock), (unsigned)B);
+    switch (L) {
+    case 8: hipLaunchKernelGGL((k_batch_warm_load<V, 8>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
+    case 16: hipLaunchKernelGGL((k_batch_warm_load<V, 16>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
+    case 32: hipLaunchKernelGGL((k_batch_warm_load<V, 32>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t batch_warm_store(int L, const BatchArgs<V> &a, int stage, void *const *q_rd, uint32_t *const *q_tbm,
+                            void *const *q_x, uint32_t *const *q_pushed, int B, int nblk, int grid, hipStream_t s) {
+    const dim3 gx((unsigned)nblk, (unsigned)a.G);
+    switch (L) {
+#define GDE_BW(LL)                                                                                                   \
+    case LL:                                                                                                         \
+        if (stage == 0)                                                                                              \
+            hipLaunchKernelGGL((k_batch_warm_store_r<V, LL>), dim3(grid), dim3(kBlock), 0, s, a, (RD<V> *const *)q_rd, \
+                               q_tbm);                                                                               \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_batch_warm_store_x<V, LL>), gx, dim3(kBlock), 0, s, a, (V *const *)q_x, q_pushed, B); \
+        break;
+        GDE_BW(8)
+        GDE_BW(16)
+        GDE_BW(32)
+#undef GDE_BW
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
 hipError_t batch_init_col_deg(const int32_t *col_idx, const V *deg, V *col_deg, int64_t nnz, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_col_deg<V>, dim3(8192), dim3(256), 0, s, col_idx, deg, col_deg, nnz);
     return hipGetLastError();
@@ -784,7 +895,11 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
                                          const long long *, int32_t *, V *, int, hipStream_t, const int32_t *,     \
                                          int, int32_t *const *, V *const *);                                       \
     template hipError_t batch_init_deg<V>(const int32_t *, V *, int32_t, hipStream_t);                            \
-    template hipError_t batch_init_col_deg<V>(const int32_t *, const V *, V *, int64_t, hipStream_t);
+    template hipError_t batch_init_col_deg<V>(const int32_t *, const V *, V *, int64_t, hipStream_t);            \
+    template hipError_t batch_warm_load<V>(int, const BatchArgs<V> &, const void *const *, const uint32_t *const *, \
+                                           int, hipStream_t);                                                     \
+    template hipError_t batch_warm_store<V>(int, const BatchArgs<V> &, int, void *const *, uint32_t *const *,      \
+                                            void *const *, uint32_t *const *, int, int, int, hipStream_t);
 
 GDE_BINST(float)
 GDE_BINST(double)

@@ -11,8 +11,11 @@
 // r_c -= (1-alpha) D (a node of degree 0 only adds (1-alpha) x_a to r_c on
 // its first new edge); for Katz r_c += beta x_a or -= beta x_a; then (2) a
 // warm LocalGD re-solve of every query from its corrected state (S_0 = the
-// active nodes, residuals may be negative), in the fixed-order iterations of
-// the deterministic mode.  Everything in between stays resident: residuals,
+// active nodes, residuals may be negative): the queries of one kind and
+// parameter run together as the lanes of one batch (every touched lane a
+// candidate, signed residuals), starting from and returning to the queries'
+// own state.  A query's first solve runs the fixed-order iterations of the
+// deterministic mode.  Everything in between stays resident: residuals,
 // estimates, touched and pushed bitmaps, degrees.
 //
 // The corrections run one thread per node that has events, walking its events
@@ -54,6 +57,9 @@ struct gde_dyn_query {
 
 struct gde_dyn {
     gde_ctx *ctx = nullptr;
+    // private context of the batched re-solves, not in the library's list of
+    // contexts: its workspace survives the CSR replacements and is refreshed
+    gde_ctx *bctx = nullptr;
     int vtype = GDE_F64;
     size_t vs = 8;
     int32_t n = 0;
@@ -217,6 +223,8 @@ int gde_dyn_create(gde_ctx *ctx, const gde_graph *g0, int32_t value_type, gde_dy
         gde_dyn_destroy(dy);
         return hip_fail(e, "dynamic graph buffers");
     }
+    dy->bctx = new gde_ctx();
+    dy->bctx->device = ctx->device;
     *out = dy;
     return GDE_OK;
 }
@@ -354,6 +362,7 @@ int gde_dyn_update(gde_dyn *dy, int32_t k_ins, const int32_t *iu, const int32_t 
     if (rc) return rc;
     GDE_HIP(hipStreamSynchronize(dy->s));
     graph_set_csr(dy->g, drp, dci, nnz, deg);
+    if ((rc = batch_workspaces_refresh(dy->g, dy->bctx, dy->s))) return rc;
     if (nsrc == 0) return GDE_OK;
     // event buffers
     if ((int64_t)dst.size() > dy->ev_cap || nsrc + 1 > dy->src_cap) {
@@ -385,9 +394,48 @@ int gde_dyn_update(gde_dyn *dy, int32_t k_ins, const int32_t *iu, const int32_t 
                                dy->ev_off, dy->ev_dst, dy->ev_sign, nsrc, d_deg0, (RD<float> *)q->rd,
                                (float *)q->x, q->tbm, ppr, param);
         GDE_HIP(hipGetLastError());
-        rc = dy->vtype == GDE_F64 ? dyn_resolve<double>(dy, q, nullptr, 0) : dyn_resolve<float>(dy, q, nullptr, 0);
-        if (rc) return rc;
     }
+    // the re-solves: one batch per kind and parameter
+    std::vector<bool> done(dy->q.size(), false);
+    for (size_t i = 0; i < dy->q.size(); i++) {
+        if (done[i]) continue;
+        const gde_params &pi = dy->q[i]->p;
+        std::vector<size_t> grp;
+        for (size_t j = i; j < dy->q.size(); j++) {
+            const gde_params &pj = dy->q[j]->p;
+            if (!done[j] && pj.kind == pi.kind && pj.alpha == pi.alpha && pj.beta == pi.beta &&
+                pj.max_iters == pi.max_iters) {
+                grp.push_back(j);
+                done[j] = true;
+            }
+        }
+        const int32_t B = (int32_t)grp.size();
+        std::vector<gde_params> ps(B);
+        std::vector<void *> rd(B), x(B);
+        std::vector<uint32_t *> pushed(B), tbm(B);
+        std::vector<gde_result> res(B);
+        for (int32_t k = 0; k < B; k++) {
+            gde_dyn_query *q = dy->q[grp[k]];
+            ps[k] = q->p;
+            rd[k] = q->rd;
+            x[k] = q->x;
+            pushed[k] = q->pushed;
+            tbm[k] = q->tbm;
+        }
+        rc = batch_warm_resolve(dy->bctx, dy->g, B, ps.data(), rd.data(), x.data(), pushed.data(), tbm.data(),
+                                res.data(), dy->s);
+        if (rc && rc != GDE_ERR_NOT_CONVERGED) return rc;
+        for (int32_t k = 0; k < B; k++) {
+            gde_dyn_query *q = dy->q[grp[k]];
+            q->iters = res[k].iters;
+            q->ops = res[k].ops;
+            q->pushes = res[k].pushes;
+            q->res_l1 = res[k].residual_l1;
+            q->res_dinf = res[k].residual_dinf;
+            q->status = res[k].status;
+        }
+    }
+    GDE_HIP(hipStreamSynchronize(dy->s));
     return GDE_OK;
 }
 
@@ -454,6 +502,7 @@ int gde_dyn_destroy(gde_dyn *dy) {
     det_ws_free(w.det);
     if (dy->h_st) (void)hipHostFree(dy->h_st);
     if (dy->s) (void)hipStreamDestroy(dy->s);
+    if (dy->bctx) gde_ctx_destroy(dy->bctx);
     if (dy->g) gde_graph_destroy(dy->g);
     delete dy;
     return GDE_OK;

@@ -537,10 +537,11 @@ class Dynamic:
         return int(q.value)
 
     def update(self, insert=(), delete=()):
-        iu = np.ascontiguousarray([e[0] for e in insert], dtype=np.int32)
-        iv = np.ascontiguousarray([e[1] for e in insert], dtype=np.int32)
-        du = np.ascontiguousarray([e[0] for e in delete], dtype=np.int32)
-        dv = np.ascontiguousarray([e[1] for e in delete], dtype=np.int32)
+        """insert / delete: edges as (k, 2) arrays or sequences of pairs."""
+        ins = np.asarray(insert, dtype=np.int32).reshape(-1, 2)
+        dels = np.asarray(delete, dtype=np.int32).reshape(-1, 2)
+        iu, iv = np.ascontiguousarray(ins[:, 0]), np.ascontiguousarray(ins[:, 1])
+        du, dv = np.ascontiguousarray(dels[:, 0]), np.ascontiguousarray(dels[:, 1])
         _check(_lib.gde_dyn_update(self.handle, len(iu), iu.ctypes.data_as(_vp), iv.ctypes.data_as(_vp), len(du),
                                    du.ctypes.data_as(_vp), dv.ctypes.data_as(_vp)))
 

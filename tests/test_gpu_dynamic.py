@@ -6,8 +6,9 @@ state and re-solves warm (oracle.localgd_warm) on the new graph.
 
 FP64: the first solve runs the deterministic iterations, so x equals the
 oracle's bit for bit; after a batch the corrections add into residuals with
-atomics (summation order differs), so the iteration counts and work must be
-equal and x within 1e-12 of the mass.  FP32: the state recomputed in FP64 on the
+atomics and the re-solve runs the batched scatter path (summation orders
+differ), so the iteration counts and work must be equal (pushes up to the
+nodes left with degree 0, see below) and x within 1e-12 of the mass.  FP32: the state recomputed in FP64 on the
 new graph satisfies the stop rule within the FP32 residual bound.  A solve from
 scratch on the same version (through gde_dyn_graph) meets the same rule.
 """
@@ -138,7 +139,12 @@ def test_dynamic_matches_oracle(gde, ctx, vt):
                   flush=True)
             assert got.status == gde.OK
             if vt == 1:
-                assert (got.iters, got.ops, got.pushes) == (ref["iters"], ref["ops"], ref["pushes"])
+                # a node left with degree 0 has threshold 0, so the rounding residue of its
+                # corrections (about 1e-21 here; 0 in exact arithmetic) decides whether it is
+                # pushed; such a push moves nothing (no edges) and adds 0 operations, so the
+                # push counts may differ by those nodes only
+                assert (got.iters, got.ops) == (ref["iters"], ref["ops"])
+                assert abs(got.pushes - ref["pushes"]) <= int((d2 == 0).sum())
                 assert err <= TOL[vt]
                 np.testing.assert_allclose(got.residual_l1, ref["residual_l1"], rtol=1e-9, atol=1e-300)
             else:
