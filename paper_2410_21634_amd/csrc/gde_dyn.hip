@@ -74,6 +74,14 @@ struct gde_dyn {
     int32_t *blk = nullptr;  // output compaction
     long long *total = nullptr;
     gde::DevState *h_st = nullptr;
+    // the device CSR in two buffer sets (the graph points at one, the next
+    // version is uploaded into the other) and its pinned host staging, so an
+    // update allocates and frees nothing once the capacities suffice
+    int32_t *d_rp[2] = {nullptr, nullptr}, *d_ci[2] = {nullptr, nullptr};
+    int64_t d_ci_cap[2] = {0, 0};
+    int cur = 0;
+    int32_t *h_rp = nullptr, *h_ci = nullptr;
+    int64_t h_ci_cap = 0;
 };
 
 namespace gde {
@@ -148,27 +156,46 @@ static int dyn_resolve(gde_dyn *dy, gde_dyn_query *q, const int32_t *forced, int
     return GDE_OK;
 }
 
+// the current adjacency as a CSR in the spare device buffer set (made the
+// current one), staged through pinned host memory; returns its arrays
 static int dyn_upload_csr(gde_dyn *dy, int32_t **rp_out, int32_t **ci_out, int64_t *nnz_out,
                           std::vector<int32_t> *deg) {
     const int32_t n = dy->n;
-    std::vector<int32_t> rp((size_t)n + 1, 0);
+    if (!dy->h_rp) GDE_HIP(hipHostMalloc((void **)&dy->h_rp, 4 * ((size_t)n + 1), 0));
+    int32_t *rp = dy->h_rp;
+    rp[0] = 0;
     deg->assign((size_t)n, 0);
     for (int32_t u = 0; u < n; u++) {
         (*deg)[u] = (int32_t)dy->adj[u].size();
         rp[u + 1] = rp[u] + (*deg)[u];
     }
     const int64_t nnz = rp[n];
-    std::vector<int32_t> ci((size_t)std::max<int64_t>(nnz, 1));
-    for (int32_t u = 0; u < n; u++) std::copy(dy->adj[u].begin(), dy->adj[u].end(), ci.begin() + rp[u]);
-    int32_t *drp = nullptr, *dci = nullptr;
-    GDE_HIP(hipMalloc((void **)&drp, 4 * ((size_t)n + 1)));
-    hipError_t e = hipMalloc((void **)&dci, 4 * ci.size());
-    if (e != hipSuccess) { (void)hipFree(drp); return hip_fail(e, "dynamic CSR"); }
-    e = hipMemcpy(drp, rp.data(), 4 * ((size_t)n + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dci, ci.data(), 4 * ci.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { (void)hipFree(drp); (void)hipFree(dci); return hip_fail(e, "dynamic CSR upload"); }
-    *rp_out = drp;
-    *ci_out = dci;
+    const int64_t need = std::max<int64_t>(nnz, 1);
+    if (need > dy->h_ci_cap) {
+        if (dy->h_ci) (void)hipHostFree(dy->h_ci);
+        dy->h_ci = nullptr;
+        dy->h_ci_cap = 0;
+        const int64_t cap = need + need / 8;  // room for growth
+        GDE_HIP(hipHostMalloc((void **)&dy->h_ci, 4 * (size_t)cap, 0));
+        dy->h_ci_cap = cap;
+    }
+    for (int32_t u = 0; u < n; u++) std::copy(dy->adj[u].begin(), dy->adj[u].end(), dy->h_ci + rp[u]);
+    const int k = dy->d_rp[dy->cur] ? dy->cur ^ 1 : dy->cur;  // the set the graph does not use
+    if (!dy->d_rp[k]) GDE_HIP(hipMalloc((void **)&dy->d_rp[k], 4 * ((size_t)n + 1)));
+    if (need > dy->d_ci_cap[k]) {
+        if (dy->d_ci[k]) (void)hipFree(dy->d_ci[k]);
+        dy->d_ci[k] = nullptr;
+        dy->d_ci_cap[k] = 0;
+        const int64_t cap = need + need / 8;
+        GDE_HIP(hipMalloc((void **)&dy->d_ci[k], 4 * (size_t)cap));
+        dy->d_ci_cap[k] = cap;
+    }
+    GDE_HIP(hipMemcpyAsync(dy->d_rp[k], rp, 4 * ((size_t)n + 1), hipMemcpyHostToDevice, dy->s));
+    GDE_HIP(hipMemcpyAsync(dy->d_ci[k], dy->h_ci, 4 * (size_t)need, hipMemcpyHostToDevice, dy->s));
+    GDE_HIP(hipStreamSynchronize(dy->s));  // the staging is reused by the next update
+    dy->cur = k;
+    *rp_out = dy->d_rp[k];
+    *ci_out = dy->d_ci[k];
     *nnz_out = nnz;
     return GDE_OK;
 }
@@ -206,8 +233,12 @@ int gde_dyn_create(gde_ctx *ctx, const gde_graph *g0, int32_t value_type, gde_dy
     int64_t nnz = 0;
     std::vector<int32_t> deg;
     int rc = dyn_upload_csr(dy, &drp, &dci, &nnz, &deg);
-    if (rc) { delete dy; return rc; }
+    if (rc) {
+        gde_dyn_destroy(dy);
+        return rc;
+    }
     dy->g = graph_wrap_device(ctx, n, nnz, drp, dci);
+    dy->g->owned = false;  // the buffer sets belong to the dynamic graph
     Workspace &w = dy->view;
     w.n = n;
     w.vtype = value_type;
@@ -360,8 +391,8 @@ int gde_dyn_update(gde_dyn *dy, int32_t k_ins, const int32_t *iu, const int32_t 
     std::vector<int32_t> deg;
     int rc = dyn_upload_csr(dy, &drp, &dci, &nnz, &deg);
     if (rc) return rc;
-    GDE_HIP(hipStreamSynchronize(dy->s));
     graph_set_csr(dy->g, drp, dci, nnz, deg);
+    dy->g->owned = false;  // the buffer sets belong to the dynamic graph
     if ((rc = batch_workspaces_refresh(dy->g, dy->bctx, dy->s))) return rc;
     if (nsrc == 0) return GDE_OK;
     // event buffers
@@ -493,6 +524,7 @@ int gde_dyn_read(gde_dyn *dy, int32_t qid, gde_result *res, uint32_t flags) {
 int gde_dyn_destroy(gde_dyn *dy) {
     if (!dy) return fail(GDE_ERR_INVALID_ARG, "null dynamic graph");
     (void)hipSetDevice(dy->ctx->device);
+    if (dy->g) dy->g->owned = false;  // freed below with the buffer sets
     if (dy->s) (void)hipStreamSynchronize(dy->s);
     for (gde_dyn_query *q : dy->q) dyn_query_free(q);
     Workspace &w = dy->view;
@@ -504,6 +536,12 @@ int gde_dyn_destroy(gde_dyn *dy) {
     if (dy->s) (void)hipStreamDestroy(dy->s);
     if (dy->bctx) gde_ctx_destroy(dy->bctx);
     if (dy->g) gde_graph_destroy(dy->g);
+    for (int k = 0; k < 2; k++) {
+        if (dy->d_rp[k]) (void)hipFree(dy->d_rp[k]);
+        if (dy->d_ci[k]) (void)hipFree(dy->d_ci[k]);
+    }
+    if (dy->h_rp) (void)hipHostFree(dy->h_rp);
+    if (dy->h_ci) (void)hipHostFree(dy->h_ci);
     delete dy;
     return GDE_OK;
 }
