@@ -231,6 +231,16 @@ int gde_graph_create(gde_ctx *ctx, int32_t n, int64_t nnz, const int32_t *row_pt
 int gde_graph_destroy(gde_graph *g);
 
 /*
+ * The graph's node and entry counts, and a synchronous copy of its CSR into
+ * caller-owned host arrays (row_ptr: n + 1 entries, col_idx: nnz entries;
+ * either may be NULL to skip it).  The current version of a dynamic graph
+ * (gde_dyn_graph) has ascending rows.  Errors: GDE_ERR_INVALID_ARG for a null
+ * graph, GDE_ERR_DEVICE if the copy fails.
+ */
+int gde_graph_info(const gde_graph *g, int32_t *n, int64_t *nnz);
+int gde_graph_download(const gde_graph *g, int32_t *row_ptr, int32_t *col_idx);
+
+/*
  * Bounds of lambda_max(A) by power iteration on A + I from the all-ones vector
  * (a global O(nnz) pass per iteration; graph preparation, not part of a solve):
  * lower = Rayleigh quotient v'Av / v'v, upper = max_u (Av)_u / v_u
@@ -370,17 +380,22 @@ int gde_batch_tuned(const gde_ctx *ctx, const gde_graph *g, int32_t kind, int32_
  * applied to every query as the Insert / Delete corrections of
  * LocalGS(Dynamic) and LocalSOR(Dynamic) (Algorithms 2-5) in the generic form
  * r = b - Q x -- each undirected edge {a, c} as the directed events a -> c and
- * c -> a, inserts before deletes; for PPR an event at a of current degree d
+ * c -> a, each source taking its inserts and then its deletes, targets
+ * ascending within each; for PPR an event at a of current degree d
  * moves D = x_a / d (insert: x_a += D, r_a -= D, r_c += (1-alpha) D; delete:
  * the opposite signs; the first edge of a degree-0 node only adds (1-alpha) x_a
  * to r_c); for Katz r_c +/-= beta x_a -- followed by a warm LocalGD re-solve
  * from the corrected state: S_0 = {u : |r_u| >= theta_u, r_u != 0}, residuals
- * may be negative.  The iterations run in the fixed order of GDE_DETERMINISTIC,
- * so results do not depend on scheduling.  The first solve of a query starts
- * from x = 0, r = b with S_0 = supp(s) forced (Definition 3.1).
+ * may be negative.  The queries of one kind and parameter are re-solved
+ * together as the lanes of one batch (the scatter path: additions are atomic,
+ * so FP summation order varies between runs).  The first solve of a query
+ * starts from x = 0, r = b with S_0 = supp(s) forced (Definition 3.1), in the
+ * fixed-order iterations of GDE_DETERMINISTIC.  The graph stays on the device:
+ * a batch's events are sorted and checked there and the next version is
+ * merged from the current one.
  *
- * gde_dyn_create : copies g0 (device CSR) as version 0; value_type GDE_F32 or
- *                  GDE_F64 for every query of this object.
+ * gde_dyn_create : copies g0 (device CSR, rows sorted ascending) as version 0;
+ *                  value_type GDE_F32 or GDE_F64 for every query of this object.
  * gde_dyn_graph  : the current version, usable with gde_solve / gde_solve_global
  *                  (e.g. to compare with a solve from scratch); valid until the
  *                  next gde_dyn_update or gde_dyn_destroy.

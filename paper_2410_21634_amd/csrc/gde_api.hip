@@ -501,9 +501,10 @@ int graph_replace_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const
     return GDE_OK;
 }
 
-// swap in a rebuilt CSR (owned) with the given current degrees, and drop every
-// context's workspaces of g (their tile tables, bins and degrees are stale)
-int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std::vector<int32_t> &deg) {
+// swap in a rebuilt CSR (owned), and drop every context's workspaces of g
+// (their tile tables, bins and degrees are stale); the host degrees follow
+// through graph_add_degrees
+int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz) {
     {
         std::lock_guard<std::mutex> lk(g_ctx_mu);
         for (gde_ctx *c : g_ctxs) drop_workspaces_of(g, c);
@@ -516,16 +517,18 @@ int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std
     g->col_idx = ci;
     g->nnz = nnz;
     g->owned = true;
-    int32_t dmax = 0;
-    for (int32_t v : deg) dmax = std::max(dmax, v);
-    g->d_max = dmax;
-    GraphHost *gh = graph_host(g);
-    if (gh) {
-        gh->deg = deg;
-        gh->row_ptr.assign(deg.size() + 1, 0);
-        for (size_t u = 0; u < deg.size(); u++) gh->row_ptr[u + 1] = gh->row_ptr[u] + deg[u];
-    }
     return GDE_OK;
+}
+
+// the host degrees of `nodes` change by delta (an edge event at each); d_max
+// stays an upper bound
+void graph_add_degrees(gde_graph *g, const int32_t *nodes, int32_t k, int32_t delta) {
+    GraphHost *gh = graph_host(g);
+    if (!gh) return;
+    for (int32_t i = 0; i < k; i++) {
+        const int32_t d = gh->deg[nodes[i]] += delta;
+        g->d_max = std::max(g->d_max, d);
+    }
 }
 
 void plain_workspaces_drop(const gde_graph *g, gde_ctx *ctx) {
@@ -1239,6 +1242,21 @@ int gde_graph_destroy(gde_graph *g) {
     }
     if (g->owned) { (void)hipFree(g->row_ptr); (void)hipFree(g->col_idx); }
     delete g;
+    return GDE_OK;
+}
+
+int gde_graph_info(const gde_graph *g, int32_t *n, int64_t *nnz) {
+    if (!g) return fail(GDE_ERR_INVALID_ARG, "null graph");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    return GDE_OK;
+}
+
+int gde_graph_download(const gde_graph *g, int32_t *row_ptr, int32_t *col_idx) {
+    if (!g) return fail(GDE_ERR_INVALID_ARG, "null graph");
+    GDE_HIP(hipSetDevice(g->device));
+    if (row_ptr) GDE_HIP(hipMemcpy(row_ptr, g->row_ptr, 4 * ((size_t)g->n + 1), hipMemcpyDeviceToHost));
+    if (col_idx && g->nnz > 0) GDE_HIP(hipMemcpy(col_idx, g->col_idx, 4 * (size_t)g->nnz, hipMemcpyDeviceToHost));
     return GDE_OK;
 }
 

@@ -609,7 +609,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     // warm start: the residuals go back to the queries before the pass clears them
     if (warm)
         GDE_HIP(batch_warm_store<V>(L, a, 0, w->lane_dst, (uint32_t *const *)(w->warm_ptr + GL), nullptr, nullptr, B,
-                                    w->nblk, grid, s));
+                                    grid, s));
     // (the level push took its norms level by level and never hits a cap)
     const bool any_sub = std::any_of(h_flag.begin(), h_flag.end(), [](int32_t f) { return f != 0; });
     if (!lvl)
@@ -620,7 +620,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     std::vector<long long> nnz(GL, 0), off(GL, 0);
     if (warm) {
         GDE_HIP(batch_warm_store<V>(L, a, 1, nullptr, nullptr, w->lane_dst + GL, (uint32_t *const *)w->warm_ptr, B,
-                                    w->nblk, grid, s));
+                                    grid, s));
     } else {
         GDE_HIP(batch_extract<V>(L, a, 0, w->cnt, w->nblk, w->lane_nnz, nullptr, nullptr, nullptr, 0, s));
         std::fill(off.begin(), off.end(), -1);

@@ -137,7 +137,7 @@ hipError_t batch_warm_load(int L, const BatchArgs<V> &a, const void *const *q_rd
                            hipStream_t s);
 template <typename V>
 hipError_t batch_warm_store(int L, const BatchArgs<V> &a, int stage, void *const *q_rd, uint32_t *const *q_tbm,
-                            void *const *q_x, uint32_t *const *q_pushed, int B, int nblk, int grid, hipStream_t s);
+                            void *const *q_x, uint32_t *const *q_pushed, int B, int grid, hipStream_t s);
 template <typename V>
 hipError_t batch_init_col_deg(const int32_t *col_idx, const V *deg, V *col_deg, int64_t nnz, hipStream_t s);
 

@@ -634,37 +634,35 @@ __global__ void __launch_bounds__(kBlock) k_batch_ex_emit(BatchArgs<V> a, const 
     }
 }
 
-// Warm start: lane j (grid.y) takes its query's residual at every node of the
-// query's touched bitmap (the only nodes where it can be nonzero); a nonzero one
-// becomes a touched entry (its degree beside it) and a candidate of iteration 0.
-// Few entries per query, so the lists are appended to one atomic at a time.
+// Warm start: one thread per (node, group) takes each lane's residual at the
+// node when the node is in that query's touched bitmap (the only nodes where it
+// can be nonzero); a nonzero one becomes a touched entry (its degree beside it)
+// and the node a candidate of iteration 0.  The appends are wave-aggregated.
 template <typename V, int L>
 __global__ void __launch_bounds__(kBlock) k_batch_warm_load(BatchArgs<V> a, const RD<V> *const *__restrict__ q_rd,
-                                                            const uint32_t *const *__restrict__ q_tbm) {
-    const int j = (int)blockIdx.y, g = j / L, l = j % L;
-    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t m = wi < a.nwords ? q_tbm[j][wi] : 0u;
-    const RD<V> *rd = q_rd[j];
-    while (m) {
-        const int b = __ffs((int)m) - 1;
-        m &= m - 1u;
-        const int32_t u = (int32_t)(wi * 32 + b);
-        const V r = rd[u].r;
-        if (r == (V)0) continue;
-        a.R[((size_t)u * a.G + g) * L + l] = r;
-        const int te = atomicAdd(&a.st->tcount, 1);
-        if (te < a.touch_cap) {
-            a.touched[te] = ((uint64_t)(uint32_t)j << 32) | (uint32_t)u;
-            if (a.tdeg) a.tdeg[te] = a.row_ptr[u + 1] - a.row_ptr[u];
-        } else {
-            a.st->ovf[0] = 1;
+                                                            const uint32_t *const *__restrict__ q_tbm, int B) {
+    const int g = (int)blockIdx.y;
+    const int64_t ui = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool in = ui < a.n;
+    const int32_t u = in ? (int32_t)ui : 0;
+    const int32_t dg = in && a.tdeg ? a.row_ptr[u + 1] - a.row_ptr[u] : 0;
+    uint32_t mask = 0u;
+    for (int l = 0; l < L; l++) {  // uniform over the wave: every lane takes part in the appends
+        const int j = g * L + l;
+        V r = (V)0;
+        if (in && j < B && ((q_tbm[j][u >> 5] >> (u & 31)) & 1u)) r = q_rd[j][u].r;
+        const bool nz = r != (V)0;
+        if (nz) {
+            a.R[((size_t)u * a.G + g) * L + l] = r;
+            mask |= 1u << l;
         }
-        if (atomicOr(&a.NM[(size_t)u * a.G + g], 1u << l) == 0u) {
-            const int sa = atomicAdd(&a.st->acount[0], 1);
-            if (sa < a.act_cap) a.act[0][sa] = ((uint64_t)(uint32_t)g << 32) | (uint32_t)u;
-            else a.st->ovf[0] = 1;
-        }
+        const int te = bwave_append64(nz, &a.st->tcount, ((uint64_t)(uint32_t)j << 32) | (uint32_t)u, a.touched,
+                                      a.touch_cap, &a.st->ovf[0]);
+        if (nz && a.tdeg && te < a.touch_cap) a.tdeg[te] = dg;
     }
+    const bool fresh = mask != 0u && atomicOr(&a.NM[(size_t)u * a.G + g], mask) == 0u;
+    bwave_append64(fresh, &a.st->acount[0], ((uint64_t)(uint32_t)g << 32) | (uint32_t)u, a.act[0], a.act_cap,
+                   &a.st->ovf[0]);
 }
 
 // stage 0 (before the residual pass): each touched entry's residual back into
@@ -684,29 +682,39 @@ __global__ void __launch_bounds__(kBlock) k_batch_warm_store_r(BatchArgs<V> a, R
     }
 }
 
+// One thread per (pushed-bitmap word, lane): the L threads of a word sit in one
+// wavefront (L divides 64), read the word together, and each owns its query's
+// pushed-bitmap word, so no atomics are needed.
 template <typename V, int L>
 __global__ void __launch_bounds__(kBlock) k_batch_warm_store_x(BatchArgs<V> a, V *const *__restrict__ q_x,
                                                                uint32_t *const *__restrict__ q_pushed, int B) {
+    static_assert(64 % L == 0, "the threads of one word must share a wavefront");
     const int g = (int)blockIdx.y;
-    const int64_t wi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t wi = t / L;
+    const int l = (int)(t % L), j = g * L + l;
     if (wi >= a.nwords) return;
-    uint32_t word = a.PB[(size_t)g * a.nwords + wi];
+    uint32_t *pw = a.PB + (size_t)g * a.nwords + wi;
+    uint32_t word = *pw;
     if (!word) return;
-    a.PB[(size_t)g * a.nwords + wi] = 0u;
-    while (word) {
-        const int b = __ffs((int)word) - 1;
-        word &= word - 1u;
-        const int32_t u = (int32_t)(wi * 32 + b);
-        V *xr = a.X + ((size_t)u * a.G + g) * L;
-        for (int l = 0; l < L; l++) {
-            const int j = g * L + l;
-            const V xv = xr[l];
-            if (xv == (V)0 || j >= B) continue;
-            q_x[j][u] = q_x[j][u] + xv;
-            atomicOr(&q_pushed[j][u >> 5], 1u << (u & 31));
-            xr[l] = (V)0;
+    if (j < B) {
+        V *__restrict__ qx = q_x[j];
+        V *__restrict__ xb = a.X + (size_t)g * L + l;
+        const size_t stride = (size_t)a.G * L;
+        uint32_t pushed = 0u;
+        for (uint32_t w = word; w; w &= w - 1u) {
+            const int b = __ffs((int)w) - 1;
+            const int32_t u = (int32_t)(wi * 32 + b);
+            V *xp = xb + (size_t)u * stride;
+            const V xv = *xp;
+            if (xv == (V)0) continue;
+            qx[u] = qx[u] + xv;
+            *xp = (V)0;
+            pushed |= 1u << b;
         }
+        if (pushed) q_pushed[j][wi] |= pushed;
     }
+    if (l == 0) *pw = 0u;
 }
 
 template <typename V>
@@ -838,11 +846,12 @@ __global__ void k_batch_col_deg(const int32_t *__restrict__ col_idx, const V *__
 template <typename V>
 hipError_t batch_warm_load(int L, const BatchArgs<V> &a, const void *const *q_rd, const uint32_t *const *q_tbm, int B,
                            hipStream_t s) {
-    const dim3 grid((unsigned)((a.nwords + kBlock - 1) / kBlock), (unsigned)B);
+    const dim3 grid((unsigned)(((int64_t)a.n + kBlock - 1) / kBlock), (unsigned)a.G);
+    const RD<V> *const *rd = (const RD<V> *const *)q_rd;
     switch (L) {
-    case 8: hipLaunchKernelGGL((k_batch_warm_load<V, 8>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
-    case 16: hipLaunchKernelGGL((k_batch_warm_load<V, 16>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
-    case 32: hipLaunchKernelGGL((k_batch_warm_load<V, 32>), grid, dim3(kBlock), 0, s, a, (const RD<V> *const *)q_rd, q_tbm); break;
+    case 8: hipLaunchKernelGGL((k_batch_warm_load<V, 8>), grid, dim3(kBlock), 0, s, a, rd, q_tbm, B); break;
+    case 16: hipLaunchKernelGGL((k_batch_warm_load<V, 16>), grid, dim3(kBlock), 0, s, a, rd, q_tbm, B); break;
+    case 32: hipLaunchKernelGGL((k_batch_warm_load<V, 32>), grid, dim3(kBlock), 0, s, a, rd, q_tbm, B); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -850,8 +859,8 @@ hipError_t batch_warm_load(int L, const BatchArgs<V> &a, const void *const *q_rd
 
 template <typename V>
 hipError_t batch_warm_store(int L, const BatchArgs<V> &a, int stage, void *const *q_rd, uint32_t *const *q_tbm,
-                            void *const *q_x, uint32_t *const *q_pushed, int B, int nblk, int grid, hipStream_t s) {
-    const dim3 gx((unsigned)nblk, (unsigned)a.G);
+                            void *const *q_x, uint32_t *const *q_pushed, int B, int grid, hipStream_t s) {
+    const dim3 gx((unsigned)((a.nwords * L + kBlock - 1) / kBlock), (unsigned)a.G);
     switch (L) {
 #define GDE_BW(LL)                                                                                                   \
     case LL:                                                                                                         \
@@ -899,7 +908,7 @@ hipError_t batch_init_deg(const int32_t *row_ptr, V *deg, int32_t n, hipStream_t
     template hipError_t batch_warm_load<V>(int, const BatchArgs<V> &, const void *const *, const uint32_t *const *, \
                                            int, hipStream_t);                                                     \
     template hipError_t batch_warm_store<V>(int, const BatchArgs<V> &, int, void *const *, uint32_t *const *,      \
-                                            void *const *, uint32_t *const *, int, int, int, hipStream_t);
+                                            void *const *, uint32_t *const *, int, int, hipStream_t);
 
 GDE_BINST(float)
 GDE_BINST(double)

@@ -18,12 +18,22 @@
 // deterministic mode.  Everything in between stays resident: residuals,
 // estimates, touched and pushed bitmaps, degrees.
 //
-// The corrections run one thread per node that has events, walking its events
-// in their order (x_a and the degree change only by the node's own events, so
-// D is exactly the sequential one); the additions into other nodes' residuals
-// are atomic.  The graph is kept as a host adjacency (validation of events,
-// CSR rebuild) and a device CSR that is replaced after each batch.
+// The graph lives on the device only, as a CSR with ascending rows in two
+// buffer sets.  A batch becomes directed events keyed (source, delete flag,
+// target) and radix-sorted on the device, so that each source's inserts come
+// before its deletes, each group in target order.  One thread per event checks
+// it against the current row (binary search: an insert must be absent, a
+// delete present, no event twice) and records the target's position in the
+// row.  The next version is then written into the spare set: new degrees, a
+// scan for the row pointers, and one wavefront per row merging the old row
+// (less its deleted entries) with its inserted targets.  The corrections run
+// one thread per source, walking its events in key order (x_a and the degree
+// change only by the node's own events, so D is exactly the sequential one);
+// the additions into other nodes' residuals are atomic.
 #include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -38,7 +48,8 @@
 
 namespace gde {
 gde_graph *graph_wrap_device(gde_ctx *ctx, int32_t n, int64_t nnz, int32_t *rp, int32_t *ci);
-int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz, const std::vector<int32_t> &deg);
+int graph_set_csr(gde_graph *g, int32_t *rp, int32_t *ci, int64_t nnz);
+void graph_add_degrees(gde_graph *g, const int32_t *nodes, int32_t k, int32_t delta);
 }  // namespace gde
 
 struct gde_dyn_query {
@@ -63,41 +74,145 @@ struct gde_dyn {
     int vtype = GDE_F64;
     size_t vs = 8;
     int32_t n = 0;
-    std::vector<std::vector<int32_t>> adj;  // sorted neighbour lists of the current graph
     gde_graph *g = nullptr;                 // the current version (owned device CSR)
     gde::Workspace view;                    // lists, counters, deterministic-mode buffers
     std::vector<gde_dyn_query *> q;
     hipStream_t s = nullptr;
-    // event buffers (device): sources, their event ranges, targets and signs
-    int32_t *ev_src = nullptr, *ev_off = nullptr, *ev_dst = nullptr, *ev_sign = nullptr;
-    int64_t ev_cap = 0, src_cap = 0;
+    // event buffers (device): keys as given and sorted, each event's position
+    // in its source's row; pinned staging of the keys; sort / scan scratch
+    uint64_t *ev_key = nullptr, *ev_sorted = nullptr, *h_key = nullptr;
+    int32_t *ev_pos = nullptr;
+    int64_t ev_cap = 0;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    // per node: first sorted event of the node as a source (-1: none), its
+    // insert and delete counts, its next degree; the check's error bits
+    int32_t *nd_first = nullptr, *nd_ins = nullptr, *nd_del = nullptr, *nd_deg = nullptr, *d_err = nullptr;
+    int32_t *h_err = nullptr;
     int32_t *blk = nullptr;  // output compaction
     long long *total = nullptr;
     gde::DevState *h_st = nullptr;
-    // the device CSR in two buffer sets (the graph points at one, the next
-    // version is uploaded into the other) and its pinned host staging, so an
-    // update allocates and frees nothing once the capacities suffice
+    // the device CSR in two buffer sets: the graph points at one, the next
+    // version is written into the other
     int32_t *d_rp[2] = {nullptr, nullptr}, *d_ci[2] = {nullptr, nullptr};
     int64_t d_ci_cap[2] = {0, 0};
     int cur = 0;
-    int32_t *h_rp = nullptr, *h_ci = nullptr;
-    int64_t h_ci_cap = 0;
 };
 
 namespace gde {
 
+// an event key: the source in the high word, then the delete flag, then the target
+__device__ __forceinline__ int32_t ev_src(uint64_t k) { return (int32_t)(k >> 32); }
+__device__ __forceinline__ int32_t ev_dst(uint64_t k) { return (int32_t)(k & 0x7fffffffu); }
+__device__ __forceinline__ bool ev_is_del(uint64_t k) { return ((k >> 31) & 1u) != 0u; }
+
+// per sorted event: a repeat of the previous key, the test against the
+// current row of its source (ascending, binary search) and the target's
+// lower-bound position in that row; a source's first event records the
+// source's event range
+__global__ void k_dyn_check(const uint64_t *__restrict__ key, int32_t m, const int32_t *__restrict__ rp,
+                            const int32_t *__restrict__ ci, int32_t *__restrict__ pos, int32_t *__restrict__ first,
+                            int32_t *__restrict__ nins, int32_t *__restrict__ ndel, int32_t *err) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= m) return;
+    const uint64_t k = key[i];
+    const int32_t a = ev_src(k), c = ev_dst(k);
+    const bool del = ev_is_del(k);
+    const int32_t b = rp[a], e = rp[a + 1];
+    int32_t lo = b, hi = e;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (ci[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    const bool found = lo < e && ci[lo] == c;
+    const int bad = (!del && found ? 1 : 0) | (del && !found ? 2 : 0) | (i > 0 && key[i - 1] == k ? 4 : 0);
+    pos[i] = lo - b;
+    if (bad) atomicOr(err, bad);
+    if (i == 0 || ev_src(key[i - 1]) != a) {
+        int32_t ni = 0, nd = 0;
+        for (int32_t j = i; j < m && ev_src(key[j]) == a; j++) {
+            if (ev_is_del(key[j])) nd++;
+            else ni++;
+        }
+        first[a] = i;
+        nins[a] = ni;
+        ndel[a] = nd;
+    }
+}
+
+// the next degrees (the scan input) and the first row pointer
+__global__ void k_dyn_degree(const int32_t *__restrict__ rp, const int32_t *__restrict__ first,
+                             const int32_t *__restrict__ nins, const int32_t *__restrict__ ndel, int32_t n,
+                             int32_t *__restrict__ deg, int32_t *__restrict__ new_rp) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u == 0) new_rp[0] = 0;
+    if (u < n) deg[u] = rp[u + 1] - rp[u] + (first[u] >= 0 ? nins[u] - ndel[u] : 0);
+}
+
+// entries of the ascending list p[0, len) below v (strictly, or up to v inclusive)
+__device__ __forceinline__ int32_t dyn_rank(const int32_t *p, int32_t len, int32_t v, bool incl) {
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (incl ? p[mid] <= v : p[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// one wavefront per row: a row without events is copied; otherwise old entry k
+// (not deleted) lands after the k - (deletes before k) old ones kept and the
+// inserts whose position is at most k, and insert j (targets ascending) with
+// position p after the p - (deletes before p) old ones kept and j inserts
+__global__ void __launch_bounds__(256) k_dyn_merge(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   const int32_t *__restrict__ new_rp, int32_t *__restrict__ new_ci,
+                                                   int32_t n, const uint64_t *__restrict__ key,
+                                                   const int32_t *__restrict__ pos, const int32_t *__restrict__ first,
+                                                   const int32_t *__restrict__ nins, const int32_t *__restrict__ ndel) {
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const int lane = (int)__lane_id();
+    const int nwaves = (int)(gridDim.x * blockDim.x / kWave);
+    for (int32_t u = wave; u < n; u += nwaves) {
+        const int32_t b = rp[u], d0 = rp[u + 1] - b, nb = new_rp[u], f = first[u];
+        if (f < 0) {
+            for (int32_t k = lane; k < d0; k += kWave) new_ci[nb + k] = ci[b + k];
+            continue;
+        }
+        const int32_t ni = nins[u], nd = ndel[u];
+        const int32_t *ip = pos + f, *dp = pos + f + ni;
+        for (int32_t k = lane; k < d0; k += kWave) {
+            const int32_t db = dyn_rank(dp, nd, k, false);
+            if (db < nd && dp[db] == k) continue;  // deleted
+            new_ci[nb + k - db + dyn_rank(ip, ni, k, true)] = ci[b + k];
+        }
+        for (int32_t j = lane; j < ni; j += kWave) {
+            const int32_t p = ip[j];
+            new_ci[nb + p - dyn_rank(dp, nd, p, false) + j] = ev_dst(key[f + j]);
+        }
+    }
+}
+
+__global__ void k_dyn_reset(const uint64_t *__restrict__ key, int32_t m, int32_t *first) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < m) first[ev_src(key[i])] = -1;
+}
+
+// one thread per source (its first sorted event), degrees from the old rows
 template <typename V>
-__global__ void k_dyn_correct(const int32_t *__restrict__ src, const int32_t *__restrict__ off,
-                              const int32_t *__restrict__ dst, const int32_t *__restrict__ sign, int32_t nsrc,
-                              const int32_t *__restrict__ deg0, RD<V> *rd, V *x, uint32_t *tbm, int ppr, double param) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsrc) return;
-    const int32_t a = src[i];
+__global__ void k_dyn_correct(const uint64_t *__restrict__ key, int32_t m, const int32_t *__restrict__ rp, RD<V> *rd,
+                              V *x, uint32_t *tbm, int ppr, double param) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= m) return;
+    const int32_t a = ev_src(key[i]);
+    if (i > 0 && ev_src(key[i - 1]) == a) return;
     double xa = (double)x[a], ra = 0.0;
-    int32_t d = deg0[i];
-    for (int32_t e = off[i]; e < off[i + 1]; e++) {
-        const int32_t c = dst[e];
-        const int sg = sign[e];
+    int32_t d = rp[a + 1] - rp[a];
+    for (int32_t e = i; e < m; e++) {
+        const uint64_t k = key[e];
+        if (ev_src(k) != a) break;
+        const int32_t c = ev_dst(k);
+        const int sg = ev_is_del(k) ? -1 : 1;
         if (ppr) {
             if (d == 0) {  // first edge of an isolated node (an insert)
                 atomicAdd(&rd[c].r, (V)((1.0 - param) * xa));
@@ -156,32 +271,10 @@ static int dyn_resolve(gde_dyn *dy, gde_dyn_query *q, const int32_t *forced, int
     return GDE_OK;
 }
 
-// the current adjacency as a CSR in the spare device buffer set (made the
-// current one), staged through pinned host memory; returns its arrays
-static int dyn_upload_csr(gde_dyn *dy, int32_t **rp_out, int32_t **ci_out, int64_t *nnz_out,
-                          std::vector<int32_t> *deg) {
-    const int32_t n = dy->n;
-    if (!dy->h_rp) GDE_HIP(hipHostMalloc((void **)&dy->h_rp, 4 * ((size_t)n + 1), 0));
-    int32_t *rp = dy->h_rp;
-    rp[0] = 0;
-    deg->assign((size_t)n, 0);
-    for (int32_t u = 0; u < n; u++) {
-        (*deg)[u] = (int32_t)dy->adj[u].size();
-        rp[u + 1] = rp[u] + (*deg)[u];
-    }
-    const int64_t nnz = rp[n];
+// buffer set k holds at least nnz column entries (12.5 % headroom on growth)
+static int dyn_reserve_set(gde_dyn *dy, int k, int64_t nnz) {
+    if (!dy->d_rp[k]) GDE_HIP(hipMalloc((void **)&dy->d_rp[k], 4 * ((size_t)dy->n + 1)));
     const int64_t need = std::max<int64_t>(nnz, 1);
-    if (need > dy->h_ci_cap) {
-        if (dy->h_ci) (void)hipHostFree(dy->h_ci);
-        dy->h_ci = nullptr;
-        dy->h_ci_cap = 0;
-        const int64_t cap = need + need / 8;  // room for growth
-        GDE_HIP(hipHostMalloc((void **)&dy->h_ci, 4 * (size_t)cap, 0));
-        dy->h_ci_cap = cap;
-    }
-    for (int32_t u = 0; u < n; u++) std::copy(dy->adj[u].begin(), dy->adj[u].end(), dy->h_ci + rp[u]);
-    const int k = dy->d_rp[dy->cur] ? dy->cur ^ 1 : dy->cur;  // the set the graph does not use
-    if (!dy->d_rp[k]) GDE_HIP(hipMalloc((void **)&dy->d_rp[k], 4 * ((size_t)n + 1)));
     if (need > dy->d_ci_cap[k]) {
         if (dy->d_ci[k]) (void)hipFree(dy->d_ci[k]);
         dy->d_ci[k] = nullptr;
@@ -190,13 +283,39 @@ static int dyn_upload_csr(gde_dyn *dy, int32_t **rp_out, int32_t **ci_out, int64
         GDE_HIP(hipMalloc((void **)&dy->d_ci[k], 4 * (size_t)cap));
         dy->d_ci_cap[k] = cap;
     }
-    GDE_HIP(hipMemcpyAsync(dy->d_rp[k], rp, 4 * ((size_t)n + 1), hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipMemcpyAsync(dy->d_ci[k], dy->h_ci, 4 * (size_t)need, hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipStreamSynchronize(dy->s));  // the staging is reused by the next update
-    dy->cur = k;
-    *rp_out = dy->d_rp[k];
-    *ci_out = dy->d_ci[k];
-    *nnz_out = nnz;
+    return GDE_OK;
+}
+
+// event buffers for m events, and sort / scan scratch for them (keys of
+// end_bit bits) and for n nodes
+static int dyn_reserve_events(gde_dyn *dy, int64_t m, int end_bit) {
+    if (m > dy->ev_cap) {
+        const int64_t cap = std::max<int64_t>(m + m / 4, 4096);
+        if (dy->ev_key) (void)hipFree(dy->ev_key);
+        if (dy->ev_sorted) (void)hipFree(dy->ev_sorted);
+        if (dy->ev_pos) (void)hipFree(dy->ev_pos);
+        if (dy->h_key) (void)hipHostFree(dy->h_key);
+        dy->ev_key = dy->ev_sorted = dy->h_key = nullptr;
+        dy->ev_pos = nullptr;
+        dy->ev_cap = 0;
+        GDE_HIP(hipMalloc((void **)&dy->ev_key, 8 * (size_t)cap));
+        GDE_HIP(hipMalloc((void **)&dy->ev_sorted, 8 * (size_t)cap));
+        GDE_HIP(hipMalloc((void **)&dy->ev_pos, 4 * (size_t)cap));
+        GDE_HIP(hipHostMalloc((void **)&dy->h_key, 8 * (size_t)cap, 0));
+        dy->ev_cap = cap;
+    }
+    size_t sort_bytes = 0, scan_bytes = 0;
+    GDE_HIP(rocprim::radix_sort_keys(nullptr, sort_bytes, dy->ev_key, dy->ev_sorted, (size_t)m, 0, end_bit, dy->s));
+    GDE_HIP(rocprim::inclusive_scan(nullptr, scan_bytes, dy->nd_deg, dy->d_rp[0], (size_t)dy->n,
+                                    rocprim::plus<int32_t>(), dy->s));
+    const size_t need = std::max(sort_bytes, scan_bytes);
+    if (need > dy->tmp_bytes) {
+        if (dy->tmp) (void)hipFree(dy->tmp);
+        dy->tmp = nullptr;
+        dy->tmp_bytes = 0;
+        GDE_HIP(hipMalloc(&dy->tmp, need));
+        dy->tmp_bytes = need;
+    }
     return GDE_OK;
 }
 
@@ -222,38 +341,43 @@ int gde_dyn_create(gde_ctx *ctx, const gde_graph *g0, int32_t value_type, gde_dy
     std::vector<int32_t> rp((size_t)n + 1), ci((size_t)std::max<int64_t>(g0->nnz, 1));
     GDE_HIP(hipMemcpy(rp.data(), g0->row_ptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost));
     if (g0->nnz > 0) GDE_HIP(hipMemcpy(ci.data(), g0->col_idx, 4 * (size_t)g0->nnz, hipMemcpyDeviceToHost));
+    for (int32_t u = 0; u < n; u++) std::sort(ci.begin() + rp[u], ci.begin() + rp[u + 1]);  // rows ascending
     gde_dyn *dy = new gde_dyn();
     dy->ctx = ctx;
     dy->vtype = value_type;
     dy->vs = value_type == GDE_F64 ? 8 : 4;
     dy->n = n;
-    dy->adj.resize(n);
-    for (int32_t u = 0; u < n; u++) dy->adj[u].assign(ci.begin() + rp[u], ci.begin() + rp[u + 1]);
-    int32_t *drp = nullptr, *dci = nullptr;
-    int64_t nnz = 0;
-    std::vector<int32_t> deg;
-    int rc = dyn_upload_csr(dy, &drp, &dci, &nnz, &deg);
+    const int64_t nnz = g0->nnz;
+    hipError_t e = hipStreamCreate(&dy->s);
+    int rc = e == hipSuccess ? dyn_reserve_set(dy, 0, nnz) : hip_fail(e, "hipStreamCreate");
+    if (!rc) {
+        Workspace &w = dy->view;
+        w.n = n;
+        w.vtype = value_type;
+        w.vsize = dy->vs;
+        e = hipMemcpy(dy->d_rp[0], rp.data(), 4 * ((size_t)n + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess && nnz > 0) e = hipMemcpy(dy->d_ci[0], ci.data(), 4 * (size_t)nnz, hipMemcpyHostToDevice);
+        for (int i = 0; i < 2 && e == hipSuccess; i++) e = hipMalloc((void **)&w.front[i], 4 * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc((void **)&w.st, sizeof(DevState));
+        if (e == hipSuccess) e = hipMalloc((void **)&dy->blk, 4 * (size_t)(dense_nblk(n) + 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&dy->total, 8);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&dy->h_st, sizeof(DevState), 0);
+        int32_t **nd[] = {&dy->nd_first, &dy->nd_ins, &dy->nd_del, &dy->nd_deg};
+        for (int32_t **a : nd)
+            if (e == hipSuccess) e = hipMalloc((void **)a, 4 * (size_t)std::max(n, 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&dy->d_err, 4);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&dy->h_err, 4, 0);
+        if (e == hipSuccess) e = hipMemset(dy->nd_first, 0xff, 4 * (size_t)std::max(n, 1));  // -1: no events
+        if (e != hipSuccess) rc = hip_fail(e, "dynamic graph buffers");
+    }
+    if (!rc) rc = dyn_reserve_events(dy, 1, 64);
     if (rc) {
         gde_dyn_destroy(dy);
         return rc;
     }
-    dy->g = graph_wrap_device(ctx, n, nnz, drp, dci);
+    dy->cur = 0;
+    dy->g = graph_wrap_device(ctx, n, nnz, dy->d_rp[0], dy->d_ci[0]);
     dy->g->owned = false;  // the buffer sets belong to the dynamic graph
-    Workspace &w = dy->view;
-    w.n = n;
-    w.vtype = value_type;
-    w.vsize = dy->vs;
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; i++) e = hipMalloc((void **)&w.front[i], 4 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc((void **)&w.st, sizeof(DevState));
-    if (e == hipSuccess) e = hipMalloc((void **)&dy->blk, 4 * (size_t)(dense_nblk(n) + 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&dy->total, 8);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&dy->h_st, sizeof(DevState), 0);
-    if (e == hipSuccess) e = hipStreamCreate(&dy->s);
-    if (e != hipSuccess) {
-        gde_dyn_destroy(dy);
-        return hip_fail(e, "dynamic graph buffers");
-    }
     dy->bctx = new gde_ctx();
     dy->bctx->device = ctx->device;
     *out = dy;
@@ -330,102 +454,88 @@ int gde_dyn_update(gde_dyn *dy, int32_t k_ins, const int32_t *iu, const int32_t 
                    const int32_t *du, const int32_t *dv) {
     if (!dy || k_ins < 0 || k_del < 0 || (k_ins > 0 && (!iu || !iv)) || (k_del > 0 && (!du || !dv)))
         return fail(GDE_ERR_INVALID_ARG, "bad event arrays");
+    if ((int64_t)k_ins + k_del > (int64_t)INT32_MAX / 2) return fail(GDE_ERR_INVALID_ARG, "too many events");
     const int32_t n = dy->n;
-    // validation against the current graph, before any change
-    std::vector<std::pair<int32_t, int32_t>> ins, del;
-    auto has = [&](int32_t a, int32_t b) { return std::binary_search(dy->adj[a].begin(), dy->adj[a].end(), b); };
+    for (int32_t i = 0; i < k_ins; i++)
+        if (iu[i] < 0 || iu[i] >= n || iv[i] < 0 || iv[i] >= n || iu[i] == iv[i])
+            return fail(GDE_ERR_INVALID_ARG, "bad inserted edge");
+    for (int32_t i = 0; i < k_del; i++)
+        if (du[i] < 0 || du[i] >= n || dv[i] < 0 || dv[i] >= n || du[i] == dv[i])
+            return fail(GDE_ERR_INVALID_ARG, "bad deleted edge");
+    const int32_t m = 2 * (k_ins + k_del);
+    if (m == 0) return GDE_OK;
+    GDE_HIP(hipSetDevice(dy->ctx->device));
+    int nbits = 1;
+    while (nbits < 31 && ((int64_t)1 << nbits) < (int64_t)n) nbits++;
+    int rc = dyn_reserve_events(dy, m, 32 + nbits);
+    if (rc) return rc;
+    // directed events keyed (source, delete flag, target): both directions of each edge
+    uint64_t *hk = dy->h_key;
+    auto key = [](int32_t a, int32_t c, uint64_t del) { return ((uint64_t)(uint32_t)a << 32) | (del << 31) | (uint32_t)c; };
     for (int32_t i = 0; i < k_ins; i++) {
-        const int32_t a = iu[i], b = iv[i];
-        if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(GDE_ERR_INVALID_ARG, "bad inserted edge");
-        if (has(a, b)) return fail(GDE_ERR_INVALID_ARG, "inserted edge already exists");
-        ins.emplace_back(std::min(a, b), std::max(a, b));
+        hk[2 * i] = key(iu[i], iv[i], 0);
+        hk[2 * i + 1] = key(iv[i], iu[i], 0);
     }
     for (int32_t i = 0; i < k_del; i++) {
-        const int32_t a = du[i], b = dv[i];
-        if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(GDE_ERR_INVALID_ARG, "bad deleted edge");
-        if (!has(a, b)) return fail(GDE_ERR_INVALID_ARG, "deleted edge does not exist");
-        del.emplace_back(std::min(a, b), std::max(a, b));
+        hk[2 * (k_ins + i)] = key(du[i], dv[i], 1);
+        hk[2 * (k_ins + i) + 1] = key(dv[i], du[i], 1);
     }
-    {
-        auto a2 = ins, b2 = del;
-        std::sort(a2.begin(), a2.end());
-        std::sort(b2.begin(), b2.end());
-        if (std::adjacent_find(a2.begin(), a2.end()) != a2.end() || std::adjacent_find(b2.begin(), b2.end()) != b2.end())
-            return fail(GDE_ERR_INVALID_ARG, "an edge appears twice in one batch");
+    const int32_t *rp = dy->d_rp[dy->cur], *ci = dy->d_ci[dy->cur];
+    const unsigned eg = (unsigned)((m + 255) / 256);
+    GDE_HIP(hipMemcpyAsync(dy->ev_key, hk, 8 * (size_t)m, hipMemcpyHostToDevice, dy->s));
+    size_t tb = dy->tmp_bytes;
+    GDE_HIP(rocprim::radix_sort_keys(dy->tmp, tb, dy->ev_key, dy->ev_sorted, (size_t)m, 0, 32 + nbits, dy->s));
+    GDE_HIP(hipMemsetAsync(dy->d_err, 0, 4, dy->s));
+    hipLaunchKernelGGL(k_dyn_check, dim3(eg), dim3(256), 0, dy->s, dy->ev_sorted, m, rp, ci, dy->ev_pos, dy->nd_first,
+                       dy->nd_ins, dy->nd_del, dy->d_err);
+    GDE_HIP(hipGetLastError());
+    GDE_HIP(hipMemcpyAsync(dy->h_err, dy->d_err, 4, hipMemcpyDeviceToHost, dy->s));
+    GDE_HIP(hipStreamSynchronize(dy->s));
+    if (const int bad = *dy->h_err) {  // nothing changes: clear the per-node marks and report
+        hipLaunchKernelGGL(k_dyn_reset, dim3(eg), dim3(256), 0, dy->s, dy->ev_sorted, m, dy->nd_first);
+        GDE_HIP(hipGetLastError());
+        GDE_HIP(hipStreamSynchronize(dy->s));
+        return fail(GDE_ERR_INVALID_ARG, (bad & 1)   ? "inserted edge already exists"
+                                         : (bad & 2) ? "deleted edge does not exist"
+                                                     : "an edge appears twice in one batch");
     }
-    GDE_HIP(hipSetDevice(dy->ctx->device));
-    // directed events in order (inserts, then deletes; a -> c then c -> a), grouped by source
-    struct Ev { int32_t a, c, sg; };
-    std::vector<Ev> evs;
-    evs.reserve(2 * ((size_t)k_ins + k_del));
-    for (int32_t i = 0; i < k_ins; i++) { evs.push_back({iu[i], iv[i], 1}); evs.push_back({iv[i], iu[i], 1}); }
-    for (int32_t i = 0; i < k_del; i++) { evs.push_back({du[i], dv[i], -1}); evs.push_back({dv[i], du[i], -1}); }
-    std::stable_sort(evs.begin(), evs.end(), [](const Ev &x, const Ev &y) { return x.a < y.a; });
-    std::vector<int32_t> src, off, dst, sgn, deg0;
-    for (size_t i = 0; i < evs.size(); i++) {
-        if (i == 0 || evs[i].a != evs[i - 1].a) {
-            src.push_back(evs[i].a);
-            off.push_back((int32_t)i);
-            deg0.push_back((int32_t)dy->adj[evs[i].a].size());
-        }
-        dst.push_back(evs[i].c);
-        sgn.push_back(evs[i].sg);
-    }
-    off.push_back((int32_t)evs.size());
-    const int32_t nsrc = (int32_t)src.size();
-    // the new graph
-    for (auto &e : ins) {
-        for (int dir = 0; dir < 2; dir++) {
-            auto &v = dy->adj[dir ? e.second : e.first];
-            v.insert(std::lower_bound(v.begin(), v.end(), dir ? e.first : e.second), dir ? e.first : e.second);
-        }
-    }
-    for (auto &e : del) {
-        for (int dir = 0; dir < 2; dir++) {
-            auto &v = dy->adj[dir ? e.second : e.first];
-            v.erase(std::lower_bound(v.begin(), v.end(), dir ? e.first : e.second));
-        }
-    }
-    int32_t *drp = nullptr, *dci = nullptr;
-    int64_t nnz = 0;
-    std::vector<int32_t> deg;
-    int rc = dyn_upload_csr(dy, &drp, &dci, &nnz, &deg);
-    if (rc) return rc;
-    graph_set_csr(dy->g, drp, dci, nnz, deg);
-    dy->g->owned = false;  // the buffer sets belong to the dynamic graph
-    if ((rc = batch_workspaces_refresh(dy->g, dy->bctx, dy->s))) return rc;
-    if (nsrc == 0) return GDE_OK;
-    // event buffers
-    if ((int64_t)dst.size() > dy->ev_cap || nsrc + 1 > dy->src_cap) {
-        void *p[] = {dy->ev_src, dy->ev_off, dy->ev_dst, dy->ev_sign};
-        for (void *v : p)
-            if (v) (void)hipFree(v);
-        dy->ev_cap = std::max<int64_t>((int64_t)dst.size(), 1024);
-        dy->src_cap = std::max<int64_t>(2 * (int64_t)(nsrc + 1), 1024);
-        GDE_HIP(hipMalloc((void **)&dy->ev_src, 8 * (size_t)dy->src_cap));  // src, then deg0
-        GDE_HIP(hipMalloc((void **)&dy->ev_off, 4 * (size_t)dy->src_cap));
-        GDE_HIP(hipMalloc((void **)&dy->ev_dst, 4 * (size_t)dy->ev_cap));
-        GDE_HIP(hipMalloc((void **)&dy->ev_sign, 4 * (size_t)dy->ev_cap));
-    }
-    int32_t *d_deg0 = dy->ev_src + dy->src_cap;
-    GDE_HIP(hipMemcpyAsync(dy->ev_src, src.data(), 4 * (size_t)nsrc, hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipMemcpyAsync(d_deg0, deg0.data(), 4 * (size_t)nsrc, hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipMemcpyAsync(dy->ev_off, off.data(), 4 * (size_t)(nsrc + 1), hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipMemcpyAsync(dy->ev_dst, dst.data(), 4 * dst.size(), hipMemcpyHostToDevice, dy->s));
-    GDE_HIP(hipMemcpyAsync(dy->ev_sign, sgn.data(), 4 * sgn.size(), hipMemcpyHostToDevice, dy->s));
+    // the next version in the spare buffer set
+    const int k = dy->cur ^ 1;
+    const int64_t nnz = dy->g->nnz + 2 * ((int64_t)k_ins - k_del);
+    if ((rc = dyn_reserve_set(dy, k, nnz))) return rc;
+    hipLaunchKernelGGL(k_dyn_degree, dim3((unsigned)(((int64_t)n + 255) / 256)), dim3(256), 0, dy->s, rp, dy->nd_first,
+                       dy->nd_ins, dy->nd_del, n, dy->nd_deg, dy->d_rp[k]);
+    GDE_HIP(hipGetLastError());
+    tb = dy->tmp_bytes;
+    GDE_HIP(rocprim::inclusive_scan(dy->tmp, tb, dy->nd_deg, dy->d_rp[k] + 1, (size_t)n, rocprim::plus<int32_t>(),
+                                    dy->s));
+    const unsigned mg = (unsigned)std::min<int64_t>(((int64_t)n + 3) / 4, 8192);  // 4 wavefronts per block
+    hipLaunchKernelGGL(k_dyn_merge, dim3(std::max(mg, 1u)), dim3(256), 0, dy->s, rp, ci, dy->d_rp[k], dy->d_ci[k], n,
+                       dy->ev_sorted, dy->ev_pos, dy->nd_first, dy->nd_ins, dy->nd_del);
+    GDE_HIP(hipGetLastError());
+    // the corrections, against the old degrees
     for (gde_dyn_query *q : dy->q) {
         const int ppr = q->p.kind == GDE_PPR;
         const double param = ppr ? q->p.alpha : q->p.beta;
         if (dy->vtype == GDE_F64)
-            hipLaunchKernelGGL(k_dyn_correct<double>, dim3((nsrc + 255) / 256), dim3(256), 0, dy->s, dy->ev_src,
-                               dy->ev_off, dy->ev_dst, dy->ev_sign, nsrc, d_deg0, (RD<double> *)q->rd,
-                               (double *)q->x, q->tbm, ppr, param);
+            hipLaunchKernelGGL(k_dyn_correct<double>, dim3(eg), dim3(256), 0, dy->s, dy->ev_sorted, m, rp,
+                               (RD<double> *)q->rd, (double *)q->x, q->tbm, ppr, param);
         else
-            hipLaunchKernelGGL(k_dyn_correct<float>, dim3((nsrc + 255) / 256), dim3(256), 0, dy->s, dy->ev_src,
-                               dy->ev_off, dy->ev_dst, dy->ev_sign, nsrc, d_deg0, (RD<float> *)q->rd,
-                               (float *)q->x, q->tbm, ppr, param);
+            hipLaunchKernelGGL(k_dyn_correct<float>, dim3(eg), dim3(256), 0, dy->s, dy->ev_sorted, m, rp,
+                               (RD<float> *)q->rd, (float *)q->x, q->tbm, ppr, param);
         GDE_HIP(hipGetLastError());
     }
+    hipLaunchKernelGGL(k_dyn_reset, dim3(eg), dim3(256), 0, dy->s, dy->ev_sorted, m, dy->nd_first);
+    GDE_HIP(hipGetLastError());
+    // the graph switches to the new set (the old one stays intact until the next batch)
+    dy->cur = k;
+    graph_set_csr(dy->g, dy->d_rp[k], dy->d_ci[k], nnz);
+    dy->g->owned = false;  // the buffer sets belong to the dynamic graph
+    graph_add_degrees(dy->g, iu, k_ins, 1);
+    graph_add_degrees(dy->g, iv, k_ins, 1);
+    graph_add_degrees(dy->g, du, k_del, -1);
+    graph_add_degrees(dy->g, dv, k_del, -1);
+    if ((rc = batch_workspaces_refresh(dy->g, dy->bctx, dy->s))) return rc;
     // the re-solves: one batch per kind and parameter
     std::vector<bool> done(dy->q.size(), false);
     for (size_t i = 0; i < dy->q.size(); i++) {
@@ -528,7 +638,8 @@ int gde_dyn_destroy(gde_dyn *dy) {
     if (dy->s) (void)hipStreamSynchronize(dy->s);
     for (gde_dyn_query *q : dy->q) dyn_query_free(q);
     Workspace &w = dy->view;
-    void *p[] = {w.front[0], w.front[1], w.st, dy->blk, dy->total, dy->ev_src, dy->ev_off, dy->ev_dst, dy->ev_sign};
+    void *p[] = {w.front[0], w.front[1], w.st, dy->blk, dy->total, dy->ev_key, dy->ev_sorted, dy->ev_pos, dy->tmp,
+                 dy->nd_first, dy->nd_ins, dy->nd_del, dy->nd_deg, dy->d_err};
     for (void *v : p)
         if (v) (void)hipFree(v);
     det_ws_free(w.det);
@@ -540,8 +651,8 @@ int gde_dyn_destroy(gde_dyn *dy) {
         if (dy->d_rp[k]) (void)hipFree(dy->d_rp[k]);
         if (dy->d_ci[k]) (void)hipFree(dy->d_ci[k]);
     }
-    if (dy->h_rp) (void)hipHostFree(dy->h_rp);
-    if (dy->h_ci) (void)hipHostFree(dy->h_ci);
+    if (dy->h_key) (void)hipHostFree(dy->h_key);
+    if (dy->h_err) (void)hipHostFree(dy->h_err);
     delete dy;
     return GDE_OK;
 }

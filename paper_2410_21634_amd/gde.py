@@ -90,6 +90,8 @@ _SIGS = {
     "gde_ctx_destroy": ([_vp], C.c_int),
     "gde_graph_create": ([_vp, _i32, _i64, _vp, _vp, C.c_uint32, _vp, C.POINTER(_vp)], C.c_int),
     "gde_graph_destroy": ([_vp], C.c_int),
+    "gde_graph_info": ([_vp, C.POINTER(_i32), C.POINTER(_i64)], C.c_int),
+    "gde_graph_download": ([_vp, _vp, _vp], C.c_int),
     "gde_graph_lambda_max": ([_vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), _vp],
                              C.c_int),
     "gde_validate": ([_i32, _i64, _vp, _vp, C.POINTER(Params), C.POINTER(Seed)], C.c_int),
@@ -225,6 +227,15 @@ class Context:
             pass
 
 
+def _download_csr(handle):
+    n, nnz = _i32(), _i64()
+    _check(_lib.gde_graph_info(handle, C.byref(n), C.byref(nnz)))
+    rp = np.zeros(n.value + 1, np.int32)
+    ci = np.zeros(max(nnz.value, 1), np.int32)
+    _check(_lib.gde_graph_download(handle, rp.ctypes.data_as(_vp), ci.ctypes.data_as(_vp)))
+    return rp, ci[:nnz.value]
+
+
 class Graph:
     """A CSR graph on the context's device.  numpy arrays are copied; torch
     device tensors are borrowed (they must stay alive with the graph)."""
@@ -248,6 +259,10 @@ class Graph:
         self.handle = h
         self.n = int(n)
         self.nnz = int(nnz)
+
+    def csr(self):
+        """(row_ptr, col_idx) copied to host numpy arrays."""
+        return _download_csr(self.handle)
 
     def lambda_max(self, max_iters=500, rtol=1e-3, stream=None):
         lo, hi = C.c_double(), C.c_double()
@@ -512,6 +527,10 @@ class _GraphView:
 
     def __init__(self, ctx, handle, n):
         self.ctx, self.handle, self.n = ctx, handle, n
+
+    def csr(self):
+        """(row_ptr, col_idx) of this version copied to host numpy arrays (rows ascending)."""
+        return _download_csr(self.handle)
 
 
 class Dynamic:

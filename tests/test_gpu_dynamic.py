@@ -123,6 +123,9 @@ def test_dynamic_matches_oracle(gde, ctx, vt):
                                     minlength=G.n).max())
         E = (E | set(ins)) - set(dels)
         G2 = W.from_edges(G.n, sorted(E))
+        # the device-built version is exactly the new graph, rows ascending
+        rp2, ci2 = dyn.graph.csr()
+        assert np.array_equal(rp2, G2.row_ptr) and np.array_equal(ci2, G2.col_idx)
         d2 = np.diff(G2.row_ptr).astype(float)
         for j, (kind, kname, param, eps, sd) in enumerate(queries):
             x0, r0 = state[j]
@@ -196,6 +199,8 @@ def test_dynamic_rejects_bad_events(gde, ctx):
     with pytest.raises(gde.GDEError):
         dyn.update(insert=[missing, missing[::-1]])
     assert np.array_equal(dyn.read(q).dense(G.n), before)  # nothing changed
+    rp, ci = dyn.graph.csr()
+    assert np.array_equal(rp, G.row_ptr) and np.array_equal(ci, G.col_idx)
     with pytest.raises(gde.GDEError):
         dyn.add(gde.make_params("hk", value_type=gde.F64), [s])
     with pytest.raises(gde.GDEError):
