@@ -410,6 +410,11 @@ def c4_inputs(W):
     return G, seeds, eps
 
 
+# returning FP32 atomic adds to random words of a 16 GB array, 2^28 updates from
+# 1M threads, measured on MI355X (16.5 G/s; 20.9 G/s when the array is 32 MB)
+RANDOM_ATOMIC_RATE = 16.5e9
+
+
 def batch_push_bytes(prof, vsize=4):
     """Algorithmic bytes of the batched push launches (the batched rule): the
     column indices of every distinct CSR row pushed in a round, once, whatever
@@ -482,6 +487,11 @@ def run_c4(args):
                 timed_launches="every push launch of the timed batches, HIP events on the solve stream",
                 byte_rule="4 B per column index of each distinct row pushed in a round + 8 B per (edge, query) "
                           "residual read-modify-write")
+    # what bounds it: one memory-side atomic per (edge, query), against the rate of
+    # returning FP32 atomics to random words of a 16 GB array measured on MI355X
+    rate = prof["batch_lane_edges"] / pl / (push_ms * 1e-3) if push_ms > 0 else 0.0
+    roof["update_rate"] = dict(lane_edge_atomics_per_s=round(rate), random_atomic_rate_per_s=RANDOM_ATOMIC_RATE,
+                               frac=round(rate / RANDOM_ATOMIC_RATE, 4))
     kms = prof["batch_ms"] / max(prof["batch_launches"], 1)
     # the plain path on the same queries, one at a time
     oi = torch.empty(G.n, dtype=torch.int32, device=dev)

@@ -93,6 +93,8 @@ def residual_of(row_ptr, col_idx, kind, param, seeds, x):
 def test_dynamic_matches_oracle(gde, ctx, vt):
     G = W.chung_lu(3000, 15000, 2.4, seed=17)
     g = gde.Graph(ctx, G.row_ptr, G.col_idx)
+    rp0, ci0 = g.csr()  # gde_graph_download round trip
+    assert np.array_equal(rp0, G.row_ptr) and np.array_equal(ci0, G.col_idx)
     lo, hi = X.lambda_bounds_power(G.row_ptr, G.col_idx, iters=300)
     beta = 0.3 / hi
     seeds = [int(s) for s in W.uniform_seeds(G, 3, seed=18)]
