@@ -643,7 +643,8 @@ int solve_plain_ws(gde_ctx *ctx, const gde_graph *g, const gde_params *p, const 
         const long long nr = w->bin_nranges;
         const long long min_binned = std::max(kBinMinEdges, nr * nr / kBinRangeSqDiv);
         bins.min_edges = (p->flags & GDE_SCATTER_BINNED) ? 0 : min_binned;
-        if (p->flags & GDE_SCATTER_ATOMIC) bins.nranges = 0;
+        if ((p->flags & GDE_SCATTER_ATOMIC) || (nr < kBinMinRanges && !(p->flags & GDE_SCATTER_BINNED)))
+            bins.nranges = 0;
         // PPR LocalGD: no iteration can reach the binning threshold when the whole
         // work bound vol(supp s) + ||s||_1 / (alpha eps) (Corollary 3.5) stays below
         // it; then neither the binned path nor the range-reduction launches are needed
