@@ -450,7 +450,7 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     a.ch = ch ? 1 : 0;
     a.force = 0;
     a.probe = 0;
-    a.cand_all = warm ? 1 : 0;  // warm start: signed residuals, no forced S_0
+    a.sgn = warm ? 1 : 0;  // warm start: signed residuals, no forced S_0
     a.D = ch ? (V *)w->D : nullptr;
     a.PM = ch ? w->PM : nullptr;
     // LocalCH scalars (the plain solver's recurrence): t = 0 is the forced first

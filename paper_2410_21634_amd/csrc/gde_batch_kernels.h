@@ -95,9 +95,12 @@ struct BatchArgs {
     // 0); residuals are signed, so every touched lane is a candidate (NM) and a
     // pushed pair is a candidate of t + 1 itself
     int32_t ch, force, probe;
-    // warm start (standing queries): LocalGD steps with signed residuals, every
-    // touched lane a candidate, as for LocalCH but h = r
-    int32_t cand_all;
+    // warm start (standing queries): LocalGD steps with signed residuals: a lane
+    // is a candidate when an update lifts |r| across its threshold, the snapshot
+    // tests its candidates again (later updates may have lowered |r|), and the
+    // final pass takes residuals by exchange (one that cancels to +0.0 is listed
+    // again when it is touched next)
+    int32_t sgn;
     V c_t, m_t;
     V *D;          // [n][G][L] Delta, the last update of each lane
     uint32_t *PM;  // [n][G] lanes active when the pair was last snapshot

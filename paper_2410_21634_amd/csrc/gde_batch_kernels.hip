@@ -103,7 +103,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
             m = a.NM[(size_t)u * a.G + g];
-            mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | ((a.ch && !a.force) || a.cand_all ? 2 : 0));
+            mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | ((a.ch && !a.force) || a.sgn ? 2 : 0));
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
             ri = ((size_t)u * a.G + g) * L + l;
@@ -318,8 +318,10 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         for (int q = 0; q < kPer; q++) {
             new_act[q] = new_touch[q] = false;
             if (wq[q] >= 0) {
-                const bool cand = a.ch || a.cand_all || (a.g_mode && (a.g_mode[gq[q]] & 2));
-                hit[q] = cand || ((old[q] < th[q]) && (old[q] + dv[q] >= th[q]));
+                const bool cand = a.ch || (a.g_mode && (a.g_mode[gq[q]] & 2));
+                const V nw = old[q] + dv[q];
+                const bool cross = a.sgn ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q]) : (old[q] < th[q] && nw >= th[q]);
+                hit[q] = cand || cross;
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) {
                     // (a candidate lane is often marked already: read before the atomic)
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchArgs<V> a, doubl
                 V *rp = &R[((size_t)w * a.G + lane_id / L) * L + lane_id % L];
                 // LocalCH: a signed residual that cancelled to +0.0 is listed again when it
                 // is touched next, so the value is taken by exchange (once) there
-                val[q] = (a.ch || a.cand_all) ? batomic_take<V>(rp) : *rp;
+                val[q] = (a.ch || a.sgn) ? batomic_take<V>(rp) : *rp;
             }
         }
 #pragma unroll

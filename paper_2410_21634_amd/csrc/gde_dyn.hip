@@ -12,9 +12,9 @@
 // its first new edge); for Katz r_c += beta x_a or -= beta x_a; then (2) a
 // warm LocalGD re-solve of every query from its corrected state (S_0 = the
 // active nodes, residuals may be negative): the queries of one kind and
-// parameter run together as the lanes of one batch (every touched lane a
-// candidate, signed residuals), starting from and returning to the queries'
-// own state.  A query's first solve runs the fixed-order iterations of the
+// parameter run together as the lanes of one batch (signed residuals: a lane
+// whose |r| an update lifts across its threshold is a candidate, tested again
+// by the snapshot), starting from and returning to the queries' own state.  A query's first solve runs the fixed-order iterations of the
 // deterministic mode.  Everything in between stays resident: residuals,
 // estimates, touched and pushed bitmaps, degrees.
 //
