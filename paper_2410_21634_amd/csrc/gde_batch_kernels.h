@@ -92,8 +92,9 @@ struct BatchArgs {
     int32_t sym;      // M = D^-1/2 A D^-1/2: seeds scaled by sqrt(d), outputs by 1/sqrt(d)
     // LocalCH (ch != 0): every lane in iteration t applies h = c_t r + m_t Delta
     // (Delta kept only for lanes active in t - 1, PM), or h = r when force (t =
-    // 0); residuals are signed, so every touched lane is a candidate (NM) and a
-    // pushed pair is a candidate of t + 1 itself
+    // 0); residuals are signed: a lane whose |r| an update lifts across its
+    // threshold is a candidate (NM), a pushed pair is a candidate of t + 1
+    // itself, and the snapshot tests every candidate
     int32_t ch, force, probe;
     // warm start (standing queries): LocalGD steps with signed residuals: a lane
     // is a candidate when an update lifts |r| across its threshold, the snapshot

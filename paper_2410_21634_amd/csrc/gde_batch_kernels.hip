@@ -318,9 +318,11 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         for (int q = 0; q < kPer; q++) {
             new_act[q] = new_touch[q] = false;
             if (wq[q] >= 0) {
-                const bool cand = a.ch || (a.g_mode && (a.g_mode[gq[q]] & 2));
+                const bool cand = a.g_mode && (a.g_mode[gq[q]] & 2);
                 const V nw = old[q] + dv[q];
-                const bool cross = a.sgn ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q]) : (old[q] < th[q] && nw >= th[q]);
+                // signed residuals (LocalCH, warm start): |r| lifted across the threshold
+                const bool cross = (a.sgn || a.ch) ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q])
+                                                   : (old[q] < th[q] && nw >= th[q]);
                 hit[q] = cand || cross;
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) {
