@@ -318,18 +318,17 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         for (int q = 0; q < kPer; q++) {
             new_act[q] = new_touch[q] = false;
             if (wq[q] >= 0) {
-                const bool cand = a.g_mode && (a.g_mode[gq[q]] & 2);
                 const V nw = old[q] + dv[q];
-                // signed residuals (LocalCH, warm start): |r| lifted across the threshold
-                const bool cross = (a.sgn || a.ch) ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q])
-                                                   : (old[q] < th[q] && nw >= th[q]);
-                hit[q] = cand || cross;
+                // signed residuals (LocalCH, warm start, serving groups corrected for
+                // inserted edges): |r| lifted across the threshold
+                const bool sg = a.sgn || a.ch || (a.g_mode && (a.g_mode[gq[q]] & 2));
+                hit[q] = sg ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q]) : (old[q] < th[q] && nw >= th[q]);
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) {
-                    // (a candidate lane is often marked already: read before the atomic)
+                    // (a lane may be marked already, by its own push: read before the atomic)
                     uint32_t *nm = &a.NM[(size_t)wq[q] * a.G + gq[q]];
                     const uint32_t bit = 1u << lq[q];
-                    new_act[q] = !(cand && (*nm & bit)) && atomicOr(nm, bit) == 0u;
+                    new_act[q] = !(*nm & bit) && atomicOr(nm, bit) == 0u;
                 }
                 if (LT) {
                     new_touch[q] = first[q];
