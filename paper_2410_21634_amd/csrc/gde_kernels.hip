@@ -502,15 +502,25 @@ __device__ void push_edges(const int32_t *__restrict__ col_idx, RD<V> *dst, DevS
             continue;
         }
         if (MODE == 2) {
+            // signed residuals: w is a candidate of t+1 when an update lifts |r_w|
+            // across its threshold (every other node stays below it: the nodes of S_t
+            // were made candidates by the snapshot), deduplicated by the stamp; a
+            // first touch marks the touched bitmap
+            V th[kPer], old[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++)  // d is read-only during the push
+                th[q] = w[q] >= 0 ? eps_eff * dst[w[q]].d : (V)0;
 #pragma unroll
             for (int q = 0; q < kPer; q++)
-                if (w[q] >= 0) unsafeAtomicAdd(&dst[w[q]].r, dv[q]);
+                old[q] = w[q] >= 0 ? unsafeAtomicAdd(&dst[w[q]].r, dv[q]) : (V)0;
 #pragma unroll
-            for (int q = 0; q < kPer; q++)
-                if (w[q] >= 0 && cstamp[w[q]] != stamp_next) hit[q] = atomicExch(&cstamp[w[q]], stamp_next) != stamp_next;
-#pragma unroll
-            for (int q = 0; q < kPer; q++)
-                if (hit[q] && tbm) atomicOr(&tbm[w[q] >> 5], 1u << (w[q] & 31));
+            for (int q = 0; q < kPer; q++) {
+                if (w[q] < 0) continue;
+                const V nw = old[q] + dv[q];
+                hit[q] = fabs(old[q]) < th[q] && fabs(nw) >= th[q] && cstamp[w[q]] != stamp_next &&
+                         atomicExch(&cstamp[w[q]], stamp_next) != stamp_next;
+                if (tbm && old[q] == (V)0 && dv[q] != (V)0) atomicOr(&tbm[w[q] >> 5], 1u << (w[q] & 31));
+            }
         } else {
             V th[kPer], old[kPer];
 #pragma unroll
@@ -808,17 +818,21 @@ __global__ void __launch_bounds__(kSnapBlock) k_small(SmallArgs<V> a) {
                 }
             }
             bool hit[kEdgesPer];
-            if (CH) {
+            if (CH) {  // signed residuals: |r_w| lifted across the threshold (see k_push)
+                V th[kEdgesPer], old[kEdgesPer];
 #pragma unroll
-                for (int q = 0; q < kEdgesPer; q++)
-                    if (w[q] >= 0) unsafeAtomicAdd(&rd[w[q]].r, dv[q]);
+                for (int q = 0; q < kEdgesPer; q++) th[q] = w[q] >= 0 ? a.eps_eff * rd[w[q]].d : (V)0;
 #pragma unroll
-                for (int q = 0; q < kEdgesPer; q++)
-                    hit[q] = w[q] >= 0 && a.cstamp[w[q]] != stamp_next &&
+                for (int q = 0; q < kEdgesPer; q++) old[q] = w[q] >= 0 ? unsafeAtomicAdd(&rd[w[q]].r, dv[q]) : (V)0;
+#pragma unroll
+                for (int q = 0; q < kEdgesPer; q++) {
+                    hit[q] = false;
+                    if (w[q] < 0) continue;
+                    const V nw = old[q] + dv[q];
+                    hit[q] = fabs(old[q]) < th[q] && fabs(nw) >= th[q] && a.cstamp[w[q]] != stamp_next &&
                              atomicExch(&a.cstamp[w[q]], stamp_next) != stamp_next;
-#pragma unroll
-                for (int q = 0; q < kEdgesPer; q++)
-                    if (hit[q]) small_mark_later(w[q], a.tbm, s_tpend, &s_tpn);
+                    if (old[q] == (V)0 && dv[q] != (V)0) small_mark_later(w[q], a.tbm, s_tpend, &s_tpn);
+                }
             } else {
                 V th[kEdgesPer], old[kEdgesPer];
 #pragma unroll
