@@ -68,7 +68,7 @@ struct BatchArgs {
     int w_div_deg;
     // optional per-group overrides (serving mixes PPR and Katz groups in one launch):
     // g_wscale[g] replaces wscale; g_mode[g] bit 0 = divide by d_u (PPR), bit 1 =
-    // candidate mode (signed residuals: every touched lane is re-tested in the snapshot)
+    // candidate mode (signed residuals: lanes marked by |r| crossing the threshold, re-tested in the snapshot)
     const V *g_wscale;
     const int32_t *g_mode;
     long long *lane_ops, *lane_pushes;  // [G*L][kStatShards]

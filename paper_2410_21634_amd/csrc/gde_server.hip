@@ -22,7 +22,8 @@
 //         r_u -= k x_u / d0, x_u *= (d0 + k) / d0.
 //   Katz: Q = I - beta A gains -beta on (u,v) and (v,u): r_u += beta x_v, r_v += beta x_u.
 // The residuals can now be negative, so the affected groups continue in
-// candidate mode (every touched lane re-tested against |r| >= theta in the snapshot).
+// candidate mode: the corrected pairs are candidates, a lane whose |r| an update
+// lifts across its threshold becomes one, and the snapshot re-tests them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
