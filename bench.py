@@ -1045,7 +1045,8 @@ def main():
     ap.add_argument("--profile-every", type=int, default=8,
                     help="time the scatter launches of every k-th plain solve with HIP events")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="end with one 256 MiB device-to-device copy kernel, the calibration for HBM byte counters")
+                    help="end with one elementwise multiply over 2 GiB (2 GiB read, 2 GiB written), the calibration "
+                         "for the HBM byte counters")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)

@@ -325,10 +325,12 @@ __device__ void batch_push(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                 hit[q] = sg ? (fabs(old[q]) < th[q] && fabs(nw) >= th[q]) : (old[q] < th[q] && nw >= th[q]);
                 first[q] = LT ? (pos_zero(old[q]) && dv[q] != (V)0) : old[q] == (V)0;
                 if (hit[q]) {
-                    // (a lane may be marked already, by its own push: read before the atomic)
+                    // (signed: a lane may be marked already, by its own push or a second
+                    // crossing, so the mask is read before the atomic; a nonnegative
+                    // residual crosses once per push and its lane is never marked)
                     uint32_t *nm = &a.NM[(size_t)wq[q] * a.G + gq[q]];
                     const uint32_t bit = 1u << lq[q];
-                    new_act[q] = !(*nm & bit) && atomicOr(nm, bit) == 0u;
+                    new_act[q] = !(sg && (*nm & bit)) && atomicOr(nm, bit) == 0u;
                 }
                 if (LT) {
                     new_touch[q] = first[q];
