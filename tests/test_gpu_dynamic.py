@@ -209,3 +209,44 @@ def test_dynamic_rejects_bad_events(gde, ctx):
         dyn.add(gde.make_params("ppr", value_type=gde.F32), [s])
     dyn.close()
     g.close()
+
+
+def test_dynamic_unsorted_rows_and_large_batch(gde, ctx):
+    """A graph whose neighbour lists are not ascending: the dynamic copy sorts
+    them, and a batch of 5,000 inserts and 2,000 deletes gives exactly the new
+    graph (rows ascending), with every PPR query meeting the stop rule."""
+    G = W.chung_lu(20000, 100000, 2.3, seed=23)
+    rng = np.random.default_rng(24)
+    ci = G.col_idx.copy()
+    for u in range(G.n):  # shuffle each row
+        a, b = G.row_ptr[u], G.row_ptr[u + 1]
+        ci[a:b] = rng.permutation(ci[a:b])
+    g = gde.Graph(ctx, G.row_ptr, ci)
+    dyn = gde.Dynamic(ctx, g, value_type=gde.F64)
+    eps = 1e-6
+    seeds = [int(s) for s in W.uniform_seeds(G, 4, seed=25)]
+    qids = [dyn.add(gde.make_params("ppr", alpha=0.15, eps=eps, value_type=gde.F64), [s]) for s in seeds]
+    E = edge_set(G)
+    ins = set()
+    while len(ins) < 5000:
+        a, b = sorted(int(v) for v in rng.integers(0, G.n, 2))
+        if a != b and (a, b) not in E:
+            ins.add((a, b))
+    pool = sorted(E)
+    dels = [pool[j] for j in rng.choice(len(pool), 2000, replace=False)]
+    ins = sorted(ins)
+    dyn.update(insert=ins, delete=dels)
+    E2 = (E | set(ins)) - set(dels)
+    G2 = W.from_edges(G.n, sorted(E2))
+    rp2, ci2 = dyn.graph.csr()
+    assert np.array_equal(rp2, G2.row_ptr) and np.array_equal(ci2, G2.col_idx)
+    d2 = np.diff(G2.row_ptr).astype(float)
+    for q, s in zip(qids, seeds):
+        got = dyn.read(q)
+        assert got.status == gde.OK
+        x = got.dense(G.n)
+        r = residual_of(G2.row_ptr, G2.col_idx, O.PPR, 0.15, [s], x) / 0.15
+        assert (np.abs(r[d2 > 0]) < eps * d2[d2 > 0] * (1 + 1e-9) + 1e-15).all()
+    dyn.close()
+    g.close()
+
