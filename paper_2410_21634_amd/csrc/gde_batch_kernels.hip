@@ -85,64 +85,50 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         if (bid == 0 && threadIdx.x == 0) *ovf = 1;
         return;
     }
-    constexpr int PPW = kWave / L;  // pairs per wavefront
-    const int sub = blane() / L, l = blane() % L;
-    const int wpb = (int)blockDim.x / kWave;
+    // one thread per active (group, node) pair, its lanes in a loop over the mask:
+    // a pair rarely has more than one active lane, so a thread per lane would
+    // leave most threads idle and multiply the reservations
+    constexpr uint32_t kAll = (L == 32) ? 0xffffffffu : ((1u << L) - 1u);
     // workgroup-uniform trip count: every thread takes part in each reservation
-    for (int bbase = bid * wpb * PPW; bbase < nact; bbase += nblocks * wpb * PPW) {
-        const int i = bbase + ((int)threadIdx.x / kWave) * PPW + sub;
+    for (int bbase = bid * (int)blockDim.x; bbase < nact; bbase += nblocks * (int)blockDim.x) {
+        const int i = bbase + (int)threadIdx.x;
         const bool valid = i < nact;
         int32_t g = 0, u = 0, beg = 0, deg = 0;
-        uint32_t m = 0u;
-        V v = (V)0;
-        bool mine = false;
+        uint32_t pm = 0u, prev = 0u;
         int mode = 0;
-        size_t ri = 0;
+        size_t r0 = 0;  // the pair's lane 0
         if (valid) {
             const uint64_t p = a.act[cur][i];
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
-            m = a.NM[(size_t)u * a.G + g];
+            uint32_t *nm = &a.NM[(size_t)u * a.G + g];
+            const uint32_t m = *nm & kAll;
+            *nm = 0u;  // each pair is listed once
             mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | ((a.ch && !a.force) || a.sgn ? 2 : 0));
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
-            ri = ((size_t)u * a.G + g) * L + l;
-            mine = (m >> l) & 1u;
-            if (mine && (mode & 2)) {  // candidate mode: the threshold decides
-                const V r = Rs[ri];
-                mine = r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg;
+            r0 = ((size_t)u * a.G + g) * L;
+            if (mode & 2) {  // candidate mode: the threshold decides
+                for (uint32_t mm = m; mm; mm &= mm - 1u) {
+                    const int l = __ffs((int)mm) - 1;
+                    const V r = Rs[r0 + l];
+                    if (r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg) pm |= 1u << l;
+                }
+            } else {
+                pm = m;
             }
             if (a.probe) {  // LocalCH at the iteration cap: record active lanes, change nothing
-                if (mine) atomicOr(&a.group_unconv[g], 1u << l);
-                mine = false;
+                if (pm) atomicOr(&a.group_unconv[g], pm);
+                pm = 0u;
             }
-            if (mine && a.ch) {  // LocalCH: h = c_t r + m_t Delta (Delta of lanes active in t - 1)
-                const uint32_t prev = a.PM[(size_t)u * a.G + g];
-                const V r = Rs[ri];
-                const V h = a.force ? r : a.c_t * r + a.m_t * (((prev >> l) & 1u) ? a.D[ri] : (V)0);
-                const V rn = r - h;
-                Rs[ri] = rn == (V)0 ? (V)-0.0 : rn;  // a zero keeps the touched mark
-                a.X[ri] += h;
-                a.D[ri] = h;
-                v = h;
-            } else if (mine) {
-                v = Rs[ri];
-                Rs[ri] = LT ? (V)-0.0 : (V)0;  // -0.0: taken, already on the touched list
-                a.X[ri] += v;
+            if (a.ch) {  // the lanes active in t - 1 (their Delta counts), then those of t
+                prev = a.PM[(size_t)u * a.G + g];
+                a.PM[(size_t)u * a.G + g] = pm;
             }
+            if (pm) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
         }
-        // the pair's active lanes, from the wave ballot
-        const unsigned long long bal = __ballot(mine);
-        const uint32_t pm = (uint32_t)((bal >> (sub * L)) & ((L == 32) ? 0xffffffffull : ((1ull << L) - 1ull)));
         const int c = __popc(pm);
-        // the whole wave has read its masks: the pair leaders clear them (LocalCH:
-        // and record which lanes were active, for the next iteration's Delta)
-        if (valid && l == 0) {
-            a.NM[(size_t)u * a.G + g] = 0u;
-            if (a.ch) a.PM[(size_t)u * a.G + g] = pm;
-            if (c > 0) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
-        }
-        const bool leader = valid && l == 0 && c > 0;
+        const bool leader = valid && c > 0;
         if (a.row_stamp) {  // measurement: count each CSR row once per round (uniform branch)
             bool fresh_row = false;
             if (leader) fresh_row = atomicExch(&a.row_stamp[u], a.round_tag) != a.round_tag;
@@ -151,47 +137,59 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         const long long le = (leader && !a.no_push) ? (long long)deg * c : 0ll;
         const unsigned long long res =
             block_reserve64(leader ? ((1ull << 40) | (unsigned long long)le) : 0ull, &st->packed[cur]);
-        int slot = (int)(res >> 40);
+        if (!leader) continue;
+        const int slot = (int)(res >> 40);
         const long long off = (long long)(res & kLaneEdgeMask);
-        slot = __shfl(slot, sub * L);  // the pair's slot, from its leader
-        if (valid && c > 0) {
-            if (slot >= a.wl_cap) {
-                *ovf = 1;
+        if (slot >= a.wl_cap) {
+            *ovf = 1;
+            continue;
+        }
+        a.wl_node[slot] = u;
+        a.wl_group[slot] = g;
+        a.wl_beg[slot] = beg;
+        a.wl_off[slot] = off;
+        a.wl_c[slot] = c;
+        const long long end = off + le;
+        for (long long k = (off + kTile - 1) / kTile; k * kTile < end; k++) {
+            if (k < a.tile_cap) a.tile_start[k] = slot;
+            else *ovf = 1;
+        }
+        const V ws = a.g_wscale ? a.g_wscale[g] : a.wscale;
+        const V w = (mode & 1) ? ws / (V)deg : ws;
+        const int shard = bid & (kStatShards - 1);
+        int k = 0;
+        for (uint32_t mm = pm; mm; mm &= mm - 1u, k++) {
+            const int l = __ffs((int)mm) - 1;
+            const size_t ri = r0 + l;
+            V v;
+            if (a.ch) {  // LocalCH: h = c_t r + m_t Delta (Delta of lanes active in t - 1)
+                const V r = Rs[ri];
+                const V h = a.force ? r : a.c_t * r + a.m_t * (((prev >> l) & 1u) ? a.D[ri] : (V)0);
+                const V rn = r - h;
+                Rs[ri] = rn == (V)0 ? (V)-0.0 : rn;  // a zero keeps the touched mark
+                a.X[ri] += h;
+                a.D[ri] = h;
+                v = h;
             } else {
-                if (l == 0) {
-                    a.wl_node[slot] = u;
-                    a.wl_group[slot] = g;
-                    a.wl_beg[slot] = beg;
-                    a.wl_off[slot] = off;
-                    a.wl_c[slot] = c;
-                    const long long end = off + le;
-                    for (long long k = (off + kTile - 1) / kTile; k * kTile < end; k++) {
-                        if (k < a.tile_cap) a.tile_start[k] = slot;
-                        else *ovf = 1;
-                    }
-                }
-                if (mine) {
-                    const int k = __popc(pm & ((1u << l) - 1u));
-                    const V ws = a.g_wscale ? a.g_wscale[g] : a.wscale;
-                    const V w = (mode & 1) ? ws / (V)deg : ws;
-                    a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
-                    // level push: (c_{t+1} / c_t) v / d_u, in the order of the series' definition
-                    a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)deg : w * v;
-                    const int lane_id = g * L + l;
-                    const int shard = bid & (kStatShards - 1);
-                    atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
-                    atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)deg);
-                    if (a.lane_T[lane_id] < t + 1) atomicMax(&a.lane_T[lane_id], t + 1);
-                    if (a.tr_size && t < a.tr_cap) {
-                        atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);
-                        atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)deg);
-                    }
-                    if (a.tr_nodes) {
-                        // positions grow across iterations, so each S_t is one contiguous run
-                        const unsigned long long k2 = atomicAdd(&a.tr_ncount[lane_id], 1ull);
-                        if ((long long)k2 < a.tr_ncap[lane_id]) a.tr_nodes[a.tr_noff[lane_id] + (long long)k2] = u;
-                    }
-                }
+                v = Rs[ri];
+                Rs[ri] = LT ? (V)-0.0 : (V)0;  // -0.0: taken, already on the touched list
+                a.X[ri] += v;
+            }
+            a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
+            // level push: (c_{t+1} / c_t) v / d_u, in the order of the series' definition
+            a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)deg : w * v;
+            const int lane_id = g * L + l;
+            atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
+            atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)deg);
+            if (a.lane_T[lane_id] < t + 1) atomicMax(&a.lane_T[lane_id], t + 1);
+            if (a.tr_size && t < a.tr_cap) {
+                atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);
+                atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)deg);
+            }
+            if (a.tr_nodes) {
+                // positions grow across iterations, so each S_t is one contiguous run
+                const unsigned long long k2 = atomicAdd(&a.tr_ncount[lane_id], 1ull);
+                if ((long long)k2 < a.tr_ncap[lane_id]) a.tr_nodes[a.tr_noff[lane_id] + (long long)k2] = u;
             }
         }
     }
