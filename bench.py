@@ -246,8 +246,8 @@ def run_c2(args):
     batched = None
     if not args.no_batch and args.phase != "plain":
         gd_q = [(eps, s) for m, eps, s in queries if m == "gd"]
-        bparams = [params[("gd", eps)] for eps, _ in gd_q]
-        bseeds = [([s], None) for _, s in gd_q]
+        bparams = gde.params_array([params[("gd", eps)] for eps, _ in gd_q])
+        bseeds = np.array([s for _, s in gd_q], dtype=np.int32)  # one seed node per query
         sched = args.schedule
         bcap = G.n // 4
         bout = (torch.empty(len(gd_q) * bcap, dtype=torch.int32, device=dev),
@@ -278,8 +278,8 @@ def run_c2(args):
         # the LocalCH queries of the step as one batch as well (batched LocalCH)
         ch_q = [(eps, s) for m, eps, s in queries if m == "ch"]
         if ch_q:
-            cparams = [params[("ch", eps)] for eps, _ in ch_q]
-            cseeds = [([s], None) for _, s in ch_q]
+            cparams = gde.params_array([params[("ch", eps)] for eps, _ in ch_q])
+            cseeds = np.array([s for _, s in ch_q], dtype=np.int32)
             del bout
             # LocalCH's support can exceed n/4 at small eps: a full-length buffer per query
             cout = (torch.empty(len(ch_q) * G.n, dtype=torch.int32, device=dev),
@@ -447,11 +447,12 @@ def run_c4(args):
     ci = torch.from_numpy(G.col_idx).to(dev)
     g = gde.Graph(ctx, rp, ci)
     params = [gde.make_params("ppr", alpha=0.1, eps=float(e), value_type=gde.F32) for e in eps]
-    bseeds = [([int(s)], None) for s in seeds]
+    bparams = gde.params_array(params)  # built once: the calls only marshal
+    bseeds = np.asarray(seeds, dtype=np.int32)  # one seed node per query
     cap = 2_000_000
     bout = (torch.empty(B * cap, dtype=torch.int32, device=dev), torch.empty(B * cap, dtype=torch.float32, device=dev))
     for i in range(args.warmup):
-        gde.solve_batch(ctx, g, params, bseeds, schedule=args.schedule, out=bout)
+        gde.solve_batch(ctx, g, bparams, bseeds, schedule=args.schedule, out=bout)
         log(f"warmup batch {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True, reset=True)
@@ -459,7 +460,7 @@ def run_c4(args):
     per_batch = []
     for i in range(args.steps):
         tb = time.perf_counter()
-        res = gde.solve_batch(ctx, g, params, bseeds, schedule=args.schedule, out=bout)  # returns when done
+        res = gde.solve_batch(ctx, g, bparams, bseeds, schedule=args.schedule, out=bout)  # returns when done
         per_batch.append(time.perf_counter() - tb)
         log(f"timed batch {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
@@ -628,13 +629,14 @@ def sub_c3():
         out[name] = dict(solves_per_s=round(len(seeds) / t, 2), mean_ops=round(ops / len(seeds), 1))
         # the same query kind for 256 uniform seeds in one gde_solve_batch call
         # (Katz: batched LocalGD; heat kernel: the batched level push)
-        bseeds = [([int(s)], None) for s in W.uniform_seeds(G, 256, seed=43)]
+        bseeds = np.asarray(W.uniform_seeds(G, 256, seed=43), dtype=np.int32)
+        bparams = gde.params_array([p] * 256)
         bo = (torch.empty(256 * cap_b, dtype=torch.int32, device=dev),
               torch.empty(256 * cap_b, dtype=torch.float32, device=dev))
-        gde.solve_batch(ctx, g, [p] * 256, bseeds, out=bo)
+        gde.solve_batch(ctx, g, bparams, bseeds, out=bo)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res = gde.solve_batch(ctx, g, [p] * 256, bseeds, out=bo)
+        res = gde.solve_batch(ctx, g, bparams, bseeds, out=bo)
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         out[name].update(batched_256_solves_per_s=round(256 / t, 1), batched_mean_ops=round(float(res.ops.mean()), 1))

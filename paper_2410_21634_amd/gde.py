@@ -445,23 +445,45 @@ class BatchResults:
         return (self[i] for i in range(len(self)))
 
 
+def params_array(params_list):
+    """A ctypes ``Params * B`` array of the queries, for repeated solve_batch calls
+    on the same queries (built once instead of per call)."""
+    return (Params * len(params_list))(*params_list)
+
+
 def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None, schedule=None, stream=None,
                 raise_on_error=True, trace_cap=4096, nodes_cap=0, out=None) -> BatchResults:
-    """B queries in one call.  ``seeds``: list of (idx, val) pairs (val None = ones).
-    ``out``: optional flat (idx, val) torch device tensors split evenly between the
-    queries (the results stay in HBM).  Argument structs are filled vectorised."""
+    """B queries in one call.  ``params_list``: a sequence of Params, or a ctypes
+    ``Params * B`` array (copied, not changed).  ``seeds``: a list of (idx, val)
+    pairs (val None = ones), or a 1-D integer array with one seed node per query
+    (value 1).  ``out``: optional flat (idx, val) torch device tensors split evenly
+    between the queries (the results stay in HBM).  Argument structs are filled
+    vectorised."""
     B = len(params_list)
-    P = (Params * B)(*params_list)
+    P = (Params * B)()
+    if isinstance(params_list, C.Array) and params_list._type_ is Params:
+        C.memmove(P, params_list, C.sizeof(P))
+    else:
+        P = (Params * B)(*params_list)
     pv = np.frombuffer(P, dtype=_PAR_DT)
     if out is not None:
         pv["flags"] |= RESULT_DEVICE
-    idx_l = [np.atleast_1d(np.asarray(i, dtype=np.int32)) for i, _ in seeds]
-    lens = np.fromiter((len(x) for x in idx_l), dtype=np.int64, count=B)
-    offs = np.zeros(B, np.int64)
-    offs[1:] = np.cumsum(lens)[:-1]
-    cat_idx = np.ascontiguousarray(np.concatenate(idx_l), dtype=np.int32)
-    cat_val = np.ascontiguousarray(np.concatenate([np.ones(len(x)) if v is None else np.atleast_1d(np.asarray(v, np.float64))
-                                                   for x, (_, v) in zip(idx_l, seeds)]), dtype=np.float64)
+    if isinstance(seeds, np.ndarray) and seeds.ndim == 1:  # one seed node per query
+        if len(seeds) != B:
+            raise ValueError("one seed node per query expected")
+        lens = np.ones(B, np.int64)
+        offs = np.arange(B, dtype=np.int64)
+        cat_idx = np.ascontiguousarray(seeds, dtype=np.int32)
+        cat_val = np.ones(B, np.float64)
+    else:
+        idx_l = [np.atleast_1d(np.asarray(i, dtype=np.int32)) for i, _ in seeds]
+        lens = np.fromiter((len(x) for x in idx_l), dtype=np.int64, count=B)
+        offs = np.zeros(B, np.int64)
+        offs[1:] = np.cumsum(lens)[:-1]
+        cat_idx = np.ascontiguousarray(np.concatenate(idx_l), dtype=np.int32)
+        cat_val = np.ascontiguousarray(np.concatenate([np.ones(len(x)) if v is None else
+                                                       np.atleast_1d(np.asarray(v, np.float64))
+                                                       for x, (_, v) in zip(idx_l, seeds)]), dtype=np.float64)
     S = (Seed * B)()
     sv = np.frombuffer(S, dtype=_SEED_DT)
     sv["nnz"] = lens
@@ -469,7 +491,7 @@ def solve_batch(ctx: Context, graph: Graph, params_list, seeds, *, capacity=None
     sv["val"] = cat_val.ctypes.data + 8 * offs
     R = (Result * B)()
     rv = np.frombuffer(R, dtype=_RES_DT)
-    vt = np.array([p.value_type for p in params_list])
+    vt = pv["value_type"].copy()
     if out is not None:
         cap = out[0].numel() // B if capacity is None else capacity
         esize = out[1].element_size()

@@ -162,6 +162,28 @@ def test_batch_alone_equals_in_mix(gde, ctx, c1):
         assert np.abs(plain.val - mix[k].val).sum() <= 1e-12
 
 
+def test_batch_array_arguments(gde, ctx, c1):
+    # a prebuilt Params array and a 1-D seed array give the same solves as the lists
+    G, g = c1
+    seeds = [int(s) for s in W.uniform_seeds(G, 24, seed=5)]
+    params = [gde.make_params("ppr", alpha=0.1, eps=1e-5 * (1 + k % 3), value_type=gde.F64) for k in range(24)]
+    ref = gde.solve_batch(ctx, g, params, [([s], None) for s in seeds])
+    parr = gde.params_array(params)
+    got = gde.solve_batch(ctx, g, parr, np.asarray(seeds, dtype=np.int32))
+    assert np.array_equal(got.iters, ref.iters) and np.array_equal(got.ops, ref.ops)
+    for k in range(24):
+        np.testing.assert_array_equal(got[k].idx, ref[k].idx)
+        assert np.abs(got[k].val - ref[k].val).sum() <= 1e-12
+    import torch
+    bo = (torch.empty(24 * G.n, dtype=torch.int32, device="cuda:0"),
+          torch.empty(24 * G.n, dtype=torch.float64, device="cuda:0"))
+    dev = gde.solve_batch(ctx, g, parr, np.asarray(seeds, dtype=np.int32), out=bo)  # sets RESULT_DEVICE in its copy
+    assert np.array_equal(dev.ops, ref.ops)
+    assert np.frombuffer(parr, dtype=gde._PAR_DT)["flags"].max() == 0  # the caller's array is not changed
+    with pytest.raises(ValueError):
+        gde.solve_batch(ctx, g, parr, np.asarray(seeds[:5], dtype=np.int32))
+
+
 def test_batch_status_paths(gde, ctx, c1):
     G, g = c1
     queries = make_queries(G, 20, seed=4)
