@@ -85,38 +85,59 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         if (bid == 0 && threadIdx.x == 0) *ovf = 1;
         return;
     }
-    // one thread per active (group, node) pair, its lanes in a loop over the mask:
-    // a pair rarely has more than one active lane, so a thread per lane would
-    // leave most threads idle and multiply the reservations
+    // one thread per active (group, node) pair for the masks and the reservation;
+    // then the wavefront spreads its pairs' pushed lanes over its 64 lanes (a pair
+    // has one active lane on a batch of unrelated queries and up to L on one of
+    // overlapping queries, so neither a thread per pair nor a thread per lane
+    // keeps the wavefront busy in both cases)
     constexpr uint32_t kAll = (L == 32) ? 0xffffffffu : ((1u << L) - 1u);
+    __shared__ uint32_t s_pm[kBatchSnapBlock];  // candidate mode: the lanes that pass, per pair
     // workgroup-uniform trip count: every thread takes part in each reservation
     for (int bbase = bid * (int)blockDim.x; bbase < nact; bbase += nblocks * (int)blockDim.x) {
         const int i = bbase + (int)threadIdx.x;
         const bool valid = i < nact;
         int32_t g = 0, u = 0, beg = 0, deg = 0;
-        uint32_t pm = 0u, prev = 0u;
+        uint32_t m = 0u, pm = 0u, prev = 0u;
         int mode = 0;
-        size_t r0 = 0;  // the pair's lane 0
         if (valid) {
             const uint64_t p = a.act[cur][i];
             g = (int32_t)(p >> 32);
             u = (int32_t)(p & 0xffffffffull);
             uint32_t *nm = &a.NM[(size_t)u * a.G + g];
-            const uint32_t m = *nm & kAll;
+            m = *nm & kAll;
             *nm = 0u;  // each pair is listed once
             mode = a.g_mode ? a.g_mode[g] : ((a.w_div_deg ? 1 : 0) | ((a.ch && !a.force) || a.sgn ? 2 : 0));
             beg = a.row_ptr[u];
             deg = a.row_ptr[u + 1] - beg;
-            r0 = ((size_t)u * a.G + g) * L;
-            if (mode & 2) {  // candidate mode: the threshold decides
-                for (uint32_t mm = m; mm; mm &= mm - 1u) {
-                    const int l = __ffs((int)mm) - 1;
-                    const V r = Rs[r0 + l];
-                    if (r != (V)0 && fabs(r) >= a.lane_eps[g * L + l] * (V)deg) pm |= 1u << l;
-                }
-            } else {
-                pm = m;
+        }
+        // candidate mode: the threshold decides, lane by lane, the wavefront's
+        // candidate lanes spread over its 64 lanes as in the pushes below
+        s_pm[threadIdx.x] = 0u;
+        {
+            const int cm = (valid && (mode & 2)) ? __popc(m) : 0;
+            const int cincl = (int)wave_incl_scan64((unsigned long long)cm);
+            const int ctotal = __shfl(cincl, kWave - 1);
+            const int wbase = (int)threadIdx.x - blane();
+            for (int tb = 0; tb < ctotal; tb += kWave) {  // uniform over the wavefront
+                const int task = tb + blane();
+                int src = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    if (__shfl(cincl, src + step - 1) <= task) src += step;
+                const int k = task - __shfl(cincl - cm, src);
+                const uint32_t msrc = (uint32_t)__shfl((int)m, src);
+                const int32_t gs = __shfl(g, src), us = __shfl(u, src), ds = __shfl(deg, src);
+                if (task >= ctotal) continue;
+                uint32_t mm = msrc;
+                for (int j = 0; j < k; j++) mm &= mm - 1u;
+                const int l = __ffs((int)mm) - 1;
+                const V r = Rs[((size_t)us * a.G + gs) * L + l];
+                if (r != (V)0 && fabs(r) >= a.lane_eps[gs * L + l] * (V)ds) atomicOr(&s_pm[wbase + src], 1u << l);
             }
+        }
+        __syncthreads();
+        if (valid) {
+            pm = (mode & 2) ? s_pm[threadIdx.x] : m;
             if (a.probe) {  // LocalCH at the iteration cap: record active lanes, change nothing
                 if (pm) atomicOr(&a.group_unconv[g], pm);
                 pm = 0u;
@@ -128,7 +149,7 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             if (pm) atomicOr(&a.PB[(size_t)g * a.nwords + (u >> 5)], 1u << (u & 31));
         }
         const int c = __popc(pm);
-        const bool leader = valid && c > 0;
+        bool leader = valid && c > 0;
         if (a.row_stamp) {  // measurement: count each CSR row once per round (uniform branch)
             bool fresh_row = false;
             if (leader) fresh_row = atomicExch(&a.row_stamp[u], a.round_tag) != a.round_tag;
@@ -137,34 +158,52 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
         const long long le = (leader && !a.no_push) ? (long long)deg * c : 0ll;
         const unsigned long long res =
             block_reserve64(leader ? ((1ull << 40) | (unsigned long long)le) : 0ull, &st->packed[cur]);
-        if (!leader) continue;
-        const int slot = (int)(res >> 40);
-        const long long off = (long long)(res & kLaneEdgeMask);
-        if (slot >= a.wl_cap) {
+        const int slot0 = (int)(res >> 40);
+        if (leader && slot0 >= a.wl_cap) {
             *ovf = 1;
-            continue;
+            leader = false;
         }
-        a.wl_node[slot] = u;
-        a.wl_group[slot] = g;
-        a.wl_beg[slot] = beg;
-        a.wl_off[slot] = off;
-        a.wl_c[slot] = c;
-        const long long end = off + le;
-        for (long long k = (off + kTile - 1) / kTile; k * kTile < end; k++) {
-            if (k < a.tile_cap) a.tile_start[k] = slot;
-            else *ovf = 1;
+        if (leader) {
+            const long long off = (long long)(res & kLaneEdgeMask);
+            a.wl_node[slot0] = u;
+            a.wl_group[slot0] = g;
+            a.wl_beg[slot0] = beg;
+            a.wl_off[slot0] = off;
+            a.wl_c[slot0] = c;
+            const long long end = off + le;
+            for (long long k = (off + kTile - 1) / kTile; k * kTile < end; k++) {
+                if (k < a.tile_cap) a.tile_start[k] = slot0;
+                else *ovf = 1;
+            }
         }
-        const V ws = a.g_wscale ? a.g_wscale[g] : a.wscale;
-        const V w = (mode & 1) ? ws / (V)deg : ws;
+        // the wavefront's pushed lanes as tasks 0 .. total-1, pair by pair
+        const int cc = leader ? c : 0;
+        const int incl = (int)wave_incl_scan64((unsigned long long)cc);
+        const int excl = incl - cc;
+        const int total = __shfl(incl, kWave - 1);
         const int shard = bid & (kStatShards - 1);
-        int k = 0;
-        for (uint32_t mm = pm; mm; mm &= mm - 1u, k++) {
+        for (int tb = 0; tb < total; tb += kWave) {  // uniform over the wavefront
+            const int task = tb + blane();
+            // the pair holding this task: the number of lanes whose count ends at or before it
+            int src = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (__shfl(incl, src + step - 1) <= task) src += step;
+            const int k = task - __shfl(excl, src);
+            const uint32_t pms = (uint32_t)__shfl((int)pm, src);
+            const int slot = __shfl(slot0, src);
+            const int32_t gs = __shfl(g, src), us = __shfl(u, src), ds = __shfl(deg, src);
+            const int ms = __shfl(mode, src);
+            const uint32_t prevs = (uint32_t)__shfl((int)prev, src);
+            if (task >= total) continue;
+            uint32_t mm = pms;  // its k-th active lane
+            for (int j = 0; j < k; j++) mm &= mm - 1u;
             const int l = __ffs((int)mm) - 1;
-            const size_t ri = r0 + l;
+            const size_t ri = ((size_t)us * a.G + gs) * L + l;
             V v;
             if (a.ch) {  // LocalCH: h = c_t r + m_t Delta (Delta of lanes active in t - 1)
                 const V r = Rs[ri];
-                const V h = a.force ? r : a.c_t * r + a.m_t * (((prev >> l) & 1u) ? a.D[ri] : (V)0);
+                const V h = a.force ? r : a.c_t * r + a.m_t * (((prevs >> l) & 1u) ? a.D[ri] : (V)0);
                 const V rn = r - h;
                 Rs[ri] = rn == (V)0 ? (V)-0.0 : rn;  // a zero keeps the touched mark
                 a.X[ri] += h;
@@ -175,21 +214,23 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
                 Rs[ri] = LT ? (V)-0.0 : (V)0;  // -0.0: taken, already on the touched list
                 a.X[ri] += v;
             }
+            const V ws = a.g_wscale ? a.g_wscale[gs] : a.wscale;
+            const V w = (ms & 1) ? ws / (V)ds : ws;
             a.wl_lanes[(size_t)slot * L + k] = (uint8_t)l;
             // level push: (c_{t+1} / c_t) v / d_u, in the order of the series' definition
-            a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)deg : w * v;
-            const int lane_id = g * L + l;
+            a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)ds : w * v;
+            const int lane_id = gs * L + l;
             atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
-            atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)deg);
+            atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)ds);
             if (a.lane_T[lane_id] < t + 1) atomicMax(&a.lane_T[lane_id], t + 1);
             if (a.tr_size && t < a.tr_cap) {
                 atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);
-                atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)deg);
+                atomicAdd((unsigned long long *)&a.tr_vol[(size_t)lane_id * a.tr_cap + t], (unsigned long long)ds);
             }
             if (a.tr_nodes) {
                 // positions grow across iterations, so each S_t is one contiguous run
                 const unsigned long long k2 = atomicAdd(&a.tr_ncount[lane_id], 1ull);
-                if ((long long)k2 < a.tr_ncap[lane_id]) a.tr_nodes[a.tr_noff[lane_id] + (long long)k2] = u;
+                if ((long long)k2 < a.tr_ncap[lane_id]) a.tr_nodes[a.tr_noff[lane_id] + (long long)k2] = us;
             }
         }
     }
