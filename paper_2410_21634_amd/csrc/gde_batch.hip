@@ -37,7 +37,7 @@ struct BatchWS {
     int32_t *wl_node = nullptr, *wl_group = nullptr, *wl_beg = nullptr, *wl_c = nullptr, *tile_start = nullptr;
     long long *wl_off = nullptr;
     uint8_t *wl_lanes = nullptr;
-    long long *lane_ops = nullptr, *lane_pushes = nullptr, *lane_nnz = nullptr, *lane_out_off = nullptr;
+    long long *lane_ops = nullptr, *lane_nnz = nullptr, *lane_out_off = nullptr;
     int32_t *lane_T = nullptr, *cnt = nullptr, *sub_flag = nullptr;
     double *lane_l1 = nullptr;
     unsigned long long *lane_dinf = nullptr;
@@ -60,7 +60,7 @@ struct BatchWS {
 void batch_ws_free(BatchWS *w) {
     void *p[] = {w->R, w->R2, w->X, w->deg, w->col_deg, w->D, w->PM, w->lane_eps, w->wl_sv, w->out_val, w->NM, w->TM, w->PB, w->group_unconv,
                  w->act[0], w->act[1], w->touched, w->touched2, w->tdeg, w->tdeg2, w->wl_node, w->wl_group, w->wl_beg, w->wl_c, w->tile_start,
-                 w->wl_off, w->wl_lanes, w->lane_ops, w->lane_pushes, w->lane_nnz, w->lane_out_off, w->lane_T,
+                 w->wl_off, w->wl_lanes, w->lane_ops, w->lane_nnz, w->lane_out_off, w->lane_T,
                  w->cnt, w->sub_flag, w->lane_l1, w->lane_dinf, w->st, w->s_lane, w->s_node, w->s_val, w->out_idx,
                  w->lane_dst, w->warm_ptr, w->row_stamp};
     for (void *q : p)
@@ -178,7 +178,6 @@ static int batch_ws_get(gde_ctx *ctx, const gde_graph *g, int vtype, int L, int 
     BALLOC(w->wl_sv, (size_t)w->wl_cap * L * w->vs);
     BALLOC(w->tile_start, (size_t)w->tile_cap * 4);
     BALLOC(w->lane_ops, (size_t)GL * kStatShards * 8);
-    BALLOC(w->lane_pushes, (size_t)GL * kStatShards * 8);
     BALLOC(w->lane_l1, (size_t)GL * kStatShards * 8);
     BALLOC(w->lane_T, (size_t)GL * 4);
     BALLOC(w->lane_dinf, (size_t)GL * 8);
@@ -234,7 +233,6 @@ void batch_args_from_ws(BatchWS *w, const gde_graph *g, int G, BatchArgs<float> 
     a->tile_cap = w->tile_cap;
     a->lane_eps = (const float *)w->lane_eps;
     a->lane_ops = w->lane_ops;
-    a->lane_pushes = w->lane_pushes;
     a->lane_T = w->lane_T;
     a->lane_l1 = w->lane_l1;
     a->lane_dinf = w->lane_dinf;
@@ -394,7 +392,6 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
     const size_t GL = (size_t)G * L;
     GDE_HIP(hipMemsetAsync(w->st, 0, sizeof(BatchDev), s));
     GDE_HIP(hipMemsetAsync(w->lane_ops, 0, GL * kStatShards * 8, s));
-    GDE_HIP(hipMemsetAsync(w->lane_pushes, 0, GL * kStatShards * 8, s));
     GDE_HIP(hipMemsetAsync(w->lane_l1, 0, GL * kStatShards * 8, s));
     GDE_HIP(hipMemsetAsync(w->lane_T, 0, GL * 4, s));
     GDE_HIP(hipMemsetAsync(w->lane_dinf, 0, GL * 8, s));
@@ -465,7 +462,6 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         ch_dlt = 1.0 / ch_sigma;
     }
     a.lane_ops = w->lane_ops;
-    a.lane_pushes = w->lane_pushes;
     a.lane_T = w->lane_T;
     a.lane_l1 = w->lane_l1;
     a.lane_dinf = w->lane_dinf;
@@ -669,13 +665,12 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
             }
         }
     }
-    std::vector<long long> ops(GL * kStatShards), pushes(GL * kStatShards);
+    std::vector<long long> ops(GL * kStatShards);
     std::vector<double> l1(GL * kStatShards);
     std::vector<int32_t> T(GL);
     std::vector<unsigned long long> dinf(GL);
     std::vector<uint32_t> unconv(G);
     GDE_HIP(hipMemcpyAsync(ops.data(), w->lane_ops, 8 * ops.size(), hipMemcpyDeviceToHost, s));
-    GDE_HIP(hipMemcpyAsync(pushes.data(), w->lane_pushes, 8 * pushes.size(), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipMemcpyAsync(l1.data(), w->lane_l1, 8 * l1.size(), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipMemcpyAsync(T.data(), w->lane_T, 4 * T.size(), hipMemcpyDeviceToHost, s));
     GDE_HIP(hipMemcpyAsync(dinf.data(), w->lane_dinf, 8 * dinf.size(), hipMemcpyDeviceToHost, s));
@@ -706,8 +701,9 @@ static int solve_batch_fused(gde_ctx *ctx, const gde_graph *g, int32_t B, const 
         long long so = 0, sp = 0;
         double sl = 0.0;
         for (int sh = 0; sh < kStatShards; sh++) {
-            so += ops[(size_t)j * kStatShards + sh];
-            sp += pushes[(size_t)j * kStatShards + sh];
+            const unsigned long long po = (unsigned long long)ops[(size_t)j * kStatShards + sh];
+            so += (long long)(po & kOpsMask);
+            sp += (long long)(po >> (64 - kPushBits));
             sl += l1[(size_t)j * kStatShards + sh];
         }
         r.nnz = nnz[j];

@@ -10,6 +10,10 @@
 namespace gde {
 
 constexpr int kStatShards = 64;  // per-lane counters are sharded to spread atomics
+// a lane's pushes and operations share one 64-bit counter per shard (one atomic
+// per push): pushes in the top kPushBits bits, operations (sum of d_u) below
+constexpr int kPushBits = 26;
+constexpr unsigned long long kOpsMask = (1ull << (64 - kPushBits)) - 1ull;
 constexpr int kResLdsLanes = 4096;  // lanes whose residual norms a workgroup can sum in LDS (64 KB)
 
 struct BatchDev {
@@ -71,7 +75,7 @@ struct BatchArgs {
     // candidate mode (signed residuals: lanes marked by |r| crossing the threshold, re-tested in the snapshot)
     const V *g_wscale;
     const int32_t *g_mode;
-    long long *lane_ops, *lane_pushes;  // [G*L][kStatShards]
+    long long *lane_ops;  // [G*L][kStatShards]: pushes and operations (kPushBits)
     int32_t *lane_T;                    // [G*L]
     double *lane_l1;                    // [G*L][kStatShards]
     unsigned long long *lane_dinf;      // [G*L]

@@ -220,8 +220,8 @@ __device__ void batch_snap(const BatchArgs<V> &a, int t, int bid, int nblocks) {
             // level push: (c_{t+1} / c_t) v / d_u, in the order of the series' definition
             a.wl_sv[(size_t)slot * L + k] = a.R2 ? (ws * v) / (V)ds : w * v;
             const int lane_id = gs * L + l;
-            atomicAdd((unsigned long long *)&a.lane_pushes[(size_t)lane_id * kStatShards + shard], 1ull);
-            atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard], (unsigned long long)ds);
+            atomicAdd((unsigned long long *)&a.lane_ops[(size_t)lane_id * kStatShards + shard],
+                      (1ull << (64 - kPushBits)) | (unsigned long long)ds);
             if (a.lane_T[lane_id] < t + 1) atomicMax(&a.lane_T[lane_id], t + 1);
             if (a.tr_size && t < a.tr_cap) {
                 atomicAdd((unsigned long long *)&a.tr_size[(size_t)lane_id * a.tr_cap + t], 1ull);

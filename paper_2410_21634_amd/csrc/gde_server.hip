@@ -527,7 +527,6 @@ static int srv_admit(gde_server *sv) {
         }
         const size_t lo = (size_t)gi * sv->L;
         GDE_HIP(hipMemsetAsync(a.lane_ops + lo * kStatShards, 0, 8 * sv->L * kStatShards, sv->s));
-        GDE_HIP(hipMemsetAsync(a.lane_pushes + lo * kStatShards, 0, 8 * sv->L * kStatShards, sv->s));
         GDE_HIP(hipMemsetAsync(a.lane_l1 + lo * kStatShards, 0, 8 * sv->L * kStatShards, sv->s));
         GDE_HIP(hipMemsetAsync(a.lane_T + lo, 0, 4 * sv->L, sv->s));
         GDE_HIP(hipMemsetAsync(a.lane_dinf + lo, 0, 8 * sv->L, sv->s));
@@ -620,7 +619,6 @@ static int srv_harvest(gde_server *sv, const std::vector<int> &hv_groups, const 
         GDE_HIP(hipMemcpyAsync(h_val.data(), sv->d_out_val, 4 * total, hipMemcpyDeviceToHost, sv->s));
     }
     const size_t GL = (size_t)G * L;
-    std::vector<long long> ops(GL * kStatShards), pushes(GL * kStatShards);
     std::vector<double> l1(GL * kStatShards);
     std::vector<int32_t> T(GL);
     std::vector<unsigned long long> dinf(GL);
